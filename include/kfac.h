@@ -1,0 +1,174 @@
+/*
+ * kfac.h -- C ABI of libkfac.so, the MI355X (gfx950) K-factor pipeline of Randomized
+ * K-FAC (Puiu, "Randomized K-FACs: Speeding up K-FAC with Randomized Numerical Linear
+ * Algebra", arXiv 2206.15397).
+ *
+ * Conventions shared by every entry point
+ *  - Every data pointer is a DEVICE pointer into memory the caller allocated and owns
+ *    (hipMalloc / a PyTorch tensor).  The library never allocates device memory and
+ *    never frees caller memory; scratch comes from the caller through `workspace`
+ *    (size from the matching *_workspace query; a larger buffer is fine).
+ *  - Matrices are row-major; a leading dimension (ld*) is the distance in elements
+ *    between consecutive rows and must be >= the row length.
+ *  - All calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL is the
+ *    default stream).  A call returns after enqueueing; results are ready once the
+ *    stream has been synchronised.
+ *  - Argument errors are reported synchronously as KFAC_EINVAL before anything is
+ *    enqueued; KFAC_EWORKSPACE if the workspace is smaller than the query says;
+ *    KFAC_EHIP if a launch failed; KFAC_EUNSUPPORTED for sizes beyond the compiled
+ *    limits (sketch width l = min(r+p, d) > KFAC_MAX_SKETCH).
+ *  - Conditions only the device can see (Cholesky breakdown, non-finite values,
+ *    eigensolver non-convergence) are OR-ed as bits into *dev_status (int32, device
+ *    memory, caller clears it); read it after synchronising the stream.
+ *  - Calls on different streams with disjoint buffers may run concurrently.  Calls that
+ *    share a workspace must be ordered on one stream.
+ */
+#ifndef KFAC_H
+#define KFAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KFAC_OK = 0,
+  KFAC_EINVAL = 1,
+  KFAC_EWORKSPACE = 2,
+  KFAC_EHIP = 3,
+  KFAC_EUNSUPPORTED = 4
+} kfac_status;
+
+typedef enum { KFAC_FP32 = 0, KFAC_BF16 = 1 } kfac_dtype;
+
+/* Which randomized decomposition.  SREVD is Alg. 3 (Rayleigh-Ritz on Q^T F Q), used by
+ * SRE-KFAC (Alg. 5).  RSVD (Alg. 2, Alg. 4) is reserved and currently returns
+ * KFAC_EUNSUPPORTED. */
+typedef enum { KFAC_SREVD = 0, KFAC_RSVD = 1 } kfac_variant;
+
+/* Precision of the sketch and power-iteration products F*Omega, F*Q (Alg. 3 "Compute
+ * X Omega" and the power iterations of Sec. 2.2).  KFAC_SKETCH_FP32: fp32 operands on
+ * fp32 MFMA.  KFAC_SKETCH_BF16: bf16 operands (a bf16 copy of F supplied by the caller,
+ * e.g. the shadow written by kfac_ea_update) with fp32 accumulation.  In both cases the
+ * Gram matrices, Cholesky factors and the (r+p)x(r+p) Rayleigh-Ritz eigensolve are fp64
+ * and the Rayleigh-Ritz product F*Q is fp32. */
+typedef enum { KFAC_SKETCH_FP32 = 0, KFAC_SKETCH_BF16 = 1 } kfac_precision;
+
+#define KFAC_MAX_SKETCH 512   /* largest l = min(r+p, d) handled by the fp64 eigensolver */
+
+/* device status bits (OR-ed into *dev_status) */
+#define KFAC_DS_CHOL_SHIFTED 0x1  /* a CholeskyQR Gram was not numerically SPD; a shift was
+                                      added (shifted CholeskyQR) and the pass repeated      */
+#define KFAC_DS_CHOL_FAILED  0x2  /* breakdown even after the shift: outputs are undefined  */
+#define KFAC_DS_NONFINITE    0x4  /* NaN/Inf met in a Gram or projected matrix               */
+#define KFAC_DS_EIG_NOCONV   0x8  /* small eigensolver hit its iteration cap                 */
+
+typedef void* kfac_stream_t; /* hipStream_t */
+
+/* Text for a status code (static storage, never NULL). */
+const char* kfac_status_string(kfac_status s);
+
+/* Library / device build information, e.g. "libkfac gfx950 hip 7.2".  Static string. */
+const char* kfac_build_info(void);
+
+/*
+ * kfac_fill_identity -- F <- I (d x d, fp32, ldf).  The EA K-factors start from the
+ * identity (Alg. 1: the EA factors at step -1 are I).
+ */
+kfac_status kfac_fill_identity(float* F, int64_t d, int64_t ldf, kfac_stream_t stream);
+
+/*
+ * kfac_ea_update -- exponential-average K-factor update (Alg. 1, forward line
+ * A_k <- rho A_{k-1} + (1-rho) A A^T and backward line for Gamma; matrix form in Sec. 3):
+ *
+ *     F <- rho * F + (1 - rho) * scale * Xh^T Xh,     Xh = [X | 1] if append_ones else X
+ *
+ *  F        d x d fp32 (ldf >= d), symmetric on entry; both triangles are written, so
+ *           it stays exactly symmetric.  d must equal d_in + append_ones.
+ *  X        n x d_in activations (forward factor: layer inputs a; backward factor:
+ *           back-propagated pre-activation gradients g), one sample per row, ldx >= d_in,
+ *           dtype xtype (fp32 or bf16).  n == 0 means "no samples": F <- rho F.
+ *  rho      EA decay in [0, 1).   scale > 0, normally 1/n.
+ *  F_bf16   optional (NULL allowed) bf16 shadow of the updated F, d x d, ldfb >= d,
+ *           rounded to nearest even; it feeds the bf16 sketch of kfac_rand_eig.
+ *  workspace/ws_bytes: scratch for split-K partial sums; size from
+ *           kfac_ea_update_workspace(d, n).  A NULL/0 workspace is allowed and disables
+ *           split-K (slower for small d and large n, identical results up to the
+ *           summation order).
+ */
+size_t kfac_ea_update_workspace(int64_t d, int64_t n);
+kfac_status kfac_ea_update(float* F, int64_t d, int64_t ldf,
+                           const void* X, kfac_dtype xtype, int64_t n, int64_t d_in, int64_t ldx,
+                           int append_ones, float rho, float scale,
+                           uint16_t* F_bf16, int64_t ldfb,
+                           void* workspace, size_t ws_bytes, kfac_stream_t stream);
+
+/*
+ * kfac_gaussian_omega -- the Gaussian test matrix Omega of Alg. 2/3 ("Sample Gaussian
+ * Matrix"), materialised for inspection.  Omega_ij for row i < d, column j < l comes
+ * from Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
+ * (i, j/4, stream_id mod 2^32, inversion_index); the four words w_t give uniforms
+ * u_t = ((w_t >> 9) + 1/2) 2^-23 and the Box-Muller pairs
+ * (z0,z1) = sqrt(-2 ln u0)(cos 2pi u1, sin 2pi u1), (z2,z3) likewise from (u2,u3);
+ * Omega_ij = z_{j mod 4}.  kfac_rand_eig draws the same Omega internally.
+ *  Omega    d x l fp32, ldo >= l (may be NULL if only words are wanted).
+ *  words    optional (NULL allowed) d x ceil(l/4) x 4 uint32 raw Philox words.
+ */
+kfac_status kfac_gaussian_omega(float* Omega, int64_t d, int64_t l, int64_t ldo,
+                                uint64_t seed, uint64_t stream_id, uint32_t inversion_index,
+                                uint32_t* words, kfac_stream_t stream);
+
+/*
+ * kfac_rand_eig -- randomized symmetric eigendecomposition of one K-factor (SREVD,
+ * Alg. 3, with the power iterations of Sec. 2.2), replacing the cubic full eig of
+ * Alg. 1:
+ *   l = min(r + p, d).  If l < d: Y = F Omega (d x l); Q = orth(Y) by CholeskyQR2
+ *   (fp64 Gram and Cholesky); q times: Y = F Q, Q = orth(Y).  If l == d: Q = I.
+ *   C = Q^T F Q (fp64, symmetrised); C = P diag(Lambda) P^T (fp64, descending);
+ *   U = Q P[:, :r], D = Lambda[:r]; each column of U is signed so that its
+ *   largest-magnitude entry is positive (ties: lowest row).
+ *  F        d x d fp32 symmetric PSD factor (ldf >= d).
+ *  F_bf16   bf16 copy of F (ldfb >= d); required iff prec == KFAC_SKETCH_BF16.
+ *  r        target rank, 1 <= r <= d.  p >= 0 oversampling.  0 <= q <= 16 power its.
+ *  seed, stream_id, inversion_index: select Omega (see kfac_gaussian_omega).
+ *  U        d x r fp32 output (ldu >= r), orthonormal columns.   D: r fp32, descending.
+ *  workspace: kfac_rand_eig_workspace(d, r, p, q, v, prec) bytes.
+ *  dev_status: device int32 that receives KFAC_DS_* bits (required).
+ */
+size_t kfac_rand_eig_workspace(int64_t d, int64_t r, int64_t p, int q,
+                               kfac_variant v, kfac_precision prec);
+kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf,
+                          const uint16_t* F_bf16, int64_t ldfb,
+                          int64_t r, int64_t p, int q,
+                          uint64_t seed, uint64_t stream_id, uint32_t inversion_index,
+                          kfac_variant v, kfac_precision prec,
+                          float* U, int64_t ldu, float* D,
+                          void* workspace, size_t ws_bytes, int32_t* dev_status,
+                          kfac_stream_t stream);
+
+/*
+ * kfac_precondition -- damped low-rank inverse application (Sec. 4.1 identity, the M and
+ * S lines of Alg. 4; Alg. 5 uses V = U):
+ *   f_a = 1/(D_a + lambda) - 1/lambda,  f_g likewise;
+ *   M = J U_a diag(f_a) U_a^T + J / lambda;
+ *   S = U_g diag(f_g) U_g^T M + M / lambda   ( = (G+lambda I)^{-1} J (A+lambda I)^{-1}
+ *       when U, D are exact eigenpairs of full rank).
+ *  J        d_g x d_a fp32 gradient Mat(g) (ldj >= d_a): rows = backward (Gamma) side,
+ *           columns = forward (A) side.
+ *  U_a, D_a d_a x r_a (ldua >= r_a) and r_a;   U_g, D_g  d_g x r_g (ldug >= r_g), r_g.
+ *  lambda   > 0.   S: d_g x d_a fp32 output (lds >= d_a); must not alias J.
+ *  workspace: kfac_precondition_workspace(d_g, d_a, r_a, r_g) bytes.
+ */
+size_t kfac_precondition_workspace(int64_t d_g, int64_t d_a, int64_t r_a, int64_t r_g);
+kfac_status kfac_precondition(const float* J, int64_t d_g, int64_t d_a, int64_t ldj,
+                              const float* U_a, int64_t ldua, const float* D_a, int64_t r_a,
+                              const float* U_g, int64_t ldug, const float* D_g, int64_t r_g,
+                              float lambda, float* S, int64_t lds,
+                              void* workspace, size_t ws_bytes, kfac_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFAC_H */

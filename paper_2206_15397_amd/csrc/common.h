@@ -1,0 +1,74 @@
+// Device-side helpers shared by the gfx950 kernels of libkfac: MFMA fragment types,
+// bf16 rounding, wavefront reductions and the Philox4x32-10 generator.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kfac {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWave = 64;
+
+// fp32 -> bf16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32 Philox
+// bijection; multipliers M0, M1 and Weyl key increments W0, W1.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0; k1 += W1;
+  }
+}
+
+// Uniform in (0,1) with 24 significant bits (exact in fp32 and fp64).
+__device__ __forceinline__ double philox_uniform(uint32_t w) {
+  return ((double)(w >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+// Four N(0,1) values for counter (row, group, stream, inversion): two Box-Muller pairs,
+// evaluated in fp64.
+__device__ __forceinline__ void gaussian4(uint32_t row, uint32_t group, uint32_t stream,
+                                          uint32_t inv, uint32_t k0, uint32_t k1, double z[4],
+                                          uint32_t words[4]) {
+  uint32_t c[4] = {row, group, stream, inv};
+  philox4x32_10(c, k0, k1);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) words[t] = c[t];
+  double u0 = philox_uniform(c[0]), u1 = philox_uniform(c[1]);
+  double u2 = philox_uniform(c[2]), u3 = philox_uniform(c[3]);
+  double r01 = sqrt(-2.0 * log(u0)), r23 = sqrt(-2.0 * log(u2));
+  double s1, c1, s3, c3;
+  sincospi(2.0 * u1, &s1, &c1);
+  sincospi(2.0 * u3, &s3, &c3);
+  z[0] = r01 * c1; z[1] = r01 * s1; z[2] = r23 * c3; z[3] = r23 * s3;
+}
+
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+
+}  // namespace kfac

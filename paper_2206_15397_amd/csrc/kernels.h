@@ -1,0 +1,46 @@
+// Launch interface between the C ABI (kfac_abi.hip) and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <stdint.h>
+#include "../../include/kfac.h"
+#include "common.h"
+#include "gemm_f32.h"
+
+namespace kfac {
+
+// fp32 kernels (kernels_f32.hip)
+hipError_t launch_fill_identity(float* F, int d, long ldf, hipStream_t s);
+hipError_t launch_gemm(const GemmP& p, bool ta, bool tb, hipStream_t s);
+int ea_tiles_per_side(int d);
+int ea_choose_ksplit(int d, long n);
+size_t ea_workspace_bytes(int d, long n);
+hipError_t launch_ea_f32(float* F, int d, long ldf, const float* X, int n, int d_in, long ldx, int ones,
+                         float rho, float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes,
+                         hipStream_t s);
+hipError_t launch_ea_bf16(float* F, int d, long ldf, const uint16_t* X, int n, int d_in, long ldx, int ones,
+                          float rho, float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes,
+                          hipStream_t s);
+hipError_t launch_omega(int d, int l, int d_pad, int l_pad, uint64_t seed, uint64_t stream_id, uint32_t inv,
+                        float* OmT, long ldt, uint16_t* OmTb, float* Om, long ldo, uint32_t* words,
+                        hipStream_t s);
+hipError_t launch_sign_normalize(float* U, long ldu, int d, int r, hipStream_t s);
+
+// bf16 sketch GEMM (kernels_bf16.hip): Ct[M x N] = A[M x K] * B[N x K]^T, both K-contiguous
+hipError_t launch_gemm_bf16_nt(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb,
+                               float* C, long ldc, hipStream_t s);
+
+// fp64 kernels (kernels_f64.hip)
+int gram_ksplit(int L, int K, int sym);
+size_t gram_workspace_bytes(int L, int K, int sym);
+hipError_t launch_gram(const float* A, long lda, const float* B, long ldb, int L, int K, int sym,
+                       double* part, double* C, long ldc, int* status, hipStream_t s);
+hipError_t launch_cholesky(const double* G, long ldg, int n, long m_rows, double* W, long ldw, double* Li,
+                           int* status, int* fail_flag, hipStream_t s);
+hipError_t launch_trsm(const double* W, long ldw, const double* Li, int n, int l_pad, const float* Yt,
+                       long ldy, int ncols, float* Qt, long ldq, uint16_t* Qtb, long ldqb, hipStream_t s);
+hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r,
+                            double* A, double* V, double* diag, double* off, double* Z, double* scratch,
+                            float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s);
+
+}  // namespace kfac

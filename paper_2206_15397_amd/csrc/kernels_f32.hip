@@ -1,0 +1,321 @@
+// fp32 kernels of the K-factor pipeline: identity init, the generic MFMA GEMM with its
+// epilogues, the symmetric EA update (Alg. 1 EA lines) with split-K, the Gaussian test
+// matrix (Alg. 2/3 "Sample Gaussian Matrix") and the column sign convention of U.
+#include "kernels.h"
+
+namespace kfac {
+
+// ------------------------------------------------------------------------------------
+__global__ void k_fill_identity(float* F, int d, long ldf) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)d * d;
+  for (; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    int i = (int)(idx / d), j = (int)(idx % d);
+    F[(long)i * ldf + j] = (i == j) ? 1.f : 0.f;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Generic GEMM: grid (ceil(N/BN), ceil(M/BM)).
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+__global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmP p) {
+  using T = TileF32<BM, BN, BK, WM, WN, TA, TB>;
+  __shared__ typename T::Smem sm;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  f32x4 acc[T::FM][T::FN];
+#pragma unroll
+  for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  T::run(p, m0, n0, 0, p.K, sm, acc);
+  T::for_each(acc, [&](int r, int c, float v) {
+    int i = m0 + r, j = n0 + c;
+    if (i >= p.M || j >= p.N) return;
+    float s = p.alpha * v;
+    if (p.rowD) s *= damp_weight(p.rowD[i], p.lam);
+    if (p.colD) s *= damp_weight(p.colD[j], p.lam);
+    if (p.X) s += p.beta * p.X[(long)i * p.ldx + j];
+    p.C[(long)i * p.ldc + j] = s;
+    if (p.Cb) p.Cb[(long)i * p.ldcb + j] = f32_to_bf16_rne(s);
+  });
+}
+
+// ------------------------------------------------------------------------------------
+// EA update F <- rho F + c * Xh^T Xh on upper-triangular BT x BT tiles.
+// A = Xh^T (stored K x M: TA), B = Xh (stored K x N).
+constexpr int EA_BT = 64, EA_BK = 16, EA_WM = 2, EA_WN = 2;
+using EaTile = TileF32<EA_BT, EA_BT, EA_BK, EA_WM, EA_WN, true, false>;
+
+struct EaOut {
+  float* F; long ldf; uint16_t* Fb; long ldfb; int d; float rho, c;
+};
+
+union EaSmem {
+  EaTile::Smem g;
+  float t[EA_BT][EA_BT + 1];
+};
+
+// Blend the (I, J) tile whose raw sums sit in `sm.t` and write it plus its mirror.
+__device__ void ea_store_tile(EaSmem& sm, const EaOut& o, int I, int J) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int r0 = I * EA_BT, c0 = J * EA_BT;
+  // upper block (rows of I, columns of J), coalesced along columns
+  for (int e = tid; e < EA_BT * EA_BT; e += nt) {
+    int a = e / EA_BT, b = e % EA_BT;
+    int i = r0 + a, j = c0 + b;
+    float v = 0.f;
+    if (i < o.d && j < o.d) {
+      v = o.rho * o.F[(long)i * o.ldf + j] + o.c * sm.t[a][b];
+    }
+    sm.t[a][b] = v;   // same thread reads and writes the same slot
+  }
+  __syncthreads();
+  for (int e = tid; e < EA_BT * EA_BT; e += nt) {
+    int a = e / EA_BT, b = e % EA_BT;
+    int i = r0 + a, j = c0 + b;
+    if (i < o.d && j < o.d && (I != J || a <= b)) {
+      float v = sm.t[a][b];
+      o.F[(long)i * o.ldf + j] = v;
+      if (o.Fb) o.Fb[(long)i * o.ldfb + j] = f32_to_bf16_rne(v);
+    }
+  }
+  // mirror block (rows of J, columns of I): element (c0+a, r0+b) = t[b][a]
+  for (int e = tid; e < EA_BT * EA_BT; e += nt) {
+    int a = e / EA_BT, b = e % EA_BT;
+    int i = c0 + a, j = r0 + b;
+    if (i < o.d && j < o.d && (I != J ? true : b < a)) {
+      float v = sm.t[b][a];
+      o.F[(long)i * o.ldf + j] = v;
+      if (o.Fb) o.Fb[(long)i * o.ldfb + j] = f32_to_bf16_rne(v);
+    }
+  }
+}
+
+// grid (n_upper_tiles, ksplit)
+__global__ __launch_bounds__(256) void k_ea_tiles(GemmP p, EaOut o, int T) {
+  __shared__ EaSmem sm;
+  int I, J;
+  upper_tile(blockIdx.x, T, I, J);
+  const int ks = blockIdx.y, nks = gridDim.y;
+  const int kchunk = ((p.K + nks - 1) / nks + EA_BK - 1) / EA_BK * EA_BK;
+  const int kb = ks * kchunk, ke = min(p.K, kb + kchunk);
+  f32x4 acc[EaTile::FM][EaTile::FN];
+#pragma unroll
+  for (int i = 0; i < EaTile::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < EaTile::FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  EaTile::run(p, I * EA_BT, J * EA_BT, kb, ke, sm.g, acc);
+  if (nks > 1) {
+    float* slot = p.part + ((long)blockIdx.x * nks + ks) * (EA_BT * EA_BT);
+    EaTile::for_each(acc, [&](int r, int c, float v) { slot[r * EA_BT + c] = v; });
+    return;
+  }
+  __syncthreads();
+  EaTile::for_each(acc, [&](int r, int c, float v) { sm.t[r][c] = v; });
+  __syncthreads();
+  ea_store_tile(sm, o, I, J);
+}
+
+// Deterministic split-K reduction (slices summed in index order) + EA epilogue.
+__global__ __launch_bounds__(256) void k_ea_finalize(const float* part, int nks, EaOut o, int T) {
+  __shared__ EaSmem sm;
+  int I, J;
+  upper_tile(blockIdx.x, T, I, J);
+  const float* base = part + (long)blockIdx.x * nks * (EA_BT * EA_BT);
+  for (int e = threadIdx.x; e < EA_BT * EA_BT; e += blockDim.x) {
+    float s = 0.f;
+    for (int k = 0; k < nks; ++k) s += base[(long)k * EA_BT * EA_BT + e];
+    sm.t[e / EA_BT][e % EA_BT] = s;
+  }
+  __syncthreads();
+  ea_store_tile(sm, o, I, J);
+}
+
+// F <- rho F (n == 0), keeps the bf16 shadow in sync.
+__global__ void k_scale_factor(float* F, long ldf, uint16_t* Fb, long ldfb, int d, float rho) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)d * d;
+  for (; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    int i = (int)(idx / d), j = (int)(idx % d);
+    float v = rho * F[(long)i * ldf + j];
+    F[(long)i * ldf + j] = v;
+    if (Fb) Fb[(long)i * ldfb + j] = f32_to_bf16_rne(v);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Gaussian test matrix.  Thread (row i, group g) draws columns 4g..4g+3.
+// Transposed workspace form: OmT[j][i] (rows j < l_pad, ld = ldt), zero outside d x l.
+// User form: Om[i][j] with ldo, plus optional raw words.
+__global__ void k_omega(int d, int l, int d_pad, int l_pad, uint32_t k0, uint32_t k1, uint32_t stream,
+                        uint32_t inv, float* OmT, long ldt, uint16_t* OmTb, float* Om, long ldo,
+                        uint32_t* words) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int g = blockIdx.y;
+  int rows = d_pad > d ? d_pad : d;
+  if (i >= rows) return;
+  double z[4] = {0, 0, 0, 0};
+  uint32_t w[4] = {0, 0, 0, 0};
+  bool live = i < d;
+  if (live) gaussian4((uint32_t)i, (uint32_t)g, stream, inv, k0, k1, z, w);
+  int groups = (l + 3) / 4;
+  if (live && words && g < groups) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) words[((long)i * groups + g) * 4 + t] = w[t];
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    int j = 4 * g + t;
+    float v = (live && j < l) ? (float)z[t] : 0.f;
+    if (OmT && j < l_pad) OmT[(long)j * ldt + i] = v;
+    if (OmTb && j < l_pad) OmTb[(long)j * ldt + i] = f32_to_bf16_rne(v);
+    if (Om && live && j < l) Om[(long)i * ldo + j] = v;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Sign convention: the largest-magnitude entry of each column of U is made positive
+// (ties: lowest row).  Block = 256 threads = 4 row groups x 64 columns.
+__global__ __launch_bounds__(256) void k_sign_normalize(float* U, long ldu, int d, int r) {
+  __shared__ float smax[4][64];
+  __shared__ int sidx[4][64];
+  __shared__ float ssgn[64];
+  const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  float best = -1.f;
+  int bidx = 0x7fffffff;
+  if (c < r) {
+    for (int i = rg; i < d; i += 4) {
+      float a = fabsf(U[(long)i * ldu + c]);
+      if (a > best) { best = a; bidx = i; }   // rows visited ascending per group
+    }
+  }
+  smax[rg][cl] = best;
+  sidx[rg][cl] = bidx;
+  __syncthreads();
+  if (rg == 0) {
+    float b = smax[0][cl];
+    int bi = sidx[0][cl];
+    for (int g = 1; g < 4; ++g) {
+      float v = smax[g][cl];
+      int vi = sidx[g][cl];
+      if (v > b || (v == b && vi < bi)) { b = v; bi = vi; }
+    }
+    float s = 1.f;
+    if (c < r && bi < d && U[(long)bi * ldu + c] < 0.f) s = -1.f;
+    ssgn[cl] = s;
+  }
+  __syncthreads();
+  if (c < r && ssgn[cl] < 0.f)
+    for (int i = rg; i < d; i += 4) U[(long)i * ldu + c] = -U[(long)i * ldu + c];
+}
+
+// ------------------------------------------------------------------------------------
+// Host launchers
+// ------------------------------------------------------------------------------------
+hipError_t launch_fill_identity(float* F, int d, long ldf, hipStream_t s) {
+  long total = (long)d * d;
+  int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_identity, dim3(blocks), dim3(256), 0, s, F, d, ldf);
+  return hipGetLastError();
+}
+
+template <bool TA, bool TB>
+static hipError_t gemm_dispatch(const GemmP& p, hipStream_t s) {
+  if (p.M <= 0 || p.N <= 0) return hipSuccess;
+  if (p.M >= 128 && p.N >= 128 && (long)p.M * p.N >= 128L * 128 * 256) {
+    dim3 grid((p.N + 127) / 128, (p.M + 127) / 128);
+    hipLaunchKernelGGL((k_gemm<128, 128, 16, 2, 2, TA, TB>), grid, dim3(256), 0, s, p);
+  } else {
+    dim3 grid((p.N + 63) / 64, (p.M + 63) / 64);
+    hipLaunchKernelGGL((k_gemm<64, 64, 16, 2, 2, TA, TB>), grid, dim3(256), 0, s, p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmP& p, bool ta, bool tb, hipStream_t s) {
+  if (!ta && !tb) return gemm_dispatch<false, false>(p, s);
+  if (!ta && tb) return gemm_dispatch<false, true>(p, s);
+  if (ta && !tb) return gemm_dispatch<true, false>(p, s);
+  return gemm_dispatch<true, true>(p, s);
+}
+
+int ea_tiles_per_side(int d) { return (d + EA_BT - 1) / EA_BT; }
+
+int ea_choose_ksplit(int d, long n) {
+  int T = ea_tiles_per_side(d);
+  long tiles = (long)T * (T + 1) / 2;
+  long want = (1024 + tiles - 1) / tiles;           // aim for >= ~1024 workgroups
+  long maxk = (n + 511) / 512;                      // at least 512 rows per slice
+  long ks = std::min(want, maxk);
+  if (ks < 1) ks = 1;
+  if (ks > 64) ks = 64;
+  return (int)ks;
+}
+
+size_t ea_workspace_bytes(int d, long n) {
+  int ks = ea_choose_ksplit(d, n);
+  if (ks <= 1) return 0;
+  int T = ea_tiles_per_side(d);
+  long tiles = (long)T * (T + 1) / 2;
+  return (size_t)tiles * ks * EA_BT * EA_BT * sizeof(float);
+}
+
+static hipError_t launch_ea_common(float* F, int d, long ldf, const float* X, const uint16_t* Xb, int n,
+                                   int d_in, long ldx, int ones, float rho, float scale, uint16_t* Fb, long ldfb,
+                                   void* ws, size_t ws_bytes, hipStream_t s) {
+  EaOut o{F, ldf, Fb, ldfb, d, rho, (1.f - rho) * scale};
+  if (n == 0) {
+    long total = (long)d * d;
+    int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_scale_factor, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, F, ldf, Fb,
+                       ldfb, d, rho);
+    return hipGetLastError();
+  }
+  GemmP p{};
+  p.M = d; p.N = d; p.K = n;
+  p.A = X; p.lda = ldx; p.B = X; p.ldb = ldx;
+  p.Ab = Xb; p.Bb = Xb;
+  p.ones_col = ones ? d_in : -1;
+  int T = ea_tiles_per_side(d);
+  int tiles = T * (T + 1) / 2;
+  int ks = ea_choose_ksplit(d, n);
+  if (ks > 1 && (ws == nullptr || ws_bytes < ea_workspace_bytes(d, n))) ks = 1;
+  p.ksplit = ks;
+  p.part = (float*)ws;
+  hipLaunchKernelGGL(k_ea_tiles, dim3(tiles, ks), dim3(256), 0, s, p, o, T);
+  if (ks > 1) hipLaunchKernelGGL(k_ea_finalize, dim3(tiles), dim3(256), 0, s, (const float*)ws, ks, o, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_ea_f32(float* F, int d, long ldf, const float* X, int n, int d_in, long ldx,
+                         int ones, float rho, float scale, uint16_t* Fb, long ldfb, void* ws,
+                         size_t ws_bytes, hipStream_t s) {
+  return launch_ea_common(F, d, ldf, X, nullptr, n, d_in, ldx, ones, rho, scale, Fb, ldfb, ws, ws_bytes, s);
+}
+
+hipError_t launch_ea_bf16(float* F, int d, long ldf, const uint16_t* X, int n, int d_in, long ldx, int ones,
+                          float rho, float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes,
+                          hipStream_t s) {
+  return launch_ea_common(F, d, ldf, nullptr, X, n, d_in, ldx, ones, rho, scale, Fb, ldfb, ws, ws_bytes, s);
+}
+
+hipError_t launch_omega(int d, int l, int d_pad, int l_pad, uint64_t seed, uint64_t stream_id,
+                        uint32_t inv, float* OmT, long ldt, uint16_t* OmTb, float* Om, long ldo,
+                        uint32_t* words, hipStream_t s) {
+  int rows = d_pad > d ? d_pad : d;
+  int groups = std::max((l + 3) / 4, (l_pad + 3) / 4);
+  dim3 grid((rows + 255) / 256, groups);
+  hipLaunchKernelGGL(k_omega, grid, dim3(256), 0, s, d, l, d_pad, l_pad, (uint32_t)(seed & 0xffffffffu),
+                     (uint32_t)(seed >> 32), (uint32_t)(stream_id & 0xffffffffu), inv, OmT, ldt, OmTb,
+                     Om, ldo, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_sign_normalize(float* U, long ldu, int d, int r, hipStream_t s) {
+  hipLaunchKernelGGL(k_sign_normalize, dim3((r + 63) / 64), dim3(256), 0, s, U, ldu, d, r);
+  return hipGetLastError();
+}
+
+}  // namespace kfac

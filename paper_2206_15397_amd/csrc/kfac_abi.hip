@@ -1,0 +1,284 @@
+// C ABI of libkfac.so: argument validation, workspace layout and the launch sequences of
+// the K-factor pipeline.  No device memory is allocated here; every buffer comes from the
+// caller.
+#include <cmath>
+#include <cstring>
+#include "kernels.h"
+
+using namespace kfac;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+inline kfac_status hip_status(hipError_t e) { return e == hipSuccess ? KFAC_OK : KFAC_EHIP; }
+
+// Layout of the kfac_rand_eig workspace; with base == nullptr it only measures.
+struct EigWs {
+  int64_t d, r, l, l_pad, ldt;
+  bool exact, bf16;
+  float *OmT, *Yt, *Qt, *P;
+  uint16_t *OmTb, *Qtb;
+  double *G, *Wc, *Li, *part, *A, *V, *diag, *off, *Z, *scr, *Dd;
+  int* fail;
+  size_t bytes;
+
+  EigWs(int64_t d_, int64_t r_, int64_t p_, bool bf16_, void* base) : d(d_), r(r_), bf16(bf16_) {
+    l = std::min<int64_t>(r + p_, d);
+    exact = (l == d);
+    l_pad = round_up(l, 32);
+    ldt = round_up(d, 8);
+    Bump b(base);
+    const int64_t n = exact ? d : l;
+    OmT = Yt = Qt = P = nullptr;
+    OmTb = Qtb = nullptr;
+    G = Wc = Li = part = nullptr;
+    if (!exact) {
+      OmT = b.take<float>(l_pad * ldt);
+      Yt = b.take<float>(l_pad * ldt);
+      Qt = b.take<float>(l_pad * ldt);
+      if (bf16) {
+        OmTb = b.take<uint16_t>(l_pad * ldt);
+        Qtb = b.take<uint16_t>(l_pad * ldt);
+      }
+      G = b.take<double>(l_pad * l_pad);
+      Wc = b.take<double>(l_pad * l_pad);
+      Li = b.take<double>(l_pad * 16);
+      size_t pb = std::max(gram_workspace_bytes((int)l_pad, (int)d, 1), gram_workspace_bytes((int)l_pad, (int)d, 0));
+      part = b.take<double>(pb / sizeof(double) + 1);
+      P = b.take<float>(l_pad * r);
+    }
+    A = b.take<double>(n * n);
+    V = b.take<double>(n * n);
+    diag = b.take<double>(n + 1);
+    off = b.take<double>(n + 1);
+    Z = b.take<double>(n * r);
+    scr = b.take<double>(5 * n * r);
+    Dd = b.take<double>(r);
+    fail = b.take<int>(16);
+    bytes = b.off + kAlign;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* kfac_status_string(kfac_status s) {
+  switch (s) {
+    case KFAC_OK: return "ok";
+    case KFAC_EINVAL: return "invalid argument";
+    case KFAC_EWORKSPACE: return "workspace too small";
+    case KFAC_EHIP: return "HIP launch error";
+    case KFAC_EUNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+const char* kfac_build_info(void) {
+  return "libkfac gfx950 (fp32/bf16 MFMA GEMM, fp64 CholeskyQR2 + tridiagonal eigensolver)";
+}
+
+kfac_status kfac_fill_identity(float* F, int64_t d, int64_t ldf, kfac_stream_t stream) {
+  if (!F || d < 1 || ldf < d || d > (1 << 30)) return KFAC_EINVAL;
+  return hip_status(launch_fill_identity(F, (int)d, ldf, (hipStream_t)stream));
+}
+
+size_t kfac_ea_update_workspace(int64_t d, int64_t n) {
+  if (d < 1 || n < 0) return 0;
+  return ea_workspace_bytes((int)d, n);
+}
+
+kfac_status kfac_ea_update(float* F, int64_t d, int64_t ldf, const void* X, kfac_dtype xtype, int64_t n,
+                           int64_t d_in, int64_t ldx, int append_ones, float rho, float scale,
+                           uint16_t* F_bf16, int64_t ldfb, void* workspace, size_t ws_bytes,
+                           kfac_stream_t stream) {
+  if (!F || d < 1 || ldf < d || n < 0 || d_in < 0) return KFAC_EINVAL;
+  if (d != d_in + (append_ones ? 1 : 0)) return KFAC_EINVAL;
+  if (n > 0 && (!X || ldx < d_in)) return KFAC_EINVAL;
+  if (!(rho >= 0.f && rho < 1.f) || !(scale > 0.f) || !std::isfinite(scale)) return KFAC_EINVAL;
+  if (xtype != KFAC_FP32 && xtype != KFAC_BF16) return KFAC_EINVAL;
+  if (F_bf16 && ldfb < d) return KFAC_EINVAL;
+  if (d > (1 << 20) || n > (1LL << 31) - 1) return KFAC_EUNSUPPORTED;
+  if (ws_bytes == 0) workspace = nullptr;          // no workspace: no split-K
+  if (workspace && ws_bytes < kfac_ea_update_workspace(d, n)) return KFAC_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (xtype == KFAC_FP32)
+    return hip_status(launch_ea_f32(F, (int)d, ldf, (const float*)X, (int)n, (int)d_in, ldx, append_ones,
+                                    rho, scale, F_bf16, ldfb, workspace, ws_bytes, s));
+  return hip_status(launch_ea_bf16(F, (int)d, ldf, (const uint16_t*)X, (int)n, (int)d_in, ldx, append_ones,
+                                   rho, scale, F_bf16, ldfb, workspace, ws_bytes, s));
+}
+
+kfac_status kfac_gaussian_omega(float* Omega, int64_t d, int64_t l, int64_t ldo, uint64_t seed,
+                                uint64_t stream_id, uint32_t inversion_index, uint32_t* words,
+                                kfac_stream_t stream) {
+  if (d < 1 || l < 1 || (!Omega && !words) || (Omega && ldo < l)) return KFAC_EINVAL;
+  if (d > (1 << 30) || l > (1 << 20)) return KFAC_EUNSUPPORTED;
+  return hip_status(launch_omega((int)d, (int)l, (int)d, 0, seed, stream_id, inversion_index, nullptr, 0,
+                                 nullptr, Omega, ldo, words, (hipStream_t)stream));
+}
+
+size_t kfac_rand_eig_workspace(int64_t d, int64_t r, int64_t p, int q, kfac_variant v, kfac_precision prec) {
+  if (d < 1 || r < 1 || r > d || p < 0 || q < 0) return 0;
+  (void)v;
+  EigWs w(d, r, p, prec == KFAC_SKETCH_BF16, nullptr);
+  return w.bytes;
+}
+
+kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t* F_bf16, int64_t ldfb,
+                          int64_t r, int64_t p, int q, uint64_t seed, uint64_t stream_id,
+                          uint32_t inversion_index, kfac_variant v, kfac_precision prec, float* U,
+                          int64_t ldu, float* D, void* workspace, size_t ws_bytes, int32_t* dev_status,
+                          kfac_stream_t stream) {
+  if (!F || !U || !D || !dev_status || !workspace) return KFAC_EINVAL;
+  if (d < 1 || ldf < d || r < 1 || r > d || p < 0 || q < 0 || q > 16 || ldu < r) return KFAC_EINVAL;
+  if (prec != KFAC_SKETCH_FP32 && prec != KFAC_SKETCH_BF16) return KFAC_EINVAL;
+  if (v != KFAC_SREVD && v != KFAC_RSVD) return KFAC_EINVAL;
+  if (prec == KFAC_SKETCH_BF16 && (!F_bf16 || ldfb < d)) return KFAC_EINVAL;
+  if (v == KFAC_RSVD) return KFAC_EUNSUPPORTED;
+  const int64_t l = std::min<int64_t>(r + p, d);
+  if (l > KFAC_MAX_SKETCH || d > (1 << 28)) return KFAC_EUNSUPPORTED;
+  EigWs w(d, r, p, prec == KFAC_SKETCH_BF16, workspace);
+  if (ws_bytes < w.bytes) return KFAC_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  int* st = (int*)dev_status;
+  hipError_t e = hipSuccess;
+#define CK(x) do { e = (x); if (e != hipSuccess) return KFAC_EHIP; } while (0)
+  if (w.exact) {
+    // l == d: the sketch spans R^d, Q = I; eigendecompose F itself, U = P[:, :r].
+    CK(launch_small_eig(nullptr, 0, F, ldf, (int)d, (int)d, (int)r, w.A, w.V, w.diag, w.off, w.Z, w.scr, U,
+                        ldu, D, w.Dd, st, s));
+    CK(launch_sign_normalize(U, ldu, (int)d, (int)r, s));
+    return KFAC_OK;
+  }
+  const bool bf = (prec == KFAC_SKETCH_BF16);
+  const int L = (int)w.l_pad, n = (int)w.l, dd = (int)d;
+  const long ldt = w.ldt;
+  // Omega^T (l_pad x d), rows >= l zero
+  CK(launch_omega(dd, n, dd, L, seed, stream_id, inversion_index, w.OmT, ldt, bf ? w.OmTb : nullptr, nullptr,
+                  0, nullptr, s));
+  auto f_times = [&](const float* At, const uint16_t* Atb, float* Out) -> hipError_t {
+    // Out^T = At^T... i.e. Out (L x d) = At (L x d) * F (d x d); F symmetric so this is (F A^T)^T.
+    if (bf) return launch_gemm_bf16_nt(L, dd, dd, Atb, ldt, F_bf16, ldfb, Out, ldt, s);
+    GemmP g{};
+    g.M = L; g.N = dd; g.K = dd;
+    g.A = At; g.lda = ldt; g.B = F; g.ldb = ldf;
+    g.C = Out; g.ldc = ldt; g.alpha = 1.f; g.ones_col = -1;
+    return launch_gemm(g, false, false, s);
+  };
+  auto cholqr = [&](float* Yt, float* Qt, uint16_t* Qtb) -> hipError_t {
+    // pass 1: Qt = L^{-1} Yt ; pass 2 on Qt in place
+    hipError_t x;
+    if ((x = launch_gram(Yt, ldt, Yt, ldt, L, dd, 1, w.part, w.G, L, st, s)) != hipSuccess) return x;
+    if ((x = launch_cholesky(w.G, L, n, dd, w.Wc, L, w.Li, st, w.fail, s)) != hipSuccess) return x;
+    if ((x = launch_trsm(w.Wc, L, w.Li, n, L, Yt, ldt, dd, Qt, ldt, nullptr, 0, s)) != hipSuccess) return x;
+    if ((x = launch_gram(Qt, ldt, Qt, ldt, L, dd, 1, w.part, w.G, L, st, s)) != hipSuccess) return x;
+    if ((x = launch_cholesky(w.G, L, n, dd, w.Wc, L, w.Li, st, w.fail, s)) != hipSuccess) return x;
+    return launch_trsm(w.Wc, L, w.Li, n, L, Qt, ldt, dd, Qt, ldt, Qtb, ldt, s);
+  };
+  // sketch Y = F Omega, then orthonormalise
+  CK(f_times(w.OmT, w.OmTb, w.Yt));
+  CK(cholqr(w.Yt, w.Qt, bf ? w.Qtb : nullptr));
+  for (int it = 0; it < q; ++it) {
+    CK(f_times(w.Qt, w.Qtb, w.Yt));
+    CK(cholqr(w.Yt, w.Qt, bf ? w.Qtb : nullptr));
+  }
+  // Rayleigh-Ritz: W = F Q (fp32), C = Q^T W (fp64)
+  {
+    GemmP g{};
+    g.M = L; g.N = dd; g.K = dd;
+    g.A = w.Qt; g.lda = ldt; g.B = F; g.ldb = ldf;
+    g.C = w.Yt; g.ldc = ldt; g.alpha = 1.f; g.ones_col = -1;
+    CK(launch_gemm(g, false, false, s));
+  }
+  CK(launch_gram(w.Qt, ldt, w.Yt, ldt, L, dd, 0, w.part, w.G, L, st, s));
+  CK(launch_small_eig(w.G, L, nullptr, 0, n, L, (int)r, w.A, w.V, w.diag, w.off, w.Z, w.scr, w.P, r, D, w.Dd,
+                      st, s));
+  // U = Q P[:, :r]  (A = Q^T stored l_pad x d, i.e. K x M)
+  {
+    GemmP g{};
+    g.M = dd; g.N = (int)r; g.K = n;
+    g.A = w.Qt; g.lda = ldt; g.B = w.P; g.ldb = r;
+    g.C = U; g.ldc = ldu; g.alpha = 1.f; g.ones_col = -1;
+    CK(launch_gemm(g, true, false, s));
+  }
+  CK(launch_sign_normalize(U, ldu, dd, (int)r, s));
+#undef CK
+  return KFAC_OK;
+}
+
+size_t kfac_precondition_workspace(int64_t d_g, int64_t d_a, int64_t r_a, int64_t r_g) {
+  if (d_g < 1 || d_a < 1 || r_a < 1 || r_g < 1) return 0;
+  Bump b(nullptr);
+  b.take<float>(d_g * r_a);
+  b.take<float>(d_g * d_a);
+  b.take<float>(r_g * d_a);
+  return b.off + kAlign;
+}
+
+kfac_status kfac_precondition(const float* J, int64_t d_g, int64_t d_a, int64_t ldj, const float* U_a,
+                              int64_t ldua, const float* D_a, int64_t r_a, const float* U_g, int64_t ldug,
+                              const float* D_g, int64_t r_g, float lambda, float* S, int64_t lds,
+                              void* workspace, size_t ws_bytes, kfac_stream_t stream) {
+  if (!J || !U_a || !D_a || !U_g || !D_g || !S || !workspace) return KFAC_EINVAL;
+  if (d_g < 1 || d_a < 1 || ldj < d_a || lds < d_a) return KFAC_EINVAL;
+  if (r_a < 1 || r_a > d_a || r_g < 1 || r_g > d_g || ldua < r_a || ldug < r_g) return KFAC_EINVAL;
+  if (!(lambda > 0.f) || !std::isfinite(lambda)) return KFAC_EINVAL;
+  if ((const void*)S == (const void*)J) return KFAC_EINVAL;
+  if (d_g > (1 << 28) || d_a > (1 << 28)) return KFAC_EUNSUPPORTED;
+  if (ws_bytes < kfac_precondition_workspace(d_g, d_a, r_a, r_g)) return KFAC_EWORKSPACE;
+  Bump b(workspace);
+  float* T1 = b.take<float>(d_g * r_a);
+  float* M = b.take<float>(d_g * d_a);
+  float* T2 = b.take<float>(r_g * d_a);
+  hipStream_t s = (hipStream_t)stream;
+  const float inv_lam = 1.0f / lambda;
+  hipError_t e;
+  {  // T1 = J U_a diag(f_a)
+    GemmP g{};
+    g.M = (int)d_g; g.N = (int)r_a; g.K = (int)d_a;
+    g.A = J; g.lda = ldj; g.B = U_a; g.ldb = ldua; g.C = T1; g.ldc = r_a;
+    g.alpha = 1.f; g.colD = D_a; g.lam = lambda; g.ones_col = -1;
+    if ((e = launch_gemm(g, false, false, s)) != hipSuccess) return KFAC_EHIP;
+  }
+  {  // M = T1 U_a^T + J / lambda
+    GemmP g{};
+    g.M = (int)d_g; g.N = (int)d_a; g.K = (int)r_a;
+    g.A = T1; g.lda = r_a; g.B = U_a; g.ldb = ldua; g.C = M; g.ldc = d_a;
+    g.alpha = 1.f; g.X = J; g.ldx = ldj; g.beta = inv_lam; g.ones_col = -1;
+    if ((e = launch_gemm(g, false, true, s)) != hipSuccess) return KFAC_EHIP;
+  }
+  {  // T2 = diag(f_g) U_g^T M
+    GemmP g{};
+    g.M = (int)r_g; g.N = (int)d_a; g.K = (int)d_g;
+    g.A = U_g; g.lda = ldug; g.B = M; g.ldb = d_a; g.C = T2; g.ldc = d_a;
+    g.alpha = 1.f; g.rowD = D_g; g.lam = lambda; g.ones_col = -1;
+    if ((e = launch_gemm(g, true, false, s)) != hipSuccess) return KFAC_EHIP;
+  }
+  {  // S = U_g T2 + M / lambda
+    GemmP g{};
+    g.M = (int)d_g; g.N = (int)d_a; g.K = (int)r_g;
+    g.A = U_g; g.lda = ldug; g.B = T2; g.ldb = d_a; g.C = S; g.ldc = lds;
+    g.alpha = 1.f; g.X = M; g.ldx = d_a; g.beta = inv_lam; g.ones_col = -1;
+    if ((e = launch_gemm(g, false, false, s)) != hipSuccess) return KFAC_EHIP;
+  }
+  return KFAC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+"""Python wrappers of the libkfac C ABI.  Argument marshalling only: tensors provide
+device memory (and workspaces), torch's current stream provides the HIP stream."""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _stream():
+    return ctypes_void(torch.cuda.current_stream().cuda_stream)
+
+
+def ctypes_void(x):
+    import ctypes
+    return ctypes.c_void_p(int(x))
+
+
+def _ptr(t):
+    import ctypes
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libkfac operates on device tensors")
+
+
+def _workspace(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def fill_identity(F: torch.Tensor) -> torch.Tensor:
+    _require_cuda(F)
+    assert F.dtype == torch.float32 and F.dim() == 2 and F.shape[0] == F.shape[1] and F.stride(1) == 1
+    check("kfac_fill_identity", lib().kfac_fill_identity(_ptr(F), F.shape[0], F.stride(0), _stream()))
+    return F
+
+
+def ea_update(F: torch.Tensor, X: torch.Tensor, rho: float, scale: float = None,
+              append_ones: bool = False, F_bf16: torch.Tensor = None, workspace=None) -> torch.Tensor:
+    """In place: F <- rho F + (1 - rho) scale [X|1]^T [X|1]; optionally refreshes F_bf16."""
+    _require_cuda(F, X, F_bf16)
+    d = F.shape[0]
+    n, d_in = X.shape
+    assert F.dtype == torch.float32 and F.stride(1) == 1 and (n == 0 or X.stride(1) == 1)
+    xtype = {torch.float32: _lib.KFAC_FP32, torch.bfloat16: _lib.KFAC_BF16}[X.dtype]
+    if scale is None:
+        scale = 1.0 / max(n, 1)
+    L = lib()
+    if workspace is None:
+        ws_bytes = L.kfac_ea_update_workspace(d, n)
+        workspace = _workspace(ws_bytes, F.device) if ws_bytes else None
+    ws_bytes = 0 if workspace is None else workspace.numel()
+    fb_ld = 0 if F_bf16 is None else F_bf16.stride(0)
+    check("kfac_ea_update", L.kfac_ea_update(
+        _ptr(F), d, F.stride(0), _ptr(X), xtype, n, d_in, X.stride(0) if n else d_in,
+        1 if append_ones else 0, float(rho), float(scale), _ptr(F_bf16), fb_ld,
+        _ptr(workspace), ws_bytes, _stream()))
+    return F
+
+
+def gaussian_omega(d: int, l: int, seed: int, stream_id: int = 0, inversion_index: int = 0,
+                   device="cuda", want_words: bool = False):
+    Om = torch.empty((d, l), dtype=torch.float32, device=device)
+    words = torch.empty((d, (l + 3) // 4, 4), dtype=torch.int32, device=device) if want_words else None
+    check("kfac_gaussian_omega", lib().kfac_gaussian_omega(
+        _ptr(Om), d, l, l, int(seed), int(stream_id), int(inversion_index), _ptr(words), _stream()))
+    return (Om, words) if want_words else Om
+
+
+def rand_eig_workspace_bytes(d, r, p, q, sketch="fp32") -> int:
+    prec = _lib.KFAC_SKETCH_BF16 if sketch == "bf16" else _lib.KFAC_SKETCH_FP32
+    return int(lib().kfac_rand_eig_workspace(d, r, p, q, _lib.KFAC_SREVD, prec))
+
+
+def rand_eig(F: torch.Tensor, r: int, p: int, q: int, seed: int, stream_id: int = 0,
+             inversion_index: int = 0, sketch: str = "fp32", F_bf16: torch.Tensor = None,
+             U: torch.Tensor = None, D: torch.Tensor = None, workspace=None, status=None):
+    """SREVD of the symmetric PSD factor F: returns (U d x r, D r descending, status int32)."""
+    _require_cuda(F, F_bf16)
+    d = F.shape[0]
+    prec = _lib.KFAC_SKETCH_BF16 if sketch == "bf16" else _lib.KFAC_SKETCH_FP32
+    if prec == _lib.KFAC_SKETCH_BF16 and F_bf16 is None:
+        F_bf16 = F.to(torch.bfloat16)
+    if U is None:
+        U = torch.empty((d, r), dtype=torch.float32, device=F.device)
+    if D is None:
+        D = torch.empty((r,), dtype=torch.float32, device=F.device)
+    if status is None:
+        status = torch.zeros((1,), dtype=torch.int32, device=F.device)
+    L = lib()
+    if workspace is None:
+        workspace = _workspace(L.kfac_rand_eig_workspace(d, r, p, q, _lib.KFAC_SREVD, prec), F.device)
+    check("kfac_rand_eig", L.kfac_rand_eig(
+        _ptr(F), d, F.stride(0), _ptr(F_bf16), 0 if F_bf16 is None else F_bf16.stride(0),
+        int(r), int(p), int(q), int(seed), int(stream_id), int(inversion_index), _lib.KFAC_SREVD, prec,
+        _ptr(U), U.stride(0), _ptr(D), _ptr(workspace), workspace.numel(), _ptr(status), _stream()))
+    return U, D, status
+
+
+def precondition_workspace_bytes(d_g, d_a, r_a, r_g) -> int:
+    return int(lib().kfac_precondition_workspace(d_g, d_a, r_a, r_g))
+
+
+def precondition(J: torch.Tensor, Ua: torch.Tensor, Da: torch.Tensor, Ug: torch.Tensor,
+                 Dg: torch.Tensor, lam: float, S: torch.Tensor = None, workspace=None) -> torch.Tensor:
+    """S = (U_g D_g U_g^T + lam I)^{-1} J (U_a D_a U_a^T + lam I)^{-1} via the low-rank identity."""
+    _require_cuda(J, Ua, Da, Ug, Dg)
+    d_g, d_a = J.shape
+    r_a, r_g = Ua.shape[1], Ug.shape[1]
+    if S is None:
+        S = torch.empty((d_g, d_a), dtype=torch.float32, device=J.device)
+    L = lib()
+    if workspace is None:
+        workspace = _workspace(L.kfac_precondition_workspace(d_g, d_a, r_a, r_g), J.device)
+    check("kfac_precondition", L.kfac_precondition(
+        _ptr(J), d_g, d_a, J.stride(0), _ptr(Ua), Ua.stride(0), _ptr(Da), r_a, _ptr(Ug), Ug.stride(0),
+        _ptr(Dg), r_g, float(lam), _ptr(S), S.stride(0), _ptr(workspace), workspace.numel(), _stream()))
+    return S

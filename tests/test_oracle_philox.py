@@ -10,11 +10,13 @@ import oracle as O
 
 
 def test_uniform_grid_and_range():
-    w = np.array([0, 255, 256, 0xFFFFFFFF, 0x80000000], dtype=np.uint32)
+    w = np.array([0, 511, 512, 0xFFFFFFFF, 0x80000000], dtype=np.uint32)
     u = O.uniforms_from_words(w)
-    np.testing.assert_array_equal(u, [0.5 * 2 ** -24, 0.5 * 2 ** -24, 1.5 * 2 ** -24,
-                                      1 - 0.5 * 2 ** -24, 0.5 + 0.5 * 2 ** -24])
+    np.testing.assert_array_equal(u, [0.5 * 2 ** -23, 0.5 * 2 ** -23, 1.5 * 2 ** -23,
+                                      1 - 0.5 * 2 ** -23, 0.5 + 0.5 * 2 ** -23])
     assert np.all(u > 0) and np.all(u < 1)
+    # every value is exactly representable in fp32
+    np.testing.assert_array_equal(u.astype(np.float32).astype(np.float64), u)
 
 
 def test_reproducible_and_counter_separation():
