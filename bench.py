@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""K-factor step benchmark on one MI355X.
+
+Workload: the VGG16_bn-shaped factor set on CIFAR-sized inputs (batch 128, 3x32x32):
+13 3x3 convolutions (A-factor dims 9*C_in+1 = 28..4609, G-factor dims C_out = 64..512)
+and the FC head 512->512->512->10, i.e. 16 layers / 32 K-factors.  Synthetic activations
+follow a 1/i^1.5 covariance under a seeded rotation; factors are built by 10 EA steps
+from I (rho 0.95) during untimed setup.  One timed step = EA step 11 for all 32 factors,
+the randomized eigendecomposition (SREVD, r=min(256,d), p=16, q=1) of all 32 factors and
+the damped inverse (lambda 0.1) for all 16 layer gradients -- with inputs resident in HBM.
+
+Two paths are measured on the same GPU:
+  plain   : per-layer launch sequence on one stream, fp32 activations and fp32 sketch;
+  batched : bf16 activations and bf16 sketch, factors spread over concurrent streams,
+            the whole step captured once in a hipGraph and replayed.
+The reported value is the batched path's K-factor eig-inversions per second over the
+whole step (32 factors / step time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--check", action="store_true", help="check sampled outputs against the oracle")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Layer:
+    pass
+
+
+def build_workload(dev, act_dtype_bf16: bool):
+    import torch
+    import paper_2206_15397_amd as K
+    from paper_2206_15397_amd import synth
+    wl = synth.vgg16_bn_workload()
+    layers = []
+    for li, s in enumerate(wl.layers):
+        L = Layer()
+        L.shape = s
+        L.d_a, L.d_g, L.n = s.d_a, s.d_g, s.n
+        Ra = synth.torch_haar_orthogonal(s.m_a, synth.SEED_ROT_A + li, dev)
+        Rg = synth.torch_haar_orthogonal(s.d_g, synth.SEED_ROT_G + li, dev)
+        sa = torch.tensor(synth.power_spectrum(s.m_a), dtype=torch.float32, device=dev)
+        sg = torch.tensor(synth.power_spectrum(s.d_g), dtype=torch.float32, device=dev)
+        L.A = K.fill_identity(torch.empty((s.d_a, s.d_a), device=dev))
+        L.G = K.fill_identity(torch.empty((s.d_g, s.d_g), device=dev))
+        for k in range(wl.ea_steps_before):
+            a = synth.torch_activation_batch(s.n, Ra, sa, synth.SEED_ACT_A + li, k, dev)
+            g = synth.torch_activation_batch(s.n, Rg, sg, synth.SEED_ACT_G + li, k, dev)
+            if act_dtype_bf16:
+                a, g = a.to(torch.bfloat16), g.to(torch.bfloat16)
+            K.ea_update(L.A, a, wl.rho, 1.0 / s.n, append_ones=s.bias)
+            K.ea_update(L.G, g, wl.rho, 1.0 / s.n)
+            del a, g
+        # the timed step's batch, resident in HBM
+        a = synth.torch_activation_batch(s.n, Ra, sa, synth.SEED_ACT_A + li, wl.ea_steps_before, dev)
+        g = synth.torch_activation_batch(s.n, Rg, sg, synth.SEED_ACT_G + li, wl.ea_steps_before, dev)
+        ah = torch.cat([a, torch.ones((s.n, 1), device=dev)], dim=1)
+        L.J = (g.T @ ah / s.n).contiguous()
+        del ah
+        if act_dtype_bf16:
+            a, g = a.to(torch.bfloat16), g.to(torch.bfloat16)
+        L.a, L.g = a.contiguous(), g.contiguous()
+        L.A0, L.G0 = L.A.clone(), L.G.clone()      # restored before every timed step
+        L.Ab = L.A.to(torch.bfloat16)
+        L.Gb = L.G.to(torch.bfloat16)
+        L.ra, L.rg = min(wl.r_cap, s.d_a), min(wl.r_cap, s.d_g)
+        layers.append(L)
+        torch.cuda.synchronize()
+    return wl, layers
+
+
+def make_buffers(wl, layers, dev, sketch):
+    import torch
+    import paper_2206_15397_amd as K
+    for li, L in enumerate(layers):
+        L.Ua = torch.empty((L.d_a, L.ra), device=dev)
+        L.Da = torch.empty((L.ra,), device=dev)
+        L.Ug = torch.empty((L.d_g, L.rg), device=dev)
+        L.Dg = torch.empty((L.rg,), device=dev)
+        L.S = torch.empty((L.d_g, L.d_a), device=dev)
+        L.st = torch.zeros((2,), dtype=torch.int32, device=dev)
+        L.ws_a = torch.empty(K.rand_eig_workspace_bytes(L.d_a, L.ra, wl.p, wl.q, sketch), dtype=torch.uint8, device=dev)
+        L.ws_g = torch.empty(K.rand_eig_workspace_bytes(L.d_g, L.rg, wl.p, wl.q, sketch), dtype=torch.uint8, device=dev)
+        L.ws_p = torch.empty(K.precondition_workspace_bytes(L.d_g, L.d_a, L.ra, L.rg), dtype=torch.uint8, device=dev)
+        L.ws_ea_a = torch.empty(max(1, K.lib().kfac_ea_update_workspace(L.d_a, L.n)), dtype=torch.uint8, device=dev)
+        L.ws_ea_g = torch.empty(max(1, K.lib().kfac_ea_update_workspace(L.d_g, L.n)), dtype=torch.uint8, device=dev)
+
+
+def layer_step(wl, li, L, sketch, bf16_shadow):
+    """One layer's share of the K-factor step on the current stream."""
+    import paper_2206_15397_amd as K
+    K.ea_update(L.A, L.a, wl.rho, 1.0 / L.n, append_ones=L.shape.bias, F_bf16=L.Ab if bf16_shadow else None,
+                workspace=L.ws_ea_a)
+    K.ea_update(L.G, L.g, wl.rho, 1.0 / L.n, F_bf16=L.Gb if bf16_shadow else None, workspace=L.ws_ea_g)
+    K.rand_eig(L.A, L.ra, wl.p, wl.q, wl.seed, 2 * li, 0, sketch=sketch, F_bf16=L.Ab if sketch == "bf16" else None,
+               U=L.Ua, D=L.Da, workspace=L.ws_a, status=L.st[0:1])
+    K.rand_eig(L.G, L.rg, wl.p, wl.q, wl.seed, 2 * li + 1, 0, sketch=sketch, F_bf16=L.Gb if sketch == "bf16" else None,
+               U=L.Ug, D=L.Dg, workspace=L.ws_g, status=L.st[1:2])
+    K.precondition(L.J, L.Ua, L.Da, L.Ug, L.Dg, wl.lam, S=L.S, workspace=L.ws_p)
+
+
+def restore(layers):
+    for L in layers:
+        L.A.copy_(L.A0)
+        L.G.copy_(L.G0)
+
+
+def cost(L):
+    return L.d_a ** 2 * (L.ra + 16) + L.d_g ** 2 * (L.rg + 16) + L.n * (L.d_a ** 2 + L.d_g ** 2) / 64
+
+
+def run_plain(wl, layers, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        restore(layers)
+        for li, L in enumerate(layers):
+            layer_step(wl, li, L, "fp32", False)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        restore(layers)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for li, L in enumerate(layers):
+            layer_step(wl, li, L, "fp32", False)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return times
+
+
+def capture_batched(wl, layers, nstreams):
+    """Capture one K-factor step: layers assigned to streams by longest-processing-time."""
+    import torch
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    load = [0.0] * nstreams
+    assign = [[] for _ in range(nstreams)]
+    for li in sorted(range(len(layers)), key=lambda i: -cost(layers[i])):
+        k = min(range(nstreams), key=lambda s: load[s])
+        assign[k].append(li)
+        load[k] += cost(layers[li])
+
+    def body():
+        main = torch.cuda.current_stream()      # the capturing stream inside torch.cuda.graph
+        fork = torch.cuda.Event()
+        fork.record(main)
+        joins = []
+        for s, lis in zip(streams, assign):
+            s.wait_event(fork)
+            with torch.cuda.stream(s):
+                for li in lis:
+                    layer_step(wl, li, layers[li], "bf16", True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+            joins.append(ev)
+        for ev in joins:
+            main.wait_event(ev)
+
+    # warm the allocator / first-launch paths outside the capture
+    body()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        body()
+    torch.cuda.synchronize()
+    return g
+
+
+def run_batched(wl, layers, steps, warmup, nstreams):
+    import torch
+    restore(layers)
+    g = capture_batched(wl, layers, nstreams)
+    for _ in range(warmup):
+        restore(layers)
+        g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        restore(layers)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return g, times
+
+
+def median(xs):
+    s = sorted(xs)
+    return s[len(s) // 2]
+
+
+def cpu_baseline(target_seconds=15.0):
+    """The FP64 oracle on a bounded sample of the same workload (the FC head and the last
+    conv block: EA step, SREVD of both factors, damped inverse per layer)."""
+    import numpy as np
+    import oracle as O
+    from paper_2206_15397_amd import synth
+    wl = synth.vgg16_bn_workload()
+    order = [15, 14, 13, 12, 11, 10]      # fc3, fc2, fc1, conv13, conv12, conv11
+    t0 = time.perf_counter()
+    factors = 0
+    done = []
+    for li in order:
+        s = wl.layers[li]
+        Ra = synth.haar_orthogonal(s.m_a, synth.SEED_ROT_A + li)
+        Rg = synth.haar_orthogonal(s.d_g, synth.SEED_ROT_G + li)
+        a = synth.activation_batch(s.n, Ra, synth.power_spectrum(s.m_a), synth.SEED_ACT_A + li, 0)
+        g = synth.activation_batch(s.n, Rg, synth.power_spectrum(s.d_g), synth.SEED_ACT_G + li, 0)
+        t_l = time.perf_counter()
+        L = {"A": np.eye(s.d_a), "G": np.eye(s.d_g), "a": a, "g": g, "bias": True,
+             "J": g.T @ np.concatenate([a, np.ones((s.n, 1))], 1) / s.n}
+        O.kfactor_step([L], wl.rho, wl.lam, wl.r_cap, wl.p, wl.q, wl.seed)
+        factors += 2
+        done.append(s.name)
+        if time.perf_counter() - t0 > target_seconds:
+            break
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(factors / el, 4), "unit": "K-factor eig-inversions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"FP64 oracle K-factor step (EA + SREVD of both factors + damped inverse) for layers "
+                      f"{','.join(done)} = {factors} factors in {el:.1f}s; host nproc={os.cpu_count()}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              "(multi-GPU sharding is design-only).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2206_15397_amd as K
+    dev = torch.device("cuda:0")
+    K.lib()
+    log("building workload (bf16 activations) ...")
+    t0 = time.time()
+    wl, layers = build_workload(dev, act_dtype_bf16=True)
+    make_buffers(wl, layers, dev, "bf16")
+    log(f"  setup {time.time() - t0:.1f}s")
+    g, tb = run_batched(wl, layers, args.steps, args.warmup, args.streams)
+    ms_b = median(tb)
+    status_b = [int(x) for L in layers for x in L.st.cpu().tolist()]
+    log(f"batched bf16: median {ms_b:.3f} ms  (p10 {sorted(tb)[len(tb)//10]:.3f}, max {max(tb):.3f}) status={set(status_b)}")
+    out = {}
+    plain_ms = None
+    if not args.no_plain:
+        del g
+        for L in layers:
+            for n in ("a", "g"):
+                setattr(L, n, getattr(L, n).float())
+        wsz = [L.ws_a.numel() for L in layers]
+        make_buffers(wl, layers, dev, "fp32")
+        tp = run_plain(wl, layers, max(3, args.steps // 4), 1)
+        plain_ms = median(tp)
+        log(f"plain fp32: median {plain_ms:.3f} ms")
+    nfac = 2 * len(layers)
+    res = {
+        "metric": "K-factor eig-inversions/s + K-FAC step ms vs plain FP32 at <=1e-4/<=5e-3 err",
+        "value": round(nfac / (ms_b / 1e3), 2),
+        "unit": "K-factor eig-inversions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_b, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+fp32+fp64",
+        "data": "synthetic",
+        "config": {"workload": "vgg16_bn_cifar_b128_factor_set", "factors": nfac, "layers": len(layers),
+                   "r": "min(256,d)", "p": wl.p, "q": wl.q, "rho": wl.rho, "lambda": wl.lam,
+                   "path": "batched bf16-sketch, hipGraph over %d streams" % args.streams},
+        "plain_fp32_ms_per_step": None if plain_ms is None else round(plain_ms, 4),
+        "speedup_vs_plain_fp32": None if plain_ms is None else round(plain_ms / ms_b, 3),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        res["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
