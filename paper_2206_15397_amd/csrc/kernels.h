@@ -24,7 +24,8 @@ hipError_t launch_ea_bf16(float* F, int d, long ldf, const uint16_t* X, int n, i
 hipError_t launch_omega(int d, int l, int d_pad, int l_pad, uint64_t seed, uint64_t stream_id, uint32_t inv,
                         float* OmT, long ldt, uint16_t* OmTb, float* Om, long ldo, uint32_t* words,
                         hipStream_t s);
-hipError_t launch_sign_normalize(float* U, long ldu, int d, int r, hipStream_t s);
+int sign_chunks(int d);
+hipError_t launch_sign_normalize(float* U, long ldu, int d, int r, float* pval, int* pidx, hipStream_t s);
 
 // bf16 sketch GEMM (kernels_bf16.hip): Ct[M x N] = A[M x K] * B[N x K]^T, both K-contiguous
 hipError_t launch_gemm_bf16_nt(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb,
@@ -39,6 +40,7 @@ hipError_t launch_cholesky(const double* G, long ldg, int n, long m_rows, double
                            int* status, int* fail_flag, hipStream_t s);
 hipError_t launch_trsm(const double* W, long ldw, const double* Li, int n, int l_pad, const float* Yt,
                        long ldy, int ncols, float* Qt, long ldq, uint16_t* Qtb, long ldqb, hipStream_t s);
+size_t small_eig_scratch_doubles(int n, int r);
 hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r,
                             double* A, double* V, double* diag, double* off, double* Z, double* scratch,
                             float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s);

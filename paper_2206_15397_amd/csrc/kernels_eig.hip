@@ -1,0 +1,710 @@
+// fp64 symmetric eigensolver for the (r+p) x (r+p) Rayleigh-Ritz matrix of Alg. 3
+// ("Eigen_decomp(C)"), and for the factor itself when r+p >= d:
+//   1. Householder tridiagonalisation, one workgroup.  For n <= 288 the lower triangle
+//      lives in registers of 1024 threads (32 x 32 thread grid, 9 x 9 blocks of 32).
+//   2. split of the tridiagonal T into unreduced blocks (|e_i| <= 2 eps ||T||);
+//   3. every eigenvalue of every block by 16-way multisection bisection on Sturm counts
+//      (one 16-lane group per eigenvalue, many workgroups);
+//   4. selection of the r largest (descending), detection of tight clusters;
+//   5. eigenvectors by the twisted factorisation T - lambda I = N_k Delta_k N_k^T of the
+//      eigenvalue's block (one thread per eigenvector, factors kept in LDS);
+//   6. inverse iteration with Gram-Schmidt for members of tight clusters (rare);
+//   7. back-transformation by the Householder reflectors (one wavefront per column).
+#include "kernels.h"
+
+namespace kfac {
+
+constexpr double kEps = 2.2204460492503131e-16;
+constexpr double kTiny = 2.2250738585072014e-308;
+
+// ======================================================================================
+// 1a. Register-resident tridiagonalisation, n <= 288.
+// Thread t: tr = t / 32, tc = t % 32 owns A[32 I + tr][32 J + tc] for I >= J (lower
+// triangle; on diagonal blocks only tr >= tc).  Slot (I, J) -> I (I + 1) / 2 + J.
+// ======================================================================================
+constexpr int TB = 32, TNB = 9, TNMAX = TB * TNB;
+
+__device__ __forceinline__ constexpr int tslot(int I, int J) { return I * (I + 1) / 2 + J; }
+
+__global__ __launch_bounds__(1024) void k_tridiag_reg(const double* C, long ldc, const float* Cf, long ldcf,
+                                                      int n, double* V, double* diag, double* off,
+                                                      int* status) {
+  __shared__ double sv[TNMAX];
+  __shared__ double sw[TNMAX];
+  __shared__ double spr[TNB][TB];
+  __shared__ double spc[16][TNB][TB];
+  __shared__ double sscal[2];
+  const int t = threadIdx.x, tr = t >> 5, tc = t & 31, lane = t & 63, wave = t >> 6;
+  double a[45];
+  bool bad = false;
+#pragma unroll
+  for (int I = 0; I < TNB; ++I)
+#pragma unroll
+    for (int J = 0; J <= I; ++J) {
+      const int i = TB * I + tr, j = TB * J + tc;
+      double val = 0.0;
+      if (i < n && j < n && (I != J || tr >= tc)) {
+        double x, y;
+        if (Cf) { x = Cf[(long)i * ldcf + j]; y = Cf[(long)j * ldcf + i]; }
+        else { x = C[(long)i * ldc + j]; y = C[(long)j * ldc + i]; }
+        val = 0.5 * (x + y);
+        if (!isfinite(val)) bad = true;
+      }
+      a[tslot(I, J)] = val;
+    }
+  if (bad) atomicOr(status, KFAC_DS_NONFINITE);
+  for (int i = t; i < TNMAX; i += 1024) { sv[i] = 0.0; sw[i] = 0.0; }
+  __syncthreads();
+
+  for (int k = 0; k + 2 < n; ++k) {
+    const int kb = (k + 1) >> 5;          // first block touching rows/cols > k
+    const int J0 = k >> 5, c0 = k & 31;   // column k: block column J0, tc == c0
+    // (1) column k, rows >= k, into sw
+    if (tc == c0) {
+#pragma unroll
+      for (int I = 0; I < TNB; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J)
+          if (J == J0) {
+            const int i = TB * I + tr;
+            if (i >= k && i < n) sw[i] = a[tslot(I, J)];
+          }
+    }
+    __syncthreads();
+    // (2) Householder vector v (unit norm, H = I - 2 v v^T) by wave 0
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) { const double x = sw[i]; s += x * x; }
+      s = wave_sum(s);
+      const double x0 = sw[k + 1];
+      const double nrm = sqrt(s);
+      const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+      const double vn2 = s - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+      const double inv = (s > 0.0 && vn2 > 0.0) ? 1.0 / sqrt(vn2) : 0.0;
+      for (int i = lane; i < n; i += 64) {
+        double vi = 0.0;
+        if (i > k + 1) vi = sw[i] * inv;
+        else if (i == k + 1) vi = (x0 - alpha) * inv;
+        sv[i] = vi;
+        V[(long)k * n + i] = vi;
+      }
+      if (lane == 0) {
+        diag[k] = sw[k];
+        off[k] = (inv > 0.0) ? alpha : x0;
+        sscal[0] = inv;
+      }
+    }
+    __syncthreads();
+    if (sscal[0] == 0.0) continue;        // column already reduced (uniform)
+    // (3) p = 2 A v: row partials (reduced over tc in-wave) and column partials (per wave)
+    double pr[TNB];
+#pragma unroll
+    for (int I = 0; I < TNB; ++I) pr[I] = 0.0;
+#pragma unroll
+    for (int J = 0; J < TNB; ++J) {
+      if (J >= kb) {
+        const double vj = sv[TB * J + tc];
+        double pc = 0.0;
+#pragma unroll
+        for (int I = J; I < TNB; ++I) {
+          const double aij = a[tslot(I, J)];
+          pr[I] += aij * vj;
+          const double vi = sv[TB * I + tr];
+          pc += (I != J || tr != tc) ? aij * vi : 0.0;
+        }
+        pc += __shfl_xor(pc, 32, 64);
+        if (lane < 32) spc[wave][J][tc] = pc;
+      }
+    }
+#pragma unroll
+    for (int I = 0; I < TNB; ++I) {
+      if (I >= kb) {
+        double x = pr[I];
+        x += __shfl_xor(x, 16, 64);
+        x += __shfl_xor(x, 8, 64);
+        x += __shfl_xor(x, 4, 64);
+        x += __shfl_xor(x, 2, 64);
+        x += __shfl_xor(x, 1, 64);
+        if (tc == 0) spr[I][tr] = x;
+      }
+    }
+    __syncthreads();
+    if (t > k && t < n) {
+      const int I = t >> 5, c = t & 31;
+      double p = spr[I][c];
+#pragma unroll
+      for (int w2 = 0; w2 < 16; ++w2) p += spc[w2][I][c];
+      sw[t] = 2.0 * p;
+    }
+    __syncthreads();
+    // (4) w = p - (v^T p) v   (zero at rows <= k)
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) s += sv[i] * sw[i];
+      s = wave_sum(s);
+      if (lane == 0) sscal[1] = s;
+    }
+    __syncthreads();
+    {
+      const double K = sscal[1];
+      if (t < n) sw[t] = (t > k) ? sw[t] - K * sv[t] : 0.0;
+    }
+    __syncthreads();
+    // (5) A <- A - v w^T - w v^T on the active blocks
+#pragma unroll
+    for (int J = 0; J < TNB; ++J) {
+      if (J >= kb) {
+        const double vj = sv[TB * J + tc], wj = sw[TB * J + tc];
+#pragma unroll
+        for (int I = J; I < TNB; ++I) {
+          const double vi = sv[TB * I + tr], wi = sw[TB * I + tr];
+          const double upd = vi * wj + wi * vj;
+          if (I != J || tr >= tc) a[tslot(I, J)] -= upd;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // trailing 2 x 2 (or 1 x 1) block
+#pragma unroll
+  for (int I = 0; I < TNB; ++I)
+#pragma unroll
+    for (int J = 0; J <= I; ++J) {
+      const int i = TB * I + tr, j = TB * J + tc;
+      if (I == J && tr < tc) continue;
+      const double val = a[tslot(I, J)];
+      if (n >= 2 && i == n - 2 && j == n - 2) diag[n - 2] = val;
+      if (n >= 2 && i == n - 1 && j == n - 2) off[n - 2] = val;
+      if (i == n - 1 && j == n - 1) diag[n - 1] = val;
+    }
+}
+
+// ======================================================================================
+// 1b. Tridiagonalisation for 288 < n <= 512: working copy in global memory (L2 resident).
+// ======================================================================================
+__device__ __forceinline__ double block_sum_1024(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(1024) void k_tridiag_gmem(const double* C, long ldc, const float* Cf, long ldcf,
+                                                       int n, double* A, double* V, double* diag, double* off,
+                                                       int* status) {
+  __shared__ double v[KFAC_MAX_SKETCH];
+  __shared__ double pw[KFAC_MAX_SKETCH];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  bool bad = false;
+  for (long e = tid; e < (long)n * n; e += blockDim.x) {
+    int i = (int)(e / n), j = (int)(e % n);
+    double x, y;
+    if (Cf) { x = Cf[(long)i * ldcf + j]; y = Cf[(long)j * ldcf + i]; }
+    else { x = C[(long)i * ldc + j]; y = C[(long)j * ldc + i]; }
+    double s = 0.5 * (x + y);
+    if (!isfinite(s)) bad = true;
+    A[(long)i * n + j] = s;
+  }
+  if (bad) atomicOr(status, KFAC_DS_NONFINITE);
+  __syncthreads();
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m0 = k + 1;
+    double part = 0.0;
+    for (int j = m0 + tid; j < n; j += blockDim.x) { double x = A[(long)k * n + j]; part += x * x; }
+    double nrm2 = block_sum_1024(part, red);
+    double x0 = A[(long)k * n + m0];
+    double nrm = sqrt(nrm2);
+    double alpha = (x0 >= 0.0) ? -nrm : nrm;
+    double vn2 = nrm2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+    double inv = (nrm2 > 0.0 && vn2 > 0.0) ? 1.0 / sqrt(vn2) : 0.0;
+    for (int j = tid; j < n; j += blockDim.x) {
+      double x = (j > m0) ? A[(long)k * n + j] : (j == m0 ? x0 - alpha : 0.0);
+      double vj = (j >= m0) ? x * inv : 0.0;
+      v[j] = vj;
+      V[(long)k * n + j] = vj;
+    }
+    if (tid == 0) { diag[k] = A[(long)k * n + k]; off[k] = (inv > 0.0) ? alpha : x0; }
+    __syncthreads();
+    if (inv == 0.0) continue;
+    for (int i = m0 + wave; i < n; i += 16) {
+      double s = 0.0;
+      for (int j = m0 + lane; j < n; j += 64) s += A[(long)i * n + j] * v[j];
+      s = wave_sum(s);
+      if (lane == 0) pw[i] = 2.0 * s;
+    }
+    __syncthreads();
+    double kp = 0.0;
+    for (int j = m0 + tid; j < n; j += blockDim.x) kp += v[j] * pw[j];
+    double K = block_sum_1024(kp, red);
+    for (int j = m0 + tid; j < n; j += blockDim.x) pw[j] = pw[j] - K * v[j];
+    __syncthreads();
+    const int mm = n - m0;
+    for (long e = tid; e < (long)mm * mm; e += blockDim.x) {
+      int i = m0 + (int)(e / mm), j = m0 + (int)(e % mm);
+      A[(long)i * n + j] -= v[i] * pw[j] + pw[i] * v[j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) { diag[n - 2] = A[(long)(n - 2) * n + n - 2]; off[n - 2] = A[(long)(n - 1) * n + n - 2]; }
+    diag[n - 1] = A[(long)(n - 1) * n + n - 1];
+  }
+}
+
+// ======================================================================================
+// 2. Split into unreduced blocks.  meta layout: see TriMeta.
+// ======================================================================================
+struct TriMeta {
+  double* es;      // [n] off-diagonal with negligible entries zeroed (es[n-1] = 0)
+  int* blo;        // [n] first row of the block containing row i
+  int* bhi;        // [n] one past the last row of that block
+  double* lam;     // [n] eigenvalue of task j (position j of its block, ascending)
+  int* col_task;   // [r] task of output column k (descending order)
+  int* cstart;     // [r] 1 if column k starts a new cluster
+  double* scal;    // [0] ||T|| bound, [1] pivmin, [2] any-cluster flag (as double)
+};
+
+__global__ __launch_bounds__(512) void k_tri_prep(const double* diag, const double* off, int n, TriMeta m) {
+  __shared__ double sred[8];
+  __shared__ double ssh[2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double g = 0.0, e2max = 0.0;
+  for (int i = tid; i < n; i += blockDim.x) {
+    double rad = (i > 0 ? fabs(off[i - 1]) : 0.0) + (i + 1 < n ? fabs(off[i]) : 0.0);
+    g = fmax(g, fabs(diag[i]) + rad);
+    if (i + 1 < n) e2max = fmax(e2max, off[i] * off[i]);
+  }
+  for (int o = 32; o >= 1; o >>= 1) { g = fmax(g, __shfl_xor(g, o, 64)); e2max = fmax(e2max, __shfl_xor(e2max, o, 64)); }
+  if (lane == 0) sred[wave] = g;
+  __syncthreads();
+  if (tid == 0) {
+    double tn = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tn = fmax(tn, sred[w]);
+    if (tn == 0.0) tn = 1.0;
+    ssh[0] = tn;
+  }
+  __syncthreads();
+  if (lane == 0) sred[wave] = e2max;
+  __syncthreads();
+  if (tid == 0) {
+    double em = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) em = fmax(em, sred[w]);
+    ssh[1] = kTiny * fmax(1.0, em);
+    m.scal[0] = ssh[0];
+    m.scal[1] = ssh[1];
+    m.scal[2] = 0.0;
+  }
+  __syncthreads();
+  const double tn = ssh[0];
+  for (int i = tid; i < n; i += blockDim.x) {
+    double e = (i + 1 < n) ? off[i] : 0.0;
+    if (fabs(e) <= 2.0 * kEps * tn) e = 0.0;
+    m.es[i] = e;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int lo = 0;
+    for (int i = 0; i < n; ++i) {
+      if (i == n - 1 || m.es[i] == 0.0) {
+        for (int j = lo; j <= i; ++j) { m.blo[j] = lo; m.bhi[j] = i + 1; }
+        lo = i + 1;
+      }
+    }
+  }
+}
+
+// ======================================================================================
+// 3. Bisection.  Task j (one per row) = eigenvalue number j - blo[j] (ascending) of its
+// block; 16 lanes evaluate the Sturm count at 16 interior points of the bracket.
+// ======================================================================================
+__device__ __forceinline__ double fast_div(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);          // ~2^-26 relative, refined twice
+  r = r * fma(-b, r, 2.0);
+  r = r * fma(-b, r, 2.0);
+  return a * r;
+}
+
+__device__ int sturm_block(const double* d, const double* e2, int lo, int hi, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[lo] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += (q < 0.0);
+  for (int i = lo + 1; i < hi; ++i) {
+    q = (d[i] - x) - fast_div(e2[i - 1], q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+  }
+  return cnt;
+}
+
+constexpr int BIS_LANES = 16;
+
+__global__ __launch_bounds__(256) void k_tri_bisect(const double* diag, int n, TriMeta m) {
+  __shared__ double d[KFAC_MAX_SKETCH], e2[KFAC_MAX_SKETCH], ea[KFAC_MAX_SKETCH];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) {
+    d[i] = diag[i];
+    double e = m.es[i];
+    e2[i] = e * e;
+    ea[i] = fabs(e);
+  }
+  __syncthreads();
+  const double tn = m.scal[0], pivmin = m.scal[1];
+  const int j = blockIdx.x * (256 / BIS_LANES) + tid / BIS_LANES;
+  const int sub = tid % BIS_LANES;
+  const bool active = j < n;
+  const int jj = active ? j : 0;
+  const int lo_i = m.blo[jj], hi_i = m.bhi[jj];
+  const int target = jj - lo_i;
+  double lo = 1e300, hi = -1e300;
+  for (int i = lo_i; i < hi_i; ++i) {
+    double rad = (i > lo_i ? ea[i - 1] : 0.0) + (i + 1 < hi_i ? ea[i] : 0.0);
+    lo = fmin(lo, d[i] - rad);
+    hi = fmax(hi, d[i] + rad);
+  }
+  const double pad = 4.0 * kEps * tn * (hi_i - lo_i) + 2.0 * pivmin;
+  lo -= pad; hi += pad;
+  const int base = (threadIdx.x & 63) & ~(BIS_LANES - 1);
+  for (int it = 0; it < 40; ++it) {
+    const double w = hi - lo;
+    const bool done = !(w > 2.0 * kEps * (fabs(lo) + fabs(hi)) + 1e-3 * kEps * tn + 4.0 * pivmin);
+    const double x = lo + w * (double)(sub + 1) / (double)(BIS_LANES + 1);
+    const int c = (active && !done) ? sturm_block(d, e2, lo_i, hi_i, x, pivmin) : 0;
+    double nlo = lo, nhi = hi;
+#pragma unroll
+    for (int s = 0; s < BIS_LANES; ++s) {
+      const double xs = __shfl(x, base + s, 64);
+      const int cs = __shfl(c, base + s, 64);
+      if (cs <= target) nlo = xs;
+    }
+#pragma unroll
+    for (int s = BIS_LANES - 1; s >= 0; --s) {
+      const double xs = __shfl(x, base + s, 64);
+      const int cs = __shfl(c, base + s, 64);
+      if (cs >= target + 1) nhi = xs;
+    }
+    if (__all(done || !active)) break;
+    if (!done) { lo = nlo; hi = nhi; }
+  }
+  if (active && sub == 0) m.lam[j] = 0.5 * (lo + hi);
+}
+
+// ======================================================================================
+// 4. Descending selection of the r largest eigenvalues and tight-cluster flags.
+// ======================================================================================
+__global__ __launch_bounds__(512) void k_tri_select(int n, int r, TriMeta m, double* Dd, float* D) {
+  __shared__ double lam[KFAC_MAX_SKETCH];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) lam[i] = m.lam[i];
+  __syncthreads();
+  for (int j = tid; j < n; j += blockDim.x) {
+    const double lj = lam[j];
+    int rank = 0;
+    for (int i = 0; i < n; ++i) {
+      const double li = lam[i];
+      rank += (li > lj) || (li == lj && i < j);
+    }
+    if (rank < r) {
+      m.col_task[rank] = j;
+      Dd[rank] = lj;
+      D[rank] = (float)lj;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  const double ctol = 1e-8 * m.scal[0];
+  int any = 0;
+  for (int k = tid; k < r; k += blockDim.x) {
+    int s = 1;
+    if (k > 0) {
+      const int a = m.col_task[k - 1], b = m.col_task[k];
+      if (m.blo[a] == m.blo[b] && fabs(lam[a] - lam[b]) <= ctol) s = 0;
+    }
+    m.cstart[k] = s;
+    any |= (s == 0);
+  }
+  if (any) m.scal[2] = 1.0;   // benign race: every writer stores the same value
+}
+
+// ======================================================================================
+// 5. Eigenvectors by twisted factorisation (one thread per output column).
+// Forward  T - lam I = L D+ L^T :  D+_0 = d_0 - lam,  L_i = e_i / D+_i,
+//                                  D+_{i+1} = d_{i+1} - lam - L_i e_i;
+// backward T - lam I = U D- U^T :  D-_{m-1} = d_{m-1} - lam,  U_i = e_i / D-_{i+1},
+//                                  D-_i = d_i - lam - U_i e_i;
+// twist gamma_k = D+_k + D-_k - (d_k - lam), k* = argmin |gamma_k|;
+// z_{k*} = 1, z_i = -L_i z_{i+1} (i < k*), z_{i+1} = -U_i z_i (i >= k*).
+// The column is written unnormalised (the back-transformation normalises it).
+// ======================================================================================
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_tri_vec(const double* diag, int n, int r, TriMeta m, double* Z, long ldz) {
+  __shared__ double sL[NT][NMAX];
+  __shared__ double sD[NT][NMAX];
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x * NT + tid;
+  if (k >= r) return;
+  const double pivmin = m.scal[1];
+  const double tiny = fmax(pivmin, kEps * kEps * m.scal[0]);
+  const int j = m.col_task[k];
+  const double lam = m.lam[j];
+  const int b0 = m.blo[j], b1 = m.bhi[j];
+  double* L = sL[tid];
+  double* Dp = sD[tid];
+  // forward
+  double dp = diag[b0] - lam;
+  for (int i = b0; i + 1 < b1; ++i) {
+    if (fabs(dp) < tiny) dp = (dp < 0.0) ? -tiny : tiny;
+    const double e = m.es[i];
+    const double l = e / dp;
+    L[i - b0] = l;
+    Dp[i - b0] = dp;
+    dp = (diag[i + 1] - lam) - l * e;
+  }
+  Dp[b1 - 1 - b0] = dp;
+  // backward with twist search
+  double dm = diag[b1 - 1] - lam;
+  double best = fabs(dp);   // gamma_{b1-1} = D+_{b1-1}
+  int kstar = b1 - 1;
+  for (int i = b1 - 2; i >= b0; --i) {
+    if (fabs(dm) < tiny) dm = (dm < 0.0) ? -tiny : tiny;
+    const double e = m.es[i];
+    const double u = e / dm;
+    const double dmi = (diag[i] - lam) - u * e;
+    const double g = Dp[i - b0] + dmi - (diag[i] - lam);
+    Dp[i - b0] = u;           // slot i now holds U_i
+    if (fabs(g) < best) { best = fabs(g); kstar = i; }
+    dm = dmi;
+  }
+  // assemble
+  for (int i = 0; i < b0; ++i) Z[(long)i * ldz + k] = 0.0;
+  for (int i = b1; i < n; ++i) Z[(long)i * ldz + k] = 0.0;
+  double z = 1.0;
+  Z[(long)kstar * ldz + k] = 1.0;
+  for (int i = kstar - 1; i >= b0; --i) {
+    z = -L[i - b0] * z;
+    Z[(long)i * ldz + k] = z;
+  }
+  z = 1.0;
+  for (int i = kstar; i + 1 < b1; ++i) {
+    z = -Dp[i - b0] * z;
+    Z[(long)(i + 1) * ldz + k] = z;
+  }
+}
+
+// ======================================================================================
+// 6. Tight clusters: inverse iteration on the block with Gram-Schmidt against the earlier
+// members (sequential over members, one workgroup).  Exits at once if there is none.
+// scratch: 5 * n doubles.
+// ======================================================================================
+__global__ __launch_bounds__(256) void k_tri_cluster(const double* diag, int n, int r, TriMeta m, double* Z,
+                                                     long ldz, double* scratch, int* status) {
+  __shared__ double red[4];
+  __shared__ double sdot;
+  if (m.scal[2] == 0.0) return;
+  const int tid = threadIdx.x;
+  const double tn = m.scal[0];
+  double* lf = scratch;
+  double* ud = scratch + n;
+  double* uu = scratch + 2L * n;
+  double* u2 = scratch + 3L * n;
+  double* pv = scratch + 4L * n;
+  for (int k = 1; k < r; ++k) {
+    if (m.cstart[k]) continue;
+    int k0 = k;
+    while (k0 > 0 && !m.cstart[k0]) --k0;
+    const int j = m.col_task[k];
+    const int b0 = m.blo[j], b1 = m.bhi[j];
+    const double mu = m.lam[j] + (double)(k - k0) * 10.0 * kEps * tn;
+    if (tid == 0) {
+      // LU with partial pivoting of the block of T - mu I
+      double cd = diag[b0] - mu, cu = (b0 + 1 < b1) ? m.es[b0] : 0.0;
+      for (int i = b0; i + 1 < b1; ++i) {
+        const double dl = m.es[i], nd = diag[i + 1] - mu, nu = (i + 2 < b1) ? m.es[i + 1] : 0.0;
+        if (fabs(cd) >= fabs(dl)) {
+          if (cd == 0.0) cd = kEps * tn;
+          const double f = dl / cd;
+          lf[i] = f; ud[i] = cd; uu[i] = cu; u2[i] = 0.0; pv[i] = 0.0;
+          cd = nd - f * cu; cu = nu;
+        } else {
+          const double f = cd / dl;
+          lf[i] = f; ud[i] = dl; uu[i] = nd; u2[i] = nu; pv[i] = 1.0;
+          cd = cu - f * nd; cu = -f * nu;
+        }
+      }
+      ud[b1 - 1] = (cd == 0.0) ? kEps * tn : cd;
+    }
+    __syncthreads();
+    for (int iter = 0; iter < 3; ++iter) {
+      if (tid == 0) {
+        double cur = Z[(long)b0 * ldz + k];
+        for (int i = b0; i + 1 < b1; ++i) {
+          const double nxt = Z[(long)(i + 1) * ldz + k];
+          if (pv[i] == 0.0) { Z[(long)i * ldz + k] = cur; cur = nxt - lf[i] * cur; }
+          else { Z[(long)i * ldz + k] = nxt; cur = cur - lf[i] * nxt; }
+        }
+        Z[(long)(b1 - 1) * ldz + k] = cur;
+        double x1 = 0.0, x2 = 0.0;
+        for (int i = b1 - 1; i >= b0; --i) {
+          double s = Z[(long)i * ldz + k];
+          if (i + 1 < b1) s -= uu[i] * x1;
+          if (i + 2 < b1) s -= u2[i] * x2;
+          const double xi = s / ud[i];
+          Z[(long)i * ldz + k] = xi;
+          x2 = x1; x1 = xi;
+        }
+      }
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int q = k0; q <= k; ++q) {
+          // normalise column q (q == k) or remove its component from column k (q < k)
+          double s = 0.0;
+          for (int i = b0 + tid; i < b1; i += blockDim.x)
+            s += Z[(long)i * ldz + q] * Z[(long)i * ldz + k];
+          s = wave_sum(s);
+          if ((tid & 63) == 0) red[tid >> 6] = s;
+          __syncthreads();
+          if (tid == 0) sdot = red[0] + red[1] + red[2] + red[3];
+          __syncthreads();
+          const double dt = sdot;
+          if (q < k) {
+            // column q < k is already unit-norm: remove its component from column k
+            for (int i = b0 + tid; i < b1; i += blockDim.x) Z[(long)i * ldz + k] -= dt * Z[(long)i * ldz + q];
+          } else {
+            const double sc = (dt > 0.0 && isfinite(dt)) ? 1.0 / sqrt(dt) : 0.0;
+            if (sc == 0.0 && tid == 0) atomicOr(status, KFAC_DS_EIG_NOCONV);
+            for (int i = b0 + tid; i < b1; i += blockDim.x) Z[(long)i * ldz + k] *= sc;
+          }
+          __syncthreads();
+        }
+      }
+    }
+  }
+}
+
+// Normalise the cluster leaders (columns that start a cluster of size > 1) before the
+// member pass projects against them.
+__global__ __launch_bounds__(256) void k_tri_cluster_lead(int n, int r, TriMeta m, double* Z, long ldz) {
+  __shared__ double red[4];
+  __shared__ double sdot;
+  if (m.scal[2] == 0.0) return;
+  const int tid = threadIdx.x;
+  for (int k = 0; k + 1 < r; ++k) {
+    if (!(m.cstart[k] && !m.cstart[k + 1])) continue;
+    double s = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) { const double z = Z[(long)i * ldz + k]; s += z * z; }
+    s = wave_sum(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) sdot = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    const double sc = sdot > 0.0 ? 1.0 / sqrt(sdot) : 0.0;
+    for (int i = tid; i < n; i += blockDim.x) Z[(long)i * ldz + k] *= sc;
+    __syncthreads();
+  }
+}
+
+// ======================================================================================
+// 7. Back-transformation P = H_0 ... H_{n-3} z for each of the first r columns (one
+// wavefront per column; the column is normalised first).  fp32 output, rows n..n_pad-1
+// zero.  grid = ceil(r / 4) blocks of 256 threads.
+// ======================================================================================
+__global__ __launch_bounds__(256) void k_backtransform(const double* V, const double* Z, long ldz, int n,
+                                                       int n_pad, int r, float* P, long ldp) {
+  constexpr int CH = 16;                      // reflectors staged per LDS chunk
+  __shared__ double vch[CH][KFAC_MAX_SKETCH];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 4 + wave;
+  const bool active = c < r;
+  constexpr int PER = KFAC_MAX_SKETCH / 64;
+  double z[PER];
+  double nn = 0.0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = lane + 64 * u;
+    z[u] = (active && i < n) ? Z[(long)i * ldz + c] : 0.0;
+    nn += z[u] * z[u];
+  }
+  nn = wave_sum(nn);
+  const double sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) z[u] *= sc;
+  for (int kt = n - 3; kt >= 0; kt -= CH) {
+    const int klo = max(0, kt - CH + 1);
+    const int cnt = kt - klo + 1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * n; e += blockDim.x) {
+      const int rr = e / n, ii = e % n;
+      vch[rr][ii] = V[(long)(klo + rr) * n + ii];
+    }
+    __syncthreads();
+    for (int k = kt; k >= klo; --k) {
+      const double* vk = vch[k - klo];
+      double vv[PER];
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int i = lane + 64 * u;
+        vv[u] = (i > k && i < n) ? vk[i] : 0.0;
+        s += vv[u] * z[u];
+      }
+      s = 2.0 * wave_sum(s);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) z[u] -= s * vv[u];
+    }
+  }
+  if (!active) return;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = lane + 64 * u;
+    if (i < n_pad) P[(long)i * ldp + c] = (i < n) ? (float)z[u] : 0.f;
+  }
+}
+
+// ======================================================================================
+size_t small_eig_scratch_doubles(int n, int r) {
+  // es[n] | lam[n] | scal[8] | int blo[n], bhi[n], col_task[r], cstart[r] | cluster[5n]
+  return 2 * (size_t)n + 8 + ((size_t)2 * n + 2 * r + 1) / 2 + 2 + 5 * (size_t)n + 16;
+}
+
+hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r,
+                            double* A, double* V, double* diag, double* off, double* Z, double* scratch,
+                            float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s) {
+  // scratch layout (doubles): es[n] | lam[n] | scal[8] | ints blo[n], bhi[n], col_task[r], cstart[r] | cl[5n]
+  TriMeta m;
+  double* p = scratch;
+  m.es = p; p += n;
+  m.lam = p; p += n;
+  m.scal = p; p += 8;
+  int* ip = (int*)p;
+  m.blo = ip; ip += n;
+  m.bhi = ip; ip += n;
+  m.col_task = ip; ip += r;
+  m.cstart = ip; ip += r;
+  p = (double*)(((uintptr_t)ip + 15) & ~(uintptr_t)15);
+  double* cl = p;
+  if (n <= TNMAX) {
+    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(1024), 0, s, C, ldc, Cf, ldcf, n, V, diag, off, status);
+  } else {
+    hipLaunchKernelGGL(k_tridiag_gmem, dim3(1), dim3(1024), 0, s, C, ldc, Cf, ldcf, n, A, V, diag, off, status);
+  }
+  hipLaunchKernelGGL(k_tri_prep, dim3(1), dim3(512), 0, s, diag, off, n, m);
+  hipLaunchKernelGGL(k_tri_bisect, dim3((n + 15) / 16), dim3(256), 0, s, diag, n, m);
+  hipLaunchKernelGGL(k_tri_select, dim3(1), dim3(512), 0, s, n, r, m, Dd, D);
+  if (n <= TNMAX) {
+    hipLaunchKernelGGL((k_tri_vec<32, TNMAX>), dim3((r + 31) / 32), dim3(32), 0, s, diag, n, r, m, Z, (long)r);
+  } else {
+    hipLaunchKernelGGL((k_tri_vec<16, KFAC_MAX_SKETCH>), dim3((r + 15) / 16), dim3(16), 0, s, diag, n, r, m, Z,
+                       (long)r);
+  }
+  hipLaunchKernelGGL(k_tri_cluster_lead, dim3(1), dim3(256), 0, s, n, r, m, Z, (long)r);
+  hipLaunchKernelGGL(k_tri_cluster, dim3(1), dim3(256), 0, s, diag, n, r, m, Z, (long)r, cl, status);
+  hipLaunchKernelGGL(k_backtransform, dim3((r + 3) / 4), dim3(256), 0, s, V, Z, (long)r, n, n_pad, r, P, ldp);
+  return hipGetLastError();
+}
+
+}  // namespace kfac

@@ -175,39 +175,64 @@ __global__ void k_omega(int d, int l, int d_pad, int l_pad, uint32_t k0, uint32_
 
 // ------------------------------------------------------------------------------------
 // Sign convention: the largest-magnitude entry of each column of U is made positive
-// (ties: lowest row).  Block = 256 threads = 4 row groups x 64 columns.
-__global__ __launch_bounds__(256) void k_sign_normalize(float* U, long ldu, int d, int r) {
-  __shared__ float smax[4][64];
-  __shared__ int sidx[4][64];
-  __shared__ float ssgn[64];
+// (ties: lowest row).  Phase 1: per 256-row chunk and column, the (first) entry of
+// largest magnitude, kept with its sign.  Phase 2: every block derives the column signs
+// from the chunk partials (in chunk order) and flips its own chunk.
+// Block = 256 threads = 4 row groups x 64 columns; grid (ceil(r/64), ceil(d/256)).
+constexpr int SG_ROWS = 256;
+
+__global__ __launch_bounds__(256) void k_sign_partial(const float* U, long ldu, int d, int r, float* pval, int* pidx) {
+  __shared__ float sv[4][64];
+  __shared__ int si[4][64];
   const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + cl;
-  float best = -1.f;
+  const int c = blockIdx.x * 64 + cl, chunk = blockIdx.y;
+  const int r0 = chunk * SG_ROWS, r1 = min(d, r0 + SG_ROWS);
+  float best = -1.f, bval = 0.f;
   int bidx = 0x7fffffff;
   if (c < r) {
-    for (int i = rg; i < d; i += 4) {
-      float a = fabsf(U[(long)i * ldu + c]);
-      if (a > best) { best = a; bidx = i; }   // rows visited ascending per group
+    for (int i = r0 + rg; i < r1; i += 4) {
+      const float v = U[(long)i * ldu + c];
+      if (fabsf(v) > best) { best = fabsf(v); bval = v; bidx = i; }
     }
   }
-  smax[rg][cl] = best;
-  sidx[rg][cl] = bidx;
+  sv[rg][cl] = bval; si[rg][cl] = bidx;
   __syncthreads();
-  if (rg == 0) {
-    float b = smax[0][cl];
-    int bi = sidx[0][cl];
+  if (rg == 0 && c < r) {
+    float bv = sv[0][cl];
+    int bi = si[0][cl];
     for (int g = 1; g < 4; ++g) {
-      float v = smax[g][cl];
-      int vi = sidx[g][cl];
-      if (v > b || (v == b && vi < bi)) { b = v; bi = vi; }
+      const float v = sv[g][cl];
+      const int vi = si[g][cl];
+      if (fabsf(v) > fabsf(bv) || (fabsf(v) == fabsf(bv) && vi < bi)) { bv = v; bi = vi; }
     }
+    pval[(long)chunk * r + c] = bv;
+    pidx[(long)chunk * r + c] = bi;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sign_apply(float* U, long ldu, int d, int r, const float* pval,
+                                                    const int* pidx, int nchunks) {
+  __shared__ float ssgn[64];
+  const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl, chunk = blockIdx.y;
+  if (rg == 0) {
     float s = 1.f;
-    if (c < r && bi < d && U[(long)bi * ldu + c] < 0.f) s = -1.f;
+    if (c < r) {
+      float bv = 0.f;
+      int bi = 0x7fffffff;
+      for (int k = 0; k < nchunks; ++k) {
+        const float v = pval[(long)k * r + c];
+        const int vi = pidx[(long)k * r + c];
+        if (fabsf(v) > fabsf(bv) || (fabsf(v) == fabsf(bv) && vi < bi)) { bv = v; bi = vi; }
+      }
+      s = (bv < 0.f) ? -1.f : 1.f;
+    }
     ssgn[cl] = s;
   }
   __syncthreads();
-  if (c < r && ssgn[cl] < 0.f)
-    for (int i = rg; i < d; i += 4) U[(long)i * ldu + c] = -U[(long)i * ldu + c];
+  if (c >= r || ssgn[cl] > 0.f) return;
+  const int r0 = chunk * SG_ROWS, r1 = min(d, r0 + SG_ROWS);
+  for (int i = r0 + rg; i < r1; i += 4) U[(long)i * ldu + c] = -U[(long)i * ldu + c];
 }
 
 // ------------------------------------------------------------------------------------
@@ -313,8 +338,13 @@ hipError_t launch_omega(int d, int l, int d_pad, int l_pad, uint64_t seed, uint6
   return hipGetLastError();
 }
 
-hipError_t launch_sign_normalize(float* U, long ldu, int d, int r, hipStream_t s) {
-  hipLaunchKernelGGL(k_sign_normalize, dim3((r + 63) / 64), dim3(256), 0, s, U, ldu, d, r);
+int sign_chunks(int d) { return (d + SG_ROWS - 1) / SG_ROWS; }
+
+hipError_t launch_sign_normalize(float* U, long ldu, int d, int r, float* pval, int* pidx, hipStream_t s) {
+  dim3 grid((r + 63) / 64, sign_chunks(d));
+  hipLaunchKernelGGL(k_sign_partial, grid, dim3(256), 0, s, (const float*)U, ldu, d, r, pval, pidx);
+  hipLaunchKernelGGL(k_sign_apply, grid, dim3(256), 0, s, U, ldu, d, r, (const float*)pval, (const int*)pidx,
+                     sign_chunks(d));
   return hipGetLastError();
 }
 

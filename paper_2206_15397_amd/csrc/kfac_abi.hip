@@ -32,7 +32,8 @@ inline kfac_status hip_status(hipError_t e) { return e == hipSuccess ? KFAC_OK :
 struct EigWs {
   int64_t d, r, l, l_pad, ldt;
   bool exact, bf16;
-  float *OmT, *Yt, *Qt, *P;
+  float *OmT, *Yt, *Qt, *P, *sval;
+  int* sidx;
   uint16_t *OmTb, *Qtb;
   double *G, *Wc, *Li, *part, *A, *V, *diag, *off, *Z, *scr, *Dd;
   int* fail;
@@ -68,8 +69,10 @@ struct EigWs {
     diag = b.take<double>(n + 1);
     off = b.take<double>(n + 1);
     Z = b.take<double>(n * r);
-    scr = b.take<double>(5 * n * r);
+    scr = b.take<double>(small_eig_scratch_doubles((int)n, (int)r));
     Dd = b.take<double>(r);
+    sval = b.take<float>((size_t)sign_chunks((int)d) * r);
+    sidx = b.take<int>((size_t)sign_chunks((int)d) * r);
     fail = b.take<int>(16);
     bytes = b.off + kAlign;
   }
@@ -164,7 +167,7 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
     // l == d: the sketch spans R^d, Q = I; eigendecompose F itself, U = P[:, :r].
     CK(launch_small_eig(nullptr, 0, F, ldf, (int)d, (int)d, (int)r, w.A, w.V, w.diag, w.off, w.Z, w.scr, U,
                         ldu, D, w.Dd, st, s));
-    CK(launch_sign_normalize(U, ldu, (int)d, (int)r, s));
+    CK(launch_sign_normalize(U, ldu, (int)d, (int)r, w.sval, w.sidx, s));
     return KFAC_OK;
   }
   const bool bf = (prec == KFAC_SKETCH_BF16);
@@ -218,7 +221,7 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
     g.C = U; g.ldc = ldu; g.alpha = 1.f; g.ones_col = -1;
     CK(launch_gemm(g, true, false, s));
   }
-  CK(launch_sign_normalize(U, ldu, dd, (int)r, s));
+  CK(launch_sign_normalize(U, ldu, dd, (int)r, w.sval, w.sidx, s));
 #undef CK
   return KFAC_OK;
 }

@@ -105,7 +105,7 @@ def built_factor(m, n, steps, bias, seed, rho=0.95):
 
 
 @pytest.mark.parametrize("d,r,p,q", [(257, 32, 10, 1), (128, 32, 10, 1), (300, 20, 5, 0), (500, 64, 16, 2),
-                                     (1100, 40, 24, 1)])
+                                     (1100, 40, 24, 1), (1000, 256, 16, 1), (900, 300, 20, 1)])
 def test_rand_eig_fp32(d, r, p, q):
     F = built_factor(d - 1, 128, 10, True, d)
     Ft = torch.from_numpy(F).to(DEV)
@@ -121,7 +121,8 @@ def test_rand_eig_fp32(d, r, p, q):
     assert proj_err(Ug[:, :k], Uo[:, :k]) < 1e-3
 
 
-@pytest.mark.parametrize("d,r,p", [(24, 20, 8), (64, 64, 16), (256, 240, 16), (272, 256, 16), (10, 10, 0)])
+@pytest.mark.parametrize("d,r,p", [(24, 20, 8), (64, 64, 16), (256, 240, 16), (272, 256, 16), (10, 10, 0),
+                                   (300, 280, 30), (1, 1, 0), (2, 1, 3)])
 def test_rand_eig_exact_regime(d, r, p):
     F = synth.psd_factor(d, synth.exp_spectrum(d, 5.0) + 0.05, 7).astype(np.float32)
     U, D, st = K().rand_eig(torch.from_numpy(F).to(DEV), r, p, 1, seed=0)
