@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--streams", type=int, default=0,
+                    help="also time per-factor calls spread over this many streams (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--check", action="store_true", help="check sampled outputs against the oracle")
@@ -207,6 +208,71 @@ def run_batched(wl, layers, steps, warmup, nstreams):
     return g, times
 
 
+def make_plan(wl, layers, sketch="bf16"):
+    """All 32 factors and 16 layers of the step in one grouped plan (bf16 activations, bf16
+    sketch): factor 2i is layer i's A factor, 2i+1 its G factor."""
+    import paper_2206_15397_amd as K
+    fd, ld = [], []
+    for li, L in enumerate(layers):
+        fd.append(dict(F=L.A, F_bf16=L.Ab, X=L.a, append_ones=L.shape.bias, scale=1.0 / L.n, r=L.ra, p=wl.p,
+                       q=wl.q, stream_id=2 * li, U=L.Ua, D=L.Da))
+        fd.append(dict(F=L.G, F_bf16=L.Gb, X=L.g, append_ones=False, scale=1.0 / L.n, r=L.rg, p=wl.p,
+                       q=wl.q, stream_id=2 * li + 1, U=L.Ug, D=L.Dg))
+        ld.append(dict(fa=2 * li, fg=2 * li + 1, J=L.J, S=L.S))
+    plan = K.Plan(fd, ld, sketch=sketch)
+    plan.set_scalars(wl.rho, wl.lam, wl.seed, 0).upload()
+    return plan
+
+
+def run_plan(wl, layers, steps, warmup):
+    import torch
+    plan = make_plan(wl, layers)
+    restore(layers)
+    plan.launch()                       # first-launch paths outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        restore(layers)
+        g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        restore(layers)
+        plan.status.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return plan, g, times
+
+
+def phase_times(plan, layers, reps):
+    """Average duration of every grouped launch of the plan: HIP events on the launch
+    stream between consecutive launches, with the queue pre-filled behind a spin kernel so
+    that host enqueue gaps do not show up as kernel time."""
+    import torch
+    names = plan.launch_names()
+    n = len(names)
+    acc = [0.0] * n
+    for _ in range(reps):
+        restore(layers)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        torch.cuda._sleep(20_000_000)
+        ev[0].record()
+        for i in range(n):
+            plan.launch_range(i, 1)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        for i in range(n):
+            acc[i] += ev[i].elapsed_time(ev[i + 1])
+    return names, [a / reps for a in acc]
+
+
 def median(xs):
     s = sorted(xs)
     return s[len(s) // 2]
@@ -260,14 +326,23 @@ def main():
     wl, layers = build_workload(dev, act_dtype_bf16=True)
     make_buffers(wl, layers, dev, "bf16")
     log(f"  setup {time.time() - t0:.1f}s")
-    g, tb = run_batched(wl, layers, args.steps, args.warmup, args.streams)
-    ms_b = median(tb)
-    status_b = [int(x) for L in layers for x in L.st.cpu().tolist()]
-    log(f"batched bf16: median {ms_b:.3f} ms  (p10 {sorted(tb)[len(tb)//10]:.3f}, max {max(tb):.3f}) status={set(status_b)}")
-    out = {}
+    plan, gp, tp_ = run_plan(wl, layers, args.steps, args.warmup)
+    ms_b = median(tp_)
+    log(f"plan bf16 ({plan.launch_count} grouped launches): median {ms_b:.3f} ms  (min {min(tp_):.3f}, "
+        f"max {max(tp_):.3f}) status={int(plan.status.item())}")
+    names, pt = phase_times(plan, layers, max(3, args.steps // 2))
+    tot = sum(pt)
+    for i, (nm, t) in enumerate(zip(names, pt)):
+        log(f"  [{i:2d}] {nm:18s} {t * 1e3:9.1f} us  {100 * t / tot:5.1f}%")
+    del gp
     plain_ms = None
-    if not args.no_plain:
+    if args.streams > 0:
+        g, tb = run_batched(wl, layers, args.steps, args.warmup, args.streams)
+        ms_s = median(tb)
+        status_b = [int(x) for L in layers for x in L.st.cpu().tolist()]
+        log(f"per-factor bf16 over {args.streams} streams: median {ms_s:.3f} ms status={set(status_b)}")
         del g
+    if not args.no_plain:
         for L in layers:
             for n in ("a", "g"):
                 setattr(L, n, getattr(L, n).float())
@@ -288,7 +363,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "vgg16_bn_cifar_b128_factor_set", "factors": nfac, "layers": len(layers),
                    "r": "min(256,d)", "p": wl.p, "q": wl.q, "rho": wl.rho, "lambda": wl.lam,
-                   "path": "batched bf16-sketch, hipGraph over %d streams" % args.streams},
+                   "path": "grouped plan (%d launches), bf16 sketch, hipGraph" % plan.launch_count},
         "plain_fp32_ms_per_step": None if plain_ms is None else round(plain_ms, 4),
         "speedup_vs_plain_fp32": None if plain_ms is None else round(plain_ms / ms_b, 3),
     }

@@ -168,6 +168,69 @@ kfac_status kfac_precondition(const float* J, int64_t d_g, int64_t d_a, int64_t 
                               float lambda, float* S, int64_t lds,
                               void* workspace, size_t ws_bytes, kfac_stream_t stream);
 
+
+/*
+ * Grouped plan -- one K-factor step of a whole network (all factors and layers) as a
+ * fixed sequence of grouped launches: every launch covers one phase (EA tiles, sketch
+ * GEMM, Gram, Cholesky, eigensolver stage, preconditioner product, ...) of every factor or
+ * layer at once, so the many small, latency-bound pieces of different factors run
+ * concurrently.  The sequence is stream-ordered and contains no allocation, copy or
+ * memset, so it can be captured into a hipGraph once and replayed.  The EA step follows
+ * Alg. 1's EA lines, the inversion Alg. 3 (SREVD) and the preconditioner the Sec. 4.1
+ * identity used by Alg. 5 -- exactly as kfac_ea_update / kfac_rand_eig /
+ * kfac_precondition do one factor or layer at a time.
+ *
+ * Usage: kfac_plan_create -> kfac_plan_workspace -> (allocate) -> kfac_plan_set_scalars
+ * -> kfac_plan_upload (copies the task tables into the workspace; call again after
+ * changing scalars, outside any graph capture) -> kfac_plan_launch (capturable, repeatable)
+ * -> kfac_plan_destroy.  Limits: l = min(r+p, d) <= 288 for every factor.
+ *
+ * Ownership: create copies the descriptors; the buffers they point to (F, F_bf16, X, U,
+ * D, J, S), the workspace and dev_status belong to the caller and must stay valid while
+ * the plan (or a graph holding its launches) is used.  The workspace head holds the task
+ * tables written by upload; the rest is scratch.  dev_status receives KFAC_DS_* bits OR-ed
+ * over all factors (the caller clears it).  Errors: KFAC_EINVAL for a bad descriptor
+ * (bad sizes or strides, a layer whose factor index is out of range, J aliasing S,
+ * missing F_bf16 on the bf16 path), KFAC_EUNSUPPORTED for l > 288, KFAC_EWORKSPACE for a
+ * short workspace, KFAC_EHIP when a launch or the table copy fails.
+ */
+typedef struct kfac_plan kfac_plan;
+
+typedef struct {
+  float* F; int64_t d, ldf;            /* factor, d x d fp32, symmetric                     */
+  uint16_t* F_bf16; int64_t ldfb;      /* bf16 copy of F; required for KFAC_SKETCH_BF16;    */
+                                       /* refreshed by the EA phase when X is given          */
+  int64_t r, p; int q;                 /* rank, oversampling, power iterations              */
+  uint64_t stream_id;                  /* Omega stream (see kfac_gaussian_omega)            */
+  const void* X; kfac_dtype xtype;     /* EA input (n x d_in, ldx); X == NULL: no EA update */
+  int64_t n, d_in, ldx; int append_ones; float scale;
+  float* U; int64_t ldu; float* D;     /* outputs: U d x r, D r                             */
+} kfac_factor_desc;
+
+typedef struct {
+  int fa, fg;                          /* factor indices of the A (input) and G (output) side */
+  const float* J; int64_t ldj;         /* gradient d_g x d_a                                  */
+  float* S; int64_t lds;               /* preconditioned gradient d_g x d_a                   */
+} kfac_layer_desc;
+
+kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac_layer_desc* layers, int nl,
+                             kfac_precision prec, kfac_plan** out);
+size_t kfac_plan_workspace(const kfac_plan* plan);
+/* Defaults: rho 0.95, lambda 0.1, seed 0, inversion_index 0, all phases on. */
+kfac_status kfac_plan_set_scalars(kfac_plan* plan, float rho, float lambda, uint64_t seed,
+                                  uint32_t inversion_index, int do_ea, int do_eig, int do_precondition);
+kfac_status kfac_plan_upload(kfac_plan* plan, void* workspace, size_t ws_bytes, int32_t* dev_status,
+                             kfac_stream_t stream);
+/* Number of grouped launches one kfac_plan_launch issues (after upload). */
+int kfac_plan_launch_count(const kfac_plan* plan);
+/* Enqueue every grouped launch on `stream` (no host synchronisation, no allocation). */
+kfac_status kfac_plan_launch(const kfac_plan* plan, kfac_stream_t stream);
+/* Enqueue launches [first, first+count) only, in order (for per-phase timing). */
+kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, kfac_stream_t stream);
+/* Phase name of launch `index` ("gemm_bf16", "tridiag", ...), NULL when out of range. */
+const char* kfac_plan_launch_name(const kfac_plan* plan, int index);
+void kfac_plan_destroy(kfac_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

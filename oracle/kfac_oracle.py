@@ -104,8 +104,9 @@ def philox4x32_10(ctr: np.ndarray, key) -> np.ndarray:
 
 
 def uniforms_from_words(w: np.ndarray) -> np.ndarray:
-    """24-bit uniforms in (0, 1): ((w >> 8) + 1/2) * 2^-24, exact in fp32 and fp64."""
-    return ((w.astype(np.uint64) >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+    """23-bit uniforms in (0, 1): ((w >> 9) + 1/2) * 2^-23 (24 significant bits, so the
+    value is exact in fp32 as well as fp64)."""
+    return ((w.astype(np.uint64) >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
 
 
 def philox_words_for(d: int, l: int, seed: int, stream_id: int, inversion_index: int) -> np.ndarray:

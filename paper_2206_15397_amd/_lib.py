@@ -30,7 +30,30 @@ SIGNATURES = {
     "kfac_precondition_workspace": (_sz, [_i64, _i64, _i64, _i64]),
     "kfac_precondition": (_i, [_p, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _f,
                                _p, _i64, _p, _sz, _p]),
+    "kfac_plan_create": (_i, [_p, _i, _p, _i, _i, _p]),
+    "kfac_plan_workspace": (_sz, [_p]),
+    "kfac_plan_set_scalars": (_i, [_p, _f, _f, _u64, _u32, _i, _i, _i]),
+    "kfac_plan_upload": (_i, [_p, _p, _sz, _p, _p]),
+    "kfac_plan_launch_count": (_i, [_p]),
+    "kfac_plan_launch": (_i, [_p, _p]),
+    "kfac_plan_launch_range": (_i, [_p, _i, _i, _p]),
+    "kfac_plan_launch_name": (ctypes.c_char_p, [_p, _i]),
+    "kfac_plan_destroy": (None, [_p]),
 }
+
+
+class FactorDesc(ctypes.Structure):
+    """Mirror of kfac_factor_desc (include/kfac.h)."""
+    _fields_ = [("F", _p), ("d", _i64), ("ldf", _i64), ("F_bf16", _p), ("ldfb", _i64),
+                ("r", _i64), ("p", _i64), ("q", _i), ("stream_id", _u64),
+                ("X", _p), ("xtype", _i), ("n", _i64), ("d_in", _i64), ("ldx", _i64),
+                ("append_ones", _i), ("scale", _f), ("U", _p), ("ldu", _i64), ("D", _p)]
+
+
+class LayerDesc(ctypes.Structure):
+    """Mirror of kfac_layer_desc (include/kfac.h)."""
+    _fields_ = [("fa", _i), ("fg", _i), ("J", _p), ("ldj", _i64), ("S", _p), ("lds", _i64)]
+
 
 _lock = threading.Lock()
 _handle = None

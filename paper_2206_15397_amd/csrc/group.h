@@ -1,0 +1,37 @@
+// Grouped launches: one launch covers a phase of many independent tasks (factors or
+// layers).  Task t owns the flat block range [off[t], off[t+1]) laid out as a gx[t]-wide
+// 2-D grid; the wrapper maps blockIdx.x to (task, bx, by) and runs the same body as the
+// single-task kernel.  Tables live in device memory (the caller's workspace).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace kfac {
+
+struct GroupMap {
+  const int* off;   // ntasks + 1 prefix offsets
+  const int* gx;    // ntasks grid widths
+  int ntasks;
+};
+
+__device__ __forceinline__ void group_locate(const GroupMap& g, int& t, int& bx, int& by) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = g.ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.off[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  t = lo;
+  const int local = b - g.off[t];
+  const int w = g.gx[t];
+  bx = local % w;
+  by = local / w;
+}
+
+#define KFAC_GROUPED_KERNEL(NAME, BODY, PARAMS, NT)                                   \
+  __global__ __launch_bounds__(NT) void NAME(const PARAMS* tasks, GroupMap gm) {        \
+    int t_, bx_, by_;                                                                   \
+    group_locate(gm, t_, bx_, by_);                                                     \
+    BODY(tasks[t_], bx_, by_);                                                          \
+  }
+
+}  // namespace kfac

@@ -6,6 +6,7 @@
 #include "../../include/kfac.h"
 #include "common.h"
 #include "gemm_f32.h"
+#include "tasks.h"
 
 namespace kfac {
 
@@ -38,11 +39,62 @@ hipError_t launch_gram(const float* A, long lda, const float* B, long ldb, int L
                        double* part, double* C, long ldc, int* status, hipStream_t s);
 hipError_t launch_cholesky(const double* G, long ldg, int n, long m_rows, double* W, long ldw, double* Li,
                            int* status, int* fail_flag, hipStream_t s);
+constexpr int kCholInvMax = 288;   // fused Cholesky-inverse path handles n <= this
+hipError_t launch_cholinv(const double* G, long ldg, int n, long m_rows, double* Linv, long ldl, int l_pad,
+                          int* status, int* fail_flag, hipStream_t s);
+hipError_t launch_trmm(const double* Li, long ldl, int n, const float* Yt, long ldy, int ncols, float* Qt, long ldq,
+                       uint16_t* Qtb, long ldqb, int l_pad, hipStream_t s);
 hipError_t launch_trsm(const double* W, long ldw, const double* Li, int n, int l_pad, const float* Yt,
                        long ldy, int ncols, float* Qt, long ldq, uint16_t* Qtb, long ldqb, hipStream_t s);
 size_t small_eig_scratch_doubles(int n, int r);
 hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r,
                             double* A, double* V, double* diag, double* off, double* Z, double* scratch,
                             float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s);
+
+
+// ---- grouped launches (one launch covers one phase of many tasks) -----------------------
+constexpr int kPlanMaxSketch = 288;   // grouped eigensolver phases use the on-chip kernels
+EaTask make_ea_task(float* F, int d, long ldf, const float* X, const uint16_t* Xb, int n, int d_in, long ldx, int ones,
+                    float rho, float scale, uint16_t* Fb, long ldfb, float* part, int ks);
+OmegaTask make_omega_task(int d, int l, int d_pad, int l_pad, uint64_t seed, uint64_t stream_id, uint32_t inv,
+                          float* OmT, long ldt, uint16_t* OmTb, float* Om, long ldo, uint32_t* words);
+dim3 omega_grid(const OmegaTask& p);
+BfGemmTask make_bf16_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, float* C,
+                          long ldc);
+int bf16_task_blocks(const BfGemmTask& q);
+GramP make_gram_task(const float* A, long lda, const float* B, long ldb, int L, int K, int sym, double* part,
+                     double* C, long ldc, int* status);
+int gram_tiles(int L, int sym);
+int gram_reduce_slices();
+int trmm_blocks_x(int ncols);
+int trmm_blocks_y(int l_pad);
+EigTask make_eig_task(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r, double* A,
+                      double* V, double* diag, double* off, double* Z, double* scratch, float* P, long ldp, float* D,
+                      double* Dd, int* status);
+int tri_bisect_blocks(int n);
+int tri_vec_blocks(int r);
+int backtransform_blocks(int r);
+int gemm_g_blocks_x(const GemmP& p);
+int gemm_g_blocks_y(const GemmP& p);
+
+hipError_t launch_ea_tiles_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_ea_finalize_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_omega_g(const OmegaTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_sign_partial_g(const SignTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_sign_apply_g(const SignTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_gemm_g(const GemmP* t, GroupMap gm, int blocks, bool ta, bool tb, hipStream_t s);
+hipError_t launch_gemm_bf16_g(const BfGemmTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_gram_partial_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_gram_reduce_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_cholinv_g(const CholInvTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_trmm_g(const TrmmTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_tridiag_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_tri_prep_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_tri_bisect_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_tri_select_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_tri_vec_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_tri_cluster_lead_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_tri_cluster_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_backtransform_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
 
 }  // namespace kfac

@@ -39,12 +39,14 @@ __device__ __forceinline__ uint4 ld16(const uint16_t* base, long ld, int row, in
 }
 
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void k_gemm_bf16_nt(int M, int N, int K, const uint16_t* A, long lda,
-                                                      const uint16_t* B, long ldb, float* C, long ldc,
-                                                      int tiles_m) {
+__device__ __forceinline__ void gemm_bf16_body(const BfGemmTask& q, int bx, int) {
   using T = TileBF16<BM, BN>;
   __shared__ typename T::Smem sm;
-  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int M = q.M, N = q.N, K = q.K, tiles_m = q.tiles_m;
+  const uint16_t* A = q.A; const uint16_t* B = q.B;
+  const long lda = q.lda, ldb = q.ldb, ldc = q.ldc;
+  float* C = q.C;
+  const int tm = bx % tiles_m, tn = bx / tiles_m;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -111,14 +113,31 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_nt(int M, int N, int K, const
       }
 }
 
+constexpr int BF_BM = 96, BF_BN = 128;
+__global__ __launch_bounds__(256) void k_gemm_bf16_nt(BfGemmTask q) { gemm_bf16_body<BF_BM, BF_BN>(q, blockIdx.x, 0); }
+__global__ __launch_bounds__(256) void k_gemm_bf16_nt_g(const BfGemmTask* tasks, GroupMap gm) {
+  int t, bx, by;
+  group_locate(gm, t, bx, by);
+  gemm_bf16_body<BF_BM, BF_BN>(tasks[t], bx, by);
+}
+
+BfGemmTask make_bf16_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, float* C,
+                          long ldc) {
+  BfGemmTask q{M, N, K, A, lda, B, ldb, C, ldc, (M + BF_BM - 1) / BF_BM};
+  return q;
+}
+int bf16_task_blocks(const BfGemmTask& q) { return q.tiles_m * ((q.N + BF_BN - 1) / BF_BN); }
+
 hipError_t launch_gemm_bf16_nt(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb,
                                float* C, long ldc, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  constexpr int BM = 96, BN = 128;
-  int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
-  hipLaunchKernelGGL((k_gemm_bf16_nt<BM, BN>), dim3(tm * tn), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc,
-                     tm);
+  BfGemmTask q = make_bf16_task(M, N, K, A, lda, B, ldb, C, ldc);
+  hipLaunchKernelGGL(k_gemm_bf16_nt, dim3(bf16_task_blocks(q)), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 
+hipError_t launch_gemm_bf16_g(const BfGemmTask* tasks, GroupMap gm, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_gemm_bf16_nt_g, dim3(blocks), dim3(256), 0, s, tasks, gm);
+  return hipGetLastError();
+}
 }  // namespace kfac

@@ -10,6 +10,7 @@
 //      eigenvalue's block (one thread per eigenvector, factors kept in LDS);
 //   6. inverse iteration with Gram-Schmidt for members of tight clusters (rare);
 //   7. back-transformation by the Householder reflectors (one wavefront per column).
+#include <utility>
 #include "kernels.h"
 
 namespace kfac {
@@ -18,69 +19,60 @@ constexpr double kEps = 2.2204460492503131e-16;
 constexpr double kTiny = 2.2250738585072014e-308;
 
 // ======================================================================================
-// 1a. Register-resident tridiagonalisation, n <= 288.
-// Thread t: tr = t / 32, tc = t % 32 owns A[32 I + tr][32 J + tc] for I >= J (lower
-// triangle; on diagonal blocks only tr >= tc).  Slot (I, J) -> I (I + 1) / 2 + J.
+// 1a. Tridiagonalisation for n <= 288 with the matrix held on chip.
+// Thread t: tr = t / 32, tc = t % 32 owns A[32 I + tr][32 J + tc] of the lower triangle:
+// the 36 off-diagonal blocks (I > J) in registers (slot I (I - 1) / 2 + J), the 9
+// diagonal blocks in LDS (Ld[I][tr][tc], entries with tr >= tc).  Block columns are
+// processed by a template per block column so every register index is a constant.
 // ======================================================================================
 constexpr int TB = 32, TNB = 9, TNMAX = TB * TNB;
 
-__device__ __forceinline__ constexpr int tslot(int I, int J) { return I * (I + 1) / 2 + J; }
+__device__ __forceinline__ constexpr int toff(int I, int J) { return I * (I - 1) / 2 + J; }   // I > J
 
-__global__ __launch_bounds__(1024) void k_tridiag_reg(const double* C, long ldc, const float* Cf, long ldcf,
-                                                      int n, double* V, double* diag, double* off,
-                                                      int* status) {
-  __shared__ double sv[TNMAX];
-  __shared__ double sw[TNMAX];
-  __shared__ double spr[TNB][TB];
-  __shared__ double spc[16][TNB][TB];
-  __shared__ double sscal[2];
+struct TriSh {
+  double (*Ld)[TB][TB + 1];
+  double* sv;
+  double* sw;
+  double (*spr)[TB];
+  double (*spc)[TNB][TB];
+  double* sscal;
+};
+
+template <int J0>
+__device__ __forceinline__ void tri_block_col(double (&a)[36], const TriSh& S, int n, double* V, double* diag,
+                                              double* off) {
   const int t = threadIdx.x, tr = t >> 5, tc = t & 31, lane = t & 63, wave = t >> 6;
-  double a[45];
-  bool bad = false;
-#pragma unroll
-  for (int I = 0; I < TNB; ++I)
-#pragma unroll
-    for (int J = 0; J <= I; ++J) {
-      const int i = TB * I + tr, j = TB * J + tc;
-      double val = 0.0;
-      if (i < n && j < n && (I != J || tr >= tc)) {
-        double x, y;
-        if (Cf) { x = Cf[(long)i * ldcf + j]; y = Cf[(long)j * ldcf + i]; }
-        else { x = C[(long)i * ldc + j]; y = C[(long)j * ldc + i]; }
-        val = 0.5 * (x + y);
-        if (!isfinite(val)) bad = true;
-      }
-      a[tslot(I, J)] = val;
-    }
-  if (bad) atomicOr(status, KFAC_DS_NONFINITE);
-  for (int i = t; i < TNMAX; i += 1024) { sv[i] = 0.0; sw[i] = 0.0; }
-  __syncthreads();
-
-  for (int k = 0; k + 2 < n; ++k) {
-    const int kb = (k + 1) >> 5;          // first block touching rows/cols > k
-    const int J0 = k >> 5, c0 = k & 31;   // column k: block column J0, tc == c0
-    // (1) column k, rows >= k, into sw
+  double (*Ld)[TB][TB + 1] = S.Ld;
+  double* sv = S.sv;
+  double* sw = S.sw;
+  if (TB * J0 + 2 >= n) return;                       // uniform
+  for (int c0 = 0; c0 < TB; ++c0) {
+    const int k = TB * J0 + c0;
+    if (k + 2 >= n) break;                            // uniform
+    const int kb = (k + 1) >> 5;                      // first block with rows/cols > k
+    // (1) column k (rows >= k) into sw
     if (tc == c0) {
+      {
+        const int i = TB * J0 + tr;
+        if (i >= k && i < n) sw[i] = Ld[J0][tr][tc];
+      }
 #pragma unroll
-      for (int I = 0; I < TNB; ++I)
-#pragma unroll
-        for (int J = 0; J <= I; ++J)
-          if (J == J0) {
-            const int i = TB * I + tr;
-            if (i >= k && i < n) sw[i] = a[tslot(I, J)];
-          }
+      for (int I = J0 + 1; I < TNB; ++I) {
+        const int i = TB * I + tr;
+        if (i < n) sw[i] = a[toff(I, J0)];
+      }
     }
     __syncthreads();
-    // (2) Householder vector v (unit norm, H = I - 2 v v^T) by wave 0
+    // (2) Householder vector (H = I - 2 v v^T, |v| = 1) by wave 0
     if (wave == 0) {
-      double s = 0.0;
-      for (int i = k + 1 + lane; i < n; i += 64) { const double x = sw[i]; s += x * x; }
-      s = wave_sum(s);
+      double s2 = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) { const double x = sw[i]; s2 += x * x; }
+      s2 = wave_sum(s2);
       const double x0 = sw[k + 1];
-      const double nrm = sqrt(s);
+      const double nrm = sqrt(s2);
       const double alpha = (x0 >= 0.0) ? -nrm : nrm;
-      const double vn2 = s - x0 * x0 + (x0 - alpha) * (x0 - alpha);
-      const double inv = (s > 0.0 && vn2 > 0.0) ? 1.0 / sqrt(vn2) : 0.0;
+      const double vn2 = s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+      const double inv = (s2 > 0.0 && vn2 > 0.0) ? 1.0 / sqrt(vn2) : 0.0;
       for (int i = lane; i < n; i += 64) {
         double vi = 0.0;
         if (i > k + 1) vi = sw[i] * inv;
@@ -91,33 +83,38 @@ __global__ __launch_bounds__(1024) void k_tridiag_reg(const double* C, long ldc,
       if (lane == 0) {
         diag[k] = sw[k];
         off[k] = (inv > 0.0) ? alpha : x0;
-        sscal[0] = inv;
+        S.sscal[0] = inv;
       }
     }
     __syncthreads();
-    if (sscal[0] == 0.0) continue;        // column already reduced (uniform)
-    // (3) p = 2 A v: row partials (reduced over tc in-wave) and column partials (per wave)
+    if (S.sscal[0] == 0.0) continue;                  // column already reduced (uniform)
+    // (3) p = 2 A v.  Row partials pr[I] (reduced over tc inside the wave), column
+    //     partials per wave in LDS.
     double pr[TNB];
 #pragma unroll
     for (int I = 0; I < TNB; ++I) pr[I] = 0.0;
 #pragma unroll
-    for (int J = 0; J < TNB; ++J) {
+    for (int J = J0; J < TNB; ++J) {
       if (J >= kb) {
         const double vj = sv[TB * J + tc];
         double pc = 0.0;
+        {   // diagonal block J
+          const double aij = (tr >= tc) ? Ld[J][tr][tc] : 0.0;
+          pr[J] += aij * vj;
+          pc += (tr != tc) ? aij * sv[TB * J + tr] : 0.0;
+        }
 #pragma unroll
-        for (int I = J; I < TNB; ++I) {
-          const double aij = a[tslot(I, J)];
+        for (int I = J + 1; I < TNB; ++I) {
+          const double aij = a[toff(I, J)];
           pr[I] += aij * vj;
-          const double vi = sv[TB * I + tr];
-          pc += (I != J || tr != tc) ? aij * vi : 0.0;
+          pc += aij * sv[TB * I + tr];
         }
         pc += __shfl_xor(pc, 32, 64);
-        if (lane < 32) spc[wave][J][tc] = pc;
+        if (lane < 32) S.spc[wave][J][tc] = pc;
       }
     }
 #pragma unroll
-    for (int I = 0; I < TNB; ++I) {
+    for (int I = J0; I < TNB; ++I) {
       if (I >= kb) {
         double x = pr[I];
         x += __shfl_xor(x, 16, 64);
@@ -125,58 +122,114 @@ __global__ __launch_bounds__(1024) void k_tridiag_reg(const double* C, long ldc,
         x += __shfl_xor(x, 4, 64);
         x += __shfl_xor(x, 2, 64);
         x += __shfl_xor(x, 1, 64);
-        if (tc == 0) spr[I][tr] = x;
+        if (tc == 0) S.spr[I][tr] = x;
       }
     }
     __syncthreads();
     if (t > k && t < n) {
       const int I = t >> 5, c = t & 31;
-      double p = spr[I][c];
+      double p = S.spr[I][c];
 #pragma unroll
-      for (int w2 = 0; w2 < 16; ++w2) p += spc[w2][I][c];
+      for (int w2 = 0; w2 < 16; ++w2) p += S.spc[w2][I][c];
       sw[t] = 2.0 * p;
     }
     __syncthreads();
-    // (4) w = p - (v^T p) v   (zero at rows <= k)
+    // (4) w = p - (v^T p) v  (zero on rows <= k)
     if (wave == 0) {
-      double s = 0.0;
-      for (int i = k + 1 + lane; i < n; i += 64) s += sv[i] * sw[i];
-      s = wave_sum(s);
-      if (lane == 0) sscal[1] = s;
+      double s2 = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) s2 += sv[i] * sw[i];
+      s2 = wave_sum(s2);
+      if (lane == 0) S.sscal[1] = s2;
     }
     __syncthreads();
     {
-      const double K = sscal[1];
+      const double K = S.sscal[1];
       if (t < n) sw[t] = (t > k) ? sw[t] - K * sv[t] : 0.0;
     }
     __syncthreads();
     // (5) A <- A - v w^T - w v^T on the active blocks
 #pragma unroll
-    for (int J = 0; J < TNB; ++J) {
+    for (int J = J0; J < TNB; ++J) {
       if (J >= kb) {
         const double vj = sv[TB * J + tc], wj = sw[TB * J + tc];
+        if (tr >= tc) {
+          const double vi = sv[TB * J + tr], wi = sw[TB * J + tr];
+          Ld[J][tr][tc] -= vi * wj + wi * vj;
+        }
 #pragma unroll
-        for (int I = J; I < TNB; ++I) {
+        for (int I = J + 1; I < TNB; ++I) {
           const double vi = sv[TB * I + tr], wi = sw[TB * I + tr];
-          const double upd = vi * wj + wi * vj;
-          if (I != J || tr >= tc) a[tslot(I, J)] -= upd;
+          a[toff(I, J)] -= vi * wj + wi * vj;
         }
       }
     }
     __syncthreads();
   }
-  // trailing 2 x 2 (or 1 x 1) block
+}
+
+template <int... Js>
+__device__ __forceinline__ void tri_all_cols(std::integer_sequence<int, Js...>, double (&a)[36], const TriSh& S,
+                                             int n, double* V, double* diag, double* off) {
+  (tri_block_col<Js>(a, S, n, V, diag, off), ...);
+}
+
+__device__ __forceinline__ void tridiag_reg_body(const EigTask& q, int, int) {
+  const double* C = q.C; const long ldc = q.ldc; const float* Cf = q.Cf; const long ldcf = q.ldcf;
+  const int n = q.n; double* V = q.V; double* diag = q.diag; double* off = q.off; int* status = q.status;
+  __shared__ double Ld[TNB][TB][TB + 1];
+  __shared__ double sv[TNMAX];
+  __shared__ double sw[TNMAX];
+  __shared__ double spr[TNB][TB];
+  __shared__ double spc[16][TNB][TB];
+  __shared__ double sscal[2];
+  const int t = threadIdx.x, tr = t >> 5, tc = t & 31;
+  double a[36];
+  bool bad = false;
+  auto sym = [&](int i, int j) -> double {
+    double x, y;
+    if (Cf) { x = Cf[(long)i * ldcf + j]; y = Cf[(long)j * ldcf + i]; }
+    else { x = C[(long)i * ldc + j]; y = C[(long)j * ldc + i]; }
+    const double v = 0.5 * (x + y);
+    if (!isfinite(v)) bad = true;
+    return v;
+  };
 #pragma unroll
-  for (int I = 0; I < TNB; ++I)
-#pragma unroll
-    for (int J = 0; J <= I; ++J) {
-      const int i = TB * I + tr, j = TB * J + tc;
-      if (I == J && tr < tc) continue;
-      const double val = a[tslot(I, J)];
-      if (n >= 2 && i == n - 2 && j == n - 2) diag[n - 2] = val;
-      if (n >= 2 && i == n - 1 && j == n - 2) off[n - 2] = val;
-      if (i == n - 1 && j == n - 1) diag[n - 1] = val;
+  for (int I = 0; I < TNB; ++I) {
+    const int i = TB * I + tr;
+    {
+      const int j = TB * I + tc;
+      Ld[I][tr][tc] = (i < n && j < n && tr >= tc) ? sym(i, j) : 0.0;
     }
+#pragma unroll
+    for (int J = 0; J < I; ++J) {
+      const int j = TB * J + tc;
+      a[toff(I, J)] = (i < n && j < n) ? sym(i, j) : 0.0;
+    }
+  }
+  if (bad) atomicOr(status, KFAC_DS_NONFINITE);
+  for (int i = t; i < TNMAX; i += 1024) { sv[i] = 0.0; sw[i] = 0.0; }
+  __syncthreads();
+  TriSh S{Ld, sv, sw, spr, spc, sscal};
+  tri_all_cols(std::make_integer_sequence<int, TNB>{}, a, S, n, V, diag, off);
+  // trailing 2 x 2 (or 1 x 1) block
+  __syncthreads();
+  if (t == 0) {
+    auto at = [&](int i, int j) { return Ld[i >> 5][i & 31][j & 31]; };   // valid when i, j share a block
+    if (n >= 2) diag[n - 2] = Ld[(n - 2) >> 5][(n - 2) & 31][(n - 2) & 31];
+    diag[n - 1] = Ld[(n - 1) >> 5][(n - 1) & 31][(n - 1) & 31];
+    (void)at;
+  }
+  if (n >= 2) {
+    const int i = n - 1, j = n - 2;
+    if ((i >> 5) == (j >> 5)) {
+      if (t == 0) off[n - 2] = Ld[i >> 5][i & 31][j & 31];
+    } else {
+      // (n-1, n-2) lies in the off-diagonal block (I, I-1): owner tr = i & 31, tc = j & 31
+#pragma unroll
+      for (int I = 1; I < TNB; ++I)
+        if (I == (i >> 5) && tr == (i & 31) && tc == (j & 31)) off[n - 2] = a[toff(I, I - 1)];
+    }
+  }
 }
 
 // ======================================================================================
@@ -193,9 +246,10 @@ __device__ __forceinline__ double block_sum_1024(double v, double* red) {
   return s;
 }
 
-__global__ __launch_bounds__(1024) void k_tridiag_gmem(const double* C, long ldc, const float* Cf, long ldcf,
-                                                       int n, double* A, double* V, double* diag, double* off,
-                                                       int* status) {
+__global__ __launch_bounds__(1024) void k_tridiag_gmem(EigTask q) {
+  const double* C = q.C; const long ldc = q.ldc; const float* Cf = q.Cf; const long ldcf = q.ldcf;
+  const int n = q.n; double* A = q.A; double* V = q.V; double* diag = q.diag; double* off = q.off;
+  int* status = q.status;
   __shared__ double v[KFAC_MAX_SKETCH];
   __shared__ double pw[KFAC_MAX_SKETCH];
   __shared__ double red[16];
@@ -259,17 +313,8 @@ __global__ __launch_bounds__(1024) void k_tridiag_gmem(const double* C, long ldc
 // ======================================================================================
 // 2. Split into unreduced blocks.  meta layout: see TriMeta.
 // ======================================================================================
-struct TriMeta {
-  double* es;      // [n] off-diagonal with negligible entries zeroed (es[n-1] = 0)
-  int* blo;        // [n] first row of the block containing row i
-  int* bhi;        // [n] one past the last row of that block
-  double* lam;     // [n] eigenvalue of task j (position j of its block, ascending)
-  int* col_task;   // [r] task of output column k (descending order)
-  int* cstart;     // [r] 1 if column k starts a new cluster
-  double* scal;    // [0] ||T|| bound, [1] pivmin, [2] any-cluster flag (as double)
-};
-
-__global__ __launch_bounds__(512) void k_tri_prep(const double* diag, const double* off, int n, TriMeta m) {
+__device__ __forceinline__ void tri_prep_body(const EigTask& q, int, int) {
+  const double* diag = q.diag; const double* off = q.off; const int n = q.n; const TriMeta& m = q.m;
   __shared__ double sred[8];
   __shared__ double ssh[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -344,7 +389,8 @@ __device__ int sturm_block(const double* d, const double* e2, int lo, int hi, do
 
 constexpr int BIS_LANES = 16;
 
-__global__ __launch_bounds__(256) void k_tri_bisect(const double* diag, int n, TriMeta m) {
+__device__ __forceinline__ void tri_bisect_body(const EigTask& q, int bx, int) {
+  const double* diag = q.diag; const int n = q.n; const TriMeta& m = q.m;
   __shared__ double d[KFAC_MAX_SKETCH], e2[KFAC_MAX_SKETCH], ea[KFAC_MAX_SKETCH];
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += blockDim.x) {
@@ -355,7 +401,7 @@ __global__ __launch_bounds__(256) void k_tri_bisect(const double* diag, int n, T
   }
   __syncthreads();
   const double tn = m.scal[0], pivmin = m.scal[1];
-  const int j = blockIdx.x * (256 / BIS_LANES) + tid / BIS_LANES;
+  const int j = bx * (256 / BIS_LANES) + tid / BIS_LANES;
   const int sub = tid % BIS_LANES;
   const bool active = j < n;
   const int jj = active ? j : 0;
@@ -397,7 +443,8 @@ __global__ __launch_bounds__(256) void k_tri_bisect(const double* diag, int n, T
 // ======================================================================================
 // 4. Descending selection of the r largest eigenvalues and tight-cluster flags.
 // ======================================================================================
-__global__ __launch_bounds__(512) void k_tri_select(int n, int r, TriMeta m, double* Dd, float* D) {
+__device__ __forceinline__ void tri_select_body(const EigTask& q, int, int) {
+  const int n = q.n, r = q.r; const TriMeta& m = q.m; double* Dd = q.Dd; float* D = q.D;
   __shared__ double lam[KFAC_MAX_SKETCH];
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += blockDim.x) lam[i] = m.lam[i];
@@ -442,11 +489,13 @@ __global__ __launch_bounds__(512) void k_tri_select(int n, int r, TriMeta m, dou
 // The column is written unnormalised (the back-transformation normalises it).
 // ======================================================================================
 template <int NT, int NMAX>
-__global__ __launch_bounds__(NT) void k_tri_vec(const double* diag, int n, int r, TriMeta m, double* Z, long ldz) {
+__device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
+  const double* diag = q.diag; const int n = q.n, r = q.r; const TriMeta& m = q.m; double* Z = q.Z;
+  const long ldz = q.ldz;
   __shared__ double sL[NT][NMAX];
   __shared__ double sD[NT][NMAX];
   const int tid = threadIdx.x;
-  const int k = blockIdx.x * NT + tid;
+  const int k = bx * NT + tid;
   if (k >= r) return;
   const double pivmin = m.scal[1];
   const double tiny = fmax(pivmin, kEps * kEps * m.scal[0]);
@@ -501,8 +550,9 @@ __global__ __launch_bounds__(NT) void k_tri_vec(const double* diag, int n, int r
 // members (sequential over members, one workgroup).  Exits at once if there is none.
 // scratch: 5 * n doubles.
 // ======================================================================================
-__global__ __launch_bounds__(256) void k_tri_cluster(const double* diag, int n, int r, TriMeta m, double* Z,
-                                                     long ldz, double* scratch, int* status) {
+__device__ __forceinline__ void tri_cluster_body(const EigTask& q, int, int) {
+  const double* diag = q.diag; const int n = q.n, r = q.r; const TriMeta& m = q.m; double* Z = q.Z;
+  const long ldz = q.ldz; double* scratch = q.cl; int* status = q.status;
   __shared__ double red[4];
   __shared__ double sdot;
   if (m.scal[2] == 0.0) return;
@@ -588,7 +638,8 @@ __global__ __launch_bounds__(256) void k_tri_cluster(const double* diag, int n, 
 
 // Normalise the cluster leaders (columns that start a cluster of size > 1) before the
 // member pass projects against them.
-__global__ __launch_bounds__(256) void k_tri_cluster_lead(int n, int r, TriMeta m, double* Z, long ldz) {
+__device__ __forceinline__ void tri_cluster_lead_body(const EigTask& q, int, int) {
+  const int n = q.n, r = q.r; const TriMeta& m = q.m; double* Z = q.Z; const long ldz = q.ldz;
   __shared__ double red[4];
   __shared__ double sdot;
   if (m.scal[2] == 0.0) return;
@@ -613,12 +664,13 @@ __global__ __launch_bounds__(256) void k_tri_cluster_lead(int n, int r, TriMeta 
 // wavefront per column; the column is normalised first).  fp32 output, rows n..n_pad-1
 // zero.  grid = ceil(r / 4) blocks of 256 threads.
 // ======================================================================================
-__global__ __launch_bounds__(256) void k_backtransform(const double* V, const double* Z, long ldz, int n,
-                                                       int n_pad, int r, float* P, long ldp) {
+__device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int) {
+  const double* V = q.V; const double* Z = q.Z; const long ldz = q.ldz; const int n = q.n, n_pad = q.n_pad;
+  const int r = q.r; float* P = q.P; const long ldp = q.ldp;
   constexpr int CH = 16;                      // reflectors staged per LDS chunk
   __shared__ double vch[CH][KFAC_MAX_SKETCH];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = blockIdx.x * 4 + wave;
+  const int c = bx * 4 + wave;
   const bool active = c < r;
   constexpr int PER = KFAC_MAX_SKETCH / 64;
   double z[PER];
@@ -665,46 +717,89 @@ __global__ __launch_bounds__(256) void k_backtransform(const double* V, const do
   }
 }
 
+// single-task and grouped entry points of the eigensolver phases
+__global__ __launch_bounds__(1024) void k_tridiag_reg(EigTask q) { tridiag_reg_body(q, 0, 0); }
+__global__ __launch_bounds__(512) void k_tri_prep(EigTask q) { tri_prep_body(q, 0, 0); }
+__global__ __launch_bounds__(256) void k_tri_bisect(EigTask q) { tri_bisect_body(q, blockIdx.x, 0); }
+__global__ __launch_bounds__(512) void k_tri_select(EigTask q) { tri_select_body(q, 0, 0); }
+template <int NT, int NMAX>
+__global__ __launch_bounds__(NT) void k_tri_vec(EigTask q) { tri_vec_body<NT, NMAX>(q, blockIdx.x, 0); }
+__global__ __launch_bounds__(256) void k_tri_cluster_lead(EigTask q) { tri_cluster_lead_body(q, 0, 0); }
+__global__ __launch_bounds__(256) void k_tri_cluster(EigTask q) { tri_cluster_body(q, 0, 0); }
+__global__ __launch_bounds__(256) void k_backtransform(EigTask q) { backtransform_body(q, blockIdx.x, 0); }
+
+KFAC_GROUPED_KERNEL(k_tridiag_reg_g, tridiag_reg_body, EigTask, 1024)
+KFAC_GROUPED_KERNEL(k_tri_prep_g, tri_prep_body, EigTask, 512)
+KFAC_GROUPED_KERNEL(k_tri_bisect_g, tri_bisect_body, EigTask, 256)
+KFAC_GROUPED_KERNEL(k_tri_select_g, tri_select_body, EigTask, 512)
+__global__ __launch_bounds__(32) void k_tri_vec_g(const EigTask* tasks, GroupMap gm) {
+  int t, bx, by;
+  group_locate(gm, t, bx, by);
+  tri_vec_body<32, TNMAX>(tasks[t], bx, by);
+}
+KFAC_GROUPED_KERNEL(k_tri_cluster_lead_g, tri_cluster_lead_body, EigTask, 256)
+KFAC_GROUPED_KERNEL(k_tri_cluster_g, tri_cluster_body, EigTask, 256)
+KFAC_GROUPED_KERNEL(k_backtransform_g, backtransform_body, EigTask, 256)
+
 // ======================================================================================
 size_t small_eig_scratch_doubles(int n, int r) {
   // es[n] | lam[n] | scal[8] | int blo[n], bhi[n], col_task[r], cstart[r] | cluster[5n]
   return 2 * (size_t)n + 8 + ((size_t)2 * n + 2 * r + 1) / 2 + 2 + 5 * (size_t)n + 16;
 }
 
+EigTask make_eig_task(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r, double* A,
+                      double* V, double* diag, double* off, double* Z, double* scratch, float* P, long ldp, float* D,
+                      double* Dd, int* status) {
+  // scratch layout (doubles): es[n] | lam[n] | scal[8] | ints blo[n], bhi[n], col_task[r], cstart[r] | cl[5n]
+  EigTask q;
+  q.C = C; q.ldc = ldc; q.Cf = Cf; q.ldcf = ldcf;
+  q.n = n; q.n_pad = n_pad; q.r = r;
+  q.A = A; q.V = V; q.diag = diag; q.off = off; q.Z = Z; q.ldz = r;
+  double* p = scratch;
+  q.m.es = p; p += n;
+  q.m.lam = p; p += n;
+  q.m.scal = p; p += 8;
+  int* ip = (int*)p;
+  q.m.blo = ip; ip += n;
+  q.m.bhi = ip; ip += n;
+  q.m.col_task = ip; ip += r;
+  q.m.cstart = ip; ip += r;
+  q.cl = (double*)(((uintptr_t)ip + 15) & ~(uintptr_t)15);
+  q.P = P; q.ldp = ldp; q.D = D; q.Dd = Dd; q.status = status;
+  return q;
+}
+
 hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r,
                             double* A, double* V, double* diag, double* off, double* Z, double* scratch,
                             float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s) {
-  // scratch layout (doubles): es[n] | lam[n] | scal[8] | ints blo[n], bhi[n], col_task[r], cstart[r] | cl[5n]
-  TriMeta m;
-  double* p = scratch;
-  m.es = p; p += n;
-  m.lam = p; p += n;
-  m.scal = p; p += 8;
-  int* ip = (int*)p;
-  m.blo = ip; ip += n;
-  m.bhi = ip; ip += n;
-  m.col_task = ip; ip += r;
-  m.cstart = ip; ip += r;
-  p = (double*)(((uintptr_t)ip + 15) & ~(uintptr_t)15);
-  double* cl = p;
-  if (n <= TNMAX) {
-    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(1024), 0, s, C, ldc, Cf, ldcf, n, V, diag, off, status);
-  } else {
-    hipLaunchKernelGGL(k_tridiag_gmem, dim3(1), dim3(1024), 0, s, C, ldc, Cf, ldcf, n, A, V, diag, off, status);
-  }
-  hipLaunchKernelGGL(k_tri_prep, dim3(1), dim3(512), 0, s, diag, off, n, m);
-  hipLaunchKernelGGL(k_tri_bisect, dim3((n + 15) / 16), dim3(256), 0, s, diag, n, m);
-  hipLaunchKernelGGL(k_tri_select, dim3(1), dim3(512), 0, s, n, r, m, Dd, D);
-  if (n <= TNMAX) {
-    hipLaunchKernelGGL((k_tri_vec<32, TNMAX>), dim3((r + 31) / 32), dim3(32), 0, s, diag, n, r, m, Z, (long)r);
-  } else {
-    hipLaunchKernelGGL((k_tri_vec<16, KFAC_MAX_SKETCH>), dim3((r + 15) / 16), dim3(16), 0, s, diag, n, r, m, Z,
-                       (long)r);
-  }
-  hipLaunchKernelGGL(k_tri_cluster_lead, dim3(1), dim3(256), 0, s, n, r, m, Z, (long)r);
-  hipLaunchKernelGGL(k_tri_cluster, dim3(1), dim3(256), 0, s, diag, n, r, m, Z, (long)r, cl, status);
-  hipLaunchKernelGGL(k_backtransform, dim3((r + 3) / 4), dim3(256), 0, s, V, Z, (long)r, n, n_pad, r, P, ldp);
+  EigTask q = make_eig_task(C, ldc, Cf, ldcf, n, n_pad, r, A, V, diag, off, Z, scratch, P, ldp, D, Dd, status);
+  if (n <= TNMAX) hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(1024), 0, s, q);
+  else hipLaunchKernelGGL(k_tridiag_gmem, dim3(1), dim3(1024), 0, s, q);
+  hipLaunchKernelGGL(k_tri_prep, dim3(1), dim3(512), 0, s, q);
+  hipLaunchKernelGGL(k_tri_bisect, dim3((n + 15) / 16), dim3(256), 0, s, q);
+  hipLaunchKernelGGL(k_tri_select, dim3(1), dim3(512), 0, s, q);
+  if (n <= TNMAX) hipLaunchKernelGGL((k_tri_vec<32, TNMAX>), dim3((r + 31) / 32), dim3(32), 0, s, q);
+  else hipLaunchKernelGGL((k_tri_vec<16, KFAC_MAX_SKETCH>), dim3((r + 15) / 16), dim3(16), 0, s, q);
+  hipLaunchKernelGGL(k_tri_cluster_lead, dim3(1), dim3(256), 0, s, q);
+  hipLaunchKernelGGL(k_tri_cluster, dim3(1), dim3(256), 0, s, q);
+  hipLaunchKernelGGL(k_backtransform, dim3((r + 3) / 4), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 
+#define KFAC_GLAUNCH(FN, KER, T, NT)                                                         \
+  hipError_t FN(const T* tasks, GroupMap gm, int blocks, hipStream_t s) {                  \
+    if (blocks > 0) hipLaunchKernelGGL(KER, dim3(blocks), dim3(NT), 0, s, tasks, gm);      \
+    return hipGetLastError();                                                              \
+  }
+KFAC_GLAUNCH(launch_tridiag_g, k_tridiag_reg_g, EigTask, 1024)
+KFAC_GLAUNCH(launch_tri_prep_g, k_tri_prep_g, EigTask, 512)
+KFAC_GLAUNCH(launch_tri_bisect_g, k_tri_bisect_g, EigTask, 256)
+KFAC_GLAUNCH(launch_tri_select_g, k_tri_select_g, EigTask, 512)
+KFAC_GLAUNCH(launch_tri_vec_g, k_tri_vec_g, EigTask, 32)
+KFAC_GLAUNCH(launch_tri_cluster_lead_g, k_tri_cluster_lead_g, EigTask, 256)
+KFAC_GLAUNCH(launch_tri_cluster_g, k_tri_cluster_g, EigTask, 256)
+KFAC_GLAUNCH(launch_backtransform_g, k_backtransform_g, EigTask, 256)
+int tri_bisect_blocks(int n) { return (n + 15) / 16; }
+int tri_vec_blocks(int r) { return (r + 31) / 32; }
+int backtransform_blocks(int r) { return (r + 3) / 4; }
 }  // namespace kfac

@@ -16,12 +16,12 @@ __global__ void k_fill_identity(float* F, int d, long ldf) {
 }
 
 // ------------------------------------------------------------------------------------
-// Generic GEMM: grid (ceil(N/BN), ceil(M/BM)).
+// Generic GEMM: block (bx, by) computes C[by*BM : , bx*BN : ].
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
-__global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmP p) {
+__device__ __forceinline__ void gemm_body(const GemmP& p, int bx, int by) {
   using T = TileF32<BM, BN, BK, WM, WN, TA, TB>;
   __shared__ typename T::Smem sm;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = by * BM, n0 = bx * BN;
   f32x4 acc[T::FM][T::FN];
 #pragma unroll
   for (int i = 0; i < T::FM; ++i)
@@ -40,15 +40,23 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmP p) {
   });
 }
 
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+__global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmP p) {
+  gemm_body<BM, BN, BK, WM, WN, TA, TB>(p, blockIdx.x, blockIdx.y);
+}
+
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+__global__ __launch_bounds__(WM * WN * 64) void k_gemm_g(const GemmP* tasks, GroupMap gm) {
+  int t, bx, by;
+  group_locate(gm, t, bx, by);
+  gemm_body<BM, BN, BK, WM, WN, TA, TB>(tasks[t], bx, by);
+}
+
 // ------------------------------------------------------------------------------------
 // EA update F <- rho F + c * Xh^T Xh on upper-triangular BT x BT tiles.
 // A = Xh^T (stored K x M: TA), B = Xh (stored K x N).
 constexpr int EA_BT = 64, EA_BK = 16, EA_WM = 2, EA_WN = 2;
 using EaTile = TileF32<EA_BT, EA_BT, EA_BK, EA_WM, EA_WN, true, false>;
-
-struct EaOut {
-  float* F; long ldf; uint16_t* Fb; long ldfb; int d; float rho, c;
-};
 
 union EaSmem {
   EaTile::Smem g;
@@ -91,12 +99,12 @@ __device__ void ea_store_tile(EaSmem& sm, const EaOut& o, int I, int J) {
   }
 }
 
-// grid (n_upper_tiles, ksplit)
-__global__ __launch_bounds__(256) void k_ea_tiles(GemmP p, EaOut o, int T) {
+__device__ __forceinline__ void ea_tiles_body(const EaTask& q, int bx, int by) {
   __shared__ EaSmem sm;
+  const GemmP& p = q.g;
   int I, J;
-  upper_tile(blockIdx.x, T, I, J);
-  const int ks = blockIdx.y, nks = gridDim.y;
+  upper_tile(bx, q.T, I, J);
+  const int ks = by, nks = q.nks;
   const int kchunk = ((p.K + nks - 1) / nks + EA_BK - 1) / EA_BK * EA_BK;
   const int kb = ks * kchunk, ke = min(p.K, kb + kchunk);
   f32x4 acc[EaTile::FM][EaTile::FN];
@@ -106,30 +114,35 @@ __global__ __launch_bounds__(256) void k_ea_tiles(GemmP p, EaOut o, int T) {
     for (int j = 0; j < EaTile::FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   EaTile::run(p, I * EA_BT, J * EA_BT, kb, ke, sm.g, acc);
   if (nks > 1) {
-    float* slot = p.part + ((long)blockIdx.x * nks + ks) * (EA_BT * EA_BT);
+    float* slot = p.part + ((long)bx * nks + ks) * (EA_BT * EA_BT);
     EaTile::for_each(acc, [&](int r, int c, float v) { slot[r * EA_BT + c] = v; });
     return;
   }
   __syncthreads();
   EaTile::for_each(acc, [&](int r, int c, float v) { sm.t[r][c] = v; });
   __syncthreads();
-  ea_store_tile(sm, o, I, J);
+  ea_store_tile(sm, q.o, I, J);
 }
 
 // Deterministic split-K reduction (slices summed in index order) + EA epilogue.
-__global__ __launch_bounds__(256) void k_ea_finalize(const float* part, int nks, EaOut o, int T) {
+__device__ __forceinline__ void ea_finalize_body(const EaTask& q, int bx, int) {
   __shared__ EaSmem sm;
   int I, J;
-  upper_tile(blockIdx.x, T, I, J);
-  const float* base = part + (long)blockIdx.x * nks * (EA_BT * EA_BT);
+  upper_tile(bx, q.T, I, J);
+  const float* base = q.g.part + (long)bx * q.nks * (EA_BT * EA_BT);
   for (int e = threadIdx.x; e < EA_BT * EA_BT; e += blockDim.x) {
     float s = 0.f;
-    for (int k = 0; k < nks; ++k) s += base[(long)k * EA_BT * EA_BT + e];
+    for (int k = 0; k < q.nks; ++k) s += base[(long)k * EA_BT * EA_BT + e];
     sm.t[e / EA_BT][e % EA_BT] = s;
   }
   __syncthreads();
-  ea_store_tile(sm, o, I, J);
+  ea_store_tile(sm, q.o, I, J);
 }
+
+__global__ __launch_bounds__(256) void k_ea_tiles(EaTask q) { ea_tiles_body(q, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(256) void k_ea_finalize(EaTask q) { ea_finalize_body(q, blockIdx.x, 0); }
+KFAC_GROUPED_KERNEL(k_ea_tiles_g, ea_tiles_body, EaTask, 256)
+KFAC_GROUPED_KERNEL(k_ea_finalize_g, ea_finalize_body, EaTask, 256)
 
 // F <- rho F (n == 0), keeps the bf16 shadow in sync.
 __global__ void k_scale_factor(float* F, long ldf, uint16_t* Fb, long ldfb, int d, float rho) {
@@ -146,32 +159,34 @@ __global__ void k_scale_factor(float* F, long ldf, uint16_t* Fb, long ldfb, int 
 // ------------------------------------------------------------------------------------
 // Gaussian test matrix.  Thread (row i, group g) draws columns 4g..4g+3.
 // Transposed workspace form: OmT[j][i] (rows j < l_pad, ld = ldt), zero outside d x l.
-// User form: Om[i][j] with ldo, plus optional raw words.
-__global__ void k_omega(int d, int l, int d_pad, int l_pad, uint32_t k0, uint32_t k1, uint32_t stream,
-                        uint32_t inv, float* OmT, long ldt, uint16_t* OmTb, float* Om, long ldo,
-                        uint32_t* words) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int g = blockIdx.y;
-  int rows = d_pad > d ? d_pad : d;
+// User form: Om[i][j] with ldo, plus optional raw words.  Block (bx, by) = (row block,
+// column group).
+__device__ __forceinline__ void omega_body(const OmegaTask& p, int bx, int by) {
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int g = by;
+  const int rows = p.d_pad > p.d ? p.d_pad : p.d;
   if (i >= rows) return;
   double z[4] = {0, 0, 0, 0};
   uint32_t w[4] = {0, 0, 0, 0};
-  bool live = i < d;
-  if (live) gaussian4((uint32_t)i, (uint32_t)g, stream, inv, k0, k1, z, w);
-  int groups = (l + 3) / 4;
-  if (live && words && g < groups) {
+  const bool live = i < p.d;
+  if (live) gaussian4((uint32_t)i, (uint32_t)g, p.stream, p.inv, p.k0, p.k1, z, w);
+  const int groups = (p.l + 3) / 4;
+  if (live && p.words && g < groups) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) words[((long)i * groups + g) * 4 + t] = w[t];
+    for (int t = 0; t < 4; ++t) p.words[((long)i * groups + g) * 4 + t] = w[t];
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    int j = 4 * g + t;
-    float v = (live && j < l) ? (float)z[t] : 0.f;
-    if (OmT && j < l_pad) OmT[(long)j * ldt + i] = v;
-    if (OmTb && j < l_pad) OmTb[(long)j * ldt + i] = f32_to_bf16_rne(v);
-    if (Om && live && j < l) Om[(long)i * ldo + j] = v;
+    const int j = 4 * g + t;
+    const float v = (live && j < p.l) ? (float)z[t] : 0.f;
+    if (p.OmT && j < p.l_pad) p.OmT[(long)j * p.ldt + i] = v;
+    if (p.OmTb && j < p.l_pad) p.OmTb[(long)j * p.ldt + i] = f32_to_bf16_rne(v);
+    if (p.Om && live && j < p.l) p.Om[(long)i * p.ldo + j] = v;
   }
 }
+
+__global__ void k_omega(OmegaTask p) { omega_body(p, blockIdx.x, blockIdx.y); }
+KFAC_GROUPED_KERNEL(k_omega_g, omega_body, OmegaTask, 256)
 
 // ------------------------------------------------------------------------------------
 // Sign convention: the largest-magnitude entry of each column of U is made positive
@@ -181,11 +196,12 @@ __global__ void k_omega(int d, int l, int d_pad, int l_pad, uint32_t k0, uint32_
 // Block = 256 threads = 4 row groups x 64 columns; grid (ceil(r/64), ceil(d/256)).
 constexpr int SG_ROWS = 256;
 
-__global__ __launch_bounds__(256) void k_sign_partial(const float* U, long ldu, int d, int r, float* pval, int* pidx) {
+__device__ __forceinline__ void sign_partial_body(const SignTask& q, int bx, int by) {
+  float* U = q.U; const long ldu = q.ldu; const int d = q.d, r = q.r; float* pval = q.pval; int* pidx = q.pidx;
   __shared__ float sv[4][64];
   __shared__ int si[4][64];
   const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + cl, chunk = blockIdx.y;
+  const int c = bx * 64 + cl, chunk = by;
   const int r0 = chunk * SG_ROWS, r1 = min(d, r0 + SG_ROWS);
   float best = -1.f, bval = 0.f;
   int bidx = 0x7fffffff;
@@ -210,11 +226,12 @@ __global__ __launch_bounds__(256) void k_sign_partial(const float* U, long ldu, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_sign_apply(float* U, long ldu, int d, int r, const float* pval,
-                                                    const int* pidx, int nchunks) {
+__device__ __forceinline__ void sign_apply_body(const SignTask& q, int bx, int by) {
+  float* U = q.U; const long ldu = q.ldu; const int d = q.d, r = q.r, nchunks = q.nchunks;
+  const float* pval = q.pval; const int* pidx = q.pidx;
   __shared__ float ssgn[64];
   const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + cl, chunk = blockIdx.y;
+  const int c = bx * 64 + cl, chunk = by;
   if (rg == 0) {
     float s = 1.f;
     if (c < r) {
@@ -234,6 +251,11 @@ __global__ __launch_bounds__(256) void k_sign_apply(float* U, long ldu, int d, i
   const int r0 = chunk * SG_ROWS, r1 = min(d, r0 + SG_ROWS);
   for (int i = r0 + rg; i < r1; i += 4) U[(long)i * ldu + c] = -U[(long)i * ldu + c];
 }
+
+__global__ __launch_bounds__(256) void k_sign_partial(SignTask q) { sign_partial_body(q, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(256) void k_sign_apply(SignTask q) { sign_apply_body(q, blockIdx.x, blockIdx.y); }
+KFAC_GROUPED_KERNEL(k_sign_partial_g, sign_partial_body, SignTask, 256)
+KFAC_GROUPED_KERNEL(k_sign_apply_g, sign_apply_body, SignTask, 256)
 
 // ------------------------------------------------------------------------------------
 // Host launchers
@@ -309,8 +331,9 @@ static hipError_t launch_ea_common(float* F, int d, long ldf, const float* X, co
   if (ks > 1 && (ws == nullptr || ws_bytes < ea_workspace_bytes(d, n))) ks = 1;
   p.ksplit = ks;
   p.part = (float*)ws;
-  hipLaunchKernelGGL(k_ea_tiles, dim3(tiles, ks), dim3(256), 0, s, p, o, T);
-  if (ks > 1) hipLaunchKernelGGL(k_ea_finalize, dim3(tiles), dim3(256), 0, s, (const float*)ws, ks, o, T);
+  EaTask q{p, o, T, ks};
+  hipLaunchKernelGGL(k_ea_tiles, dim3(tiles, ks), dim3(256), 0, s, q);
+  if (ks > 1) hipLaunchKernelGGL(k_ea_finalize, dim3(tiles), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 
@@ -326,26 +349,76 @@ hipError_t launch_ea_bf16(float* F, int d, long ldf, const uint16_t* X, int n, i
   return launch_ea_common(F, d, ldf, nullptr, X, n, d_in, ldx, ones, rho, scale, Fb, ldfb, ws, ws_bytes, s);
 }
 
+OmegaTask make_omega_task(int d, int l, int d_pad, int l_pad, uint64_t seed, uint64_t stream_id, uint32_t inv,
+                          float* OmT, long ldt, uint16_t* OmTb, float* Om, long ldo, uint32_t* words) {
+  OmegaTask p;
+  p.d = d; p.l = l; p.d_pad = d_pad; p.l_pad = l_pad;
+  p.k0 = (uint32_t)(seed & 0xffffffffu); p.k1 = (uint32_t)(seed >> 32);
+  p.stream = (uint32_t)(stream_id & 0xffffffffu); p.inv = inv;
+  p.OmT = OmT; p.ldt = ldt; p.OmTb = OmTb; p.Om = Om; p.ldo = ldo; p.words = words;
+  return p;
+}
+
+dim3 omega_grid(const OmegaTask& p) {
+  const int rows = p.d_pad > p.d ? p.d_pad : p.d;
+  const int groups = std::max((p.l + 3) / 4, (p.l_pad + 3) / 4);
+  return dim3((rows + 255) / 256, groups);
+}
+
 hipError_t launch_omega(int d, int l, int d_pad, int l_pad, uint64_t seed, uint64_t stream_id,
                         uint32_t inv, float* OmT, long ldt, uint16_t* OmTb, float* Om, long ldo,
                         uint32_t* words, hipStream_t s) {
-  int rows = d_pad > d ? d_pad : d;
-  int groups = std::max((l + 3) / 4, (l_pad + 3) / 4);
-  dim3 grid((rows + 255) / 256, groups);
-  hipLaunchKernelGGL(k_omega, grid, dim3(256), 0, s, d, l, d_pad, l_pad, (uint32_t)(seed & 0xffffffffu),
-                     (uint32_t)(seed >> 32), (uint32_t)(stream_id & 0xffffffffu), inv, OmT, ldt, OmTb,
-                     Om, ldo, words);
+  OmegaTask p = make_omega_task(d, l, d_pad, l_pad, seed, stream_id, inv, OmT, ldt, OmTb, Om, ldo, words);
+  hipLaunchKernelGGL(k_omega, omega_grid(p), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
 int sign_chunks(int d) { return (d + SG_ROWS - 1) / SG_ROWS; }
 
 hipError_t launch_sign_normalize(float* U, long ldu, int d, int r, float* pval, int* pidx, hipStream_t s) {
+  SignTask q{U, ldu, d, r, pval, pidx, sign_chunks(d)};
   dim3 grid((r + 63) / 64, sign_chunks(d));
-  hipLaunchKernelGGL(k_sign_partial, grid, dim3(256), 0, s, (const float*)U, ldu, d, r, pval, pidx);
-  hipLaunchKernelGGL(k_sign_apply, grid, dim3(256), 0, s, U, ldu, d, r, (const float*)pval, (const int*)pidx,
-                     sign_chunks(d));
+  hipLaunchKernelGGL(k_sign_partial, grid, dim3(256), 0, s, q);
+  hipLaunchKernelGGL(k_sign_apply, grid, dim3(256), 0, s, q);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// grouped launchers
+#define KFAC_GLAUNCH(FN, KER, T, NT)                                                         \
+  hipError_t FN(const T* tasks, GroupMap gm, int blocks, hipStream_t s) {                  \
+    if (blocks > 0) hipLaunchKernelGGL(KER, dim3(blocks), dim3(NT), 0, s, tasks, gm);      \
+    return hipGetLastError();                                                              \
+  }
+KFAC_GLAUNCH(launch_ea_tiles_g, k_ea_tiles_g, EaTask, 256)
+KFAC_GLAUNCH(launch_ea_finalize_g, k_ea_finalize_g, EaTask, 256)
+KFAC_GLAUNCH(launch_omega_g, k_omega_g, OmegaTask, 256)
+KFAC_GLAUNCH(launch_sign_partial_g, k_sign_partial_g, SignTask, 256)
+KFAC_GLAUNCH(launch_sign_apply_g, k_sign_apply_g, SignTask, 256)
+
+hipError_t launch_gemm_g(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_g<64, 64, 16, 2, 2, false, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_g<64, 64, 16, 2, 2, false, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_g<64, 64, 16, 2, 2, true, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  else hipLaunchKernelGGL((k_gemm_g<64, 64, 16, 2, 2, true, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  return hipGetLastError();
+}
+int gemm_g_blocks_x(const GemmP& p) { return (p.N + 63) / 64; }
+int gemm_g_blocks_y(const GemmP& p) { return (p.M + 63) / 64; }
+
+EaTask make_ea_task(float* F, int d, long ldf, const float* X, const uint16_t* Xb, int n, int d_in, long ldx, int ones,
+                    float rho, float scale, uint16_t* Fb, long ldfb, float* part, int ks) {
+  EaOut o{F, ldf, Fb, ldfb, d, rho, (1.f - rho) * scale};
+  GemmP p{};
+  p.M = d; p.N = d; p.K = n;
+  p.A = X; p.lda = ldx; p.B = X; p.ldb = ldx;
+  p.Ab = Xb; p.Bb = Xb;
+  p.ones_col = ones ? d_in : -1;
+  p.ksplit = ks;
+  p.part = part;
+  EaTask q{p, o, ea_tiles_per_side(d), ks};
+  return q;
 }
 
 }  // namespace kfac

@@ -3,81 +3,19 @@
 // caller.
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include "kernels.h"
 
 using namespace kfac;
 
+#include "workspace.h"
+
+using kfac::Bump;
+using kfac::EigWs;
+using kfac::round_up;
+
 namespace {
-
-constexpr size_t kAlign = 256;
-
-struct Bump {
-  char* base;
-  size_t off = 0;
-  explicit Bump(void* b) : base((char*)b) {}
-  template <typename T>
-  T* take(size_t count) {
-    off = (off + kAlign - 1) / kAlign * kAlign;
-    T* p = base ? (T*)(base + off) : nullptr;
-    off += count * sizeof(T);
-    return p;
-  }
-};
-
-inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
-
 inline kfac_status hip_status(hipError_t e) { return e == hipSuccess ? KFAC_OK : KFAC_EHIP; }
-
-// Layout of the kfac_rand_eig workspace; with base == nullptr it only measures.
-struct EigWs {
-  int64_t d, r, l, l_pad, ldt;
-  bool exact, bf16;
-  float *OmT, *Yt, *Qt, *P, *sval;
-  int* sidx;
-  uint16_t *OmTb, *Qtb;
-  double *G, *Wc, *Li, *part, *A, *V, *diag, *off, *Z, *scr, *Dd;
-  int* fail;
-  size_t bytes;
-
-  EigWs(int64_t d_, int64_t r_, int64_t p_, bool bf16_, void* base) : d(d_), r(r_), bf16(bf16_) {
-    l = std::min<int64_t>(r + p_, d);
-    exact = (l == d);
-    l_pad = round_up(l, 32);
-    ldt = round_up(d, 8);
-    Bump b(base);
-    const int64_t n = exact ? d : l;
-    OmT = Yt = Qt = P = nullptr;
-    OmTb = Qtb = nullptr;
-    G = Wc = Li = part = nullptr;
-    if (!exact) {
-      OmT = b.take<float>(l_pad * ldt);
-      Yt = b.take<float>(l_pad * ldt);
-      Qt = b.take<float>(l_pad * ldt);
-      if (bf16) {
-        OmTb = b.take<uint16_t>(l_pad * ldt);
-        Qtb = b.take<uint16_t>(l_pad * ldt);
-      }
-      G = b.take<double>(l_pad * l_pad);
-      Wc = b.take<double>(l_pad * l_pad);
-      Li = b.take<double>(l_pad * 16);
-      size_t pb = std::max(gram_workspace_bytes((int)l_pad, (int)d, 1), gram_workspace_bytes((int)l_pad, (int)d, 0));
-      part = b.take<double>(pb / sizeof(double) + 1);
-      P = b.take<float>(l_pad * r);
-    }
-    A = b.take<double>(n * n);
-    V = b.take<double>(n * n);
-    diag = b.take<double>(n + 1);
-    off = b.take<double>(n + 1);
-    Z = b.take<double>(n * r);
-    scr = b.take<double>(small_eig_scratch_doubles((int)n, (int)r));
-    Dd = b.take<double>(r);
-    sval = b.take<float>((size_t)sign_chunks((int)d) * r);
-    sidx = b.take<int>((size_t)sign_chunks((int)d) * r);
-    fail = b.take<int>(16);
-    bytes = b.off + kAlign;
-  }
-};
-
 }  // namespace
 
 extern "C" {
@@ -185,39 +123,56 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
     g.C = Out; g.ldc = ldt; g.alpha = 1.f; g.ones_col = -1;
     return launch_gemm(g, false, false, s);
   };
-  auto cholqr = [&](float* Yt, float* Qt, uint16_t* Qtb) -> hipError_t {
-    // pass 1: Qt = L^{-1} Yt ; pass 2 on Qt in place
+  // CholeskyQR2: Q1 = Y L1^{-T}, Q = Q1 L2^{-T} (fp64 Gram, Cholesky and triangular
+  // product).  For l <= 288 the Cholesky also forms L^{-1} and the product is a plain
+  // fp64 MFMA GEMM (out of place, so the basis ends in *cur); larger l uses blocked
+  // forward substitution in place.  `cur` points at the buffer holding Q afterwards.
+  float* cur = nullptr;
+  auto cholqr = [&](float* Yt, float* other, uint16_t* Qtb) -> hipError_t {
     hipError_t x;
-    if ((x = launch_gram(Yt, ldt, Yt, ldt, L, dd, 1, w.part, w.G, L, st, s)) != hipSuccess) return x;
-    if ((x = launch_cholesky(w.G, L, n, dd, w.Wc, L, w.Li, st, w.fail, s)) != hipSuccess) return x;
-    if ((x = launch_trsm(w.Wc, L, w.Li, n, L, Yt, ldt, dd, Qt, ldt, nullptr, 0, s)) != hipSuccess) return x;
-    if ((x = launch_gram(Qt, ldt, Qt, ldt, L, dd, 1, w.part, w.G, L, st, s)) != hipSuccess) return x;
-    if ((x = launch_cholesky(w.G, L, n, dd, w.Wc, L, w.Li, st, w.fail, s)) != hipSuccess) return x;
-    return launch_trsm(w.Wc, L, w.Li, n, L, Qt, ldt, dd, Qt, ldt, Qtb, ldt, s);
+    float* src = Yt;
+    float* dst = other;
+    for (int pass = 0; pass < 2; ++pass) {
+      uint16_t* qb = (pass == 1) ? Qtb : nullptr;
+      if ((x = launch_gram(src, ldt, src, ldt, L, dd, 1, w.part, w.G, L, st, s)) != hipSuccess) return x;
+      if (n <= kCholInvMax) {
+        if ((x = launch_cholinv(w.G, L, n, dd, w.Wc, L, L, st, w.fail, s)) != hipSuccess) return x;
+        if ((x = launch_trmm(w.Wc, L, n, src, ldt, dd, dst, ldt, qb, ldt, L, s)) != hipSuccess) return x;
+        std::swap(src, dst);
+      } else {
+        if ((x = launch_cholesky(w.G, L, n, dd, w.Wc, L, w.Li, st, w.fail, s)) != hipSuccess) return x;
+        if ((x = launch_trsm(w.Wc, L, w.Li, n, L, src, ldt, dd, src, ldt, qb, ldt, s)) != hipSuccess) return x;
+      }
+    }
+    cur = src;
+    return hipSuccess;
   };
   // sketch Y = F Omega, then orthonormalise
   CK(f_times(w.OmT, w.OmTb, w.Yt));
   CK(cholqr(w.Yt, w.Qt, bf ? w.Qtb : nullptr));
   for (int it = 0; it < q; ++it) {
-    CK(f_times(w.Qt, w.Qtb, w.Yt));
-    CK(cholqr(w.Yt, w.Qt, bf ? w.Qtb : nullptr));
+    float* spare = (cur == w.Yt) ? w.Qt : w.Yt;
+    CK(f_times(cur, w.Qtb, spare));
+    CK(cholqr(spare, cur, bf ? w.Qtb : nullptr));
   }
+  float* Qt = cur;
+  float* Wt = (cur == w.Yt) ? w.Qt : w.Yt;
   // Rayleigh-Ritz: W = F Q (fp32), C = Q^T W (fp64)
   {
     GemmP g{};
     g.M = L; g.N = dd; g.K = dd;
-    g.A = w.Qt; g.lda = ldt; g.B = F; g.ldb = ldf;
-    g.C = w.Yt; g.ldc = ldt; g.alpha = 1.f; g.ones_col = -1;
+    g.A = Qt; g.lda = ldt; g.B = F; g.ldb = ldf;
+    g.C = Wt; g.ldc = ldt; g.alpha = 1.f; g.ones_col = -1;
     CK(launch_gemm(g, false, false, s));
   }
-  CK(launch_gram(w.Qt, ldt, w.Yt, ldt, L, dd, 0, w.part, w.G, L, st, s));
+  CK(launch_gram(Qt, ldt, Wt, ldt, L, dd, 0, w.part, w.G, L, st, s));
   CK(launch_small_eig(w.G, L, nullptr, 0, n, L, (int)r, w.A, w.V, w.diag, w.off, w.Z, w.scr, w.P, r, D, w.Dd,
                       st, s));
   // U = Q P[:, :r]  (A = Q^T stored l_pad x d, i.e. K x M)
   {
     GemmP g{};
     g.M = dd; g.N = (int)r; g.K = n;
-    g.A = w.Qt; g.lda = ldt; g.B = w.P; g.ldb = r;
+    g.A = Qt; g.lda = ldt; g.B = w.P; g.ldb = r;
     g.C = U; g.ldc = ldu; g.alpha = 1.f; g.ones_col = -1;
     CK(launch_gemm(g, true, false, s));
   }

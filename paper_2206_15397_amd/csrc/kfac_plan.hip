@@ -1,0 +1,469 @@
+// Grouped plan: the K-factor step of many factors/layers as a fixed list of grouped
+// launches.  Task tables (per-task parameter blocks plus block-offset maps) are built on
+// the host against the caller's workspace and copied into its head by kfac_plan_upload;
+// kfac_plan_launch only enqueues kernels, so it can be captured into a hipGraph.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+#include "workspace.h"
+
+using namespace kfac;
+
+namespace {
+
+enum Kind {
+  K_EA_TILES, K_EA_FIN, K_OMEGA, K_GEMM, K_BF16, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRMM, K_TRIDIAG, K_PREP,
+  K_BISECT, K_SELECT, K_VEC, K_CLEAD, K_CLUSTER, K_BT, K_SIGN_P, K_SIGN_A
+};
+
+struct LaunchRec {
+  int kind;
+  size_t tasks_off, off_off, gx_off;
+  int ntasks, blocks;
+  bool ta, tb;
+};
+
+// Serialises one launch: [tasks][off (ntasks+1)][gx (ntasks)], each 256-byte aligned.
+struct Tables {
+  std::vector<char> bytes;
+  std::vector<LaunchRec> recs;
+  size_t align(size_t n) {
+    size_t o = (bytes.size() + 255) / 256 * 256;
+    bytes.resize(o + n);
+    return o;
+  }
+  template <typename T>
+  void add(int kind, const std::vector<T>& tasks, const std::vector<int>& gx, const std::vector<int>& nblk,
+           bool ta = false, bool tb = false) {
+    if (tasks.empty()) return;
+    LaunchRec r{};
+    r.kind = kind;
+    r.ntasks = (int)tasks.size();
+    r.ta = ta; r.tb = tb;
+    r.tasks_off = align(sizeof(T) * tasks.size());
+    std::memcpy(bytes.data() + r.tasks_off, tasks.data(), sizeof(T) * tasks.size());
+    r.off_off = align(sizeof(int) * (tasks.size() + 1));
+    int* off = (int*)(bytes.data() + r.off_off);
+    off[0] = 0;
+    for (size_t i = 0; i < tasks.size(); ++i) off[i + 1] = off[i] + nblk[i];
+    r.blocks = off[tasks.size()];
+    r.gx_off = align(sizeof(int) * tasks.size());
+    std::memcpy(bytes.data() + r.gx_off, gx.data(), sizeof(int) * tasks.size());
+    if (r.blocks > 0) recs.push_back(r);
+  }
+};
+
+struct FactorInfo {
+  int d, r, l, l_pad, q;
+  long ldt;
+  bool exact, ea;
+  int ea_ks;
+  size_t ws_off, ws_bytes;   // EigWs region
+  size_t ea_off, ea_bytes;   // EA split-K partials
+};
+
+struct LayerInfo {
+  size_t off, bytes;
+};
+
+}  // namespace
+
+struct kfac_plan {
+  std::vector<kfac_factor_desc> f;
+  std::vector<kfac_layer_desc> lyr;
+  kfac_precision prec;
+  float rho = 0.95f, lam = 0.1f;
+  uint64_t seed = 0;
+  uint32_t inv = 0;
+  int do_ea = 1, do_eig = 1, do_pre = 1;
+  std::vector<FactorInfo> fi;
+  std::vector<LayerInfo> li;
+  size_t table_bytes = 0;      // reserved head of the workspace
+  size_t ws_bytes = 0;
+  Tables tab;                  // built by upload
+  char* dev = nullptr;         // uploaded workspace base
+};
+
+namespace {
+
+// Build all task tables for workspace base `base` (null: sizes only) and status pointer.
+void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
+  const bool bf = (P->prec == KFAC_SKETCH_BF16);
+  const size_t head = P->table_bytes;
+  auto wsp = [&](size_t off) -> void* { return base ? (void*)(base + head + off) : nullptr; };
+  std::vector<EigWs> W;
+  for (size_t i = 0; i < P->f.size(); ++i)
+    W.emplace_back(P->fi[i].d, P->fi[i].r, P->f[i].p, bf, wsp(P->fi[i].ws_off));
+
+  // ---- EA --------------------------------------------------------------------------
+  if (P->do_ea) {
+    std::vector<EaTask> t, tf;
+    std::vector<int> gx, nb, gxf, nbf;
+    for (size_t i = 0; i < P->f.size(); ++i) {
+      const kfac_factor_desc& F = P->f[i];
+      const FactorInfo& I = P->fi[i];
+      if (!I.ea) continue;
+      const bool xb = (F.xtype == KFAC_BF16);
+      EaTask q = make_ea_task(F.F, I.d, F.ldf, xb ? nullptr : (const float*)F.X, xb ? (const uint16_t*)F.X : nullptr,
+                              (int)F.n, (int)F.d_in, F.ldx, F.append_ones, P->rho, F.scale,
+                              F.F_bf16, F.ldfb, (float*)wsp(I.ea_off), I.ea_ks);
+      const int tiles = q.T * (q.T + 1) / 2;
+      t.push_back(q); gx.push_back(tiles); nb.push_back(tiles * I.ea_ks);
+      if (I.ea_ks > 1) { tf.push_back(q); gxf.push_back(tiles); nbf.push_back(tiles); }
+    }
+    T.add(K_EA_TILES, t, gx, nb);
+    T.add(K_EA_FIN, tf, gxf, nbf);
+  }
+  if (P->do_eig) {
+    // ---- randomized range finder with CholeskyQR2 -----------------------------------
+    std::vector<int> rnd;
+    for (size_t i = 0; i < P->f.size(); ++i)
+      if (!P->fi[i].exact) rnd.push_back((int)i);
+    std::vector<float*> basis(P->f.size(), nullptr), spare(P->f.size(), nullptr);
+    if (!rnd.empty()) {
+      std::vector<OmegaTask> om;
+      std::vector<int> gx, nb;
+      for (int i : rnd) {
+        const FactorInfo& I = P->fi[i];
+        OmegaTask q = make_omega_task(I.d, I.l, I.d, I.l_pad, P->seed, P->f[i].stream_id, P->inv, W[i].OmT, I.ldt,
+                                      bf ? W[i].OmTb : nullptr, nullptr, 0, nullptr);
+        dim3 g = omega_grid(q);
+        om.push_back(q); gx.push_back((int)g.x); nb.push_back((int)(g.x * g.y));
+      }
+      T.add(K_OMEGA, om, gx, nb);
+      for (int i : rnd) { basis[i] = W[i].Yt; spare[i] = W[i].Qt; }
+      const int qmax = [&] { int m = 0; for (int i : rnd) m = std::max(m, P->fi[i].q); return m; }();
+      for (int it = 0; it <= qmax; ++it) {
+        // sketch (it == 0: F Omega) or power step (F Q), into the buffer that will hold
+        // the new basis after CholeskyQR2
+        std::vector<int> act;
+        for (int i : rnd) if (it <= P->fi[i].q) act.push_back(i);
+        if (act.empty()) break;
+        if (bf) {
+          std::vector<BfGemmTask> g;
+          std::vector<int> gx2, nb2;
+          for (int i : act) {
+            const FactorInfo& I = P->fi[i];
+            const uint16_t* A = (it == 0) ? W[i].OmTb : W[i].Qtb;
+            float* out = (it == 0) ? basis[i] : spare[i];
+            BfGemmTask q = make_bf16_task(I.l_pad, I.d, I.d, A, I.ldt, P->f[i].F_bf16, P->f[i].ldfb, out, I.ldt);
+            g.push_back(q); gx2.push_back(bf16_task_blocks(q)); nb2.push_back(bf16_task_blocks(q));
+          }
+          T.add(K_BF16, g, gx2, nb2);
+        } else {
+          std::vector<GemmP> g;
+          std::vector<int> gx2, nb2;
+          for (int i : act) {
+            const FactorInfo& I = P->fi[i];
+            GemmP q{};
+            q.M = I.l_pad; q.N = I.d; q.K = I.d;
+            q.A = (it == 0) ? W[i].OmT : basis[i]; q.lda = I.ldt;
+            q.B = P->f[i].F; q.ldb = P->f[i].ldf;
+            q.C = (it == 0) ? basis[i] : spare[i]; q.ldc = I.ldt;
+            q.alpha = 1.f; q.ones_col = -1;
+            g.push_back(q); gx2.push_back(gemm_g_blocks_x(q)); nb2.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
+          }
+          T.add(K_GEMM, g, gx2, nb2, false, false);
+        }
+        if (it > 0) for (int i : act) std::swap(basis[i], spare[i]);
+        // CholeskyQR2 on basis[i]: pass 0 basis -> spare, pass 1 spare -> basis
+        for (int pass = 0; pass < 2; ++pass) {
+          std::vector<GramP> gp;
+          std::vector<CholInvTask> ch;
+          std::vector<TrmmTask> tm;
+          std::vector<int> gxg, nbg, gxr, nbr, gxc, nbc, gxt, nbt;
+          for (int i : act) {
+            const FactorInfo& I = P->fi[i];
+            float* src = pass == 0 ? basis[i] : spare[i];
+            float* dst = pass == 0 ? spare[i] : basis[i];
+            GramP g = make_gram_task(src, I.ldt, src, I.ldt, I.l_pad, I.d, 1, W[i].part, W[i].G, I.l_pad, status);
+            const int tiles = gram_tiles(I.l_pad, 1);
+            gp.push_back(g); gxg.push_back(tiles); nbg.push_back(tiles * g.ksplit);
+            gxr.push_back(tiles); nbr.push_back(tiles * gram_reduce_slices());
+            CholInvTask c{W[i].G, I.l_pad, I.l, I.d, W[i].Wc, I.l_pad, I.l_pad, status, W[i].fail, 0};
+            ch.push_back(c); gxc.push_back(1); nbc.push_back(1);
+            TrmmTask tt{W[i].Wc, I.l_pad, I.l, src, I.ldt, I.d, dst, I.ldt,
+                        (bf && pass == 1) ? W[i].Qtb : nullptr, I.ldt, I.l_pad};
+            const int bx = trmm_blocks_x(I.d), by = trmm_blocks_y(I.l_pad);
+            tm.push_back(tt); gxt.push_back(bx); nbt.push_back(bx * by);
+          }
+          T.add(K_GRAM_P, gp, gxg, nbg);
+          T.add(K_GRAM_R, gp, gxr, nbr);
+          T.add(K_CHOLINV, ch, gxc, nbc);
+          for (auto& c : ch) c.attempt = 1;
+          T.add(K_CHOLINV, ch, gxc, nbc);
+          T.add(K_TRMM, tm, gxt, nbt);
+        }
+      }
+      // Rayleigh-Ritz: W = F Q (fp32) into spare, C = Q^T W (fp64) into G
+      std::vector<GemmP> g;
+      std::vector<int> gx2, nb2;
+      std::vector<GramP> gp;
+      std::vector<int> gxg, nbg, gxr, nbr;
+      for (int i : rnd) {
+        const FactorInfo& I = P->fi[i];
+        GemmP q{};
+        q.M = I.l_pad; q.N = I.d; q.K = I.d;
+        q.A = basis[i]; q.lda = I.ldt; q.B = P->f[i].F; q.ldb = P->f[i].ldf;
+        q.C = spare[i]; q.ldc = I.ldt; q.alpha = 1.f; q.ones_col = -1;
+        g.push_back(q); gx2.push_back(gemm_g_blocks_x(q)); nb2.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
+        GramP gr = make_gram_task(basis[i], I.ldt, spare[i], I.ldt, I.l_pad, I.d, 0, W[i].part, W[i].G, I.l_pad,
+                                  status);
+        const int tiles = gram_tiles(I.l_pad, 0);
+        gp.push_back(gr); gxg.push_back(tiles); nbg.push_back(tiles * gr.ksplit);
+        gxr.push_back(tiles); nbr.push_back(tiles * gram_reduce_slices());
+      }
+      T.add(K_GEMM, g, gx2, nb2, false, false);
+      T.add(K_GRAM_P, gp, gxg, nbg);
+      T.add(K_GRAM_R, gp, gxr, nbr);
+    }
+    // ---- small eigensolver (randomized: C = Q^T F Q; exact: F itself) --------------
+    std::vector<EigTask> et;
+    std::vector<int> one, onen, gxb, nbb, gxv, nbv, gxbt, nbbt;
+    for (size_t i = 0; i < P->f.size(); ++i) {
+      const FactorInfo& I = P->fi[i];
+      const kfac_factor_desc& F = P->f[i];
+      EigTask q;
+      if (I.exact)
+        q = make_eig_task(nullptr, 0, F.F, F.ldf, I.d, I.d, I.r, W[i].A, W[i].V, W[i].diag, W[i].off, W[i].Z,
+                          W[i].scr, F.U, F.ldu, F.D, W[i].Dd, status);
+      else
+        q = make_eig_task(W[i].G, I.l_pad, nullptr, 0, I.l, I.l_pad, I.r, W[i].A, W[i].V, W[i].diag, W[i].off,
+                          W[i].Z, W[i].scr, W[i].P, I.r, F.D, W[i].Dd, status);
+      et.push_back(q);
+      one.push_back(1); onen.push_back(1);
+      gxb.push_back(tri_bisect_blocks(q.n)); nbb.push_back(tri_bisect_blocks(q.n));
+      gxv.push_back(tri_vec_blocks(q.r)); nbv.push_back(tri_vec_blocks(q.r));
+      gxbt.push_back(backtransform_blocks(q.r)); nbbt.push_back(backtransform_blocks(q.r));
+    }
+    T.add(K_TRIDIAG, et, one, onen);
+    T.add(K_PREP, et, one, onen);
+    T.add(K_BISECT, et, gxb, nbb);
+    T.add(K_SELECT, et, one, onen);
+    T.add(K_VEC, et, gxv, nbv);
+    T.add(K_CLEAD, et, one, onen);
+    T.add(K_CLUSTER, et, one, onen);
+    T.add(K_BT, et, gxbt, nbbt);
+    // ---- Ritz vectors U = Q P[:, :r] --------------------------------------------------
+    {
+      std::vector<GemmP> g;
+      std::vector<int> gx2, nb2;
+      for (int i : rnd) {
+        const FactorInfo& I = P->fi[i];
+        GemmP q{};
+        q.M = I.d; q.N = I.r; q.K = I.l;
+        q.A = basis[i]; q.lda = I.ldt; q.B = W[i].P; q.ldb = I.r;
+        q.C = P->f[i].U; q.ldc = P->f[i].ldu; q.alpha = 1.f; q.ones_col = -1;
+        g.push_back(q); gx2.push_back(gemm_g_blocks_x(q)); nb2.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
+      }
+      T.add(K_GEMM, g, gx2, nb2, true, false);
+    }
+    // ---- column signs -------------------------------------------------------------------
+    {
+      std::vector<SignTask> st;
+      std::vector<int> gx2, nb2;
+      for (size_t i = 0; i < P->f.size(); ++i) {
+        const FactorInfo& I = P->fi[i];
+        SignTask s{P->f[i].U, P->f[i].ldu, I.d, I.r, W[i].sval, W[i].sidx, sign_chunks(I.d)};
+        st.push_back(s);
+        const int bx = (I.r + 63) / 64;
+        gx2.push_back(bx); nb2.push_back(bx * sign_chunks(I.d));
+      }
+      T.add(K_SIGN_P, st, gx2, nb2);
+      T.add(K_SIGN_A, st, gx2, nb2);
+    }
+  }
+  // ---- damped inverse per layer -----------------------------------------------------------
+  if (P->do_pre && !P->lyr.empty()) {
+    std::vector<GemmP> g1, g2, g3, g4;
+    std::vector<int> x1, n1, x2, n2, x3, n3, x4, n4;
+    const float inv_lam = 1.0f / P->lam;
+    for (size_t l = 0; l < P->lyr.size(); ++l) {
+      const kfac_layer_desc& L = P->lyr[l];
+      const kfac_factor_desc& A = P->f[L.fa];
+      const kfac_factor_desc& G = P->f[L.fg];
+      const int dg = (int)G.d, da = (int)A.d, ra = (int)A.r, rg = (int)G.r;
+      Bump b(wsp(P->li[l].off));
+      float* T1 = b.take<float>((size_t)dg * ra);
+      float* M = b.take<float>((size_t)dg * da);
+      float* T2 = b.take<float>((size_t)rg * da);
+      auto push = [&](std::vector<GemmP>& v, std::vector<int>& gx, std::vector<int>& nb, const GemmP& q) {
+        v.push_back(q); gx.push_back(gemm_g_blocks_x(q)); nb.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
+      };
+      GemmP q{};
+      q.ones_col = -1; q.alpha = 1.f; q.lam = P->lam;
+      GemmP a = q;  // T1 = J U_a diag(f_a)
+      a.M = dg; a.N = ra; a.K = da; a.A = L.J; a.lda = L.ldj; a.B = A.U; a.ldb = A.ldu; a.C = T1; a.ldc = ra; a.colD = A.D;
+      push(g1, x1, n1, a);
+      GemmP m = q;  // M = T1 U_a^T + J / lambda
+      m.M = dg; m.N = da; m.K = ra; m.A = T1; m.lda = ra; m.B = A.U; m.ldb = A.ldu; m.C = M; m.ldc = da;
+      m.X = L.J; m.ldx = L.ldj; m.beta = inv_lam;
+      push(g2, x2, n2, m);
+      GemmP t2 = q;  // T2 = diag(f_g) U_g^T M
+      t2.M = rg; t2.N = da; t2.K = dg; t2.A = G.U; t2.lda = G.ldu; t2.B = M; t2.ldb = da; t2.C = T2; t2.ldc = da;
+      t2.rowD = G.D;
+      push(g3, x3, n3, t2);
+      GemmP sq = q;  // S = U_g T2 + M / lambda
+      sq.M = dg; sq.N = da; sq.K = rg; sq.A = G.U; sq.lda = G.ldu; sq.B = T2; sq.ldb = da; sq.C = L.S; sq.ldc = L.lds;
+      sq.X = M; sq.ldx = da; sq.beta = inv_lam;
+      push(g4, x4, n4, sq);
+    }
+    T.add(K_GEMM, g1, x1, n1, false, false);
+    T.add(K_GEMM, g2, x2, n2, false, true);
+    T.add(K_GEMM, g3, x3, n3, true, false);
+    T.add(K_GEMM, g4, x4, n4, false, false);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac_layer_desc* layers, int nl,
+                             kfac_precision prec, kfac_plan** out) {
+  if (!out || nf < 1 || (nl > 0 && !layers) || !factors) return KFAC_EINVAL;
+  if (prec != KFAC_SKETCH_FP32 && prec != KFAC_SKETCH_BF16) return KFAC_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < nf; ++i) {
+    const kfac_factor_desc& F = factors[i];
+    if (!F.F || F.d < 1 || F.ldf < F.d || F.r < 1 || F.r > F.d || F.p < 0 || F.q < 0 || F.q > 16) return KFAC_EINVAL;
+    if (!F.U || F.ldu < F.r || !F.D) return KFAC_EINVAL;
+    if (prec == KFAC_SKETCH_BF16 && (!F.F_bf16 || F.ldfb < F.d)) return KFAC_EINVAL;
+    if (F.X) {
+      if (F.n < 1 || F.d != F.d_in + (F.append_ones ? 1 : 0) || F.ldx < F.d_in || !(F.scale > 0.f)) return KFAC_EINVAL;
+      if (F.xtype != KFAC_FP32 && F.xtype != KFAC_BF16) return KFAC_EINVAL;
+    }
+    if (std::min<int64_t>(F.r + F.p, F.d) > kPlanMaxSketch) return KFAC_EUNSUPPORTED;
+  }
+  for (int l = 0; l < nl; ++l) {
+    const kfac_layer_desc& L = layers[l];
+    if (L.fa < 0 || L.fa >= nf || L.fg < 0 || L.fg >= nf || !L.J || !L.S) return KFAC_EINVAL;
+    if (L.ldj < factors[L.fa].d || L.lds < factors[L.fa].d || (const void*)L.J == (const void*)L.S) return KFAC_EINVAL;
+  }
+  kfac_plan* P = new (std::nothrow) kfac_plan();
+  if (!P) return KFAC_EINVAL;
+  P->f.assign(factors, factors + nf);
+  if (nl > 0) P->lyr.assign(layers, layers + nl);
+  P->prec = prec;
+  const bool bf = (prec == KFAC_SKETCH_BF16);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { off = (off + kAlign - 1) / kAlign * kAlign; size_t o = off; off += bytes; return o; };
+  for (int i = 0; i < nf; ++i) {
+    const kfac_factor_desc& F = factors[i];
+    FactorInfo I{};
+    I.d = (int)F.d; I.r = (int)F.r; I.q = F.q;
+    I.l = (int)std::min<int64_t>(F.r + F.p, F.d);
+    I.l_pad = (int)round_up(I.l, 32);
+    I.ldt = round_up(F.d, 8);
+    I.exact = (I.l == I.d);
+    I.ea = (F.X != nullptr);
+    EigWs w(F.d, F.r, F.p, bf, nullptr);
+    I.ws_bytes = w.bytes;
+    I.ws_off = take(w.bytes);
+    I.ea_ks = I.ea ? ea_choose_ksplit(I.d, F.n) : 1;
+    I.ea_bytes = (I.ea && I.ea_ks > 1) ? ea_workspace_bytes(I.d, F.n) : 0;
+    I.ea_off = take(I.ea_bytes + 16);
+    P->fi.push_back(I);
+  }
+  for (int l = 0; l < nl; ++l) {
+    const kfac_layer_desc& L = layers[l];
+    const int64_t dg = factors[L.fg].d, da = factors[L.fa].d, ra = factors[L.fa].r, rg = factors[L.fg].r;
+    LayerInfo I{};
+    I.bytes = kfac_precondition_workspace(dg, da, ra, rg);
+    I.off = take(I.bytes);
+    P->li.push_back(I);
+  }
+  // size the table head with every phase enabled
+  Tables T;
+  P->table_bytes = 0;
+  build_tables(P, nullptr, nullptr, T);
+  P->table_bytes = (T.bytes.size() + 2 * kAlign) / kAlign * kAlign;
+  P->ws_bytes = P->table_bytes + off + kAlign;
+  *out = P;
+  return KFAC_OK;
+}
+
+size_t kfac_plan_workspace(const kfac_plan* plan) { return plan ? plan->ws_bytes : 0; }
+
+kfac_status kfac_plan_set_scalars(kfac_plan* plan, float rho, float lambda, uint64_t seed, uint32_t inversion_index,
+                                  int do_ea, int do_eig, int do_precondition) {
+  if (!plan || !(rho >= 0.f && rho < 1.f) || !(lambda > 0.f) || !std::isfinite(lambda)) return KFAC_EINVAL;
+  plan->rho = rho; plan->lam = lambda; plan->seed = seed; plan->inv = inversion_index;
+  plan->do_ea = do_ea != 0; plan->do_eig = do_eig != 0; plan->do_pre = do_precondition != 0;
+  return KFAC_OK;
+}
+
+kfac_status kfac_plan_upload(kfac_plan* plan, void* workspace, size_t ws_bytes, int32_t* dev_status,
+                             kfac_stream_t stream) {
+  if (!plan || !workspace || !dev_status) return KFAC_EINVAL;
+  if (ws_bytes < plan->ws_bytes) return KFAC_EWORKSPACE;
+  Tables T;
+  build_tables(plan, (char*)workspace, (int*)dev_status, T);
+  if (T.bytes.size() > plan->table_bytes) return KFAC_EUNSUPPORTED;
+  plan->tab = std::move(T);
+  plan->dev = (char*)workspace;
+  hipError_t e = hipMemcpyAsync(workspace, plan->tab.bytes.data(), plan->tab.bytes.size(), hipMemcpyHostToDevice,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) return KFAC_EHIP;
+  // the host copy must stay valid until the transfer has been consumed
+  e = hipStreamSynchronize((hipStream_t)stream);
+  return e == hipSuccess ? KFAC_OK : KFAC_EHIP;
+}
+
+int kfac_plan_launch_count(const kfac_plan* plan) { return plan ? (int)plan->tab.recs.size() : 0; }
+
+const char* kfac_plan_launch_name(const kfac_plan* plan, int index) {
+  static const char* names[] = {"ea_tiles", "ea_finalize", "omega", "gemm_f32", "gemm_bf16", "gram_partial",
+                                "gram_reduce", "cholinv", "trmm", "tridiag", "tri_prep", "tri_bisect",
+                                "tri_select", "tri_vec", "tri_cluster_lead", "tri_cluster", "backtransform",
+                                "sign_partial", "sign_apply"};
+  if (!plan || index < 0 || index >= (int)plan->tab.recs.size()) return nullptr;
+  return names[plan->tab.recs[index].kind];
+}
+
+kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, kfac_stream_t stream) {
+  if (!plan || !plan->dev || first < 0 || count < 0 || first + count > (int)plan->tab.recs.size())
+    return KFAC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* d = plan->dev;
+  for (int i = first; i < first + count; ++i) {
+    const LaunchRec& r = plan->tab.recs[i];
+    GroupMap gm{(const int*)(d + r.off_off), (const int*)(d + r.gx_off), r.ntasks};
+    const void* tp = d + r.tasks_off;
+    hipError_t e = hipSuccess;
+    switch (r.kind) {
+      case K_EA_TILES: e = launch_ea_tiles_g((const EaTask*)tp, gm, r.blocks, s); break;
+      case K_EA_FIN: e = launch_ea_finalize_g((const EaTask*)tp, gm, r.blocks, s); break;
+      case K_OMEGA: e = launch_omega_g((const OmegaTask*)tp, gm, r.blocks, s); break;
+      case K_GEMM: e = launch_gemm_g((const GemmP*)tp, gm, r.blocks, r.ta, r.tb, s); break;
+      case K_BF16: e = launch_gemm_bf16_g((const BfGemmTask*)tp, gm, r.blocks, s); break;
+      case K_GRAM_P: e = launch_gram_partial_g((const GramP*)tp, gm, r.blocks, s); break;
+      case K_GRAM_R: e = launch_gram_reduce_g((const GramP*)tp, gm, r.blocks, s); break;
+      case K_CHOLINV: e = launch_cholinv_g((const CholInvTask*)tp, gm, r.blocks, s); break;
+      case K_TRMM: e = launch_trmm_g((const TrmmTask*)tp, gm, r.blocks, s); break;
+      case K_TRIDIAG: e = launch_tridiag_g((const EigTask*)tp, gm, r.blocks, s); break;
+      case K_PREP: e = launch_tri_prep_g((const EigTask*)tp, gm, r.blocks, s); break;
+      case K_BISECT: e = launch_tri_bisect_g((const EigTask*)tp, gm, r.blocks, s); break;
+      case K_SELECT: e = launch_tri_select_g((const EigTask*)tp, gm, r.blocks, s); break;
+      case K_VEC: e = launch_tri_vec_g((const EigTask*)tp, gm, r.blocks, s); break;
+      case K_CLEAD: e = launch_tri_cluster_lead_g((const EigTask*)tp, gm, r.blocks, s); break;
+      case K_CLUSTER: e = launch_tri_cluster_g((const EigTask*)tp, gm, r.blocks, s); break;
+      case K_BT: e = launch_backtransform_g((const EigTask*)tp, gm, r.blocks, s); break;
+      case K_SIGN_P: e = launch_sign_partial_g((const SignTask*)tp, gm, r.blocks, s); break;
+      case K_SIGN_A: e = launch_sign_apply_g((const SignTask*)tp, gm, r.blocks, s); break;
+      default: return KFAC_EINVAL;
+    }
+    if (e != hipSuccess) return KFAC_EHIP;
+  }
+  return KFAC_OK;
+}
+
+kfac_status kfac_plan_launch(const kfac_plan* plan, kfac_stream_t stream) {
+  if (!plan || !plan->dev) return KFAC_EINVAL;
+  return kfac_plan_launch_range(plan, 0, (int)plan->tab.recs.size(), stream);
+}
+
+void kfac_plan_destroy(kfac_plan* plan) { delete plan; }
+
+}  // extern "C"

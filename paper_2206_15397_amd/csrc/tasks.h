@@ -1,0 +1,88 @@
+// Per-task parameter blocks of the kernels.  A single-task launch passes one by value;
+// a grouped launch passes a device array of them plus a GroupMap (group.h).
+#pragma once
+#include <stdint.h>
+#include "gemm_f32.h"
+#include "group.h"
+
+namespace kfac {
+
+struct EaOut {
+  float* F; long ldf; uint16_t* Fb; long ldfb; int d; float rho, c;
+};
+
+struct EaTask {          // EA update: block (upper tile, K slice)
+  GemmP g;
+  EaOut o;
+  int T;                 // tiles per side
+  int nks;               // K slices
+};
+
+struct OmegaTask {       // Gaussian test matrix: block (row block, column group)
+  int d, l, d_pad, l_pad;
+  uint32_t k0, k1, stream, inv;
+  float* OmT; long ldt; uint16_t* OmTb;
+  float* Om; long ldo; uint32_t* words;
+};
+
+struct SignTask {        // column sign convention: block (column block, row chunk)
+  float* U; long ldu; int d, r;
+  float* pval; int* pidx; int nchunks;
+};
+
+struct BfGemmTask {      // C = A B^T, bf16 operands, K contiguous: block (flat tile)
+  int M, N, K;
+  const uint16_t* A; long lda;
+  const uint16_t* B; long ldb;
+  float* C; long ldc;
+  int tiles_m;
+};
+
+struct GramP {           // C = A B^T in fp64 from fp32 rows: block (tile, K slice)
+  const float* A; long lda;
+  const float* B; long ldb;
+  int L;                 // rows of A and B (l_pad)
+  int K;                 // contraction length (d)
+  int sym;               // 1: A == B, only upper tiles
+  int ksplit;
+  double* part;          // [tile][ks][64*64]
+  double* C; long ldc;
+  int* status;
+};
+
+struct CholInvTask {     // fused Cholesky + inverse of the l x l Gram (one block)
+  const double* G; long ldg; int n; long m_rows;
+  double* Linv; long ldl; int l_pad;
+  int* status; int* fail_flag; int attempt;
+};
+
+struct TrmmTask {        // Q^T = L^{-1} Y^T: block (column tile, row tile)
+  const double* Li; long ldl; int n;
+  const float* Yt; long ldy; int ncols;
+  float* Qt; long ldq; uint16_t* Qtb; long ldqb; int l_pad;
+};
+
+struct TriMeta {         // tridiagonal eigensolver state (see kernels_eig.hip)
+  double* es;            // [n] off-diagonal with negligible entries zeroed
+  int* blo;              // [n] first row of the block containing row i
+  int* bhi;              // [n] one past the last row of that block
+  double* lam;           // [n] eigenvalue of task j
+  int* col_task;         // [r] task of output column k (descending order)
+  int* cstart;           // [r] 1 if column k starts a new cluster
+  double* scal;          // [0] ||T|| bound, [1] pivmin, [2] any-cluster flag
+};
+
+struct EigTask {         // one small symmetric eigenproblem
+  const double* C; long ldc;      // fp64 input (or null)
+  const float* Cf; long ldcf;     // fp32 input (exact regime)
+  int n, n_pad, r;
+  double* A; double* V; double* diag; double* off;
+  double* Z; long ldz;
+  TriMeta m;
+  double* cl;                     // cluster scratch, 5 n
+  float* P; long ldp;             // fp32 eigenvectors (n_pad x r)
+  float* D; double* Dd;
+  int* status;
+};
+
+}  // namespace kfac

@@ -120,3 +120,91 @@ def precondition(J: torch.Tensor, Ua: torch.Tensor, Da: torch.Tensor, Ug: torch.
         _ptr(J), d_g, d_a, J.stride(0), _ptr(Ua), Ua.stride(0), _ptr(Da), r_a, _ptr(Ug), Ug.stride(0),
         _ptr(Dg), r_g, float(lam), _ptr(S), S.stride(0), _ptr(workspace), workspace.numel(), _stream()))
     return S
+
+
+class Plan:
+    """Grouped K-factor step over many factors and layers (kfac_plan_* in the C ABI).
+
+    factors: list of dicts with keys F (d x d fp32), r, p, q, stream_id, and optionally
+             F_bf16, X (n x d_in, fp32 or bf16), append_ones, scale, U, D.
+    layers:  list of dicts with keys fa, fg (factor indices), J (d_g x d_a); S optional.
+    The plan owns its workspace and status tensors; launch() only enqueues kernels and may
+    be captured in a CUDA/HIP graph after upload()."""
+
+    def __init__(self, factors, layers=(), sketch="bf16", device=None):
+        import ctypes
+        L = lib()
+        self._L = L
+        self.factors = [dict(f) for f in factors]
+        self.layers = [dict(l) for l in layers]
+        dev = device or self.factors[0]["F"].device
+        prec = _lib.KFAC_SKETCH_BF16 if sketch == "bf16" else _lib.KFAC_SKETCH_FP32
+        fds = (_lib.FactorDesc * len(self.factors))()
+        for i, f in enumerate(self.factors):
+            F = f["F"]
+            d = F.shape[0]
+            r = int(f["r"])
+            _require_cuda(F)
+            if prec == _lib.KFAC_SKETCH_BF16 and f.get("F_bf16") is None:
+                f["F_bf16"] = F.to(torch.bfloat16)
+            f.setdefault("U", torch.empty((d, r), dtype=torch.float32, device=dev))
+            f.setdefault("D", torch.empty((r,), dtype=torch.float32, device=dev))
+            x = f.get("X")
+            fd = fds[i]
+            fd.F, fd.d, fd.ldf = F.data_ptr(), d, F.stride(0)
+            fb = f.get("F_bf16")
+            fd.F_bf16, fd.ldfb = (fb.data_ptr(), fb.stride(0)) if fb is not None else (None, 0)
+            fd.r, fd.p, fd.q, fd.stream_id = r, int(f["p"]), int(f["q"]), int(f.get("stream_id", i))
+            if x is not None:
+                fd.X = x.data_ptr()
+                fd.xtype = _lib.KFAC_BF16 if x.dtype == torch.bfloat16 else _lib.KFAC_FP32
+                fd.n, fd.d_in, fd.ldx = x.shape[0], x.shape[1], x.stride(0)
+                fd.append_ones = 1 if f.get("append_ones") else 0
+                fd.scale = float(f.get("scale", 1.0 / x.shape[0]))
+            fd.U, fd.ldu, fd.D = f["U"].data_ptr(), f["U"].stride(0), f["D"].data_ptr()
+        lds = (_lib.LayerDesc * max(1, len(self.layers)))()
+        for k, l in enumerate(self.layers):
+            J = l["J"]
+            l.setdefault("S", torch.empty_like(J))
+            ld = lds[k]
+            ld.fa, ld.fg = int(l["fa"]), int(l["fg"])
+            ld.J, ld.ldj, ld.S, ld.lds = J.data_ptr(), J.stride(0), l["S"].data_ptr(), l["S"].stride(0)
+        self._fds, self._lds = fds, lds
+        h = ctypes.c_void_p()
+        check("kfac_plan_create", L.kfac_plan_create(ctypes.byref(fds), len(self.factors),
+                                                     ctypes.byref(lds) if self.layers else None,
+                                                     len(self.layers), prec, ctypes.byref(h)))
+        self._h = h
+        self.workspace = torch.empty(int(L.kfac_plan_workspace(h)), dtype=torch.uint8, device=dev)
+        self.status = torch.zeros((1,), dtype=torch.int32, device=dev)
+
+    def set_scalars(self, rho=0.95, lam=0.1, seed=0, inversion_index=0, do_ea=True, do_eig=True,
+                    do_precondition=True):
+        check("kfac_plan_set_scalars", self._L.kfac_plan_set_scalars(
+            self._h, float(rho), float(lam), int(seed), int(inversion_index), int(do_ea), int(do_eig),
+            int(do_precondition)))
+        return self
+
+    def upload(self):
+        check("kfac_plan_upload", self._L.kfac_plan_upload(self._h, _ptr(self.workspace), self.workspace.numel(),
+                                                           _ptr(self.status), _stream()))
+        return self
+
+    @property
+    def launch_count(self):
+        return int(self._L.kfac_plan_launch_count(self._h))
+
+    def launch(self):
+        check("kfac_plan_launch", self._L.kfac_plan_launch(self._h, _stream()))
+
+    def launch_range(self, first, count):
+        check("kfac_plan_launch_range", self._L.kfac_plan_launch_range(self._h, int(first), int(count), _stream()))
+
+    def launch_names(self):
+        return [self._L.kfac_plan_launch_name(self._h, i).decode() for i in range(self.launch_count)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._L.kfac_plan_destroy(h)
+            self._h = None
