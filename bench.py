@@ -9,12 +9,16 @@ from I (rho 0.95) during untimed setup.  One timed step = EA step 11 for all 32 
 the randomized eigendecomposition (SREVD, r=min(256,d), p=16, q=1) of all 32 factors and
 the damped inverse (lambda 0.1) for all 16 layer gradients -- with inputs resident in HBM.
 
-Two paths are measured on the same GPU:
-  plain   : per-layer launch sequence on one stream, fp32 activations and fp32 sketch;
-  batched : bf16 activations and bf16 sketch, factors spread over concurrent streams,
-            the whole step captured once in a hipGraph and replayed.
-The reported value is the batched path's K-factor eig-inversions per second over the
-whole step (32 factors / step time).
+Paths measured on the same GPU:
+  plan    : the grouped plan (kfac_plan_*): every phase of all 32 factors / 16 layers in one
+            launch, bf16 activations and bf16 sketch, captured once in a hipGraph and
+            replayed -- this is the reported `value` (32 factors / median step time);
+  plain   : per-layer entry-point calls on one stream, fp32 activations and fp32 sketch;
+  streams : (optional, --streams N) per-factor calls spread over N streams in a hipGraph.
+After the timed replays the plan's launches are replayed eagerly with a HIP event between
+consecutive launches (queue pre-filled behind a spin kernel), which gives each grouped
+launch's duration; the `roofline` object reports the kernel with the largest share of the
+step against the published MI355X peak for its arithmetic type.
 """
 from __future__ import annotations
 
@@ -83,8 +87,8 @@ def build_workload(dev, act_dtype_bf16: bool):
             a, g = a.to(torch.bfloat16), g.to(torch.bfloat16)
         L.a, L.g = a.contiguous(), g.contiguous()
         L.A0, L.G0 = L.A.clone(), L.G.clone()      # restored before every timed step
-        L.Ab = L.A.to(torch.bfloat16)
-        L.Gb = L.G.to(torch.bfloat16)
+        L.Ab = K.bf16_shadow(L.A)
+        L.Gb = K.bf16_shadow(L.G)
         L.ra, L.rg = min(wl.r_cap, s.d_a), min(wl.r_cap, s.d_g)
         layers.append(L)
         torch.cuda.synchronize()
@@ -273,6 +277,49 @@ def phase_times(plan, layers, reps):
     return names, [a / reps for a in acc]
 
 
+# Published MI355X peaks: HBM3E bandwidth and dense matrix / vector throughput.
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+# arithmetic type and unit kind of each grouped launch: "mfma" for matrix-core kernels,
+# "alu" for the fp64 vector kernels (single-workgroup factorisations and eigensolver)
+KIND = {
+    "ea_tiles_bf16": ("bf16", "mfma"), "gemm_bf16": ("bf16", "mfma"),
+    "ea_tiles": ("fp32", "mfma"), "gemm_f32": ("fp32", "mfma"),
+    "gram_partial": ("fp64", "mfma"), "trmm": ("fp64", "mfma"),
+    "cholinv": ("fp64", "alu"), "tridiag": ("fp64", "alu"), "backtransform": ("fp64", "alu"),
+}
+
+
+def roofline(plan, names, times_ms):
+    """Roofline of the kernel with the largest share of the step: algorithmic work of its
+    launches (kfac_plan_launch_work) over their measured durations."""
+    tot = {}
+    for i, (nm, t) in enumerate(zip(names, times_ms)):
+        f, b = plan.launch_work(i)
+        a = tot.setdefault(nm, [0.0, 0.0, 0.0, 0])
+        a[0] += t
+        a[1] += f
+        a[2] += b
+        a[3] += 1
+    nm = max(tot, key=lambda k: tot[k][0])
+    t_ms, flops, nbytes, count = tot[nm]
+    dt, unit_kind = KIND.get(nm, ("fp32", "hbm"))
+    peak_f = PEAK_TFLOPS[dt] * 1e12
+    if unit_kind == "hbm" or nbytes / (PEAK_HBM_GBS * 1e9) >= flops / peak_f:
+        ach = nbytes / (t_ms * 1e-3) / 1e9
+        out = {"bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+               "frac": round(ach / PEAK_HBM_GBS, 5)}
+    else:
+        ach = flops / (t_ms * 1e-3) / 1e12
+        out = {"bound": unit_kind, "achieved": round(ach, 4), "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+               "frac": round(ach / PEAK_TFLOPS[dt], 6)}
+    out.update({"traffic": None, "kernel": nm, "dtype": dt, "launches_per_step": count,
+                "avg_launch_us": round(1e3 * t_ms / count, 2),
+                "flops_per_launch": flops / count, "bytes_per_launch": nbytes / count,
+                "share_of_step": round(t_ms / sum(times_ms), 4)})
+    return out
+
+
 def median(xs):
     s = sorted(xs)
     return s[len(s) // 2]
@@ -334,6 +381,8 @@ def main():
     tot = sum(pt)
     for i, (nm, t) in enumerate(zip(names, pt)):
         log(f"  [{i:2d}] {nm:18s} {t * 1e3:9.1f} us  {100 * t / tot:5.1f}%")
+    roof = roofline(plan, names, pt)
+    log(f"roofline: {roof}")
     del gp
     plain_ms = None
     if args.streams > 0:
@@ -366,6 +415,7 @@ def main():
                    "path": "grouped plan (%d launches), bf16 sketch, hipGraph" % plan.launch_count},
         "plain_fp32_ms_per_step": None if plain_ms is None else round(plain_ms, 4),
         "speedup_vs_plain_fp32": None if plain_ms is None else round(plain_ms / ms_b, 3),
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

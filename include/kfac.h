@@ -229,6 +229,10 @@ kfac_status kfac_plan_launch(const kfac_plan* plan, kfac_stream_t stream);
 kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, kfac_stream_t stream);
 /* Phase name of launch `index` ("gemm_bf16", "tridiag", ...), NULL when out of range. */
 const char* kfac_plan_launch_name(const kfac_plan* plan, int index);
+/* Algorithmic work of launch `index`, summed over its tasks: flops of the operation as
+ * defined (no padding, no split-K partials) and the minimum bytes it must move (each
+ * operand read once, each result written once).  KFAC_EINVAL when out of range. */
+kfac_status kfac_plan_launch_work(const kfac_plan* plan, int index, double* flops, double* bytes);
 void kfac_plan_destroy(kfac_plan* plan);
 
 #ifdef __cplusplus

@@ -38,6 +38,7 @@ SIGNATURES = {
     "kfac_plan_launch": (_i, [_p, _p]),
     "kfac_plan_launch_range": (_i, [_p, _i, _i, _p]),
     "kfac_plan_launch_name": (ctypes.c_char_p, [_p, _i]),
+    "kfac_plan_launch_work": (_i, [_p, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "kfac_plan_destroy": (None, [_p]),
 }
 

@@ -13,8 +13,15 @@ struct GroupMap {
   int ntasks;
 };
 
-__device__ __forceinline__ void group_locate(const GroupMap& g, int& t, int& bx, int& by) {
-  const int b = blockIdx.x;
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  This
+// bijection on [0, n) gives every XCD a contiguous range of logical block indices, so
+// neighbouring tiles that share an operand panel run under the same L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, slot = b >> 3;
+  return x * q + (x < r ? x : r) + slot;
+}
+
+__device__ __forceinline__ void group_locate_at(const GroupMap& g, int b, int& t, int& bx, int& by) {
   int lo = 0, hi = g.ntasks - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -27,10 +34,25 @@ __device__ __forceinline__ void group_locate(const GroupMap& g, int& t, int& bx,
   by = local / w;
 }
 
+__device__ __forceinline__ void group_locate(const GroupMap& g, int& t, int& bx, int& by) {
+  group_locate_at(g, blockIdx.x, t, bx, by);
+}
+
+__device__ __forceinline__ void group_locate_xcd(const GroupMap& g, int& t, int& bx, int& by) {
+  group_locate_at(g, xcd_swizzle(blockIdx.x, gridDim.x), t, bx, by);
+}
+
 #define KFAC_GROUPED_KERNEL(NAME, BODY, PARAMS, NT)                                   \
   __global__ __launch_bounds__(NT) void NAME(const PARAMS* tasks, GroupMap gm) {        \
     int t_, bx_, by_;                                                                   \
     group_locate(gm, t_, bx_, by_);                                                     \
+    BODY(tasks[t_], bx_, by_);                                                          \
+  }
+
+#define KFAC_GROUPED_KERNEL_XCD(NAME, BODY, PARAMS, NT)                               \
+  __global__ __launch_bounds__(NT) void NAME(const PARAMS* tasks, GroupMap gm) {        \
+    int t_, bx_, by_;                                                                   \
+    group_locate_xcd(gm, t_, bx_, by_);                                                 \
     BODY(tasks[t_], bx_, by_);                                                          \
   }
 

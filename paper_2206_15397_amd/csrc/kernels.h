@@ -7,15 +7,19 @@
 #include "common.h"
 #include "gemm_f32.h"
 #include "tasks.h"
+#include "ea_tile.h"
 
 namespace kfac {
 
 // fp32 kernels (kernels_f32.hip)
 hipError_t launch_fill_identity(float* F, int d, long ldf, hipStream_t s);
 hipError_t launch_gemm(const GemmP& p, bool ta, bool tb, hipStream_t s);
-int ea_tiles_per_side(int d);
-int ea_choose_ksplit(int d, long n);
-size_t ea_workspace_bytes(int d, long n);
+// EA tiles are 64 x 64 (fp32 MFMA) for fp32 activations and 128 x 128 (bf16 MFMA) for
+// bf16 activations; `bf` selects the variant.
+int ea_tiles_per_side(int d, bool bf);
+int ea_choose_ksplit(int d, long n, bool bf);
+size_t ea_workspace_bytes(int d, long n, bool bf);
+size_t ea_workspace_bytes(int d, long n);   // enough for either variant
 hipError_t launch_ea_f32(float* F, int d, long ldf, const float* X, int n, int d_in, long ldx, int ones,
                          float rho, float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes,
                          hipStream_t s);
@@ -79,6 +83,11 @@ int gemm_g_blocks_y(const GemmP& p);
 
 hipError_t launch_ea_tiles_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_ea_finalize_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
+constexpr int kEaBf16Tile = 128;
+hipError_t launch_ea_bf16_tiles(const EaTask& q, int tiles, int ks, hipStream_t s);
+hipError_t launch_ea_bf16_finalize(const EaTask& q, int tiles, hipStream_t s);
+hipError_t launch_ea_bf16_tiles_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_ea_bf16_finalize_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_omega_g(const OmegaTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_sign_partial_g(const SignTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_sign_apply_g(const SignTask* t, GroupMap gm, int blocks, hipStream_t s);

@@ -5,19 +5,20 @@
 namespace kfac {
 
 // C[M x N] = A[M x K] * B[N x K]^T ; A, B bf16 row-major, K contiguous; C fp32.
-// Tiles BM x BN x 32, 4 waves (2 x 2).  LDS rows hold 32 k-values + 8 pad (80 bytes),
-// each lane reads its 8 consecutive k (16 bytes) of one row per fragment.
+// Tiles BM x BN x 64, 4 waves (2 x 2), two LDS buffers (one barrier per k-step).  LDS rows
+// hold 64 k-values + 8 pad (144 bytes), so the 16 rows read by one 16-lane group fall on
+// distinct banks; each lane reads its 8 consecutive k (16 bytes) of one row per operand.
 template <int BM, int BN>
 struct TileBF16 {
-  static constexpr int BK = 32, PAD = 8, SK = BK + PAD;
+  static constexpr int BK = 64, PAD = 8, SK = BK + PAD;
   static constexpr int FM = BM / 2 / 16, FN = BN / 2 / 16;
   static constexpr int NT = 256;
   static constexpr int NVA = BM * BK / 8, NVB = BN * BK / 8;   // 16-byte vectors per tile
   static constexpr int VA = (NVA + NT - 1) / NT;                 // per thread (last guarded)
   static constexpr int VB = (NVB + NT - 1) / NT;
   struct Smem {
-    uint16_t a[BM][SK];
-    uint16_t b[BN][SK];
+    uint16_t a[2][BM][SK];
+    uint16_t b[2][BN][SK];
   };
 };
 
@@ -68,38 +69,46 @@ __device__ __forceinline__ void gemm_bf16_body(const BfGemmTask& q, int bx, int)
       rb[u] = (e < T::NVB) ? ld16(B, ldb, n0 + row, N, k0 + kc, K) : make_uint4(0, 0, 0, 0);
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < K; k0 += T::BK) {
-    __syncthreads();
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < T::VA; ++u) {
       int e = tid + u * 256, row = e / (T::BK / 8), kc = (e % (T::BK / 8)) * 8;
-      if (e < T::NVA) *(uint4*)&sm.a[row][kc] = ra[u];
+      if (e < T::NVA) *(uint4*)&sm.a[buf][row][kc] = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < T::VB; ++u) {
       int e = tid + u * 256, row = e / (T::BK / 8), kc = (e % (T::BK / 8)) * 8;
-      if (e < T::NVB) *(uint4*)&sm.b[row][kc] = rb[u];
+      if (e < T::NVB) *(uint4*)&sm.b[buf][row][kc] = rb[u];
     }
+  };
+  if (K > 0) {
+    fetch(0);
+    stash(0);
     __syncthreads();
-    if (k0 + T::BK < K) fetch(k0 + T::BK);
-    const int kq = (lane >> 4) * 8;
-    bf16x8 af[T::FM], bfr[T::FN];
+  }
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += T::BK) {
+    const bool more = k0 + T::BK < K;
+    if (more) fetch(k0 + T::BK);
 #pragma unroll
-    for (int i = 0; i < T::FM; ++i) {
-      uint4 v = *(const uint4*)&sm.a[wm * (BM / 2) + i * 16 + (lane & 15)][kq];
-      af[i] = __builtin_bit_cast(bf16x8, v);
-    }
+    for (int kk = 0; kk < T::BK; kk += 32) {
+      const int kq = kk + (lane >> 4) * 8;
+      bf16x8 af[T::FM], bfr[T::FN];
 #pragma unroll
-    for (int j = 0; j < T::FN; ++j) {
-      uint4 v = *(const uint4*)&sm.b[wn * (BN / 2) + j * 16 + (lane & 15)][kq];
-      bfr[j] = __builtin_bit_cast(bf16x8, v);
-    }
-#pragma unroll
-    for (int i = 0; i < T::FM; ++i)
+      for (int i = 0; i < T::FM; ++i)
+        af[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&sm.a[buf][wm * (BM / 2) + i * 16 + (lane & 15)][kq]);
 #pragma unroll
       for (int j = 0; j < T::FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        bfr[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&sm.b[buf][wn * (BN / 2) + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < T::FM; ++i)
@@ -113,11 +122,184 @@ __device__ __forceinline__ void gemm_bf16_body(const BfGemmTask& q, int bx, int)
       }
 }
 
+// ------------------------------------------------------------------------------------
+// EA update from bf16 activations on bf16 MFMA: F <- rho F + c * Xh^T Xh (Alg. 1 EA lines),
+// upper 128 x 128 tiles, 4 waves of 64 x 64.  The contraction runs over the batch rows of
+// X, which are strided in memory, so each thread loads an 8 (rows) x 8 (columns) block
+// with 16-byte row loads, transposes it in registers and stores 8 column vectors of 8
+// consecutive rows into LDS (column-major tiles, k contiguous).  Every MFMA operand is then
+// one 16-byte LDS read.  Two LDS buffers: one barrier per 64-row step.  The 144-byte LDS
+// row pitch keeps both the 16-lane column stores and the 16-lane operand reads on
+// distinct banks.
+constexpr int EB_BT = kEaBf16Tile, EB_BK = 64, EB_SK = EB_BK + 8;
+struct EbSmem {
+  union {
+    struct {
+      uint16_t a[2][EB_BT][EB_SK];
+      uint16_t b[2][EB_BT][EB_SK];
+    } g;
+    float t[EB_BT][EB_BT + 1];
+  };
+};
+
+// Column c of the (row-major) 8 x 8 bf16 block held as v[row] (8 halves per uint4).
+__device__ __forceinline__ uint4 col_of_block(const uint4 v[8], int c) {
+  auto half = [&](int r) -> uint32_t {
+    const uint4& x = v[r];
+    const uint32_t w = (c >> 1) == 0 ? x.x : (c >> 1) == 1 ? x.y : (c >> 1) == 2 ? x.z : x.w;
+    return (c & 1) ? (w >> 16) : (w & 0xffffu);
+  };
+  return make_uint4(half(0) | (half(1) << 16), half(2) | (half(3) << 16), half(4) | (half(5) << 16),
+                    half(6) | (half(7) << 16));
+}
+
+// Rows [k0, k0+8) x columns [c0, c0+8) of Xh (bf16, ones column appended at d_in when
+// ones != 0, zero beyond d and beyond row ke).
+__device__ __forceinline__ void eb_load_block(const uint16_t* X, long ldx, int d_in, int d, bool ones, bool vec,
+                                              int k0, int ke, int c0, uint4 v[8]) {
+  const bool full = vec && (c0 + 8 <= d_in);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int k = k0 + r;
+    v[r] = make_uint4(0, 0, 0, 0);
+    if (k >= ke) continue;
+    const uint16_t* p = X + (long)k * ldx + c0;
+    if (full) {
+      v[r] = *(const uint4*)p;
+    } else {
+      uint16_t t[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = c0 + j;
+        t[j] = (c < d_in) ? p[j] : ((ones && c == d_in && c < d) ? (uint16_t)0x3f80 : (uint16_t)0);
+      }
+      v[r] = make_uint4(t[0] | ((uint32_t)t[1] << 16), t[2] | ((uint32_t)t[3] << 16),
+                        t[4] | ((uint32_t)t[5] << 16), t[6] | ((uint32_t)t[7] << 16));
+    }
+  }
+}
+
+template <int DUMMY = 0>
+__device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int by) {
+  __shared__ EbSmem sm;
+  const GemmP& p = q.g;
+  int I, J;
+  upper_tile(bx, q.T, I, J);
+  int kb, ke;
+  ea_slice(p.K, q.nks, by, EB_BK, kb, ke);
+  const bool diag = (I == J);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int d = p.M, d_in = p.ones_col >= 0 ? p.ones_col : d;
+  const bool ones = p.ones_col >= 0;
+  const uint16_t* X = p.Ab;
+  const long ldx = p.lda;
+  const bool vec = ((ldx & 7) == 0) && ((((uintptr_t)X) & 15) == 0);
+  // loader role: threads 0..127 fill the A tile (columns of block I), 128..255 the B tile
+  const int op = tid >> 7, tt = tid & 127, cg = tt >> 3, rg = tt & 7;
+  const bool loader = !(diag && op == 1);
+  const int c0 = (op ? J : I) * EB_BT + cg * 8;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 v[8];
+  auto stash = [&](int buf) {
+    uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf] : sm.g.a[buf];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][rg * 8] = col_of_block(v, c);
+  };
+  if (kb < ke) {
+    if (loader) {
+      eb_load_block(X, ldx, d_in, d, ones, vec, kb + rg * 8, ke, c0, v);
+      stash(0);
+    }
+    __syncthreads();
+  }
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += EB_BK) {
+    const bool more = k0 + EB_BK < ke;
+    if (more && loader) eb_load_block(X, ldx, d_in, d, ones, vec, k0 + EB_BK + rg * 8, ke, c0, v);
+    uint16_t (*A)[EB_SK] = sm.g.a[buf];
+    uint16_t (*B)[EB_SK] = diag ? sm.g.a[buf] : sm.g.b[buf];
+#pragma unroll
+    for (int kk = 0; kk < EB_BK; kk += 32) {
+      const int kq = kk + (lane >> 4) * 8;
+      bf16x8 af[4], bfr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        af[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&A[wm * 64 + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bfr[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&B[wn * 64 + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    if (more && loader) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  auto for_each = [&](auto&& fn) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          fn(wm * 64 + i * 16 + 4 * (lane >> 4) + r, wn * 64 + j * 16 + (lane & 15), acc[i][j][r]);
+  };
+  if (q.nks > 1) {
+    float* slot = p.part + ((long)bx * q.nks + by) * (EB_BT * EB_BT);
+    for_each([&](int r, int c, float x) { slot[r * EB_BT + c] = x; });
+    return;
+  }
+  __syncthreads();
+  for_each([&](int r, int c, float x) { sm.t[r][c] = x; });
+  __syncthreads();
+  ea_store_tile_t<EB_BT>(sm.t, q.o, I, J);
+}
+
+__device__ __forceinline__ void ea_bf16_finalize_body(const EaTask& q, int bx, int) {
+  __shared__ float t[EB_BT][EB_BT + 1];
+  int I, J;
+  upper_tile(bx, q.T, I, J);
+  ea_sum_slices<EB_BT>(t, q.g.part + (long)bx * q.nks * (EB_BT * EB_BT), q.nks);
+  __syncthreads();
+  ea_store_tile_t<EB_BT>(t, q.o, I, J);
+}
+
+__global__ __launch_bounds__(256) void k_ea_bf16_tiles(EaTask q) { ea_bf16_tiles_body(q, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(256) void k_ea_bf16_finalize(EaTask q) { ea_bf16_finalize_body(q, blockIdx.x, 0); }
+KFAC_GROUPED_KERNEL_XCD(k_ea_bf16_tiles_g, ea_bf16_tiles_body<0>, EaTask, 256)
+KFAC_GROUPED_KERNEL(k_ea_bf16_finalize_g, ea_bf16_finalize_body, EaTask, 256)
+
+hipError_t launch_ea_bf16_tiles(const EaTask& q, int tiles, int ks, hipStream_t s) {
+  hipLaunchKernelGGL(k_ea_bf16_tiles, dim3(tiles, ks), dim3(256), 0, s, q);
+  return hipGetLastError();
+}
+hipError_t launch_ea_bf16_finalize(const EaTask& q, int tiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_ea_bf16_finalize, dim3(tiles), dim3(256), 0, s, q);
+  return hipGetLastError();
+}
+hipError_t launch_ea_bf16_tiles_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_ea_bf16_tiles_g, dim3(blocks), dim3(256), 0, s, t, gm);
+  return hipGetLastError();
+}
+hipError_t launch_ea_bf16_finalize_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_ea_bf16_finalize_g, dim3(blocks), dim3(256), 0, s, t, gm);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
 constexpr int BF_BM = 96, BF_BN = 128;
 __global__ __launch_bounds__(256) void k_gemm_bf16_nt(BfGemmTask q) { gemm_bf16_body<BF_BM, BF_BN>(q, blockIdx.x, 0); }
 __global__ __launch_bounds__(256) void k_gemm_bf16_nt_g(const BfGemmTask* tasks, GroupMap gm) {
   int t, bx, by;
-  group_locate(gm, t, bx, by);
+  group_locate_xcd(gm, t, bx, by);
   gemm_bf16_body<BF_BM, BF_BN>(tasks[t], bx, by);
 }
 

@@ -63,50 +63,14 @@ union EaSmem {
   float t[EA_BT][EA_BT + 1];
 };
 
-// Blend the (I, J) tile whose raw sums sit in `sm.t` and write it plus its mirror.
-__device__ void ea_store_tile(EaSmem& sm, const EaOut& o, int I, int J) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int r0 = I * EA_BT, c0 = J * EA_BT;
-  // upper block (rows of I, columns of J), coalesced along columns
-  for (int e = tid; e < EA_BT * EA_BT; e += nt) {
-    int a = e / EA_BT, b = e % EA_BT;
-    int i = r0 + a, j = c0 + b;
-    float v = 0.f;
-    if (i < o.d && j < o.d) {
-      v = o.rho * o.F[(long)i * o.ldf + j] + o.c * sm.t[a][b];
-    }
-    sm.t[a][b] = v;   // same thread reads and writes the same slot
-  }
-  __syncthreads();
-  for (int e = tid; e < EA_BT * EA_BT; e += nt) {
-    int a = e / EA_BT, b = e % EA_BT;
-    int i = r0 + a, j = c0 + b;
-    if (i < o.d && j < o.d && (I != J || a <= b)) {
-      float v = sm.t[a][b];
-      o.F[(long)i * o.ldf + j] = v;
-      if (o.Fb) o.Fb[(long)i * o.ldfb + j] = f32_to_bf16_rne(v);
-    }
-  }
-  // mirror block (rows of J, columns of I): element (c0+a, r0+b) = t[b][a]
-  for (int e = tid; e < EA_BT * EA_BT; e += nt) {
-    int a = e / EA_BT, b = e % EA_BT;
-    int i = c0 + a, j = r0 + b;
-    if (i < o.d && j < o.d && (I != J ? true : b < a)) {
-      float v = sm.t[b][a];
-      o.F[(long)i * o.ldf + j] = v;
-      if (o.Fb) o.Fb[(long)i * o.ldfb + j] = f32_to_bf16_rne(v);
-    }
-  }
-}
-
 __device__ __forceinline__ void ea_tiles_body(const EaTask& q, int bx, int by) {
   __shared__ EaSmem sm;
   const GemmP& p = q.g;
   int I, J;
   upper_tile(bx, q.T, I, J);
   const int ks = by, nks = q.nks;
-  const int kchunk = ((p.K + nks - 1) / nks + EA_BK - 1) / EA_BK * EA_BK;
-  const int kb = ks * kchunk, ke = min(p.K, kb + kchunk);
+  int kb, ke;
+  ea_slice(p.K, nks, ks, EA_BK, kb, ke);
   f32x4 acc[EaTile::FM][EaTile::FN];
 #pragma unroll
   for (int i = 0; i < EaTile::FM; ++i)
@@ -121,7 +85,7 @@ __device__ __forceinline__ void ea_tiles_body(const EaTask& q, int bx, int by) {
   __syncthreads();
   EaTile::for_each(acc, [&](int r, int c, float v) { sm.t[r][c] = v; });
   __syncthreads();
-  ea_store_tile(sm, q.o, I, J);
+  ea_store_tile_t<EA_BT>(sm.t, q.o, I, J);
 }
 
 // Deterministic split-K reduction (slices summed in index order) + EA epilogue.
@@ -129,14 +93,9 @@ __device__ __forceinline__ void ea_finalize_body(const EaTask& q, int bx, int) {
   __shared__ EaSmem sm;
   int I, J;
   upper_tile(bx, q.T, I, J);
-  const float* base = q.g.part + (long)bx * q.nks * (EA_BT * EA_BT);
-  for (int e = threadIdx.x; e < EA_BT * EA_BT; e += blockDim.x) {
-    float s = 0.f;
-    for (int k = 0; k < q.nks; ++k) s += base[(long)k * EA_BT * EA_BT + e];
-    sm.t[e / EA_BT][e % EA_BT] = s;
-  }
+  ea_sum_slices<EA_BT>(sm.t, q.g.part + (long)bx * q.nks * (EA_BT * EA_BT), q.nks);
   __syncthreads();
-  ea_store_tile(sm, q.o, I, J);
+  ea_store_tile_t<EA_BT>(sm.t, q.o, I, J);
 }
 
 __global__ __launch_bounds__(256) void k_ea_tiles(EaTask q) { ea_tiles_body(q, blockIdx.x, blockIdx.y); }
@@ -288,31 +247,39 @@ hipError_t launch_gemm(const GemmP& p, bool ta, bool tb, hipStream_t s) {
   return gemm_dispatch<true, true>(p, s);
 }
 
-int ea_tiles_per_side(int d) { return (d + EA_BT - 1) / EA_BT; }
+int ea_tiles_per_side(int d, bool bf) {
+  const int bt = bf ? kEaBf16Tile : EA_BT;
+  return (d + bt - 1) / bt;
+}
 
-int ea_choose_ksplit(int d, long n) {
-  int T = ea_tiles_per_side(d);
+int ea_choose_ksplit(int d, long n, bool bf) {
+  int T = ea_tiles_per_side(d, bf);
   long tiles = (long)T * (T + 1) / 2;
   long want = (1024 + tiles - 1) / tiles;           // aim for >= ~1024 workgroups
-  long maxk = (n + 511) / 512;                      // at least 512 rows per slice
+  const long rows = bf ? 1024 : 512;                // rows per slice at least
+  long maxk = (n + rows - 1) / rows;
   long ks = std::min(want, maxk);
   if (ks < 1) ks = 1;
   if (ks > 64) ks = 64;
   return (int)ks;
 }
 
-size_t ea_workspace_bytes(int d, long n) {
-  int ks = ea_choose_ksplit(d, n);
+size_t ea_workspace_bytes(int d, long n, bool bf) {
+  int ks = ea_choose_ksplit(d, n, bf);
   if (ks <= 1) return 0;
-  int T = ea_tiles_per_side(d);
+  const long bt = bf ? kEaBf16Tile : EA_BT;
+  int T = ea_tiles_per_side(d, bf);
   long tiles = (long)T * (T + 1) / 2;
-  return (size_t)tiles * ks * EA_BT * EA_BT * sizeof(float);
+  return (size_t)tiles * ks * bt * bt * sizeof(float);
+}
+
+size_t ea_workspace_bytes(int d, long n) {
+  return std::max(ea_workspace_bytes(d, n, false), ea_workspace_bytes(d, n, true));
 }
 
 static hipError_t launch_ea_common(float* F, int d, long ldf, const float* X, const uint16_t* Xb, int n,
                                    int d_in, long ldx, int ones, float rho, float scale, uint16_t* Fb, long ldfb,
                                    void* ws, size_t ws_bytes, hipStream_t s) {
-  EaOut o{F, ldf, Fb, ldfb, d, rho, (1.f - rho) * scale};
   if (n == 0) {
     long total = (long)d * d;
     int blocks = (int)std::min<long>((total + 255) / 256, 4096);
@@ -320,18 +287,16 @@ static hipError_t launch_ea_common(float* F, int d, long ldf, const float* X, co
                        ldfb, d, rho);
     return hipGetLastError();
   }
-  GemmP p{};
-  p.M = d; p.N = d; p.K = n;
-  p.A = X; p.lda = ldx; p.B = X; p.ldb = ldx;
-  p.Ab = Xb; p.Bb = Xb;
-  p.ones_col = ones ? d_in : -1;
-  int T = ea_tiles_per_side(d);
-  int tiles = T * (T + 1) / 2;
-  int ks = ea_choose_ksplit(d, n);
-  if (ks > 1 && (ws == nullptr || ws_bytes < ea_workspace_bytes(d, n))) ks = 1;
-  p.ksplit = ks;
-  p.part = (float*)ws;
-  EaTask q{p, o, T, ks};
+  const bool bf = (Xb != nullptr);
+  int ks = ea_choose_ksplit(d, n, bf);
+  if (ks > 1 && (ws == nullptr || ws_bytes < ea_workspace_bytes(d, n, bf))) ks = 1;
+  EaTask q = make_ea_task(F, d, ldf, X, Xb, n, d_in, ldx, ones, rho, scale, Fb, ldfb, (float*)ws, ks);
+  const int tiles = q.T * (q.T + 1) / 2;
+  if (bf) {
+    hipError_t e = launch_ea_bf16_tiles(q, tiles, ks, s);
+    if (e != hipSuccess || ks == 1) return e;
+    return launch_ea_bf16_finalize(q, tiles, s);
+  }
   hipLaunchKernelGGL(k_ea_tiles, dim3(tiles, ks), dim3(256), 0, s, q);
   if (ks > 1) hipLaunchKernelGGL(k_ea_finalize, dim3(tiles), dim3(256), 0, s, q);
   return hipGetLastError();
@@ -417,7 +382,7 @@ EaTask make_ea_task(float* F, int d, long ldf, const float* X, const uint16_t* X
   p.ones_col = ones ? d_in : -1;
   p.ksplit = ks;
   p.part = part;
-  EaTask q{p, o, ea_tiles_per_side(d), ks};
+  EaTask q{p, o, ea_tiles_per_side(d, Xb != nullptr), ks};
   return q;
 }
 

@@ -13,7 +13,7 @@ using namespace kfac;
 namespace {
 
 enum Kind {
-  K_EA_TILES, K_EA_FIN, K_OMEGA, K_GEMM, K_BF16, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRMM, K_TRIDIAG, K_PREP,
+  K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRMM, K_TRIDIAG, K_PREP,
   K_BISECT, K_SELECT, K_VEC, K_CLEAD, K_CLUSTER, K_BT, K_SIGN_P, K_SIGN_A
 };
 
@@ -22,7 +22,18 @@ struct LaunchRec {
   size_t tasks_off, off_off, gx_off;
   int ntasks, blocks;
   bool ta, tb;
+  double flops, bytes;   // algorithmic work of the launch (all tasks)
 };
+
+// Algorithmic work: flops of the operation as defined (padding and split-K excluded) and
+// the bytes it must move at least (each operand read once, each result written once).
+struct Work {
+  double flops = 0, bytes = 0;
+  void operator+=(const Work& o) { flops += o.flops; bytes += o.bytes; }
+};
+inline Work gemm_work(double M, double N, double K, bool extra) {
+  return Work{2 * M * N * K, 4 * (M * K + K * N + M * N + (extra ? M * N : 0))};
+}
 
 // Serialises one launch: [tasks][off (ntasks+1)][gx (ntasks)], each 256-byte aligned.
 struct Tables {
@@ -35,10 +46,12 @@ struct Tables {
   }
   template <typename T>
   void add(int kind, const std::vector<T>& tasks, const std::vector<int>& gx, const std::vector<int>& nblk,
-           bool ta = false, bool tb = false) {
+           bool ta = false, bool tb = false, Work w = Work{}) {
     if (tasks.empty()) return;
     LaunchRec r{};
     r.kind = kind;
+    r.flops = w.flops;
+    r.bytes = w.bytes;
     r.ntasks = (int)tasks.size();
     r.ta = ta; r.tb = tb;
     r.tasks_off = align(sizeof(T) * tasks.size());
@@ -98,22 +111,30 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
 
   // ---- EA --------------------------------------------------------------------------
   if (P->do_ea) {
-    std::vector<EaTask> t, tf;
-    std::vector<int> gx, nb, gxf, nbf;
-    for (size_t i = 0; i < P->f.size(); ++i) {
-      const kfac_factor_desc& F = P->f[i];
-      const FactorInfo& I = P->fi[i];
-      if (!I.ea) continue;
-      const bool xb = (F.xtype == KFAC_BF16);
-      EaTask q = make_ea_task(F.F, I.d, F.ldf, xb ? nullptr : (const float*)F.X, xb ? (const uint16_t*)F.X : nullptr,
-                              (int)F.n, (int)F.d_in, F.ldx, F.append_ones, P->rho, F.scale,
-                              F.F_bf16, F.ldfb, (float*)wsp(I.ea_off), I.ea_ks);
-      const int tiles = q.T * (q.T + 1) / 2;
-      t.push_back(q); gx.push_back(tiles); nb.push_back(tiles * I.ea_ks);
-      if (I.ea_ks > 1) { tf.push_back(q); gxf.push_back(tiles); nbf.push_back(tiles); }
+    // fp32 activations use the fp32-MFMA kernel, bf16 activations the bf16-MFMA one
+    for (int xb = 0; xb < 2; ++xb) {
+      std::vector<EaTask> t, tf;
+      std::vector<int> gx, nb, gxf, nbf;
+      Work wt, wf;
+      for (size_t i = 0; i < P->f.size(); ++i) {
+        const kfac_factor_desc& F = P->f[i];
+        const FactorInfo& I = P->fi[i];
+        if (!I.ea || (F.xtype == KFAC_BF16) != (xb == 1)) continue;
+        EaTask q = make_ea_task(F.F, I.d, F.ldf, xb ? nullptr : (const float*)F.X,
+                                xb ? (const uint16_t*)F.X : nullptr, (int)F.n, (int)F.d_in, F.ldx,
+                                F.append_ones, P->rho, F.scale, F.F_bf16, F.ldfb, (float*)wsp(I.ea_off), I.ea_ks);
+        const int tiles = q.T * (q.T + 1) / 2;
+        t.push_back(q); gx.push_back(tiles); nb.push_back(tiles * I.ea_ks);
+        if (I.ea_ks > 1) { tf.push_back(q); gxf.push_back(tiles); nbf.push_back(tiles); }
+        // sums over the upper triangle; F: upper half read, full F written (+ bf16 shadow)
+        const double d = I.d, n = (double)F.n;
+        const Work x{n * d * (d + 1), n * (double)F.d_in * (xb ? 2 : 4)};
+        const Work f{0, 4 * d * (d + 1) / 2 + 4 * d * d + (F.F_bf16 ? 2 * d * d : 0)};
+        if (I.ea_ks > 1) { wt += x; wf += f; } else { wt += x; wt += f; }
+      }
+      T.add(xb ? K_EA_TILES_BF : K_EA_TILES, t, gx, nb, false, false, wt);
+      T.add(xb ? K_EA_FIN_BF : K_EA_FIN, tf, gxf, nbf, false, false, wf);
     }
-    T.add(K_EA_TILES, t, gx, nb);
-    T.add(K_EA_FIN, tf, gxf, nbf);
   }
   if (P->do_eig) {
     // ---- randomized range finder with CholeskyQR2 -----------------------------------
@@ -124,14 +145,16 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
     if (!rnd.empty()) {
       std::vector<OmegaTask> om;
       std::vector<int> gx, nb;
+      Work wo;
       for (int i : rnd) {
         const FactorInfo& I = P->fi[i];
+        wo += Work{0, (double)I.l * I.d * (bf ? 6 : 4)};
         OmegaTask q = make_omega_task(I.d, I.l, I.d, I.l_pad, P->seed, P->f[i].stream_id, P->inv, W[i].OmT, I.ldt,
                                       bf ? W[i].OmTb : nullptr, nullptr, 0, nullptr);
         dim3 g = omega_grid(q);
         om.push_back(q); gx.push_back((int)g.x); nb.push_back((int)(g.x * g.y));
       }
-      T.add(K_OMEGA, om, gx, nb);
+      T.add(K_OMEGA, om, gx, nb, false, false, wo);
       for (int i : rnd) { basis[i] = W[i].Yt; spare[i] = W[i].Qt; }
       const int qmax = [&] { int m = 0; for (int i : rnd) m = std::max(m, P->fi[i].q); return m; }();
       for (int it = 0; it <= qmax; ++it) {
@@ -140,6 +163,11 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
         std::vector<int> act;
         for (int i : rnd) if (it <= P->fi[i].q) act.push_back(i);
         if (act.empty()) break;
+        Work ws;
+        for (int i : act) {
+          const double l = P->fi[i].l, d = P->fi[i].d;
+          ws += bf ? Work{2 * l * d * d, 2 * d * d + 2 * l * d + 4 * l * d} : gemm_work(l, d, d, false);
+        }
         if (bf) {
           std::vector<BfGemmTask> g;
           std::vector<int> gx2, nb2;
@@ -150,7 +178,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             BfGemmTask q = make_bf16_task(I.l_pad, I.d, I.d, A, I.ldt, P->f[i].F_bf16, P->f[i].ldfb, out, I.ldt);
             g.push_back(q); gx2.push_back(bf16_task_blocks(q)); nb2.push_back(bf16_task_blocks(q));
           }
-          T.add(K_BF16, g, gx2, nb2);
+          T.add(K_BF16, g, gx2, nb2, false, false, ws);
         } else {
           std::vector<GemmP> g;
           std::vector<int> gx2, nb2;
@@ -164,7 +192,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             q.alpha = 1.f; q.ones_col = -1;
             g.push_back(q); gx2.push_back(gemm_g_blocks_x(q)); nb2.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
           }
-          T.add(K_GEMM, g, gx2, nb2, false, false);
+          T.add(K_GEMM, g, gx2, nb2, false, false, ws);
         }
         if (it > 0) for (int i : act) std::swap(basis[i], spare[i]);
         // CholeskyQR2 on basis[i]: pass 0 basis -> spare, pass 1 spare -> basis
@@ -173,8 +201,14 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           std::vector<CholInvTask> ch;
           std::vector<TrmmTask> tm;
           std::vector<int> gxg, nbg, gxr, nbr, gxc, nbc, gxt, nbt;
+          Work wg, wr, wc, wm;
           for (int i : act) {
             const FactorInfo& I = P->fi[i];
+            const double l = I.l, d = I.d;
+            wg += Work{l * (l + 1) * d, 4 * l * d};
+            wr += Work{0, 8 * l * l};
+            wc += Work{2 * l * l * l / 3, 16 * l * l};
+            wm += Work{l * (l + 1) * d, 8 * l * d + 8 * l * l / 2 + ((bf && pass == 1) ? 2 * l * d : 0)};
             float* src = pass == 0 ? basis[i] : spare[i];
             float* dst = pass == 0 ? spare[i] : basis[i];
             GramP g = make_gram_task(src, I.ldt, src, I.ldt, I.l_pad, I.d, 1, W[i].part, W[i].G, I.l_pad, status);
@@ -188,12 +222,12 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             const int bx = trmm_blocks_x(I.d), by = trmm_blocks_y(I.l_pad);
             tm.push_back(tt); gxt.push_back(bx); nbt.push_back(bx * by);
           }
-          T.add(K_GRAM_P, gp, gxg, nbg);
-          T.add(K_GRAM_R, gp, gxr, nbr);
-          T.add(K_CHOLINV, ch, gxc, nbc);
+          T.add(K_GRAM_P, gp, gxg, nbg, false, false, wg);
+          T.add(K_GRAM_R, gp, gxr, nbr, false, false, wr);
+          T.add(K_CHOLINV, ch, gxc, nbc, false, false, wc);
           for (auto& c : ch) c.attempt = 1;
-          T.add(K_CHOLINV, ch, gxc, nbc);
-          T.add(K_TRMM, tm, gxt, nbt);
+          T.add(K_CHOLINV, ch, gxc, nbc);   // re-run only where attempt 0 broke down
+          T.add(K_TRMM, tm, gxt, nbt, false, false, wm);
         }
       }
       // Rayleigh-Ritz: W = F Q (fp32) into spare, C = Q^T W (fp64) into G
@@ -201,8 +235,13 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       std::vector<int> gx2, nb2;
       std::vector<GramP> gp;
       std::vector<int> gxg, nbg, gxr, nbr;
+      Work wrr, wg, wr;
       for (int i : rnd) {
         const FactorInfo& I = P->fi[i];
+        const double l = I.l, d = I.d;
+        wrr += gemm_work(l, d, d, false);
+        wg += Work{2 * l * l * d, 8 * l * d};
+        wr += Work{0, 8 * l * l};
         GemmP q{};
         q.M = I.l_pad; q.N = I.d; q.K = I.d;
         q.A = basis[i]; q.lda = I.ldt; q.B = P->f[i].F; q.ldb = P->f[i].ldf;
@@ -214,16 +253,20 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
         gp.push_back(gr); gxg.push_back(tiles); nbg.push_back(tiles * gr.ksplit);
         gxr.push_back(tiles); nbr.push_back(tiles * gram_reduce_slices());
       }
-      T.add(K_GEMM, g, gx2, nb2, false, false);
-      T.add(K_GRAM_P, gp, gxg, nbg);
-      T.add(K_GRAM_R, gp, gxr, nbr);
+      T.add(K_GEMM, g, gx2, nb2, false, false, wrr);
+      T.add(K_GRAM_P, gp, gxg, nbg, false, false, wg);
+      T.add(K_GRAM_R, gp, gxr, nbr, false, false, wr);
     }
     // ---- small eigensolver (randomized: C = Q^T F Q; exact: F itself) --------------
     std::vector<EigTask> et;
     std::vector<int> one, onen, gxb, nbb, gxv, nbv, gxbt, nbbt;
+    Work wtri, wbt;
     for (size_t i = 0; i < P->f.size(); ++i) {
       const FactorInfo& I = P->fi[i];
       const kfac_factor_desc& F = P->f[i];
+      const double n = I.l, r = I.r;
+      wtri += Work{4 * n * n * n / 3, 8 * n * n + 16 * n};   // Householder tridiagonalisation
+      wbt += Work{2 * n * n * r, 8 * n * r + 4 * n * r};    // back-transformation of r vectors
       EigTask q;
       if (I.exact)
         q = make_eig_task(nullptr, 0, F.F, F.ldf, I.d, I.d, I.r, W[i].A, W[i].V, W[i].diag, W[i].off, W[i].Z,
@@ -237,53 +280,63 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       gxv.push_back(tri_vec_blocks(q.r)); nbv.push_back(tri_vec_blocks(q.r));
       gxbt.push_back(backtransform_blocks(q.r)); nbbt.push_back(backtransform_blocks(q.r));
     }
-    T.add(K_TRIDIAG, et, one, onen);
+    T.add(K_TRIDIAG, et, one, onen, false, false, wtri);
     T.add(K_PREP, et, one, onen);
     T.add(K_BISECT, et, gxb, nbb);
     T.add(K_SELECT, et, one, onen);
     T.add(K_VEC, et, gxv, nbv);
     T.add(K_CLEAD, et, one, onen);
     T.add(K_CLUSTER, et, one, onen);
-    T.add(K_BT, et, gxbt, nbbt);
+    T.add(K_BT, et, gxbt, nbbt, false, false, wbt);
     // ---- Ritz vectors U = Q P[:, :r] --------------------------------------------------
     {
       std::vector<GemmP> g;
       std::vector<int> gx2, nb2;
+      Work wu;
       for (int i : rnd) {
         const FactorInfo& I = P->fi[i];
+        wu += gemm_work(I.d, I.r, I.l, false);
         GemmP q{};
         q.M = I.d; q.N = I.r; q.K = I.l;
         q.A = basis[i]; q.lda = I.ldt; q.B = W[i].P; q.ldb = I.r;
         q.C = P->f[i].U; q.ldc = P->f[i].ldu; q.alpha = 1.f; q.ones_col = -1;
         g.push_back(q); gx2.push_back(gemm_g_blocks_x(q)); nb2.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
       }
-      T.add(K_GEMM, g, gx2, nb2, true, false);
+      T.add(K_GEMM, g, gx2, nb2, true, false, wu);
     }
     // ---- column signs -------------------------------------------------------------------
     {
       std::vector<SignTask> st;
       std::vector<int> gx2, nb2;
+      Work wsp, wsa;
       for (size_t i = 0; i < P->f.size(); ++i) {
         const FactorInfo& I = P->fi[i];
+        wsp += Work{0, 4.0 * I.d * I.r};
+        wsa += Work{0, 8.0 * I.d * I.r};
         SignTask s{P->f[i].U, P->f[i].ldu, I.d, I.r, W[i].sval, W[i].sidx, sign_chunks(I.d)};
         st.push_back(s);
         const int bx = (I.r + 63) / 64;
         gx2.push_back(bx); nb2.push_back(bx * sign_chunks(I.d));
       }
-      T.add(K_SIGN_P, st, gx2, nb2);
-      T.add(K_SIGN_A, st, gx2, nb2);
+      T.add(K_SIGN_P, st, gx2, nb2, false, false, wsp);
+      T.add(K_SIGN_A, st, gx2, nb2, false, false, wsa);
     }
   }
   // ---- damped inverse per layer -----------------------------------------------------------
   if (P->do_pre && !P->lyr.empty()) {
     std::vector<GemmP> g1, g2, g3, g4;
     std::vector<int> x1, n1, x2, n2, x3, n3, x4, n4;
+    Work w1, w2, w3, w4;
     const float inv_lam = 1.0f / P->lam;
     for (size_t l = 0; l < P->lyr.size(); ++l) {
       const kfac_layer_desc& L = P->lyr[l];
       const kfac_factor_desc& A = P->f[L.fa];
       const kfac_factor_desc& G = P->f[L.fg];
       const int dg = (int)G.d, da = (int)A.d, ra = (int)A.r, rg = (int)G.r;
+      w1 += gemm_work(dg, ra, da, false);
+      w2 += gemm_work(dg, da, ra, true);
+      w3 += gemm_work(rg, da, dg, false);
+      w4 += gemm_work(dg, da, rg, true);
       Bump b(wsp(P->li[l].off));
       float* T1 = b.take<float>((size_t)dg * ra);
       float* M = b.take<float>((size_t)dg * da);
@@ -309,10 +362,10 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       sq.X = M; sq.ldx = da; sq.beta = inv_lam;
       push(g4, x4, n4, sq);
     }
-    T.add(K_GEMM, g1, x1, n1, false, false);
-    T.add(K_GEMM, g2, x2, n2, false, true);
-    T.add(K_GEMM, g3, x3, n3, true, false);
-    T.add(K_GEMM, g4, x4, n4, false, false);
+    T.add(K_GEMM, g1, x1, n1, false, false, w1);
+    T.add(K_GEMM, g2, x2, n2, false, true, w2);
+    T.add(K_GEMM, g3, x3, n3, true, false, w3);
+    T.add(K_GEMM, g4, x4, n4, false, false, w4);
   }
 }
 
@@ -361,8 +414,9 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
     EigWs w(F.d, F.r, F.p, bf, nullptr);
     I.ws_bytes = w.bytes;
     I.ws_off = take(w.bytes);
-    I.ea_ks = I.ea ? ea_choose_ksplit(I.d, F.n) : 1;
-    I.ea_bytes = (I.ea && I.ea_ks > 1) ? ea_workspace_bytes(I.d, F.n) : 0;
+    const bool xb = (F.xtype == KFAC_BF16);
+    I.ea_ks = I.ea ? ea_choose_ksplit(I.d, F.n, xb) : 1;
+    I.ea_bytes = (I.ea && I.ea_ks > 1) ? ea_workspace_bytes(I.d, F.n, xb) : 0;
     I.ea_off = take(I.ea_bytes + 16);
     P->fi.push_back(I);
   }
@@ -414,12 +468,19 @@ kfac_status kfac_plan_upload(kfac_plan* plan, void* workspace, size_t ws_bytes, 
 int kfac_plan_launch_count(const kfac_plan* plan) { return plan ? (int)plan->tab.recs.size() : 0; }
 
 const char* kfac_plan_launch_name(const kfac_plan* plan, int index) {
-  static const char* names[] = {"ea_tiles", "ea_finalize", "omega", "gemm_f32", "gemm_bf16", "gram_partial",
+  static const char* names[] = {"ea_tiles", "ea_finalize", "ea_tiles_bf16", "ea_finalize_bf16", "omega", "gemm_f32", "gemm_bf16", "gram_partial",
                                 "gram_reduce", "cholinv", "trmm", "tridiag", "tri_prep", "tri_bisect",
                                 "tri_select", "tri_vec", "tri_cluster_lead", "tri_cluster", "backtransform",
                                 "sign_partial", "sign_apply"};
   if (!plan || index < 0 || index >= (int)plan->tab.recs.size()) return nullptr;
   return names[plan->tab.recs[index].kind];
+}
+
+kfac_status kfac_plan_launch_work(const kfac_plan* plan, int index, double* flops, double* bytes) {
+  if (!plan || !flops || !bytes || index < 0 || index >= (int)plan->tab.recs.size()) return KFAC_EINVAL;
+  *flops = plan->tab.recs[index].flops;
+  *bytes = plan->tab.recs[index].bytes;
+  return KFAC_OK;
 }
 
 kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, kfac_stream_t stream) {
@@ -435,6 +496,8 @@ kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, 
     switch (r.kind) {
       case K_EA_TILES: e = launch_ea_tiles_g((const EaTask*)tp, gm, r.blocks, s); break;
       case K_EA_FIN: e = launch_ea_finalize_g((const EaTask*)tp, gm, r.blocks, s); break;
+      case K_EA_TILES_BF: e = launch_ea_bf16_tiles_g((const EaTask*)tp, gm, r.blocks, s); break;
+      case K_EA_FIN_BF: e = launch_ea_bf16_finalize_g((const EaTask*)tp, gm, r.blocks, s); break;
       case K_OMEGA: e = launch_omega_g((const OmegaTask*)tp, gm, r.blocks, s); break;
       case K_GEMM: e = launch_gemm_g((const GemmP*)tp, gm, r.blocks, r.ta, r.tb, s); break;
       case K_BF16: e = launch_gemm_bf16_g((const BfGemmTask*)tp, gm, r.blocks, s); break;

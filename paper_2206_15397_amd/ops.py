@@ -84,7 +84,7 @@ def rand_eig(F: torch.Tensor, r: int, p: int, q: int, seed: int, stream_id: int 
     d = F.shape[0]
     prec = _lib.KFAC_SKETCH_BF16 if sketch == "bf16" else _lib.KFAC_SKETCH_FP32
     if prec == _lib.KFAC_SKETCH_BF16 and F_bf16 is None:
-        F_bf16 = F.to(torch.bfloat16)
+        F_bf16 = bf16_shadow(F)
     if U is None:
         U = torch.empty((d, r), dtype=torch.float32, device=F.device)
     if D is None:
@@ -122,6 +122,17 @@ def precondition(J: torch.Tensor, Ua: torch.Tensor, Da: torch.Tensor, Ug: torch.
     return S
 
 
+def bf16_shadow(F: torch.Tensor) -> torch.Tensor:
+    """bf16 copy of F whose row pitch is a multiple of 64 elements (128 bytes), so the
+    bf16 sketch kernels read it with aligned 16-byte loads."""
+    d = F.shape[0]
+    ld = (F.shape[1] + 63) // 64 * 64
+    buf = torch.empty((d, ld), dtype=torch.bfloat16, device=F.device)
+    out = buf[:, :F.shape[1]]
+    out.copy_(F)
+    return out
+
+
 class Plan:
     """Grouped K-factor step over many factors and layers (kfac_plan_* in the C ABI).
 
@@ -146,7 +157,7 @@ class Plan:
             r = int(f["r"])
             _require_cuda(F)
             if prec == _lib.KFAC_SKETCH_BF16 and f.get("F_bf16") is None:
-                f["F_bf16"] = F.to(torch.bfloat16)
+                f["F_bf16"] = bf16_shadow(F)
             f.setdefault("U", torch.empty((d, r), dtype=torch.float32, device=dev))
             f.setdefault("D", torch.empty((r,), dtype=torch.float32, device=dev))
             x = f.get("X")
@@ -199,6 +210,14 @@ class Plan:
 
     def launch_range(self, first, count):
         check("kfac_plan_launch_range", self._L.kfac_plan_launch_range(self._h, int(first), int(count), _stream()))
+
+    def launch_work(self, index):
+        """(flops, bytes) of launch `index`: algorithmic work over all its tasks."""
+        import ctypes
+        f, b = ctypes.c_double(), ctypes.c_double()
+        check("kfac_plan_launch_work", self._L.kfac_plan_launch_work(self._h, int(index), ctypes.byref(f),
+                                                                     ctypes.byref(b)))
+        return f.value, b.value
 
     def launch_names(self):
         return [self._L.kfac_plan_launch_name(self._h, i).decode() for i in range(self.launch_count)]

@@ -77,9 +77,12 @@ def test_ea_update(d, n, ones, dtype):
     assert torch.equal(Fb, F.to(torch.bfloat16))
 
 
-def test_ea_update_no_workspace_matches_split():
-    d, n = 100, 20000
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_ea_update_no_workspace_matches_split(dtype):
+    d, n = 300, 20000
     X = torch.randn((n, d - 1), device=DEV, generator=torch.Generator(DEV).manual_seed(0))
+    if dtype == "bf16":
+        X = X.to(torch.bfloat16)
     F1 = K().fill_identity(torch.empty((d, d), device=DEV))
     F2 = F1.clone()
     K().ea_update(F1, X, 0.9, 1.0 / n, append_ones=True)
@@ -90,6 +93,22 @@ def test_ea_update_no_workspace_matches_split():
     K().ea_update(F3, X, 0.9, 1.0 / n, append_ones=True)
     torch.cuda.synchronize()
     assert torch.equal(F1, F3)   # deterministic: bitwise identical reruns
+
+
+@pytest.mark.parametrize("d_in,n,offset", [(576, 3000, 1), (1152, 777, 0), (27, 4100, 3), (64, 64, 8)])
+def test_ea_update_bf16_strided_views(d_in, n, offset):
+    """bf16 activations given as column-offset views of a wider buffer: misaligned rows
+    take the element-wise load path, aligned ones the 16-byte path; same result."""
+    rng = np.random.default_rng(d_in + n)
+    W = torch.from_numpy(rng.standard_normal((n, d_in + offset + 5)).astype(np.float32)).to(DEV)
+    Xv = W.to(torch.bfloat16)[:, offset:offset + d_in]
+    d = d_in + 1
+    F0 = synth.psd_factor(d, synth.power_spectrum(d), 4).astype(np.float32) + np.eye(d, dtype=np.float32)
+    F = torch.from_numpy(F0).to(DEV)
+    K().ea_update(F, Xv, 0.95, 1.0 / n, append_ones=True)
+    torch.cuda.synchronize()
+    Fo = O.ea_update(F0.astype(np.float64), to_np(Xv), 0.95, 1.0 / n, append_ones=True)
+    assert rel(to_np(F), Fo) <= 1e-5
 
 
 # --------------------------------------------------------------------------------------
