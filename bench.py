@@ -286,7 +286,8 @@ KIND = {
     "ea_tiles_bf16": ("bf16", "mfma"), "gemm_bf16": ("bf16", "mfma"),
     "ea_tiles": ("fp32", "mfma"), "gemm_f32": ("fp32", "mfma"),
     "gram_partial": ("fp64", "mfma"), "trmm": ("fp64", "mfma"),
-    "cholinv": ("fp64", "alu"), "tridiag": ("fp64", "alu"), "backtransform": ("fp64", "alu"),
+    "cholinv": ("fp64", "alu"), "trtri_cols": ("fp64", "mfma"),
+    "tridiag": ("fp64", "alu"), "backtransform": ("fp64", "alu"),
 }
 
 

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <utility>
+#include <type_traits>
 
 namespace kfac {
 
@@ -70,5 +72,16 @@ __device__ __forceinline__ void gaussian4(uint32_t row, uint32_t group, uint32_t
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1.  Register arrays
+// indexed with the constant stay in registers (no dynamic indexing, no scratch).
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 }  // namespace kfac

@@ -43,8 +43,8 @@ hipError_t launch_gram(const float* A, long lda, const float* B, long ldb, int L
                        double* part, double* C, long ldc, int* status, hipStream_t s);
 hipError_t launch_cholesky(const double* G, long ldg, int n, long m_rows, double* W, long ldw, double* Li,
                            int* status, int* fail_flag, hipStream_t s);
-constexpr int kCholInvMax = 288;   // fused Cholesky-inverse path handles n <= this
-hipError_t launch_cholinv(const double* G, long ldg, int n, long m_rows, double* Linv, long ldl, int l_pad,
+constexpr int kCholInvMax = 288;   // blocked Cholesky-inverse path handles l_pad <= this
+hipError_t launch_cholinv(double* G, long ldg, int n, long m_rows, double* Linv, long ldl, int l_pad, double* dsave,
                           int* status, int* fail_flag, hipStream_t s);
 hipError_t launch_trmm(const double* Li, long ldl, int n, const float* Yt, long ldy, int ncols, float* Qt, long ldq,
                        uint16_t* Qtb, long ldqb, int l_pad, hipStream_t s);
@@ -96,6 +96,8 @@ hipError_t launch_gemm_bf16_g(const BfGemmTask* t, GroupMap gm, int blocks, hipS
 hipError_t launch_gram_partial_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_gram_reduce_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_cholinv_g(const CholInvTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_trtri_cols_g(const CholInvTask* t, GroupMap gm, int blocks, hipStream_t s);
+int trtri_col_blocks(int l_pad);
 hipError_t launch_trmm_g(const TrmmTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_tridiag_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_tri_prep_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);

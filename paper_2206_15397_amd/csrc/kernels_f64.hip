@@ -313,317 +313,329 @@ __global__ __launch_bounds__(256) void k_trsm(const double* W, long ldw, const d
 }
 
 // ======================================================================================
-// Register-resident Cholesky for n <= 288 (1024 threads; same 32 x 32 thread grid and
-// 9 x 9 blocks of 32 as the tridiagonalisation).  Right-looking, one column per step:
-// the pivot owner publishes a_kk, the owners of column k scale it (l_ik = a_ik / l_kk,
-// written to W and LDS), every thread applies a_ij -= l_ik l_jk to its active slots.
-// Retried once with the shifted-CholeskyQR shift.  Afterwards the 16 x 16 diagonal
-// blocks of L are inverted in parallel (one wavefront per block) into Li.
+// Blocked Cholesky and inverse for l_pad <= 288.
+// Launch 1 (k_cholinv, one workgroup of 1024 threads per Gram, run as attempt 0 and then
+// attempt 1 = shifted retry only where attempt 0 broke down):
+//   G = L L^T; L overwrites the lower triangle of G in place (the strict upper triangle
+//   and a saved copy of the diagonal keep G for the retry).  Right-looking over 32-wide
+//   block columns K:
+//   (a) one wavefront factors the diagonal block (element (r, c) of the block lives in
+//       lane c + 32 (r mod 2), register r / 2; columns are broadcast through LDS) and
+//       inverts it the same way; X_KK = L_KK^{-1} goes to the output;
+//   (b) panel  L_IK = A_IK X_KK^T               (fp64 MFMA, rows below the block);
+//   (c) update A_IJ -= L_IK L_JK^T, I >= J       (fp64 MFMA on the lower triangle of the
+//       trailing matrix; the panel is staged in LDS, the next tile is prefetched).
+// Launch 2 (k_trtri_cols, one workgroup per (Gram, block column K)): the off-diagonal
+//   blocks of X = L^{-1} down column K, X_IK = -X_II sum_{J=K}^{I-1} L_IJ X_JK, with the
+//   column panel of X in LDS.
+// Rows and columns >= n are treated as identity (and are zero in X).  The shift follows
+// shifted CholeskyQR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yamazaki 2020):
+// s = 11 (m l + l (l + 1)) u ||Y||_2^2, with ||Y||_2^2 bounded by trace(G).
+// Output X (l_pad x l_pad, zero above the diagonal and outside n x n).
 // ======================================================================================
-constexpr int RB = 32, RNB = 9, RNMAX = RB * RNB;
+constexpr int BC = 16, BC_NT = 1024, TT_NT = 256;
+constexpr int BC_RG = 64 / BC;            // row groups of the factoring wavefront
+constexpr int BC_RT = BC / BC_RG;         // block rows per lane
+static_assert(BC % 16 == 0 && BC_RT * BC_RG == BC, "block shape");
 
-__device__ __forceinline__ constexpr int rslot(int I, int J) { return I * (I + 1) / 2 + J; }
-
-__device__ void invert_diag_blocks(const double* W, long ldw, int n, double* Li) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int nblk = (n + CH_NB - 1) / CH_NB;
-  const int i = lane & (CH_NB - 1);
-  for (int b = wave; b < nblk; b += nw) {
-    const int kb = b * CH_NB, nbk = min(CH_NB, n - kb);
-    double row[CH_NB];
-    _Pragma("clang loop unroll(full)")
-    for (int j = 0; j < CH_NB; ++j) {
-      double v = (i == j) ? 1.0 : 0.0;
-      if (i < nbk && j < nbk && j <= i) v = W[(long)(kb + i) * ldw + kb + j];
-      row[j] = v;
-    }
-    double xc[CH_NB];
-    _Pragma("clang loop unroll(full)")
-    for (int j = 0; j < CH_NB; ++j) xc[j] = (i == j) ? 1.0 : 0.0;
-    _Pragma("clang loop unroll(full)")
-    for (int j = 0; j < CH_NB; ++j) {
-      _Pragma("clang loop unroll(full)")
-      for (int sr = j; sr < CH_NB; ++sr) {
-        if (i == sr) xc[j] = xc[j] / row[sr];
-        const double xs = __shfl(xc[j], sr, 64);
-        if (i > sr) xc[j] -= row[sr] * xs;
-      }
-    }
-    if (lane < CH_NB) {
-      _Pragma("clang loop unroll(full)")
-      for (int j = 0; j < CH_NB; ++j) Li[(long)b * CH_NB * CH_NB + i * CH_NB + j] = xc[j];
-    }
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_cholesky_reg(const double* G, long ldg, int n, long m_rows, double* W,
-                                                       long ldw, double* Li, int* status, int* fail_flag) {
-  __shared__ double scol[RNMAX];
-  __shared__ double spiv;
-  __shared__ double strace;
-  __shared__ int sfail;
-  const int t = threadIdx.x, tr = t >> 5, tc = t & 31, lane = t & 63, wave = t >> 6;
-  if (wave == 0) {
-    double s = 0.0;
-    for (int i = lane; i < n; i += 64) s += G[(long)i * ldg + i];
-    s = wave_sum(s);
-    if (lane == 0) strace = s;
-  }
-  __syncthreads();
-  const double shift = 11.0 * ((double)m_rows * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * strace;
-  double a[45];
-  int failed = 0;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-#pragma unroll
-    for (int I = 0; I < RNB; ++I)
-#pragma unroll
-      for (int J = 0; J <= I; ++J) {
-        const int i = RB * I + tr, j = RB * J + tc;
-        double v = 0.0;
-        if (i < n && j < n && (I != J || tr >= tc)) {
-          v = G[(long)i * ldg + j];
-          if (attempt == 1 && i == j) v += shift;
-        }
-        a[rslot(I, J)] = v;
-      }
-    if (t == 0) { spiv = a[0]; sfail = 0; }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-      const double piv = spiv;
-      if (!(piv > 0.0) || !isfinite(piv)) { if (t == 0) sfail = 1; break; }   // uniform
-      const double lkk = sqrt(piv), inv = 1.0 / lkk;
-      const int J0 = k >> 5, c0 = k & 31;
-      if (tc == c0) {
-#pragma unroll
-        for (int I = 0; I < RNB; ++I)
-#pragma unroll
-          for (int J = 0; J <= I; ++J)
-            if (J == J0) {
-              const int i = RB * I + tr;
-              if (i == k) {
-                a[rslot(I, J)] = lkk;
-                W[(long)k * ldw + k] = lkk;
-              } else if (i > k && i < n) {
-                const double l = a[rslot(I, J)] * inv;
-                a[rslot(I, J)] = l;
-                scol[i] = l;
-                W[(long)i * ldw + k] = l;
-              }
-            }
-      }
-      __syncthreads();
-      const int kb = (k + 1) >> 5;
-#pragma unroll
-      for (int J = 0; J < RNB; ++J) {
-        if (J >= kb) {
-          const int j = RB * J + tc;
-          const double lj = (j > k && j < n) ? scol[j] : 0.0;
-#pragma unroll
-          for (int I = J; I < RNB; ++I) {
-            const int i = RB * I + tr;
-            const double li = (i > k && i < n) ? scol[i] : 0.0;
-            if (I != J || tr >= tc) a[rslot(I, J)] -= li * lj;
-          }
-        }
-      }
-      // publish the next pivot
-      const int k1 = k + 1;
-      if (k1 < n && tr == (k1 & 31) && tc == (k1 & 31)) {
-#pragma unroll
-        for (int I = 0; I < RNB; ++I)
-          if (I == (k1 >> 5)) spiv = a[rslot(I, I)];
-      }
-      __syncthreads();
-    }
-    __syncthreads();
-    failed = sfail;
-    if (!failed) break;
-    if (t == 0) atomicOr(status, attempt == 0 ? KFAC_DS_CHOL_SHIFTED : KFAC_DS_CHOL_FAILED);
-    __syncthreads();
-  }
-  if (t == 0) *fail_flag = failed;
-  __syncthreads();
-  invert_diag_blocks(W, ldw, n, Li);
-}
-
-// ======================================================================================
-// Fused Cholesky and inverse for n <= 288 (one workgroup of 1024 threads):
-//   G = L L^T  and  X = L^{-1}, computed in place in one lower triangle M.
-// Right-looking over k: with l_kk = sqrt(M_kk),
-//   column k (rows i > k):  l_ik = M_ik / l_kk,   M_ik <- -l_ik / l_kk      (= X_ik)
-//   row k (cols j < k):     M_kj <- M_kj / l_kk (= X_kj),   M_kk <- 1 / l_kk
-//   rows i > k, j != k:     M_ij -= l_ik u_j,  u_j = l_jk (j > k) or X_kj (j < k)
-// so columns > k hold the trailing Cholesky matrix and columns <= k hold the rows of
-// L^{-1} built by forward substitution of L X = I.  Thread grid 32 x 32 over 9 x 9
-// blocks of 32: off-diagonal blocks in registers, diagonal blocks in LDS.  Retried
-// once with the shifted-CholeskyQR shift.  Output Linv (l_pad x l_pad, zero above the
-// diagonal and outside n x n).
-// ======================================================================================
-constexpr int CB = 32, CNB = 9, CNMAX = CB * CNB;
-
-__device__ __forceinline__ constexpr int oslot(int I, int J) { return I * (I - 1) / 2 + J; }   // I > J
-
-struct CholSh {
-  double (*Ld)[CB][CB + 1];
-  double* sl;
-  double* su;
-  double* spiv;
-  int* sfail;
+struct BcSmem {
+  double P[288][BC + 1];          // panel of block column K (absolute rows)
+  double X[BC][BC + 1];           // inverse of the current diagonal block
+  double L[BC][BC + 1];           // the current diagonal block of L
+  double col[BC];                 // column broadcast inside the factoring wavefront
+  double shift;
+  int fail;
 };
 
-// Columns k = 32 K0 + c0 of block column K0 (compile-time).
-template <int K0>
-__device__ __forceinline__ void cholinv_block_col(double (&a)[36], const CholSh& S, int n) {
-  const int t = threadIdx.x, tr = t >> 5, tc = t & 31;
-  double (*Ld)[CB][CB + 1] = S.Ld;
-  double* sl = S.sl;
-  double* su = S.su;
-  if (CB * K0 >= n || *S.sfail) return;                    // uniform
-  for (int c0 = 0; c0 < CB; ++c0) {
-    const int k = CB * K0 + c0;
-    if (k >= n) break;                                      // uniform
-    const double piv = *S.spiv;
-    if (!(piv > 0.0) || !isfinite(piv)) { if (t == 0) *S.sfail = 1; break; }   // uniform
-    const double lkk = sqrt(piv), inv = 1.0 / lkk;
-    // (A) column k below the diagonal (l_ik, then X_ik = -l_ik / l_kk) and row k
-    if (tc == c0) {
-      {
-        const int i = CB * K0 + tr;
-        if (i > k && i < n) { const double l = Ld[K0][tr][tc] * inv; sl[i] = l; Ld[K0][tr][tc] = -l * inv; }
-      }
-#pragma unroll
-      for (int I = K0 + 1; I < CNB; ++I) {
-        const int i = CB * I + tr;
-        if (i < n) {
-          const double l = a[oslot(I, K0)] * inv;
-          sl[i] = l;
-          a[oslot(I, K0)] = -l * inv;
-        }
-      }
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// (a) for block K (wavefront 0 only).  Element (r, c) of the block is handled by lane
+// c + BC (r mod BC_RG) (slot r / BC_RG); pivots and columns are broadcast through LDS and
+// the loops over pivots stay rolled, so only BC_RT values per lane are live.
+// Returns false on a non-positive or non-finite pivot (uniform over the wavefront).
+__device__ __forceinline__ bool bc_diag_block(double* G, long ldg, int n, int K, double* Xo, long ldx, BcSmem& sm) {
+  const int lane = threadIdx.x & 63;
+  const int k0 = K * BC;
+  // The lane split goes through an opaque move so that lane-dependent addresses and
+  // predicates are recomputed at each call instead of being hoisted out of the caller's
+  // loop over K (hoisted, they stay live across the factorisation and spill).
+  int c, rg;
+  asm volatile("v_and_b32 %0, %2, %1" : "=v"(c) : "v"(lane), "i"(BC - 1));
+  asm volatile("v_lshrrev_b32 %0, %2, %1" : "=v"(rg) : "v"(lane), "i"(__builtin_ctz(BC)));
+  double d[BC_RT];                                    // d[t] = block element (rg + BC_RG t, c)
+  static_for<BC_RT>([&](auto T) {
+    constexpr int t = T;
+    const int r = rg + BC_RG * t;
+    double v = (r == c) ? 1.0 : 0.0;
+    if (c <= r && k0 + r < n && k0 + c < n) v = G[(long)(k0 + r) * ldg + k0 + c];
+    d[t] = v;
+  });
+  bool ok = true;
+  for (int j = 0; j < BC; ++j) {
+    // publish column j, read the pivot
+    if (c == j) static_for<BC_RT>([&](auto T) { sm.col[rg + BC_RG * T] = d[T]; });
+    wave_lds_order();
+    const double piv = sm.col[j];
+    if (!(piv > 0.0) || !isfinite(piv)) { ok = false; break; }   // uniform
+    const double ljj = sqrt(piv), inv = 1.0 / ljj;
+    wave_lds_order();
+    // scale column j (one lane per row) and publish it
+    if (lane < BC) {
+      const double v = sm.col[lane];
+      const double l = (lane == j) ? ljj : ((lane > j) ? v * inv : 0.0);
+      wave_lds_order();
+      sm.col[lane] = l;
     }
-    if (tr == c0) {
-#pragma unroll
-      for (int J = 0; J < K0; ++J) {
-        const double x = a[oslot(K0, J)] * inv;
-        su[CB * J + tc] = x;
-        a[oslot(K0, J)] = x;
-      }
-      const int j = CB * K0 + tc;
-      if (j < k) { const double x = Ld[K0][tr][tc] * inv; su[j] = x; Ld[K0][tr][tc] = x; }
-      else if (j == k) Ld[K0][tr][tc] = inv;
-    }
-    __syncthreads();
-    // (B) rows i > k:  M_ij -= l_ik u_j,  u_j = l_jk (j > k) or X_kj (j < k), u_k = 0
-#pragma unroll
-    for (int I = K0; I < CNB; ++I) {
-      const int i = CB * I + tr;
-      const double li = (i > k && i < n) ? sl[i] : 0.0;
-      {
-        const int j = CB * I + tc;
-        const double uj = (j > k && j < n) ? sl[j] : ((j < k) ? su[j] : 0.0);
-        if (tr >= tc) Ld[I][tr][tc] -= li * uj;
-      }
-#pragma unroll
-      for (int J = 0; J < I; ++J) {
-        const int j = CB * J + tc;
-        const double uj = (j > k && j < n) ? sl[j] : ((j < k) ? su[j] : 0.0);
-        a[oslot(I, J)] -= li * uj;
-      }
-    }
-    __syncthreads();
-    const int k1 = k + 1;
-    if (t == 0 && k1 < n) *S.spiv = Ld[k1 >> 5][k1 & 31][k1 & 31];
-    __syncthreads();
+    wave_lds_order();
+    const double lcj = sm.col[c];
+    double lrj[BC_RT];
+    static_for<BC_RT>([&](auto T) { lrj[T] = sm.col[rg + BC_RG * T]; });
+    static_for<BC_RT>([&](auto T) {
+      constexpr int t = T;
+      const int r = rg + BC_RG * t;
+      if (c == j) d[t] = lrj[t];                             // column j is final
+      else d[t] -= lrj[t] * ((c > j && r >= c) ? lcj : 0.0);
+    });
+    wave_lds_order();
   }
+  if (!ok) return false;
+  // L_KK to G (lower part) and to LDS; X = I in LDS
+  static_for<BC_RT>([&](auto T) {
+    constexpr int t = T;
+    const int r = rg + BC_RG * t;
+    if (c <= r && k0 + r < n && k0 + c < n) G[(long)(k0 + r) * ldg + k0 + c] = d[t];
+    sm.L[r][c] = (c <= r) ? d[t] : 0.0;
+    sm.X[r][c] = (r == c) ? 1.0 : 0.0;
+  });
+  wave_lds_order();
+  // X = L_KK^{-1} (solve L X = I one row of L at a time): X_k. /= l_kk, then
+  // X_r. -= l_rk X_k. for r > k
+  for (int k = 0; k < BC; ++k) {
+    const double xk = sm.X[k][c] / sm.L[k][k];
+    double lrk[BC_RT], xr[BC_RT];
+    static_for<BC_RT>([&](auto T) {
+      lrk[T] = sm.L[rg + BC_RG * T][k];
+      xr[T] = sm.X[rg + BC_RG * T][c];
+    });
+    wave_lds_order();
+    if (rg == 0) sm.X[k][c] = xk;
+    static_for<BC_RT>([&](auto T) {
+      constexpr int t = T;
+      const int r = rg + BC_RG * t;
+      if (r > k) sm.X[r][c] = xr[t] - lrk[t] * xk;
+    });
+    wave_lds_order();
+  }
+  static_for<BC_RT>([&](auto T) {
+    constexpr int t = T;
+    const int r = rg + BC_RG * t;
+    const bool in = (k0 + r < n && k0 + c < n && c <= r);
+    Xo[(long)(k0 + r) * ldx + k0 + c] = in ? sm.X[r][c] : 0.0;     // zero outside n x n
+  });
+  wave_lds_order();
+  static_for<BC_RT>([&](auto T) {
+    constexpr int t = T;
+    const int r = rg + BC_RG * t;
+    if (!(k0 + r < n && k0 + c < n && c <= r)) sm.X[r][c] = 0.0;
+  });
+  return true;
 }
 
-template <int... Ks>
-__device__ __forceinline__ void cholinv_all_cols(std::integer_sequence<int, Ks...>, double (&a)[36],
-                                                 const CholSh& S, int n) {
-  (cholinv_block_col<Ks>(a, S, n), ...);
+// Lower-triangle tile t of a T x T grid of tiles, row-major over I >= J.
+__device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  I = i;
+  J = t - i * (i + 1) / 2;
 }
 
-// attempt 0: plain Cholesky; attempt 1 (launched right after): returns at once unless
-// attempt 0 broke down, else retries with the shifted-CholeskyQR shift.
 __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
-  const double* G = q.G; const long ldg = q.ldg; const int n = q.n; const long m_rows = q.m_rows;
-  double* Linv = q.Linv; const long ldl = q.ldl; const int l_pad = q.l_pad;
-  int* status = q.status; int* fail_flag = q.fail_flag; const int attempt = q.attempt;
-  __shared__ double Ld[CNB][CB][CB + 1];
-  __shared__ double sl[CNMAX];
-  __shared__ double su[CNMAX];
-  __shared__ double spiv;
-  __shared__ double sshift;
-  __shared__ int sfail;
-  if (attempt == 1 && *fail_flag == 0) return;             // uniform
-  const int t = threadIdx.x, tr = t >> 5, tc = t & 31, lane = t & 63, wave = t >> 6;
-  if (attempt == 1) {
+  double* G = q.G; const long ldg = q.ldg; const int n = q.n;
+  double* X = q.Linv; const long ldx = q.ldl; const int l_pad = q.l_pad;
+  __shared__ BcSmem sm;
+  const int attempt = q.attempt;
+  if (attempt == 1 && *q.fail_flag == 0) return;             // uniform
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = BC_NT / 64;
+  const int NB = l_pad / BC;
+  // ---- set-up: save the diagonal (attempt 0) or restore G and shift it (attempt 1)
+  if (attempt == 0) {
+    for (int i = tid; i < n; i += BC_NT) q.dsave[i] = G[(long)i * ldg + i];
+    if (tid == 0) sm.shift = 0.0;
+  } else {
+    for (int e = tid; e < n * n; e += BC_NT) {
+      const int i = e / n, j = e % n;
+      if (i > j) G[(long)i * ldg + j] = G[(long)j * ldg + i];
+    }
     if (wave == 0) {
-      double sm = 0.0;
-      for (int i = lane; i < n; i += 64) sm += G[(long)i * ldg + i];
-      sm = wave_sum(sm);
-      if (lane == 0) sshift = 11.0 * ((double)m_rows * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * sm;
+      double tr = 0.0;
+      for (int i = lane; i < n; i += 64) tr += q.dsave[i];
+      tr = wave_sum(tr);
+      if (lane == 0) sm.shift = 11.0 * ((double)q.m_rows * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * tr;
     }
-  } else if (t == 0) {
-    sshift = 0.0;
+    __syncthreads();
+    for (int i = tid; i < n; i += BC_NT) G[(long)i * ldg + i] = q.dsave[i] + sm.shift;
+  }
+  if (tid == 0) sm.fail = 0;
+  // zero the strict upper block triangle of the output
+  for (int e = tid; e < l_pad * l_pad; e += BC_NT) {
+    const int i = e / l_pad, j = e % l_pad;
+    if (j / BC > i / BC) X[(long)i * ldx + j] = 0.0;
   }
   __syncthreads();
-  const double shift = sshift;
-  double a[36];
+  constexpr int CT = BC / 16;                                  // 16-column tiles per block
+  for (int K = 0; K < NB; ++K) {
+    const int k0 = K * BC, r0 = k0 + BC, m = l_pad - r0;
+    if (wave == 0) {
+      const bool ok = bc_diag_block(G, ldg, n, K, X, ldx, sm);
+      if (!ok && lane == 0) sm.fail = 1;
+    }
+    __syncthreads();
+    if (sm.fail) break;                                       // uniform
+    // (b) panel rows [r0, l_pad): L_iK = A_iK X_KK^T, 16 x 16 tiles
+    const int ptiles = (m / 16) * CT;
+    for (int t = wave; t < ptiles; t += nw) {
+      const int i0 = r0 + (t / CT) * 16, c0 = (t % CT) * 16;
+      const int ai = i0 + (lane & 15);
+      double a[BC / 4];
 #pragma unroll
-  for (int I = 0; I < CNB; ++I) {
-    const int i = CB * I + tr;
-    {
-      const int j = CB * I + tc;
-      double v = 0.0;
-      if (i < n && j < n && tr >= tc) {
-        v = G[(long)i * ldg + j];
-        if (i == j) v += shift;
+      for (int u = 0; u < BC / 4; ++u) {
+        const int kc = 4 * u + (lane >> 4);
+        a[u] = (ai < n && k0 + kc < n) ? G[(long)ai * ldg + k0 + kc] : 0.0;
       }
-      Ld[I][tr][tc] = v;
-    }
+      f64x4 acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int J = 0; J < I; ++J) {
-      const int j = CB * J + tc;
-      a[oslot(I, J)] = (i < n && j < n) ? G[(long)i * ldg + j] : 0.0;
+      for (int u = 0; u < BC / 4; ++u)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], sm.X[c0 + (lane & 15)][4 * u + (lane >> 4)], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + (lane >> 4) + 4 * r, col = c0 + (lane & 15);
+        const double v = (row < n && k0 + col < n) ? acc[r] : 0.0;
+        sm.P[row][col] = v;
+        if (row < n && k0 + col < n) G[(long)row * ldg + k0 + col] = v;
+      }
     }
+    __syncthreads();
+    // (c) trailing update of the lower triangle, 16 x 16 tiles; the next tile's values
+    // are loaded before the current tile's MFMAs
+    const int T16 = m / 16, utiles = T16 * (T16 + 1) / 2;
+    auto load_tile = [&](int t, f64x4& v) {
+      int ti, tj;
+      lower_tile(t, ti, tj);
+      const int i0 = r0 + ti * 16, j0 = r0 + tj * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + (lane >> 4) + 4 * r, col = j0 + (lane & 15);
+        v[r] = (row < n && col < n) ? G[(long)row * ldg + col] : 0.0;
+      }
+    };
+    f64x4 nxt = {0, 0, 0, 0};
+    if (wave < utiles) load_tile(wave, nxt);
+    for (int t = wave; t < utiles; t += nw) {
+      f64x4 acc = nxt;
+      if (t + nw < utiles) load_tile(t + nw, nxt);
+      int ti, tj;
+      lower_tile(t, ti, tj);
+      const int i0 = r0 + ti * 16, j0 = r0 + tj * 16;
+#pragma unroll
+      for (int kk = 0; kk < BC; kk += 4) {
+        const int kc = kk + (lane >> 4);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sm.P[i0 + (lane & 15)][kc], sm.P[j0 + (lane & 15)][kc], acc,
+                                                   0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + (lane >> 4) + 4 * r, col = j0 + (lane & 15);
+        if (row < n && col < n && (ti != tj || col <= row)) G[(long)row * ldg + col] = acc[r];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (t == 0) { spiv = Ld[0][0][0]; sfail = 0; }
-  __syncthreads();
-  const CholSh S{Ld, sl, su, &spiv, &sfail};
-  cholinv_all_cols(std::make_integer_sequence<int, CNB>{}, a, S, n);
-  __syncthreads();
-  const int failed = sfail;
-  if (t == 0) {
-    *fail_flag = failed;
-    if (failed) atomicOr(status, attempt == 0 ? KFAC_DS_CHOL_SHIFTED : KFAC_DS_CHOL_FAILED);
-  }
-  // write L^{-1} (lower), zeros elsewhere inside l_pad x l_pad
-#pragma unroll
-  for (int I = 0; I < CNB; ++I) {
-    const int i = CB * I + tr;
-    if (i >= l_pad) continue;
-    double* row = Linv + (long)i * ldl;
-    {
-      const int j = CB * I + tc;
-      if (j < l_pad) row[j] = (i < n && j < n && tr >= tc) ? Ld[I][tr][tc] : 0.0;
-    }
-#pragma unroll
-    for (int J = 0; J < I; ++J) {
-      const int j = CB * J + tc;
-      if (j < l_pad) row[j] = (i < n && j < n) ? a[oslot(I, J)] : 0.0;
-    }
-#pragma unroll
-    for (int J = I + 1; J < CNB; ++J) {
-      const int j = CB * J + tc;
-      if (j < l_pad) row[j] = 0.0;
-    }
+  if (tid == 0) {
+    const int failed = sm.fail;
+    *q.fail_flag = failed;
+    if (failed) atomicOr(q.status, attempt == 0 ? KFAC_DS_CHOL_SHIFTED : KFAC_DS_CHOL_FAILED);
   }
 }
 
-__global__ __launch_bounds__(1024) void k_cholinv_reg(CholInvTask q) { cholinv_body(q, 0, 0); }
-KFAC_GROUPED_KERNEL(k_cholinv_reg_g, cholinv_body, CholInvTask, 1024)
+__global__ __launch_bounds__(BC_NT) void k_cholinv(CholInvTask q) { cholinv_body(q, 0, 0); }
+KFAC_GROUPED_KERNEL(k_cholinv_g, cholinv_body, CholInvTask, BC_NT)
+
+// Launch 2: block column K = bx of X = L^{-1} below the diagonal.  For each block row
+// I > K: T = L_I,[K, I) X_[K, I),K with the contraction split over the four wavefronts
+// (partial tiles summed through LDS), then X_IK = -X_II T.
+struct TtSmem {
+  double Xc[288][BC + 1];         // X_JK for J >= K (absolute rows)
+  double Lr[BC][288 + 1];         // L_I, [BC K, BC I) (columns relative to BC K)
+  double Tp[4][BC][BC + 1];       // per-wavefront partial T
+  double Xd[BC][BC + 1];          // X_II
+};
+
+__device__ __forceinline__ void trtri_cols_body(const CholInvTask& q, int bx, int) {
+  const double* L = q.G; const long ldg = q.ldg; const int n = q.n;
+  double* X = q.Linv; const long ldx = q.ldl; const int l_pad = q.l_pad;
+  __shared__ TtSmem sm;
+  constexpr int CT = BC / 16, NTILE = CT * CT, KS = 4 / NTILE;   // tiles of T, contraction split
+  static_assert(NTILE * KS == 4, "four wavefronts");
+  const int NB = l_pad / BC, K = bx;
+  if (K >= NB - 1) return;                                     // uniform
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k0 = K * BC;
+  for (int e = tid; e < BC * BC; e += TT_NT) sm.Xc[k0 + e / BC][e % BC] = X[(long)(k0 + e / BC) * ldx + k0 + e % BC];
+  const int tile = wave % NTILE, ks = wave / NTILE;
+  const int rt = tile % CT, ct = tile / CT;
+  for (int I = K + 1; I < NB; ++I) {
+    const int i0 = I * BC, w = i0 - k0;
+    for (int e = tid; e < BC * w; e += TT_NT) {
+      const int r = e / w, cc = e % w;
+      sm.Lr[r][cc] = (i0 + r < n && k0 + cc < n) ? L[(long)(i0 + r) * ldg + k0 + cc] : 0.0;
+    }
+    for (int e = tid; e < BC * BC; e += TT_NT) sm.Xd[e / BC][e % BC] = X[(long)(i0 + e / BC) * ldx + i0 + e % BC];
+    __syncthreads();
+    {
+      f64x4 acc = {0, 0, 0, 0};
+      for (int kk = 4 * ks; kk < w; kk += 4 * KS) {
+        const int kc = kk + (lane >> 4);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sm.Lr[rt * 16 + (lane & 15)][kc], sm.Xc[k0 + kc][ct * 16 + (lane & 15)],
+                                                   acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sm.Tp[ks][rt * 16 + (lane >> 4) + 4 * r][ct * 16 + (lane & 15)] = acc[r];
+    }
+    __syncthreads();
+    if (KS > 1) {
+      for (int e = tid; e < BC * BC; e += TT_NT) {
+        double v = 0.0;
+        for (int u = 0; u < KS; ++u) v += sm.Tp[u][e / BC][e % BC];
+        sm.Tp[0][e / BC][e % BC] = v;
+      }
+      __syncthreads();
+    }
+    // X_IK = -X_II T
+    if (wave < NTILE) {
+      f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < BC; kk += 4) {
+        const int kc = kk + (lane >> 4);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sm.Xd[rt * 16 + (lane & 15)][kc], sm.Tp[0][kc][ct * 16 + (lane & 15)],
+                                                   acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + (lane >> 4) + 4 * r, col = ct * 16 + (lane & 15);
+        const double v = (i0 + row < n && k0 + col < n) ? acc[r] : 0.0;
+        sm.Xc[i0 + row][col] = v;
+        X[(long)(i0 + row) * ldx + k0 + col] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(TT_NT) void k_trtri_cols(CholInvTask q) { trtri_cols_body(q, blockIdx.x, 0); }
+KFAC_GROUPED_KERNEL(k_trtri_cols_g, trtri_cols_body, CholInvTask, TT_NT)
 
 // ======================================================================================
 // Q^T = L^{-1} Y^T on fp64 MFMA: L^{-1} (l_pad x l_pad fp64, lower), Y^T (l_pad x d fp32),
@@ -742,19 +754,17 @@ hipError_t launch_gram(const float* A, long lda, const float* B, long ldb, int L
 
 hipError_t launch_cholesky(const double* G, long ldg, int n, long m_rows, double* W, long ldw, double* Li,
                            int* status, int* fail_flag, hipStream_t s) {
-  if (n <= RNMAX)
-    hipLaunchKernelGGL(k_cholesky_reg, dim3(1), dim3(1024), 0, s, G, ldg, n, m_rows, W, ldw, Li, status, fail_flag);
-  else
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(512), 0, s, G, ldg, n, m_rows, W, ldw, Li, status, fail_flag);
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(512), 0, s, G, ldg, n, m_rows, W, ldw, Li, status, fail_flag);
   return hipGetLastError();
 }
 
-hipError_t launch_cholinv(const double* G, long ldg, int n, long m_rows, double* Linv, long ldl, int l_pad,
+hipError_t launch_cholinv(double* G, long ldg, int n, long m_rows, double* Linv, long ldl, int l_pad, double* dsave,
                           int* status, int* fail_flag, hipStream_t s) {
-  CholInvTask q{G, ldg, n, m_rows, Linv, ldl, l_pad, status, fail_flag, 0};
-  hipLaunchKernelGGL(k_cholinv_reg, dim3(1), dim3(1024), 0, s, q);
+  CholInvTask q{G, ldg, n, m_rows, Linv, ldl, l_pad, dsave, status, fail_flag, 0};
+  hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(BC_NT), 0, s, q);
   q.attempt = 1;
-  hipLaunchKernelGGL(k_cholinv_reg, dim3(1), dim3(1024), 0, s, q);
+  hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(BC_NT), 0, s, q);
+  if (l_pad > BC) hipLaunchKernelGGL(k_trtri_cols, dim3(l_pad / BC - 1), dim3(TT_NT), 0, s, q);
   return hipGetLastError();
 }
 
@@ -785,7 +795,9 @@ hipError_t launch_trsm(const double* W, long ldw, const double* Li, int n, int l
   }
 KFAC_GLAUNCH(launch_gram_partial_g, k_gram_partial_g, GramP, 256)
 KFAC_GLAUNCH(launch_gram_reduce_g, k_gram_reduce_g, GramP, 256)
-KFAC_GLAUNCH(launch_cholinv_g, k_cholinv_reg_g, CholInvTask, 1024)
+KFAC_GLAUNCH(launch_cholinv_g, k_cholinv_g, CholInvTask, BC_NT)
+KFAC_GLAUNCH(launch_trtri_cols_g, k_trtri_cols_g, CholInvTask, TT_NT)
+int trtri_col_blocks(int l_pad) { return l_pad / BC - 1; }
 KFAC_GLAUNCH(launch_trmm_g, k_trmm_f64_g, TrmmTask, 256)
 int gram_reduce_slices() { return GR_T * GR_T / 256; }
 int trmm_blocks_x(int ncols) { return (ncols + GR_T - 1) / GR_T; }

@@ -135,8 +135,8 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
     for (int pass = 0; pass < 2; ++pass) {
       uint16_t* qb = (pass == 1) ? Qtb : nullptr;
       if ((x = launch_gram(src, ldt, src, ldt, L, dd, 1, w.part, w.G, L, st, s)) != hipSuccess) return x;
-      if (n <= kCholInvMax) {
-        if ((x = launch_cholinv(w.G, L, n, dd, w.Wc, L, L, st, w.fail, s)) != hipSuccess) return x;
+      if (L <= kCholInvMax) {
+        if ((x = launch_cholinv(w.G, L, n, dd, w.Wc, L, L, w.Li, st, w.fail, s)) != hipSuccess) return x;
         if ((x = launch_trmm(w.Wc, L, n, src, ldt, dd, dst, ldt, qb, ldt, L, s)) != hipSuccess) return x;
         std::swap(src, dst);
       } else {

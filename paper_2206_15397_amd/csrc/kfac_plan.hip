@@ -13,7 +13,7 @@ using namespace kfac;
 namespace {
 
 enum Kind {
-  K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRMM, K_TRIDIAG, K_PREP,
+  K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRTRI, K_TRMM, K_TRIDIAG, K_PREP,
   K_BISECT, K_SELECT, K_VEC, K_CLEAD, K_CLUSTER, K_BT, K_SIGN_P, K_SIGN_A
 };
 
@@ -200,14 +200,15 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           std::vector<GramP> gp;
           std::vector<CholInvTask> ch;
           std::vector<TrmmTask> tm;
-          std::vector<int> gxg, nbg, gxr, nbr, gxc, nbc, gxt, nbt;
-          Work wg, wr, wc, wm;
+          std::vector<int> gxg, nbg, gxr, nbr, gxc, nbc, gxt, nbt, gxi, nbi;
+          Work wg, wr, wc, wi, wm;
           for (int i : act) {
             const FactorInfo& I = P->fi[i];
             const double l = I.l, d = I.d;
             wg += Work{l * (l + 1) * d, 4 * l * d};
             wr += Work{0, 8 * l * l};
-            wc += Work{2 * l * l * l / 3, 16 * l * l};
+            wc += Work{l * l * l / 3, 16 * l * l};       // Cholesky
+            wi += Work{l * l * l / 3, 16 * l * l};       // triangular inverse
             wm += Work{l * (l + 1) * d, 8 * l * d + 8 * l * l / 2 + ((bf && pass == 1) ? 2 * l * d : 0)};
             float* src = pass == 0 ? basis[i] : spare[i];
             float* dst = pass == 0 ? spare[i] : basis[i];
@@ -215,8 +216,9 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             const int tiles = gram_tiles(I.l_pad, 1);
             gp.push_back(g); gxg.push_back(tiles); nbg.push_back(tiles * g.ksplit);
             gxr.push_back(tiles); nbr.push_back(tiles * gram_reduce_slices());
-            CholInvTask c{W[i].G, I.l_pad, I.l, I.d, W[i].Wc, I.l_pad, I.l_pad, status, W[i].fail, 0};
+            CholInvTask c{W[i].G, I.l_pad, I.l, I.d, W[i].Wc, I.l_pad, I.l_pad, W[i].Li, status, W[i].fail, 0};
             ch.push_back(c); gxc.push_back(1); nbc.push_back(1);
+            gxi.push_back(trtri_col_blocks(I.l_pad)); nbi.push_back(trtri_col_blocks(I.l_pad));
             TrmmTask tt{W[i].Wc, I.l_pad, I.l, src, I.ldt, I.d, dst, I.ldt,
                         (bf && pass == 1) ? W[i].Qtb : nullptr, I.ldt, I.l_pad};
             const int bx = trmm_blocks_x(I.d), by = trmm_blocks_y(I.l_pad);
@@ -227,6 +229,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           T.add(K_CHOLINV, ch, gxc, nbc, false, false, wc);
           for (auto& c : ch) c.attempt = 1;
           T.add(K_CHOLINV, ch, gxc, nbc);   // re-run only where attempt 0 broke down
+          T.add(K_TRTRI, ch, gxi, nbi, false, false, wi);
           T.add(K_TRMM, tm, gxt, nbt, false, false, wm);
         }
       }
@@ -469,7 +472,7 @@ int kfac_plan_launch_count(const kfac_plan* plan) { return plan ? (int)plan->tab
 
 const char* kfac_plan_launch_name(const kfac_plan* plan, int index) {
   static const char* names[] = {"ea_tiles", "ea_finalize", "ea_tiles_bf16", "ea_finalize_bf16", "omega", "gemm_f32", "gemm_bf16", "gram_partial",
-                                "gram_reduce", "cholinv", "trmm", "tridiag", "tri_prep", "tri_bisect",
+                                "gram_reduce", "cholinv", "trtri_cols", "trmm", "tridiag", "tri_prep", "tri_bisect",
                                 "tri_select", "tri_vec", "tri_cluster_lead", "tri_cluster", "backtransform",
                                 "sign_partial", "sign_apply"};
   if (!plan || index < 0 || index >= (int)plan->tab.recs.size()) return nullptr;
@@ -504,6 +507,7 @@ kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, 
       case K_GRAM_P: e = launch_gram_partial_g((const GramP*)tp, gm, r.blocks, s); break;
       case K_GRAM_R: e = launch_gram_reduce_g((const GramP*)tp, gm, r.blocks, s); break;
       case K_CHOLINV: e = launch_cholinv_g((const CholInvTask*)tp, gm, r.blocks, s); break;
+      case K_TRTRI: e = launch_trtri_cols_g((const CholInvTask*)tp, gm, r.blocks, s); break;
       case K_TRMM: e = launch_trmm_g((const TrmmTask*)tp, gm, r.blocks, s); break;
       case K_TRIDIAG: e = launch_tridiag_g((const EigTask*)tp, gm, r.blocks, s); break;
       case K_PREP: e = launch_tri_prep_g((const EigTask*)tp, gm, r.blocks, s); break;

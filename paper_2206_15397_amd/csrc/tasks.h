@@ -50,9 +50,10 @@ struct GramP {           // C = A B^T in fp64 from fp32 rows: block (tile, K sli
   int* status;
 };
 
-struct CholInvTask {     // fused Cholesky + inverse of the l x l Gram (one block)
-  const double* G; long ldg; int n; long m_rows;
+struct CholInvTask {     // blocked Cholesky + inverse of the l x l Gram (one block)
+  double* G; long ldg; int n; long m_rows;   // G: lower triangle overwritten by L
   double* Linv; long ldl; int l_pad;
+  double* dsave;                             // n doubles: diagonal of G for the retry
   int* status; int* fail_flag; int attempt;
 };
 

@@ -170,6 +170,26 @@ def test_rand_eig_repeated_eigenvalues_exact_regime():
     np.testing.assert_allclose(Ug[:, :6] @ Ug[:, :6].T, R[:, :6] @ R[:, :6].T, atol=1e-5)
 
 
+@pytest.mark.parametrize("d,k,p,q", [(300, 20, 22, 1), (700, 37, 50, 0), (100, 5, 90, 1)])
+def test_rand_eig_rank_deficient_takes_shifted_retry(d, k, p, q):
+    """F = blockdiag(A_k, 0): the sketch has exactly k nonzero rows, so every Gram in
+    CholeskyQR2 is singular, plain Cholesky breaks down and the shifted retry runs
+    (status bit CHOL_SHIFTED, never CHOL_FAILED).  The k nonzero eigenvalues are still
+    recovered: the shifted basis is an isometry on range(F)."""
+    sig = np.linspace(1.0, 0.05, k)
+    F = np.zeros((d, d))
+    F[:k, :k] = synth.psd_factor(k, sig, 5)
+    F = F.astype(np.float32)
+    U, D, st = K().rand_eig(torch.from_numpy(F).to(DEV), k, p, q, seed=3)
+    torch.cuda.synchronize()
+    s = int(st.item())
+    assert s & 1 and not s & 2, s
+    np.testing.assert_allclose(to_np(D), np.sort(np.linalg.eigvalsh(F.astype(np.float64)))[::-1][:k], rtol=1e-4)
+    Ug = to_np(U)
+    assert np.abs(Ug.T @ Ug - np.eye(k)).max() < 1e-4
+    assert np.abs(Ug[k:]).max() < 1e-5     # spans the first k coordinates
+
+
 # --------------------------------------------------------------------------------------
 @pytest.mark.parametrize("dg,da,ra,rg", [(128, 257, 32, 32), (10, 513, 200, 10), (64, 70, 70, 3),
                                          (300, 200, 150, 100)])
