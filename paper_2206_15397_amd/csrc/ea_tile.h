@@ -3,6 +3,7 @@
 // tile and its mirror, plus the optional bf16 shadow of F.
 #pragma once
 #include "tasks.h"
+#include "gemm_f32.h"
 
 namespace kfac {
 
@@ -48,6 +49,48 @@ __device__ void ea_sum_slices(float (*t)[BT + 1], const float* base, int nks) {
     float s = 0.f;
     for (int k = 0; k < nks; ++k) s += base[(long)k * BT * BT + e];
     t[e / BT][e % BT] = s;
+  }
+}
+
+// Split-K finalize of one 16-row chunk of an upper BT x BT tile: block bx = tile * (BT/16)
+// + chunk.  Sums the slices in index order, blends into F (upper element read once, the
+// blended value written to the element and its mirror) and refreshes the bf16 shadow.
+constexpr int kEaChunk = 16;
+template <int BT>
+__device__ void ea_finalize_chunk(const EaTask& q, int bx, float (*v)[BT + 1]) {
+  constexpr int NCH = BT / kEaChunk;
+  const int tile = bx / NCH, a0 = (bx % NCH) * kEaChunk;
+  int I, J;
+  upper_tile(tile, q.T, I, J);
+  const EaOut& o = q.o;
+  const int r0 = I * BT, c0 = J * BT, nks = q.nks;
+  const float* base = q.g.part + (long)tile * nks * (BT * BT) + (long)a0 * BT;
+  for (int e = threadIdx.x; e < kEaChunk * BT; e += blockDim.x) {
+    float s = 0.f;
+#pragma unroll 8
+    for (int k = 0; k < nks; ++k) s += base[(long)k * BT * BT + e];
+    const int a = e / BT, b = e % BT;
+    const int i = r0 + a0 + a, j = c0 + b;
+    float val = 0.f;
+    if (i < o.d && j < o.d) {
+      val = o.rho * o.F[(long)i * o.ldf + j] + o.c * s;
+      if (I != J || a0 + a <= b) {
+        o.F[(long)i * o.ldf + j] = val;
+        if (o.Fb) o.Fb[(long)i * o.ldfb + j] = f32_to_bf16_rne(val);
+      }
+    }
+    v[a][b] = val;
+  }
+  __syncthreads();
+  // mirror: element (c0 + b, r0 + a0 + a) = v[a][b], 16 contiguous columns per row
+  for (int e = threadIdx.x; e < kEaChunk * BT; e += blockDim.x) {
+    const int b = e / kEaChunk, a = e % kEaChunk;
+    const int i = c0 + b, j = r0 + a0 + a;
+    if (i < o.d && j < o.d && (I != J || b > a0 + a)) {
+      const float val = v[a][b];
+      o.F[(long)i * o.ldf + j] = val;
+      if (o.Fb) o.Fb[(long)i * o.ldfb + j] = f32_to_bf16_rne(val);
+    }
   }
 }
 

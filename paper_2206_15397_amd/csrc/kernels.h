@@ -20,6 +20,7 @@ int ea_tiles_per_side(int d, bool bf);
 int ea_choose_ksplit(int d, long n, bool bf);
 size_t ea_workspace_bytes(int d, long n, bool bf);
 size_t ea_workspace_bytes(int d, long n);   // enough for either variant
+int ea_finalize_chunks(bool bf);             // finalize blocks per tile
 hipError_t launch_ea_f32(float* F, int d, long ldf, const float* X, int n, int d_in, long ldx, int ones,
                          float rho, float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes,
                          hipStream_t s);

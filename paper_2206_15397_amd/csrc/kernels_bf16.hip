@@ -264,12 +264,8 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
 }
 
 __device__ __forceinline__ void ea_bf16_finalize_body(const EaTask& q, int bx, int) {
-  __shared__ float t[EB_BT][EB_BT + 1];
-  int I, J;
-  upper_tile(bx, q.T, I, J);
-  ea_sum_slices<EB_BT>(t, q.g.part + (long)bx * q.nks * (EB_BT * EB_BT), q.nks);
-  __syncthreads();
-  ea_store_tile_t<EB_BT>(t, q.o, I, J);
+  __shared__ float v[kEaChunk][EB_BT + 1];
+  ea_finalize_chunk<EB_BT>(q, bx, v);
 }
 
 __global__ __launch_bounds__(256) void k_ea_bf16_tiles(EaTask q) { ea_bf16_tiles_body(q, blockIdx.x, blockIdx.y); }
@@ -282,7 +278,7 @@ hipError_t launch_ea_bf16_tiles(const EaTask& q, int tiles, int ks, hipStream_t 
   return hipGetLastError();
 }
 hipError_t launch_ea_bf16_finalize(const EaTask& q, int tiles, hipStream_t s) {
-  hipLaunchKernelGGL(k_ea_bf16_finalize, dim3(tiles), dim3(256), 0, s, q);
+  hipLaunchKernelGGL(k_ea_bf16_finalize, dim3(tiles * ea_finalize_chunks(true)), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 hipError_t launch_ea_bf16_tiles_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s) {

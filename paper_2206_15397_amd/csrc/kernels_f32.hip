@@ -88,14 +88,11 @@ __device__ __forceinline__ void ea_tiles_body(const EaTask& q, int bx, int by) {
   ea_store_tile_t<EA_BT>(sm.t, q.o, I, J);
 }
 
-// Deterministic split-K reduction (slices summed in index order) + EA epilogue.
+// Deterministic split-K reduction (slices summed in index order) + EA epilogue, one
+// 16-row chunk of a tile per block.
 __device__ __forceinline__ void ea_finalize_body(const EaTask& q, int bx, int) {
-  __shared__ EaSmem sm;
-  int I, J;
-  upper_tile(bx, q.T, I, J);
-  ea_sum_slices<EA_BT>(sm.t, q.g.part + (long)bx * q.nks * (EA_BT * EA_BT), q.nks);
-  __syncthreads();
-  ea_store_tile_t<EA_BT>(sm.t, q.o, I, J);
+  __shared__ float v[kEaChunk][EA_BT + 1];
+  ea_finalize_chunk<EA_BT>(q, bx, v);
 }
 
 __global__ __launch_bounds__(256) void k_ea_tiles(EaTask q) { ea_tiles_body(q, blockIdx.x, blockIdx.y); }
@@ -273,6 +270,8 @@ size_t ea_workspace_bytes(int d, long n, bool bf) {
   return (size_t)tiles * ks * bt * bt * sizeof(float);
 }
 
+int ea_finalize_chunks(bool bf) { return (bf ? kEaBf16Tile : EA_BT) / kEaChunk; }
+
 size_t ea_workspace_bytes(int d, long n) {
   return std::max(ea_workspace_bytes(d, n, false), ea_workspace_bytes(d, n, true));
 }
@@ -298,7 +297,7 @@ static hipError_t launch_ea_common(float* F, int d, long ldf, const float* X, co
     return launch_ea_bf16_finalize(q, tiles, s);
   }
   hipLaunchKernelGGL(k_ea_tiles, dim3(tiles, ks), dim3(256), 0, s, q);
-  if (ks > 1) hipLaunchKernelGGL(k_ea_finalize, dim3(tiles), dim3(256), 0, s, q);
+  if (ks > 1) hipLaunchKernelGGL(k_ea_finalize, dim3(tiles * ea_finalize_chunks(false)), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 

@@ -125,7 +125,10 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
                                 F.append_ones, P->rho, F.scale, F.F_bf16, F.ldfb, (float*)wsp(I.ea_off), I.ea_ks);
         const int tiles = q.T * (q.T + 1) / 2;
         t.push_back(q); gx.push_back(tiles); nb.push_back(tiles * I.ea_ks);
-        if (I.ea_ks > 1) { tf.push_back(q); gxf.push_back(tiles); nbf.push_back(tiles); }
+        if (I.ea_ks > 1) {
+          const int fb = tiles * ea_finalize_chunks(xb == 1);
+          tf.push_back(q); gxf.push_back(fb); nbf.push_back(fb);
+        }
         // sums over the upper triangle; F: upper half read, full F written (+ bf16 shadow)
         const double d = I.d, n = (double)F.n;
         const Work x{n * d * (d + 1), n * (double)F.d_in * (xb ? 2 : 4)};
