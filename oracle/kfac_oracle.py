@@ -86,7 +86,11 @@ def philox4x32_10(ctr: np.ndarray, key) -> np.ndarray:
 
     One round maps (c0, c1, c2, c3) to (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2),
     hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)); between rounds the key is bumped by the Weyl
-    constants (W0, W1)."""
+    constants (W0, W1).
+
+    Parity unpinned against the generator's published known-answer vectors (none are
+    available offline): the words are pinned by CPU/GPU bit equality, counter
+    separation and the moment / distribution tests of the Gaussians built from them."""
     c = np.array(ctr, dtype=np.uint64) & _MASK32
     k0 = np.uint64(int(key[0]) & _MASK32)
     k1 = np.uint64(int(key[1]) & _MASK32)
