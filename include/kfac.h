@@ -170,6 +170,41 @@ kfac_status kfac_precondition(const float* J, int64_t d_g, int64_t d_a, int64_t 
 
 
 /*
+ * K-FAC linear layer (Alg. 1: the forward pass that provides the activations a of the
+ * forward factor, and the backward pass that provides the weight gradient and the
+ * back-propagated gradients g of the backward factor).  bf16 operands on MFMA with fp32
+ * accumulation; row-major; a batch row per sample.
+ *
+ * kfac_linear_forward:   y = x W^T + b.
+ *  x  n x d_in bf16 (ldx >= d_in);  W  d_out x d_in bf16 (ldw >= d_in);
+ *  bias  d_out fp32 or NULL;  y  n x d_out bf16 output (ldy >= d_out).
+ *
+ * kfac_linear_backward:  one call for the layer's backward:
+ *   dx = g W                                     (bf16, skipped when dx == NULL)
+ *   [dW | db] = g^T [x | 1]                      (fp32 d_out x (d_in + with_bias), lddw >=
+ *                                                 d_in + with_bias; column d_in holds db)
+ *   Gamma <- rho Gamma + (1 - rho) scale g^T g   (Alg. 1's EA of the backward factor, fused
+ *                                                 into the dW launch; skipped when Gamma ==
+ *                                                 NULL; both triangles + optional bf16 shadow)
+ *  g  n x d_out bf16 (ldg >= d_out); x as in the forward; W as in the forward.
+ *  Gamma  d_out x d_out fp32 (ldgam >= d_out), Gamma_bf16 nullable (ldgb >= d_out).
+ *  rho in [0, 1), scale > 0 (typically 1/n).  n == 0 gives dW = 0 and Gamma <- rho Gamma
+ *  (g, x, dx may then be NULL); the forward with n == 0 does nothing.
+ * Errors: KFAC_EINVAL for null required pointers, non-positive sizes or short leading
+ * dimensions; KFAC_EHIP when a launch fails.
+ */
+kfac_status kfac_linear_forward(const uint16_t* x, int64_t n, int64_t d_in, int64_t ldx,
+                                const uint16_t* W, int64_t d_out, int64_t ldw, const float* bias,
+                                uint16_t* y, int64_t ldy, kfac_stream_t stream);
+kfac_status kfac_linear_backward(const uint16_t* g, int64_t n, int64_t d_out, int64_t ldg,
+                                 const uint16_t* x, int64_t d_in, int64_t ldx,
+                                 const uint16_t* W, int64_t ldw,
+                                 uint16_t* dx, int64_t lddx,
+                                 float* dWb, int64_t lddw, int with_bias,
+                                 float* Gamma, int64_t ldgam, uint16_t* Gamma_bf16, int64_t ldgb,
+                                 float rho, float scale, kfac_stream_t stream);
+
+/*
  * Grouped plan -- one K-factor step of a whole network (all factors and layers) as a
  * fixed sequence of grouped launches: every launch covers one phase (EA tiles, sketch
  * GEMM, Gram, Cholesky, eigensolver stage, preconditioner product, ...) of every factor or

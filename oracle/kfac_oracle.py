@@ -27,6 +27,7 @@ __all__ = [
     "philox_words_for", "householder_qr", "jacobi_eig", "jacobi_svd", "sign_normalize", "range_finder",
     "srevd", "rsvd", "damping_weights", "precondition", "exact_precondition",
     "prop31_r_eps", "prop31_max_modes", "full_eig", "kfactor_step", "oracle_library_path",
+    "linear_forward", "linear_backward",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -388,3 +389,19 @@ def kfactor_step(layers, rho: float, lam: float, r_cap: int, p: int, q: int, see
         S = precondition(L["J"], U_a, D_a, U_g, D_g, lam)
         out.append({"A": A, "G": G, "U_a": U_a, "D_a": D_a, "U_g": U_g, "D_g": D_g, "S": S})
     return out
+
+
+def linear_forward(x: np.ndarray, W: np.ndarray, b: np.ndarray = None) -> np.ndarray:
+    """Forward pass of a fully-connected layer over a batch (rows are samples): s = a W^T + b
+    (Alg. 1 forward pass, whose inputs a feed the forward factor)."""
+    y = x @ W.T
+    if b is not None:
+        y = y + b[None, :]
+    return y
+
+
+def linear_backward(x: np.ndarray, W: np.ndarray, g: np.ndarray):
+    """Backward pass of s = a W^T + b for a batch, given g = dL/ds (rows are samples):
+    dL/da = g W, dL/dW = g^T a, dL/db = sum over rows of g (Alg. 1 backward pass: Mat(g) of
+    the layer and the back-propagated gradients that feed the backward factor)."""
+    return g @ W, g.T @ x, g.sum(axis=0)

@@ -30,6 +30,9 @@ SIGNATURES = {
     "kfac_precondition_workspace": (_sz, [_i64, _i64, _i64, _i64]),
     "kfac_precondition": (_i, [_p, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _f,
                                _p, _i64, _p, _sz, _p]),
+    "kfac_linear_forward": (_i, [_p, _i64, _i64, _i64, _p, _i64, _i64, _p, _p, _i64, _p]),
+    "kfac_linear_backward": (_i, [_p, _i64, _i64, _i64, _p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i,
+                                  _p, _i64, _p, _i64, _f, _f, _p]),
     "kfac_plan_create": (_i, [_p, _i, _p, _i, _i, _p]),
     "kfac_plan_workspace": (_sz, [_p]),
     "kfac_plan_set_scalars": (_i, [_p, _f, _f, _u64, _u32, _i, _i, _i]),

@@ -25,11 +25,63 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Cross-lane moves on the DPP network (no LDS round trip).  Control codes of the GFX9
+// DPP encoding: quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E, row_mirror = 0x140,
+// row_half_mirror = 0x141, row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Lanes of rows
+// outside ROW_MASK keep `old`.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double old, double src) {
+  const long long o = __builtin_bit_cast(long long, old), v = __builtin_bit_cast(long long, src);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f32(float old, float src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                               __builtin_bit_cast(int, src), CTRL, ROW_MASK, 0xf,
+                                                               false));
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_t(double old, double src) { return dpp_f64<CTRL, ROW_MASK>(old, src); }
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_t(float old, float src) { return dpp_f32<CTRL, ROW_MASK>(old, src); }
+
+// Sum over each row of 16 lanes; every lane of the row receives it.
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+  v += dpp_t<0xB1>(T(0), v);
+  v += dpp_t<0x4E>(T(0), v);
+  v += dpp_t<0x141>(T(0), v);
+  v += dpp_t<0x140>(T(0), v);
+  return v;
+}
+
+// Sum over each half wavefront (lanes 0-31, 32-63); the result is valid in lanes 16-31
+// and 48-63 (rows 1 and 3).
+template <typename T>
+__device__ __forceinline__ T half_sum_hi(T v) {
+  v = row16_sum(v);
+  v += dpp_t<0x142, 0xA>(T(0), v);
+  return v;
+}
+
+__device__ __forceinline__ double readlane_t(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float readlane_t(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Sum over the wavefront (all 64 lanes active), returned to every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v = half_sum_hi(v);
+  v += dpp_t<0x143, 0xC>(T(0), v);      // row 3 now holds the total
+  return readlane_t(v, 63);
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32 Philox

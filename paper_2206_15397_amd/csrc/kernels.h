@@ -37,6 +37,14 @@ hipError_t launch_sign_normalize(float* U, long ldu, int d, int r, float* pval, 
 hipError_t launch_gemm_bf16_nt(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb,
                                float* C, long ldc, hipStream_t s);
 
+// K-FAC linear layer (kernels_linear.hip)
+hipError_t launch_linear_forward(const uint16_t* x, int n, int d_in, long ldx, const uint16_t* W, int d_out, long ldw,
+                                 const float* bias, uint16_t* y, long ldy, hipStream_t s);
+hipError_t launch_linear_backward(const uint16_t* g, int n, int d_out, long ldg, const uint16_t* x, int d_in, long ldx,
+                                  const uint16_t* W, long ldw, uint16_t* dx, long lddx, float* dWb, long lddw,
+                                  int with_bias, float* Gam, long ldgam, uint16_t* Gamb, long ldgb, float rho,
+                                  float scale, hipStream_t s);
+
 // fp64 kernels (kernels_f64.hip)
 int gram_ksplit(int L, int K, int sym);
 size_t gram_workspace_bytes(int L, int K, int sym);

@@ -116,13 +116,8 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36], const TriSh& S, i
 #pragma unroll
     for (int I = J0; I < TNB; ++I) {
       if (I >= kb) {
-        double x = pr[I];
-        x += __shfl_xor(x, 16, 64);
-        x += __shfl_xor(x, 8, 64);
-        x += __shfl_xor(x, 4, 64);
-        x += __shfl_xor(x, 2, 64);
-        x += __shfl_xor(x, 1, 64);
-        if (tc == 0) S.spr[I][tr] = x;
+        const double x = half_sum_hi(pr[I]);          // sum over tc, valid in tc >= 16
+        if (tc == 16) S.spr[I][tr] = x;
       }
     }
     __syncthreads();

@@ -1,0 +1,282 @@
+// K-FAC linear layer on bf16 MFMA (fp32 accumulation):
+//   forward   y = x W^T + b                         (A = x, B = W, both K-contiguous)
+//   backward  dx = g W                              (A = g K-contiguous, B = W K-major)
+//             [dW | db] = g^T [x | 1]               (both operands K-major: batch rows)
+//             Gamma <- rho Gamma + (1 - rho) s g^T g  (the backward-factor EA of Alg. 1, fused
+//                                                     into the same launch as dW: the g
+//                                                     columns it reads are the dW tiles' A)
+// 128 x 128 tiles, 4 waves of 64 x 64 on v_mfma_f32_16x16x32_bf16, 64-deep k-steps with two
+// LDS buffers.  Operands whose contraction index is the row index (K-major) are loaded as
+// 8 x 8 blocks and transposed in registers, so LDS always holds k-contiguous rows.
+#include "kernels.h"
+
+namespace kfac {
+
+constexpr int LN_T = 128, LN_BK = 64, LN_SK = LN_BK + 8;
+
+struct LinSmem {
+  union {
+    struct {
+      uint16_t a[2][LN_T][LN_SK];
+      uint16_t b[2][LN_T][LN_SK];
+    } g;
+    float t[LN_T][LN_T + 1];
+  };
+};
+
+// Column c of the row-major 8 x 8 bf16 block v[row].
+__device__ __forceinline__ uint4 ln_col_of_block(const uint4 v[8], int c) {
+  auto half = [&](int r) -> uint32_t {
+    const uint4& x = v[r];
+    const uint32_t w = (c >> 1) == 0 ? x.x : (c >> 1) == 1 ? x.y : (c >> 1) == 2 ? x.z : x.w;
+    return (c & 1) ? (w >> 16) : (w & 0xffffu);
+  };
+  return make_uint4(half(0) | (half(1) << 16), half(2) | (half(3) << 16), half(4) | (half(5) << 16),
+                    half(6) | (half(7) << 16));
+}
+
+// Rows [k0, k0+8) x columns [c0, c0+8) of a K-major operand with `cols` stored columns and an
+// optional ones column at index `cols` (zero beyond, and beyond row K).
+__device__ __forceinline__ void ln_load_kmajor(const uint16_t* X, long ld, int cols, bool ones, bool vec, int k0,
+                                               int K, int c0, uint4 v[8]) {
+  const bool full = vec && (c0 + 8 <= cols);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int k = k0 + r;
+    v[r] = make_uint4(0, 0, 0, 0);
+    if (k >= K) continue;
+    const uint16_t* p = X + (long)k * ld + c0;
+    if (full) {
+      v[r] = *(const uint4*)p;
+    } else {
+      uint16_t t[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = c0 + j;
+        t[j] = (c < cols) ? p[j] : ((ones && c == cols) ? (uint16_t)0x3f80 : (uint16_t)0);
+      }
+      v[r] = make_uint4(t[0] | ((uint32_t)t[1] << 16), t[2] | ((uint32_t)t[3] << 16),
+                        t[4] | ((uint32_t)t[5] << 16), t[6] | ((uint32_t)t[7] << 16));
+    }
+  }
+}
+
+// 16 bytes (8 k-values) of row `row` of a K-contiguous operand.
+__device__ __forceinline__ uint4 ln_ld16(const uint16_t* base, long ld, int row, int nrows, int k, int K, bool vec) {
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (row < nrows) {
+    const uint16_t* p = base + (long)row * ld + k;
+    if (vec && k + 8 <= K) {
+      v = *(const uint4*)p;
+    } else {
+      uint16_t t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = (k + i < K) ? p[i] : (uint16_t)0;
+      v = make_uint4(t[0] | ((uint32_t)t[1] << 16), t[2] | ((uint32_t)t[3] << 16), t[4] | ((uint32_t)t[5] << 16),
+                     t[6] | ((uint32_t)t[7] << 16));
+    }
+  }
+  return v;
+}
+
+// One operand tile (128 rows of M or N by 64 k) per k-step, filled by 128 threads.
+struct LnOperand {
+  const uint16_t* X; long ld;
+  int rows;        // M or N extent (K-contiguous) / stored columns (K-major)
+  bool ones;       // K-major: implicit ones column at index `rows`
+  bool vec;        // 16-byte loads allowed
+};
+
+template <bool KMAJ>
+struct LnLoader {
+  uint4 v[8];
+  __device__ __forceinline__ void load(const LnOperand& o, int tt, int r0, int k0, int K) {
+    if (KMAJ) {
+      const int cg = tt >> 3, rg = tt & 7;
+      ln_load_kmajor(o.X, o.ld, o.rows, o.ones, o.vec, k0 + rg * 8, K, r0 + cg * 8, v);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tt + 128 * u, row = e >> 3, kc = (e & 7) * 8;
+        v[u] = ln_ld16(o.X, o.ld, r0 + row, o.rows, k0 + kc, K, o.vec);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(uint16_t (*dst)[LN_SK], int tt) {
+    if (KMAJ) {
+      const int cg = tt >> 3, rg = tt & 7;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][rg * 8] = ln_col_of_block(v, c);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tt + 128 * u, row = e >> 3, kc = (e & 7) * 8;
+        *(uint4*)&dst[row][kc] = v[u];
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ bool ln_vec_ok(const uint16_t* X, long ld) {
+  return ((ld & 7) == 0) && ((((uintptr_t)X) & 15) == 0);
+}
+
+// Block bx of a LinTask.  AK / BK: operand stored K-major (rows = contraction index).
+template <bool AK, bool BK>
+__device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
+  __shared__ LinSmem sm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int nplain = q.tiles_m * q.tiles_n;
+  const bool gam = bx >= nplain;
+  int m0, n0, GI = 0, GJ = 0;
+  LnOperand oa{q.A, q.lda, q.M, false, ln_vec_ok(q.A, q.lda)};
+  LnOperand ob{q.B, q.ldb, BK ? (q.b_ones ? q.N - 1 : q.N) : q.N, BK && q.b_ones != 0, ln_vec_ok(q.B, q.ldb)};
+  if (!gam) {
+    m0 = (bx % q.tiles_m) * LN_T;
+    n0 = (bx / q.tiles_m) * LN_T;
+  } else {
+    upper_tile(bx - nplain, q.gam_T, GI, GJ);
+    m0 = GI * LN_T;
+    n0 = GJ * LN_T;
+    ob = oa;                       // g^T g: both operands are g's columns
+  }
+  const bool same = gam && GI == GJ;
+  const int K = q.K;
+  const int op = tid >> 7, tt = tid & 127;
+  const bool loader = !(same && op == 1);
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // one register set per thread: threads 0-127 fill the A tile, 128-255 the B tile (with
+  // equal layouts a single loader object, so its registers are never selected at run time)
+  LnLoader<AK> la;
+  LnLoader<BK> lb;
+  auto fetch = [&](int k0) {
+    if (!loader) return;
+    if constexpr (AK == BK) {
+      la.load(op ? ob : oa, tt, op ? n0 : m0, k0, K);
+    } else {
+      if (op == 0) la.load(oa, tt, m0, k0, K);
+      else lb.load(ob, tt, n0, k0, K);
+    }
+  };
+  auto stash = [&](int buf) {
+    if (!loader) return;
+    if constexpr (AK == BK) {
+      la.store(op ? sm.g.b[buf] : sm.g.a[buf], tt);
+    } else {
+      if (op == 0) la.store(sm.g.a[buf], tt);
+      else lb.store(sm.g.b[buf], tt);
+    }
+  };
+  if (K > 0) {
+    fetch(0);
+    stash(0);
+    __syncthreads();
+  }
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += LN_BK) {
+    const bool more = k0 + LN_BK < K;
+    if (more) fetch(k0 + LN_BK);
+    uint16_t (*As)[LN_SK] = sm.g.a[buf];
+    uint16_t (*Bs)[LN_SK] = same ? sm.g.a[buf] : sm.g.b[buf];
+#pragma unroll
+    for (int kk = 0; kk < LN_BK; kk += 32) {
+      const int kq = kk + (lane >> 4) * 8;
+      bf16x8 af[4], bfr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        af[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&As[wm * 64 + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bfr[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&Bs[wn * 64 + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  if (gam) {
+    // backward-factor EA tile: stage raw sums, blend, write tile + mirror + bf16 shadow
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          sm.t[wm * 64 + i * 16 + 4 * (lane >> 4) + r][wn * 64 + j * 16 + (lane & 15)] = acc[i][j][r];
+    __syncthreads();
+    ea_store_tile_t<LN_T>(sm.t, q.gam, GI, GJ);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (row < q.M && col < q.N) {
+          const float v = acc[i][j][r] + (q.bias ? q.bias[col] : 0.f);
+          if (q.C) q.C[(long)row * q.ldc + col] = v;
+          if (q.Cb) q.Cb[(long)row * q.ldcb + col] = f32_to_bf16_rne(v);
+        }
+      }
+}
+
+__global__ __launch_bounds__(256) void k_lin_nt(LinTask q) { lin_body<false, false>(q, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_lin_nn(LinTask q) { lin_body<false, true>(q, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_lin_tn(LinTask q) { lin_body<true, true>(q, blockIdx.x); }
+
+static LinTask lin_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, int b_ones,
+                        float* C, long ldc, uint16_t* Cb, long ldcb, const float* bias) {
+  LinTask q{};
+  q.M = M; q.N = N; q.K = K;
+  q.A = A; q.lda = lda; q.B = B; q.ldb = ldb; q.b_ones = b_ones;
+  q.C = C; q.ldc = ldc; q.Cb = Cb; q.ldcb = ldcb; q.bias = bias;
+  q.tiles_m = (M + LN_T - 1) / LN_T;
+  q.tiles_n = (N + LN_T - 1) / LN_T;
+  q.gam_T = 0;
+  return q;
+}
+
+hipError_t launch_linear_forward(const uint16_t* x, int n, int d_in, long ldx, const uint16_t* W, int d_out, long ldw,
+                                 const float* bias, uint16_t* y, long ldy, hipStream_t s) {
+  LinTask q = lin_task(n, d_out, d_in, x, ldx, W, ldw, 0, nullptr, 0, y, ldy, bias);
+  const int blocks = q.tiles_m * q.tiles_n;
+  if (blocks > 0) hipLaunchKernelGGL(k_lin_nt, dim3(blocks), dim3(256), 0, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_linear_backward(const uint16_t* g, int n, int d_out, long ldg, const uint16_t* x, int d_in, long ldx,
+                                  const uint16_t* W, long ldw, uint16_t* dx, long lddx, float* dWb, long lddw,
+                                  int with_bias, float* Gam, long ldgam, uint16_t* Gamb, long ldgb, float rho,
+                                  float scale, hipStream_t s) {
+  if (dx) {
+    // dx[n x d_in] = g[n x d_out] W[d_out x d_in]
+    LinTask q = lin_task(n, d_in, d_out, g, ldg, W, ldw, 0, nullptr, 0, dx, lddx, nullptr);
+    const int blocks = q.tiles_m * q.tiles_n;
+    if (blocks > 0) hipLaunchKernelGGL(k_lin_nn, dim3(blocks), dim3(256), 0, s, q);
+  }
+  // [dW | db][d_out x (d_in + 1)] = g^T [x | 1], plus the upper tiles of g^T g for Gamma
+  const int N = d_in + (with_bias ? 1 : 0);
+  LinTask q = lin_task(d_out, N, n, g, ldg, x, ldx, with_bias, dWb, lddw, nullptr, 0, nullptr);
+  int blocks = q.tiles_m * q.tiles_n;
+  if (Gam) {
+    q.gam = EaOut{Gam, ldgam, Gamb, ldgb, d_out, rho, (1.f - rho) * scale};
+    q.gam_T = q.tiles_m;
+    blocks += q.gam_T * (q.gam_T + 1) / 2;
+  }
+  if (blocks > 0) hipLaunchKernelGGL(k_lin_tn, dim3(blocks), dim3(256), 0, s, q);
+  return hipGetLastError();
+}
+
+}  // namespace kfac

@@ -239,4 +239,33 @@ kfac_status kfac_precondition(const float* J, int64_t d_g, int64_t d_a, int64_t 
   return KFAC_OK;
 }
 
+kfac_status kfac_linear_forward(const uint16_t* x, int64_t n, int64_t d_in, int64_t ldx, const uint16_t* W,
+                                int64_t d_out, int64_t ldw, const float* bias, uint16_t* y, int64_t ldy,
+                                kfac_stream_t stream) {
+  if (!W || (n > 0 && (!x || !y))) return KFAC_EINVAL;
+  if (n < 0 || d_in < 1 || d_out < 1 || ldx < d_in || ldw < d_in || ldy < d_out) return KFAC_EINVAL;
+  if (n == 0) return KFAC_OK;
+  if (n > INT32_MAX || d_in > INT32_MAX || d_out > INT32_MAX) return KFAC_EUNSUPPORTED;
+  return hip_status(launch_linear_forward(x, (int)n, (int)d_in, ldx, W, (int)d_out, ldw, bias, y, ldy,
+                                          (hipStream_t)stream));
+}
+
+kfac_status kfac_linear_backward(const uint16_t* g, int64_t n, int64_t d_out, int64_t ldg, const uint16_t* x,
+                                 int64_t d_in, int64_t ldx, const uint16_t* W, int64_t ldw, uint16_t* dx,
+                                 int64_t lddx, float* dWb, int64_t lddw, int with_bias, float* Gamma, int64_t ldgam,
+                                 uint16_t* Gamma_bf16, int64_t ldgb, float rho, float scale, kfac_stream_t stream) {
+  if (!W || !dWb || (n > 0 && (!g || !x))) return KFAC_EINVAL;
+  if (n < 0 || d_in < 1 || d_out < 1 || ldg < d_out || ldx < d_in || ldw < d_in) return KFAC_EINVAL;
+  if (lddw < d_in + (with_bias ? 1 : 0)) return KFAC_EINVAL;
+  if (dx && lddx < d_in) return KFAC_EINVAL;
+  if (Gamma) {
+    if (ldgam < d_out || !(rho >= 0.f && rho < 1.f) || !(scale > 0.f)) return KFAC_EINVAL;
+    if (Gamma_bf16 && ldgb < d_out) return KFAC_EINVAL;
+  }
+  if (n > INT32_MAX || d_in > INT32_MAX || d_out > INT32_MAX) return KFAC_EUNSUPPORTED;
+  return hip_status(launch_linear_backward(g, (int)n, (int)d_out, ldg, x, (int)d_in, ldx, W, ldw, dx, lddx, dWb, lddw,
+                                           with_bias ? 1 : 0, Gamma, ldgam, Gamma_bf16, ldgb, rho, scale,
+                                           (hipStream_t)stream));
+}
+
 }  // extern "C"

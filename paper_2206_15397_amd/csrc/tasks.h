@@ -38,6 +38,19 @@ struct BfGemmTask {      // C = A B^T, bf16 operands, K contiguous: block (flat 
   int tiles_m;
 };
 
+struct LinTask {         // K-FAC linear layer GEMMs on bf16 MFMA: block (flat tile)
+  int M, N, K;
+  const uint16_t* A; long lda;
+  const uint16_t* B; long ldb;
+  int b_ones;            // K-major B: implicit ones column at index N - 1
+  float* C; long ldc;    // fp32 output (nullable)
+  uint16_t* Cb; long ldcb;   // bf16 output (nullable)
+  const float* bias;     // per output column (nullable)
+  int tiles_m, tiles_n;
+  EaOut gam;             // fused backward-factor EA (upper tiles after the plain tiles)
+  int gam_T;             // tiles per side of gam (0: none)
+};
+
 struct GramP {           // C = A B^T in fp64 from fp32 rows: block (tile, K slice)
   const float* A; long lda;
   const float* B; long ldb;

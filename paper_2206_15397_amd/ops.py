@@ -122,6 +122,46 @@ def precondition(J: torch.Tensor, Ua: torch.Tensor, Da: torch.Tensor, Ug: torch.
     return S
 
 
+def linear_forward(x: torch.Tensor, W: torch.Tensor, bias: torch.Tensor = None, y: torch.Tensor = None):
+    """y = x W^T + b on bf16 MFMA (x: n x d_in bf16, W: d_out x d_in bf16, bias fp32)."""
+    _require_cuda(x, W, bias)
+    n, d_in = x.shape
+    d_out = W.shape[0]
+    assert x.dtype == torch.bfloat16 and W.dtype == torch.bfloat16 and W.shape[1] == d_in
+    assert (n == 0 or x.stride(1) == 1) and W.stride(1) == 1
+    assert bias is None or (bias.dtype == torch.float32 and bias.is_contiguous() and bias.numel() == d_out)
+    if y is None:
+        y = torch.empty((n, d_out), dtype=torch.bfloat16, device=x.device)
+    check("kfac_linear_forward", lib().kfac_linear_forward(
+        _ptr(x), n, d_in, x.stride(0) if n else d_in, _ptr(W), d_out, W.stride(0), _ptr(bias), _ptr(y),
+        y.stride(0), _stream()))
+    return y
+
+
+def linear_backward(g: torch.Tensor, x: torch.Tensor, W: torch.Tensor, with_bias: bool = True,
+                    want_dx: bool = True, Gamma: torch.Tensor = None, Gamma_bf16: torch.Tensor = None,
+                    rho: float = 0.95, scale: float = None):
+    """dx = g W (bf16), [dW | db] = g^T [x | 1] (fp32, d_out x (d_in + with_bias)), and, when
+    Gamma is given, Gamma <- rho Gamma + (1 - rho) scale g^T g in place (fused)."""
+    _require_cuda(g, x, W, Gamma, Gamma_bf16)
+    n, d_out = g.shape
+    d_in = x.shape[1]
+    assert g.dtype == torch.bfloat16 and x.dtype == torch.bfloat16 and W.dtype == torch.bfloat16
+    assert (n == 0 or (g.stride(1) == 1 and x.stride(1) == 1)) and W.stride(1) == 1 and x.shape[0] == n
+    dx = torch.empty((n, d_in), dtype=torch.bfloat16, device=g.device) if want_dx else None
+    dWb = torch.empty((d_out, d_in + (1 if with_bias else 0)), dtype=torch.float32, device=g.device)
+    if scale is None:
+        scale = 1.0 / max(n, 1)
+    if Gamma is not None:
+        assert Gamma.dtype == torch.float32 and Gamma.stride(1) == 1 and Gamma.shape == (d_out, d_out)
+    check("kfac_linear_backward", lib().kfac_linear_backward(
+        _ptr(g), n, d_out, g.stride(0) if n else d_out, _ptr(x), d_in, x.stride(0) if n else d_in, _ptr(W),
+        W.stride(0), _ptr(dx), d_in if dx is None else dx.stride(0), _ptr(dWb), dWb.stride(0),
+        1 if with_bias else 0, _ptr(Gamma), d_out if Gamma is None else Gamma.stride(0), _ptr(Gamma_bf16),
+        d_out if Gamma_bf16 is None else Gamma_bf16.stride(0), float(rho), float(scale), _stream()))
+    return dx, dWb
+
+
 def bf16_shadow(F: torch.Tensor) -> torch.Tensor:
     """bf16 copy of F whose row pitch is a multiple of 64 elements (128 bytes), so the
     bf16 sketch kernels read it with aligned 16-byte loads."""
