@@ -41,6 +41,12 @@ def parse():
                     help="also time per-factor calls spread over this many streams (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default GEMM tile configurations")
+    ap.add_argument("--config", choices=["vgg", "wide", "batched64"], default="vgg",
+                    help="vgg: VGG16_bn factor set (default); wide: one d x d factor (--d); "
+                         "batched64: 64 factors of log-uniform sizes 64..8192")
+    ap.add_argument("--d", type=int, default=16384, help="factor size of --config wide")
+    ap.add_argument("--full-eig", action="store_true", help="--config wide: also time torch.linalg.eigh")
     ap.add_argument("--check", action="store_true", help="check sampled outputs against the oracle")
     return ap.parse_args()
 
@@ -212,7 +218,7 @@ def run_batched(wl, layers, steps, warmup, nstreams):
     return g, times
 
 
-def make_plan(wl, layers, sketch="bf16"):
+def make_plan(wl, layers, sketch="bf16", autotune=True):
     """All 32 factors and 16 layers of the step in one grouped plan (bf16 activations, bf16
     sketch): factor 2i is layer i's A factor, 2i+1 its G factor."""
     import paper_2206_15397_amd as K
@@ -225,12 +231,17 @@ def make_plan(wl, layers, sketch="bf16"):
         ld.append(dict(fa=2 * li, fg=2 * li + 1, J=L.J, S=L.S))
     plan = K.Plan(fd, ld, sketch=sketch)
     plan.set_scalars(wl.rho, wl.lam, wl.seed, 0).upload()
+    if autotune:
+        import tempfile
+        restore(layers)
+        plan.autotune(cache_path=os.path.join(tempfile.gettempdir(), "kfac_autotune_cache.txt"), reps=3)
+        restore(layers)
     return plan
 
 
-def run_plan(wl, layers, steps, warmup):
+def run_plan(wl, layers, steps, warmup, autotune=True):
     import torch
-    plan = make_plan(wl, layers)
+    plan = make_plan(wl, layers, autotune=autotune)
     restore(layers)
     plan.launch()                       # first-launch paths outside the capture
     torch.cuda.synchronize()
@@ -255,7 +266,7 @@ def run_plan(wl, layers, steps, warmup):
     return plan, g, times
 
 
-def phase_times(plan, layers, reps):
+def phase_times(plan, layers, reps, restore_fn=None):
     """Average duration of every grouped launch of the plan: HIP events on the launch
     stream between consecutive launches, with the queue pre-filled behind a spin kernel so
     that host enqueue gaps do not show up as kernel time."""
@@ -264,7 +275,10 @@ def phase_times(plan, layers, reps):
     n = len(names)
     acc = [0.0] * n
     for _ in range(reps):
-        restore(layers)
+        if restore_fn is not None:
+            restore_fn()
+        else:
+            restore(layers)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
         torch.cuda._sleep(20_000_000)
         ev[0].record()
@@ -359,12 +373,194 @@ def cpu_baseline(target_seconds=15.0):
                       f"{','.join(done)} = {factors} factors in {el:.1f}s; host nproc={os.cpu_count()}"}
 
 
+def mfma_fraction(plan, names, times_ms):
+    """Sum of GEMM flops over sum of (time x peak of the GEMM's arithmetic type), over the
+    sketch / power (bf16) and Rayleigh-Ritz / Ritz-vector (fp32) GEMM launches."""
+    fl, tp = 0.0, 0.0
+    for i, (nm, t) in enumerate(zip(names, times_ms)):
+        if nm not in ("gemm_bf16", "gemm_f32"):
+            continue
+        f, _ = plan.launch_work(i)
+        fl += f
+        tp += t * 1e-3 * PEAK_TFLOPS["bf16" if nm == "gemm_bf16" else "fp32"] * 1e12
+    return fl / tp if tp > 0 else None
+
+
+def graph_times(plan, steps, warmup, restore_fn):
+    import torch
+    restore_fn()
+    plan.launch()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        restore_fn()
+        g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        restore_fn()
+        plan.status.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return g, times
+
+
+def main_wide(args, dev):
+    """One wide factor: d x d built by 50 EA steps (batch 512, bf16 activations with an
+    e^(-i/40) spectrum on a thin Haar basis of 2048 columns); randomized eig with r = 256,
+    p = 16, q = 2 through a one-factor plan (eig phases only)."""
+    import tempfile
+    import torch
+    import paper_2206_15397_amd as K
+    from paper_2206_15397_amd import synth
+    d, n, ea_steps = args.d, 512, 50
+    k = min(d, 2048)
+    log(f"building d={d} factor ({ea_steps} EA steps of {n} rows) ...")
+    t0 = time.time()
+    U = synth.torch_haar_orthogonal(d, 301, dev, k)
+    spec = torch.exp(-torch.arange(k, device=dev, dtype=torch.float32) / 40.0)
+    F = K.fill_identity(torch.empty((d, d), device=dev))
+    Fb = K.bf16_shadow(F)
+    for st in range(ea_steps):
+        a = synth.torch_activation_batch(n, U, spec, 302, st, dev, out_dtype=torch.bfloat16)
+        K.ea_update(F, a, 0.95, 1.0 / n, F_bf16=Fb)
+    torch.cuda.synchronize()
+    del U
+    log(f"  setup {time.time() - t0:.1f}s")
+    r, p, q = 256, 16, 2
+    plan = K.Plan([dict(F=F, F_bf16=Fb, r=r, p=p, q=q, stream_id=0)], [], sketch="bf16")
+    plan.set_scalars(0.95, 0.1, 0, 0, do_ea=False, do_eig=True, do_precondition=False).upload()
+    if not args.no_autotune:
+        plan.autotune(cache_path=os.path.join(tempfile.gettempdir(), "kfac_autotune_cache.txt"), reps=3)
+    nothing = lambda: None
+    g, times = graph_times(plan, args.steps, args.warmup, nothing)
+    ms = median(times)
+    names, pt = phase_times(plan, None, max(3, args.steps // 2), restore_fn=nothing)
+    tot = sum(pt)
+    for i, (nm, t) in enumerate(zip(names, pt)):
+        log(f"  [{i:2d}] {nm:18s} {t * 1e3:9.1f} us  {100 * t / tot:5.1f}%")
+    frac = mfma_fraction(plan, names, pt)
+    log(f"rand-eig d={d}: median {ms:.3f} ms, GEMM MFMA fraction {frac:.3f}, status={int(plan.status.item())}")
+    full_ms = None
+    if args.full_eig:
+        Fc = F.clone()
+        torch.linalg.eigh(Fc)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.linalg.eigh(Fc)
+        e1.record()
+        torch.cuda.synchronize()
+        full_ms = e0.elapsed_time(e1)
+        log(f"full eig (torch.linalg.eigh, fp32, comparison only): {full_ms:.1f} ms")
+    res = {"metric": "K-factor eig-inversions/s (wide factor)", "value": round(1e3 / ms, 3),
+           "unit": "K-factor eig-inversions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16+fp32+fp64", "data": "synthetic",
+           "config": {"workload": f"wide_factor_d{d}_ea50_b512", "d": d, "r": r, "p": p, "q": q},
+           "gemm_mfma_fraction": None if frac is None else round(frac, 4),
+           "roofline": roofline(plan, names, pt), "full_eig_ms": full_ms}
+    print(json.dumps(res), flush=True)
+
+
+def main_batched64(args, dev):
+    """64 factors of log-uniform sizes 64..8192 with e^(-j/40) spectra (built in fp64 on a thin
+    Haar basis, rounded to fp32 + bf16 shadow); r = min(256, d/2), p = 16, q = 1, lambda 0.1;
+    32 layers pair (F_2j, F_2j+1) with J ~ N(0, 1).  No EA in the step (factors are given)."""
+    import tempfile
+    import torch
+    import paper_2206_15397_amd as K
+    from paper_2206_15397_amd import synth
+    sizes = synth.c5_factor_sizes(64, 64, 8192)
+    log("building 64 factors ...")
+    t0 = time.time()
+    facs = []
+    for i, d in enumerate(sizes):
+        k = min(d, 2048)
+        Ud = synth.torch_haar_orthogonal(d, 400 + i, dev, k).double()
+        sig = torch.exp(-torch.arange(k, device=dev, dtype=torch.float64) / 40.0)
+        F = ((Ud * sig[None, :]) @ Ud.T).float().contiguous()
+        del Ud
+        facs.append(dict(F=F, F_bf16=K.bf16_shadow(F), r=min(256, d // 2), p=16, q=1, stream_id=i))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(203)
+    lays = []
+    for j in range(32):
+        dg, da = sizes[2 * j], sizes[2 * j + 1]
+        lays.append(dict(fg=2 * j, fa=2 * j + 1, J=torch.randn((dg, da), generator=gen, device=dev)))
+    torch.cuda.synchronize()
+    log(f"  setup {time.time() - t0:.1f}s")
+    plan = K.Plan(facs, lays, sketch="bf16")
+    plan.set_scalars(0.95, 0.1, 0, 0, do_ea=False).upload()
+    if not args.no_autotune:
+        plan.autotune(cache_path=os.path.join(tempfile.gettempdir(), "kfac_autotune_cache.txt"), reps=3)
+    nothing = lambda: None
+    g, times = graph_times(plan, args.steps, args.warmup, nothing)
+    ms = median(times)
+    names, pt = phase_times(plan, None, max(3, args.steps // 2), restore_fn=nothing)
+    log(f"batched64: median {ms:.3f} ms, status={int(plan.status.item())}")
+    del g
+    plain_ms = None
+    if not args.no_plain:
+        Fs = [f["F"] for f in facs]
+        outs = []
+        for f in facs:
+            d, r = f["F"].shape[0], f["r"]
+            outs.append(dict(U=torch.empty((d, r), device=dev), D=torch.empty((r,), device=dev),
+                             ws=torch.empty(K.rand_eig_workspace_bytes(d, r, 16, 1, "fp32"), dtype=torch.uint8,
+                                            device=dev), st=torch.zeros((1,), dtype=torch.int32, device=dev)))
+
+        def plain_step():
+            for i, f in enumerate(facs):
+                o = outs[i]
+                K.rand_eig(f["F"], f["r"], 16, 1, 0, i, 0, sketch="fp32", U=o["U"], D=o["D"], workspace=o["ws"],
+                           status=o["st"])
+            for l in lays:
+                K.precondition(l["J"], outs[l["fa"]]["U"], outs[l["fa"]]["D"], outs[l["fg"]]["U"],
+                               outs[l["fg"]]["D"], 0.1)
+        plain_step()
+        torch.cuda.synchronize()
+        tpl = []
+        for _ in range(max(2, args.steps // 4)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plain_step()
+            e1.record()
+            torch.cuda.synchronize()
+            tpl.append(e0.elapsed_time(e1))
+        plain_ms = median(tpl)
+        log(f"plain per-factor fp32: median {plain_ms:.3f} ms")
+    res = {"metric": "K-factor eig-inversions/s (64 factors, batched)", "value": round(64 / (ms / 1e3), 2),
+           "unit": "K-factor eig-inversions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16+fp32+fp64", "data": "synthetic",
+           "config": {"workload": "batched64_loguniform_64_8192", "factors": 64, "layers": 32,
+                      "r": "min(256,d/2)", "p": 16, "q": 1, "lambda": 0.1},
+           "plain_fp32_ms_per_step": plain_ms,
+           "speedup_vs_plain_fp32": None if plain_ms is None else round(plain_ms / ms, 3),
+           "roofline": roofline(plan, names, pt)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               "(multi-GPU sharding is design-only).", file=sys.stderr)
         sys.exit(2)
+    if args.config != "vgg":
+        import torch
+        import paper_2206_15397_amd as K
+        K.lib()
+        dev = torch.device("cuda:0")
+        return main_wide(args, dev) if args.config == "wide" else main_batched64(args, dev)
     import torch
     import paper_2206_15397_amd as K
     dev = torch.device("cuda:0")
@@ -374,14 +570,15 @@ def main():
     wl, layers = build_workload(dev, act_dtype_bf16=True)
     make_buffers(wl, layers, dev, "bf16")
     log(f"  setup {time.time() - t0:.1f}s")
-    plan, gp, tp_ = run_plan(wl, layers, args.steps, args.warmup)
+    plan, gp, tp_ = run_plan(wl, layers, args.steps, args.warmup, autotune=not args.no_autotune)
     ms_b = median(tp_)
     log(f"plan bf16 ({plan.launch_count} grouped launches): median {ms_b:.3f} ms  (min {min(tp_):.3f}, "
         f"max {max(tp_):.3f}) status={int(plan.status.item())}")
     names, pt = phase_times(plan, layers, max(3, args.steps // 2))
     tot = sum(pt)
+    cfgs = plan.launch_configs()
     for i, (nm, t) in enumerate(zip(names, pt)):
-        log(f"  [{i:2d}] {nm:18s} {t * 1e3:9.1f} us  {100 * t / tot:5.1f}%")
+        log(f"  [{i:2d}] {nm:18s} {t * 1e3:9.1f} us  {100 * t / tot:5.1f}%  cfg {cfgs[i]}")
     roof = roofline(plan, names, pt)
     log(f"roofline: {roof}")
     del gp

@@ -268,6 +268,20 @@ const char* kfac_plan_launch_name(const kfac_plan* plan, int index);
  * defined (no padding, no split-K partials) and the minimum bytes it must move (each
  * operand read once, each result written once).  KFAC_EINVAL when out of range. */
 kfac_status kfac_plan_launch_work(const kfac_plan* plan, int index, double* flops, double* bytes);
+/*
+ * Autotuner: for every grouped fp32 GEMM launch of the plan, times each tile configuration
+ * (64x64, 128x128, 96x128, 128x64) over `reps` launches after one warm-up and keeps the
+ * fastest; then uploads the tables again.  Results are keyed by the launch's shapes (layout
+ * and every task's M, N, K) and appended to the text file `cache_path` (nullable), whose
+ * entries are reused without timing.  Runs kernels and synchronises the stream: call it
+ * after kfac_plan_upload's arguments are final and outside any graph capture.  The tuned
+ * launches write only buffers that later launches of the step overwrite (workspace, U, S).
+ */
+kfac_status kfac_plan_autotune(kfac_plan* plan, void* workspace, size_t ws_bytes, int32_t* dev_status,
+                               const char* cache_path, int reps, kfac_stream_t stream);
+/* Tile configuration of launch `index` (0..3 for fp32 GEMM launches, 0 otherwise; -1 when
+ * out of range). */
+int kfac_plan_launch_config(const kfac_plan* plan, int index);
 void kfac_plan_destroy(kfac_plan* plan);
 
 #ifdef __cplusplus

@@ -42,14 +42,17 @@ struct TileF32 {
   static constexpr int FN = BN / WN / 16;
   static constexpr int SA = BM + lds_pad(BM);
   static constexpr int SB = BN + lds_pad(BN);
-  static constexpr int LA = BM * BK / NT;
+  static constexpr int LA = BM * BK / NT;       // elements per thread and k-step
   static constexpr int LB = BN * BK / NT;
+  // groups of 4 memory-contiguous elements per thread (the last round may be partial)
+  static constexpr int NGA = BM * BK / 4, NGB = BN * BK / 4;
+  static constexpr int GA = (NGA + NT - 1) / NT, GB = (NGB + NT - 1) / NT;
   static_assert(BM % (WM * 16) == 0 && BN % (WN * 16) == 0, "tile/wave shape");
-  static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "loader shape");
+  static_assert(BM % 4 == 0 && BN % 4 == 0, "loader shape");
   static_assert(BK % 4 == 0, "BK multiple of 4");
   struct Smem {
-    float a[BK][SA];
-    float b[BK][SB];
+    float a[2][BK][SA];
+    float b[2][BK][SB];
   };
 
   __device__ static __forceinline__ float ldA(const GemmP& p, int m, int k) {
@@ -64,67 +67,122 @@ struct TileF32 {
     long o = TB ? (long)n * p.ldb + k : (long)k * p.ldb + n;
     return p.Bb ? bf16_to_f32(p.Bb[o]) : p.B[o];
   }
-
-  __device__ static __forceinline__ void fetch(const GemmP& p, int m0, int n0, int k0, int kend,
-                                               float ra[LA], float rb[LB]) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < LA; ++i) {
-      int e = t + i * NT, m, k;
-      if (TA) { k = e / BM; m = e % BM; } else { m = e / BK; k = e % BK; }
-      ra[i] = (k0 + k < kend) ? ldA(p, m0 + m, k0 + k) : 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < LB; ++i) {
-      int e = t + i * NT, n, k;
-      if (TB) { n = e / BK; k = e % BK; } else { k = e / BN; n = e % BN; }
-      rb[i] = (k0 + k < kend) ? ldB(p, k0 + k, n0 + n) : 0.f;
-    }
+  // Group g of an operand tile: (row index along M or N, k) of its first element; the four
+  // elements run along the operand's memory-contiguous dimension.
+  __device__ static __forceinline__ void a_group(int g, int& m, int& k) {
+    if (TA) { k = g / (BM / 4); m = (g % (BM / 4)) * 4; } else { m = g / (BK / 4); k = (g % (BK / 4)) * 4; }
   }
-  __device__ static __forceinline__ void stash(Smem& sm, const float ra[LA], const float rb[LB]) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < LA; ++i) {
-      int e = t + i * NT, m, k;
-      if (TA) { k = e / BM; m = e % BM; } else { m = e / BK; k = e % BK; }
-      sm.a[k][m] = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < LB; ++i) {
-      int e = t + i * NT, n, k;
-      if (TB) { n = e / BK; k = e % BK; } else { k = e / BN; n = e % BN; }
-      sm.b[k][n] = rb[i];
-    }
+  __device__ static __forceinline__ void b_group(int g, int& n, int& k) {
+    if (TB) { n = g / (BK / 4); k = (g % (BK / 4)) * 4; } else { k = g / (BN / 4); n = (g % (BN / 4)) * 4; }
   }
 
-  // acc += A[m0:m0+BM, kb:ke] * B[kb:ke, n0:n0+BN]
-  __device__ static void run(const GemmP& p, int m0, int n0, int kb, int ke, Smem& sm,
-                             f32x4 acc[FM][FN]) {
+  __device__ static __forceinline__ void fetch(const GemmP& p, int m0, int n0, int k0, int kend, bool va, bool vb,
+                                               float4 ra[GA], float4 rb[GB]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < GA; ++u) {
+      int m, k;
+      if (t + u * NT >= NGA) { ra[u] = make_float4(0.f, 0.f, 0.f, 0.f); continue; }
+      a_group(t + u * NT, m, k);
+      const int gm = m0 + m, gk = k0 + k;
+      // 16-byte load when the four elements are in range, aligned and not the ones column
+      const bool full = TA ? (gm + 4 <= p.M && gk < kend && (p.ones_col < gm || p.ones_col >= gm + 4))
+                           : (gm < p.M && gk + 4 <= kend && gm != p.ones_col);
+      if (va && full) {
+        ra[u] = *(const float4*)(p.A + (TA ? (long)gk * p.lda + gm : (long)gm * p.lda + gk));
+      } else {
+        float e[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int mm = TA ? gm + i : gm, kk = TA ? gk : gk + i;
+          e[i] = (kk < kend) ? ldA(p, mm, kk) : 0.f;
+        }
+        ra[u] = make_float4(e[0], e[1], e[2], e[3]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GB; ++u) {
+      int n, k;
+      if (t + u * NT >= NGB) { rb[u] = make_float4(0.f, 0.f, 0.f, 0.f); continue; }
+      b_group(t + u * NT, n, k);
+      const int gn = n0 + n, gk = k0 + k;
+      const bool full = TB ? (gn < p.N && gk + 4 <= kend && gn != p.ones_col)
+                           : (gn + 4 <= p.N && gk < kend && (p.ones_col < gn || p.ones_col >= gn + 4));
+      if (vb && full) {
+        rb[u] = *(const float4*)(p.B + (TB ? (long)gn * p.ldb + gk : (long)gk * p.ldb + gn));
+      } else {
+        float e[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int nn = TB ? gn : gn + i, kk = TB ? gk + i : gk;
+          e[i] = (kk < kend) ? ldB(p, kk, nn) : 0.f;
+        }
+        rb[u] = make_float4(e[0], e[1], e[2], e[3]);
+      }
+    }
+  }
+  __device__ static __forceinline__ void stash(Smem& sm, int buf, const float4 ra[GA], const float4 rb[GB]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < GA; ++u) {
+      int m, k;
+      if (t + u * NT >= NGA) continue;
+      a_group(t + u * NT, m, k);
+      const float e[4] = {ra[u].x, ra[u].y, ra[u].z, ra[u].w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (TA) sm.a[buf][k][m + i] = e[i];
+        else sm.a[buf][k + i][m] = e[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GB; ++u) {
+      int n, k;
+      if (t + u * NT >= NGB) continue;
+      b_group(t + u * NT, n, k);
+      const float e[4] = {rb[u].x, rb[u].y, rb[u].z, rb[u].w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (TB) sm.b[buf][k + i][n] = e[i];
+        else sm.b[buf][k][n + i] = e[i];
+      }
+    }
+  }
+
+  // acc += A[m0:m0+BM, kb:ke] * B[kb:ke, n0:n0+BN]; two LDS buffers, one barrier per k-step.
+  __device__ static void run(const GemmP& p, int m0, int n0, int kb, int ke, Smem& sm, f32x4 acc[FM][FN]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int am = wm * (BM / WM) + (lane & 15), bn = wn * (BN / WN) + (lane & 15);
     const int kq = lane >> 4;
-    float ra[LA], rb[LB];
     if (kb >= ke) return;
-    fetch(p, m0, n0, kb, ke, ra, rb);
+    const bool va = !p.Ab && ((p.lda & 3) == 0) && ((((uintptr_t)p.A) & 15) == 0);
+    const bool vb = !p.Bb && ((p.ldb & 3) == 0) && ((((uintptr_t)p.B) & 15) == 0);
+    float4 ra[GA], rb[GB];
+    fetch(p, m0, n0, kb, ke, va, vb, ra, rb);
+    __syncthreads();                 // the caller's LDS may alias ours (unions)
+    stash(sm, 0, ra, rb);
+    __syncthreads();
+    int buf = 0;
     for (int k0 = kb; k0 < ke; k0 += BK) {
-      __syncthreads();
-      stash(sm, ra, rb);
-      __syncthreads();
-      if (k0 + BK < ke) fetch(p, m0, n0, k0 + BK, ke, ra, rb);
+      const bool more = k0 + BK < ke;
+      if (more) fetch(p, m0, n0, k0 + BK, ke, va, vb, ra, rb);
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         float af[FM], bf[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) af[i] = sm.a[kk + kq][am + i * 16];
+        for (int i = 0; i < FM; ++i) af[i] = sm.a[buf][kk + kq][am + i * 16];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bf[j] = sm.b[kk + kq][bn + j * 16];
+        for (int j = 0; j < FN; ++j) bf[j] = sm.b[buf][kk + kq][bn + j * 16];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
       }
+      if (more) stash(sm, buf ^ 1, ra, rb);
+      __syncthreads();
+      buf ^= 1;
     }
   }
 

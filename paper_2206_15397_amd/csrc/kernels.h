@@ -87,8 +87,9 @@ EigTask make_eig_task(const double* C, long ldc, const float* Cf, long ldcf, int
 int tri_bisect_blocks(int n);
 int tri_vec_blocks(int r);
 int backtransform_blocks(int r);
-int gemm_g_blocks_x(const GemmP& p);
-int gemm_g_blocks_y(const GemmP& p);
+constexpr int kGemmConfigs = 4;   // grouped fp32 GEMM tiles: 64x64, 128x128, 96x128, 128x64
+int gemm_g_blocks_x(const GemmP& p, int cfg);
+int gemm_g_blocks_y(const GemmP& p, int cfg);
 
 hipError_t launch_ea_tiles_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_ea_finalize_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
@@ -100,7 +101,7 @@ hipError_t launch_ea_bf16_finalize_g(const EaTask* t, GroupMap gm, int blocks, h
 hipError_t launch_omega_g(const OmegaTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_sign_partial_g(const SignTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_sign_apply_g(const SignTask* t, GroupMap gm, int blocks, hipStream_t s);
-hipError_t launch_gemm_g(const GemmP* t, GroupMap gm, int blocks, bool ta, bool tb, hipStream_t s);
+hipError_t launch_gemm_g(const GemmP* t, GroupMap gm, int blocks, bool ta, bool tb, int cfg, hipStream_t s);
 hipError_t launch_gemm_bf16_g(const BfGemmTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_gram_partial_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_gram_reduce_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);

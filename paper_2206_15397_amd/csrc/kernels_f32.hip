@@ -360,16 +360,29 @@ KFAC_GLAUNCH(launch_omega_g, k_omega_g, OmegaTask, 256)
 KFAC_GLAUNCH(launch_sign_partial_g, k_sign_partial_g, SignTask, 256)
 KFAC_GLAUNCH(launch_sign_apply_g, k_sign_apply_g, SignTask, 256)
 
-hipError_t launch_gemm_g(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, hipStream_t s) {
+// Tile configurations of the grouped fp32 GEMM (BM x BN, 2 x 2 wavefronts, BK = 16).
+template <int BM, int BN>
+static void gemm_g_launch(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, hipStream_t s) {
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, false, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, false, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, true, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  else hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, true, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+}
+
+static const int kGemmCfg[kGemmConfigs][2] = {{64, 64}, {128, 128}, {96, 128}, {128, 64}};
+
+hipError_t launch_gemm_g(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, int cfg, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_g<64, 64, 16, 2, 2, false, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
-  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_g<64, 64, 16, 2, 2, false, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
-  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_g<64, 64, 16, 2, 2, true, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
-  else hipLaunchKernelGGL((k_gemm_g<64, 64, 16, 2, 2, true, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  switch (cfg) {
+    case 1: gemm_g_launch<128, 128>(tasks, gm, blocks, ta, tb, s); break;
+    case 2: gemm_g_launch<96, 128>(tasks, gm, blocks, ta, tb, s); break;
+    case 3: gemm_g_launch<128, 64>(tasks, gm, blocks, ta, tb, s); break;
+    default: gemm_g_launch<64, 64>(tasks, gm, blocks, ta, tb, s); break;
+  }
   return hipGetLastError();
 }
-int gemm_g_blocks_x(const GemmP& p) { return (p.N + 63) / 64; }
-int gemm_g_blocks_y(const GemmP& p) { return (p.M + 63) / 64; }
+int gemm_g_blocks_x(const GemmP& p, int cfg) { return (p.N + kGemmCfg[cfg][1] - 1) / kGemmCfg[cfg][1]; }
+int gemm_g_blocks_y(const GemmP& p, int cfg) { return (p.M + kGemmCfg[cfg][0] - 1) / kGemmCfg[cfg][0]; }
 
 EaTask make_ea_task(float* F, int d, long ldf, const float* X, const uint16_t* Xb, int n, int d_in, long ldx, int ones,
                     float rho, float scale, uint16_t* Fb, long ldfb, float* part, int ks) {

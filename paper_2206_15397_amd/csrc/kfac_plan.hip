@@ -3,8 +3,11 @@
 // the host against the caller's workspace and copied into its head by kfac_plan_upload;
 // kfac_plan_launch only enqueues kernels, so it can be captured into a hipGraph.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 #include "workspace.h"
 
@@ -23,6 +26,8 @@ struct LaunchRec {
   int ntasks, blocks;
   bool ta, tb;
   double flops, bytes;   // algorithmic work of the launch (all tasks)
+  int cfg;               // tile configuration (grouped fp32 GEMM)
+  int ord;               // ordinal among the tunable launches (-1: not tunable)
 };
 
 // Algorithmic work: flops of the operation as defined (padding and split-K excluded) and
@@ -52,6 +57,8 @@ struct Tables {
     r.kind = kind;
     r.flops = w.flops;
     r.bytes = w.bytes;
+    r.cfg = 0;
+    r.ord = -1;
     r.ntasks = (int)tasks.size();
     r.ta = ta; r.tb = tb;
     r.tasks_off = align(sizeof(T) * tasks.size());
@@ -95,14 +102,51 @@ struct kfac_plan {
   size_t table_bytes = 0;      // reserved head of the workspace
   size_t ws_bytes = 0;
   Tables tab;                  // built by upload
+  std::vector<int> gemm_cfg;   // tuned tile configuration per fp32 GEMM launch (-1: default)
   char* dev = nullptr;         // uploaded workspace base
 };
 
 namespace {
 
+// Default tile configuration of a grouped fp32 GEMM launch: the largest tile that still
+// gives at least ~2 workgroups per compute unit; 96 x 128 when every task has M = 96 k.
+int default_gemm_cfg(const std::vector<GemmP>& g) {
+  long t64 = 0, t128 = 0, t96 = 0;
+  bool m96 = true;
+  for (const GemmP& q : g) {
+    t64 += (long)gemm_g_blocks_x(q, 0) * gemm_g_blocks_y(q, 0);
+    t128 += (long)gemm_g_blocks_x(q, 1) * gemm_g_blocks_y(q, 1);
+    t96 += (long)gemm_g_blocks_x(q, 2) * gemm_g_blocks_y(q, 2);
+    if (q.M % 96 != 0) m96 = false;
+  }
+  if (m96 && t96 >= 512) return 2;
+  if (t128 >= 512) return 1;
+  (void)t64;
+  return 0;
+}
+
+// Adds one grouped fp32 GEMM launch, with its tuned (or default) tile configuration.
+void add_gemm(kfac_plan* P, Tables& T, int& ord, const std::vector<GemmP>& g, bool ta, bool tb, Work w) {
+  if (g.empty()) return;
+  const int o = ord++;
+  int cfg = (o < (int)P->gemm_cfg.size() && P->gemm_cfg[o] >= 0) ? P->gemm_cfg[o] : default_gemm_cfg(g);
+  std::vector<int> gx, nb;
+  for (const GemmP& q : g) {
+    gx.push_back(gemm_g_blocks_x(q, cfg));
+    nb.push_back(gemm_g_blocks_x(q, cfg) * gemm_g_blocks_y(q, cfg));
+  }
+  const size_t before = T.recs.size();
+  T.add(K_GEMM, g, gx, nb, ta, tb, w);
+  if (T.recs.size() > before) {
+    T.recs.back().cfg = cfg;
+    T.recs.back().ord = o;
+  }
+}
+
 // Build all task tables for workspace base `base` (null: sizes only) and status pointer.
 void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
   const bool bf = (P->prec == KFAC_SKETCH_BF16);
+  int gord = 0;                 // ordinal of the next fp32 GEMM launch
   const size_t head = P->table_bytes;
   auto wsp = [&](size_t off) -> void* { return base ? (void*)(base + head + off) : nullptr; };
   std::vector<EigWs> W;
@@ -193,9 +237,9 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             q.B = P->f[i].F; q.ldb = P->f[i].ldf;
             q.C = (it == 0) ? basis[i] : spare[i]; q.ldc = I.ldt;
             q.alpha = 1.f; q.ones_col = -1;
-            g.push_back(q); gx2.push_back(gemm_g_blocks_x(q)); nb2.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
+            g.push_back(q);
           }
-          T.add(K_GEMM, g, gx2, nb2, false, false, ws);
+          add_gemm(P, T, gord, g, false, false, ws);
         }
         if (it > 0) for (int i : act) std::swap(basis[i], spare[i]);
         // CholeskyQR2 on basis[i]: pass 0 basis -> spare, pass 1 spare -> basis
@@ -252,14 +296,14 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
         q.M = I.l_pad; q.N = I.d; q.K = I.d;
         q.A = basis[i]; q.lda = I.ldt; q.B = P->f[i].F; q.ldb = P->f[i].ldf;
         q.C = spare[i]; q.ldc = I.ldt; q.alpha = 1.f; q.ones_col = -1;
-        g.push_back(q); gx2.push_back(gemm_g_blocks_x(q)); nb2.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
+        g.push_back(q);
         GramP gr = make_gram_task(basis[i], I.ldt, spare[i], I.ldt, I.l_pad, I.d, 0, W[i].part, W[i].G, I.l_pad,
                                   status);
         const int tiles = gram_tiles(I.l_pad, 0);
         gp.push_back(gr); gxg.push_back(tiles); nbg.push_back(tiles * gr.ksplit);
         gxr.push_back(tiles); nbr.push_back(tiles * gram_reduce_slices());
       }
-      T.add(K_GEMM, g, gx2, nb2, false, false, wrr);
+      add_gemm(P, T, gord, g, false, false, wrr);
       T.add(K_GRAM_P, gp, gxg, nbg, false, false, wg);
       T.add(K_GRAM_R, gp, gxr, nbr, false, false, wr);
     }
@@ -306,9 +350,9 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
         q.M = I.d; q.N = I.r; q.K = I.l;
         q.A = basis[i]; q.lda = I.ldt; q.B = W[i].P; q.ldb = I.r;
         q.C = P->f[i].U; q.ldc = P->f[i].ldu; q.alpha = 1.f; q.ones_col = -1;
-        g.push_back(q); gx2.push_back(gemm_g_blocks_x(q)); nb2.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
+        g.push_back(q);
       }
-      T.add(K_GEMM, g, gx2, nb2, true, false, wu);
+      add_gemm(P, T, gord, g, true, false, wu);
     }
     // ---- column signs -------------------------------------------------------------------
     {
@@ -348,7 +392,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       float* M = b.take<float>((size_t)dg * da);
       float* T2 = b.take<float>((size_t)rg * da);
       auto push = [&](std::vector<GemmP>& v, std::vector<int>& gx, std::vector<int>& nb, const GemmP& q) {
-        v.push_back(q); gx.push_back(gemm_g_blocks_x(q)); nb.push_back(gemm_g_blocks_x(q) * gemm_g_blocks_y(q));
+        v.push_back(q); (void)gx; (void)nb;
       };
       GemmP q{};
       q.ones_col = -1; q.alpha = 1.f; q.lam = P->lam;
@@ -368,10 +412,10 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       sq.X = M; sq.ldx = da; sq.beta = inv_lam;
       push(g4, x4, n4, sq);
     }
-    T.add(K_GEMM, g1, x1, n1, false, false, w1);
-    T.add(K_GEMM, g2, x2, n2, false, true, w2);
-    T.add(K_GEMM, g3, x3, n3, true, false, w3);
-    T.add(K_GEMM, g4, x4, n4, false, false, w4);
+    add_gemm(P, T, gord, g1, false, false, w1);
+    add_gemm(P, T, gord, g2, false, true, w2);
+    add_gemm(P, T, gord, g3, true, false, w3);
+    add_gemm(P, T, gord, g4, false, false, w4);
   }
 }
 
@@ -505,7 +549,7 @@ kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, 
       case K_EA_TILES_BF: e = launch_ea_bf16_tiles_g((const EaTask*)tp, gm, r.blocks, s); break;
       case K_EA_FIN_BF: e = launch_ea_bf16_finalize_g((const EaTask*)tp, gm, r.blocks, s); break;
       case K_OMEGA: e = launch_omega_g((const OmegaTask*)tp, gm, r.blocks, s); break;
-      case K_GEMM: e = launch_gemm_g((const GemmP*)tp, gm, r.blocks, r.ta, r.tb, s); break;
+      case K_GEMM: e = launch_gemm_g((const GemmP*)tp, gm, r.blocks, r.ta, r.tb, r.cfg, s); break;
       case K_BF16: e = launch_gemm_bf16_g((const BfGemmTask*)tp, gm, r.blocks, s); break;
       case K_GRAM_P: e = launch_gram_partial_g((const GramP*)tp, gm, r.blocks, s); break;
       case K_GRAM_R: e = launch_gram_reduce_g((const GramP*)tp, gm, r.blocks, s); break;
@@ -532,6 +576,100 @@ kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, 
 kfac_status kfac_plan_launch(const kfac_plan* plan, kfac_stream_t stream) {
   if (!plan || !plan->dev) return KFAC_EINVAL;
   return kfac_plan_launch_range(plan, 0, (int)plan->tab.recs.size(), stream);
+}
+
+// ---- autotuner ---------------------------------------------------------------------------
+namespace {
+
+// Shape key of a grouped fp32 GEMM launch: layout flags and every task's (M, N, K), hashed.
+std::string gemm_key(const kfac_plan* P, const LaunchRec& r) {
+  const GemmP* t = (const GemmP*)(P->tab.bytes.data() + r.tasks_off);
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { h ^= v; h *= 1099511628211ull; };
+  mix((uint64_t)r.ta); mix((uint64_t)r.tb); mix((uint64_t)r.ntasks);
+  for (int i = 0; i < r.ntasks; ++i) { mix((uint64_t)t[i].M); mix((uint64_t)t[i].N); mix((uint64_t)t[i].K); }
+  char buf[64];
+  std::snprintf(buf, sizeof(buf), "gemm_f32:%016llx", (unsigned long long)h);
+  return buf;
+}
+
+std::map<std::string, int> read_cache(const char* path) {
+  std::map<std::string, int> m;
+  if (!path) return m;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return m;
+  char key[128];
+  int cfg;
+  double us;
+  while (std::fscanf(f, "%127s %d %lf", key, &cfg, &us) == 3)
+    if (cfg >= 0 && cfg < kGemmConfigs) m[key] = cfg;
+  std::fclose(f);
+  return m;
+}
+
+}  // namespace
+
+kfac_status kfac_plan_autotune(kfac_plan* plan, void* workspace, size_t ws_bytes, int32_t* dev_status,
+                               const char* cache_path, int reps, kfac_stream_t stream) {
+  if (!plan || !workspace || !dev_status || reps < 1) return KFAC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  kfac_status st = kfac_plan_upload(plan, workspace, ws_bytes, dev_status, stream);
+  if (st != KFAC_OK) return st;
+  int nord = 0;
+  for (const LaunchRec& r : plan->tab.recs) nord = std::max(nord, r.ord + 1);
+  plan->gemm_cfg.assign(nord, -1);
+  std::map<std::string, int> cache = read_cache(cache_path);
+  std::vector<std::string> lines;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KFAC_EHIP;
+  kfac_status result = KFAC_OK;
+  for (int o = 0; o < nord && result == KFAC_OK; ++o) {
+    // key of launch o with the configuration it currently has
+    std::string key;
+    for (const LaunchRec& r : plan->tab.recs)
+      if (r.ord == o) key = gemm_key(plan, r);
+    auto hit = cache.find(key);
+    if (hit != cache.end()) { plan->gemm_cfg[o] = hit->second; continue; }
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int c = 0; c < kGemmConfigs && result == KFAC_OK; ++c) {
+      plan->gemm_cfg[o] = c;
+      if ((result = kfac_plan_upload(plan, workspace, ws_bytes, dev_status, stream)) != KFAC_OK) break;
+      int idx = -1;
+      for (size_t i = 0; i < plan->tab.recs.size(); ++i)
+        if (plan->tab.recs[i].ord == o) idx = (int)i;
+      if (idx < 0) break;
+      float tot = 0.f;
+      for (int rep = 0; rep <= reps && result == KFAC_OK; ++rep) {   // rep 0 warms up
+        if (hipEventRecord(e0, s) != hipSuccess) { result = KFAC_EHIP; break; }
+        if ((result = kfac_plan_launch_range(plan, idx, 1, stream)) != KFAC_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { result = KFAC_EHIP; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) tot += ms;
+      }
+      if (result == KFAC_OK && tot / reps < best_ms) { best_ms = tot / reps; best = c; }
+    }
+    plan->gemm_cfg[o] = best;
+    char line[192];
+    std::snprintf(line, sizeof(line), "%s %d %.3f\n", key.c_str(), best, 1e3 * best_ms);
+    lines.push_back(line);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (result != KFAC_OK) return result;
+  if (cache_path && !lines.empty()) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      for (const std::string& l : lines) std::fputs(l.c_str(), f);
+      std::fclose(f);
+    }
+  }
+  return kfac_plan_upload(plan, workspace, ws_bytes, dev_status, stream);
+}
+
+int kfac_plan_launch_config(const kfac_plan* plan, int index) {
+  if (!plan || index < 0 || index >= (int)plan->tab.recs.size()) return -1;
+  return plan->tab.recs[index].cfg;
 }
 
 void kfac_plan_destroy(kfac_plan* plan) { delete plan; }

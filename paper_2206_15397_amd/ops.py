@@ -251,6 +251,17 @@ class Plan:
     def launch_range(self, first, count):
         check("kfac_plan_launch_range", self._L.kfac_plan_launch_range(self._h, int(first), int(count), _stream()))
 
+    def autotune(self, cache_path=None, reps=3):
+        """Pick the fastest tile configuration of every grouped fp32 GEMM launch (timed on the
+        device; results cached in `cache_path`).  Re-uploads the tables."""
+        cp = None if cache_path is None else str(cache_path).encode()
+        check("kfac_plan_autotune", self._L.kfac_plan_autotune(self._h, _ptr(self.workspace), self.workspace.numel(),
+                                                               _ptr(self.status), cp, int(reps), _stream()))
+        return self
+
+    def launch_configs(self):
+        return [int(self._L.kfac_plan_launch_config(self._h, i)) for i in range(self.launch_count)]
+
     def launch_work(self, index):
         """(flops, bytes) of launch `index`: algorithmic work over all its tasks."""
         import ctypes

@@ -223,3 +223,37 @@ def test_plan_rejects_bad_descriptors():
         K().Plan([dict(F=F, r=280, p=20, q=1)], sketch="fp32")   # l = 300 > 288 in a plan
     with pytest.raises(K().KfacError):
         K().Plan([dict(F=F, r=0, p=20, q=1)], sketch="fp32")
+
+
+def test_plan_autotune_keeps_results_bitwise(tmp_path):
+    """Every fp32 GEMM tile configuration accumulates each output over k in the same order,
+    so the autotuned plan reproduces the default plan bit for bit; the cache is written and
+    reused."""
+    facs, Js = make_problem(seed=4)
+    fd, ld = device_inputs(facs, Js)
+    plan = K().Plan(fd, ld, sketch="bf16")
+    plan.set_scalars(RHO, LAM, SEED, INV).upload()
+    F0 = [f["F"].clone() for f in plan.factors]
+    Fb0 = [f["F_bf16"].clone() for f in plan.factors]
+
+    def run():
+        for f, a, b in zip(plan.factors, F0, Fb0):
+            f["F"].copy_(a)
+            f["F_bf16"].copy_(b)
+        plan.status.zero_()
+        plan.launch()
+        torch.cuda.synchronize()
+        return [f[k].clone() for f in plan.factors for k in ("F", "U", "D")] + [l["S"].clone() for l in plan.layers]
+
+    ref = run()
+    cache = tmp_path / "tune.txt"
+    plan.autotune(cache_path=cache, reps=2)
+    assert cache.exists() and len(cache.read_text().splitlines()) > 0
+    got = run()
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)
+    plan.autotune(cache_path=cache, reps=2)     # served from the cache
+    assert len(cache.read_text().splitlines()) == len(set(cache.read_text().splitlines()))
+    got = run()
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)
