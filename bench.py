@@ -297,7 +297,7 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 # arithmetic type and unit kind of each grouped launch: "mfma" for matrix-core kernels,
 # "alu" for the fp64 vector kernels (single-workgroup factorisations and eigensolver)
 KIND = {
-    "ea_tiles_bf16": ("bf16", "mfma"), "gemm_bf16": ("bf16", "mfma"),
+    "ea_tiles_bf16": ("bf16", "mfma"), "gemm_bf16": ("bf16", "mfma"), "gemm_bf16_skinny": ("bf16", "mfma"),
     "ea_tiles": ("fp32", "mfma"), "gemm_f32": ("fp32", "mfma"),
     "gram_partial": ("fp64", "mfma"), "trmm": ("fp64", "mfma"),
     "cholinv": ("fp64", "alu"), "trtri_cols": ("fp64", "mfma"),
@@ -378,11 +378,11 @@ def mfma_fraction(plan, names, times_ms):
     sketch / power (bf16) and Rayleigh-Ritz / Ritz-vector (fp32) GEMM launches."""
     fl, tp = 0.0, 0.0
     for i, (nm, t) in enumerate(zip(names, times_ms)):
-        if nm not in ("gemm_bf16", "gemm_f32"):
+        if nm not in ("gemm_bf16", "gemm_bf16_skinny", "skinny_reduce", "gemm_f32"):
             continue
         f, _ = plan.launch_work(i)
         fl += f
-        tp += t * 1e-3 * PEAK_TFLOPS["bf16" if nm == "gemm_bf16" else "fp32"] * 1e12
+        tp += t * 1e-3 * PEAK_TFLOPS["fp32" if nm == "gemm_f32" else "bf16"] * 1e12
     return fl / tp if tp > 0 else None
 
 

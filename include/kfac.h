@@ -270,16 +270,24 @@ const char* kfac_plan_launch_name(const kfac_plan* plan, int index);
 kfac_status kfac_plan_launch_work(const kfac_plan* plan, int index, double* flops, double* bytes);
 /*
  * Autotuner: for every grouped fp32 GEMM launch of the plan, times each tile configuration
- * (64x64, 128x128, 96x128, 128x64) over `reps` launches after one warm-up and keeps the
- * fastest; then uploads the tables again.  Results are keyed by the launch's shapes (layout
+ * (64x64, 128x128, 96x128, 128x64, and 288x64 over the whole sketch width where M <= 288 and
+ * no operand is transposed), and for every bf16 sketch / power-iteration launch each
+ * kernel (96x128 tiles, or full-sketch-width tiles with split-K and its reduction), over
+ * `reps` launches after one warm-up, and keeps the fastest; then uploads the tables again.  Results are keyed by the launch's shapes (layout
  * and every task's M, N, K) and appended to the text file `cache_path` (nullable), whose
  * entries are reused without timing.  Runs kernels and synchronises the stream: call it
  * after kfac_plan_upload's arguments are final and outside any graph capture.  The tuned
  * launches write only buffers that later launches of the step overwrite (workspace, U, S).
+ * With the environment variable KFAC_AUTOTUNE_VERBOSE set (non-zero), every candidate's
+ * time is printed to stderr.
  */
 kfac_status kfac_plan_autotune(kfac_plan* plan, void* workspace, size_t ws_bytes, int32_t* dev_status,
                                const char* cache_path, int reps, kfac_stream_t stream);
-/* Tile configuration of launch `index` (0..3 for fp32 GEMM launches, 0 otherwise; -1 when
+/* Sets every fp32 GEMM launch to configuration cfg_gemm_f32 (0..4; 4, the whole-sketch-width
+ * tile, only where it applies) and every bf16 sketch launch to cfg_sketch_bf16 (0..1); -1
+ * keeps the default.  Takes effect at the next kfac_plan_upload.  For tests and experiments. */
+kfac_status kfac_plan_force_config(kfac_plan* plan, int cfg_gemm_f32, int cfg_sketch_bf16);
+/* Configuration of launch `index` (fp32 GEMM: 0..4; bf16 sketch: 0..1; 0 otherwise; -1 when
  * out of range). */
 int kfac_plan_launch_config(const kfac_plan* plan, int index);
 void kfac_plan_destroy(kfac_plan* plan);

@@ -43,6 +43,7 @@ SIGNATURES = {
     "kfac_plan_launch_name": (ctypes.c_char_p, [_p, _i]),
     "kfac_plan_launch_work": (_i, [_p, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "kfac_plan_autotune": (_i, [_p, _p, _sz, _p, ctypes.c_char_p, _i, _p]),
+    "kfac_plan_force_config": (_i, [_p, _i, _i]),
     "kfac_plan_launch_config": (_i, [_p, _i]),
     "kfac_plan_destroy": (None, [_p]),
 }

@@ -35,6 +35,13 @@ struct GemmP {
 
 __host__ __device__ constexpr int lds_pad(int bm) { return ((16 - bm) % 64 + 64) % 64; }
 
+// Element j (run-time, 0..3) of a float4, by selects (no dynamic register indexing).
+__device__ __forceinline__ float f4_elem(const float4& v, int j) {
+  const float a = (j & 1) ? v.y : v.x;
+  const float b = (j & 1) ? v.w : v.z;
+  return (j & 2) ? b : a;
+}
+
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 struct TileF32 {
   static constexpr int NT = WM * WN * kWave;
@@ -50,7 +57,7 @@ struct TileF32 {
   static_assert(BM % (WM * 16) == 0 && BN % (WN * 16) == 0, "tile/wave shape");
   static_assert(BM % 4 == 0 && BN % 4 == 0, "loader shape");
   static_assert(BK % 4 == 0, "BK multiple of 4");
-  struct Smem {
+  struct alignas(16) Smem {
     float a[2][BK][SA];
     float b[2][BK][SB];
   };
@@ -128,11 +135,17 @@ struct TileF32 {
       int m, k;
       if (t + u * NT >= NGA) continue;
       a_group(t + u * NT, m, k);
-      const float e[4] = {ra[u].x, ra[u].y, ra[u].z, ra[u].w};
+      if (TA) {
+        *(float4*)&sm.a[buf][k][m] = ra[u];          // four consecutive m: one 16-byte store
+      } else {
+        // four consecutive k of one m: rotate the order by k/4 so the lanes of one store
+        // hit four different k-rows (bank groups) instead of the same one
+        const int rot = (k >> 2) & 3;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        if (TA) sm.a[buf][k][m + i] = e[i];
-        else sm.a[buf][k + i][m] = e[i];
+        for (int i = 0; i < 4; ++i) {
+          const int j = (i + rot) & 3;
+          sm.a[buf][k + j][m] = f4_elem(ra[u], j);
+        }
       }
     }
 #pragma unroll
@@ -140,11 +153,15 @@ struct TileF32 {
       int n, k;
       if (t + u * NT >= NGB) continue;
       b_group(t + u * NT, n, k);
-      const float e[4] = {rb[u].x, rb[u].y, rb[u].z, rb[u].w};
+      if (!TB) {
+        *(float4*)&sm.b[buf][k][n] = rb[u];
+      } else {
+        const int rot = (k >> 2) & 3;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        if (TB) sm.b[buf][k + i][n] = e[i];
-        else sm.b[buf][k][n + i] = e[i];
+        for (int i = 0; i < 4; ++i) {
+          const int j = (i + rot) & 3;
+          sm.b[buf][k + j][n] = f4_elem(rb[u], j);
+        }
       }
     }
   }

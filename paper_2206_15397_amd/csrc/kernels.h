@@ -75,6 +75,15 @@ dim3 omega_grid(const OmegaTask& p);
 BfGemmTask make_bf16_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, float* C,
                           long ldc);
 int bf16_task_blocks(const BfGemmTask& q);
+// skinny sketch GEMM (M <= 288): grouped launch + split-K reduction
+int skinny_ksplit(int N, int K);
+SkinnyTask make_skinny_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, float* C,
+                            long ldc, float* part, int ksplit);
+int skinny_blocks(const SkinnyTask& q);
+int skinny_reduce_blocks(const SkinnyTask& q);
+size_t skinny_part_bytes(int M, int N, int K);
+hipError_t launch_skinny_g(const SkinnyTask* t, GroupMap gm, int blocks, hipStream_t s);
+hipError_t launch_skinny_reduce_g(const SkinnyTask* t, GroupMap gm, int blocks, hipStream_t s);
 GramP make_gram_task(const float* A, long lda, const float* B, long ldb, int L, int K, int sym, double* part,
                      double* C, long ldc, int* status);
 int gram_tiles(int L, int sym);
@@ -87,7 +96,9 @@ EigTask make_eig_task(const double* C, long ldc, const float* Cf, long ldcf, int
 int tri_bisect_blocks(int n);
 int tri_vec_blocks(int r);
 int backtransform_blocks(int r);
-constexpr int kGemmConfigs = 4;   // grouped fp32 GEMM tiles: 64x64, 128x128, 96x128, 128x64
+// grouped fp32 GEMM tiles: 64x64, 128x128, 96x128, 128x64, and 288x64 "skinny" (whole
+// sketch width, no transposes, M <= 288)
+constexpr int kGemmConfigs = 5;
 int gemm_g_blocks_x(const GemmP& p, int cfg);
 int gemm_g_blocks_y(const GemmP& p, int cfg);
 

@@ -132,7 +132,7 @@ __device__ __forceinline__ void gemm_bf16_body(const BfGemmTask& q, int bx, int)
 // row pitch keeps both the 16-lane column stores and the 16-lane operand reads on
 // distinct banks.
 constexpr int EB_BT = kEaBf16Tile, EB_BK = 64, EB_SK = EB_BK + 8;
-struct EbSmem {
+struct alignas(16) EbSmem {
   union {
     struct {
       uint16_t a[2][EB_BT][EB_SK];
@@ -318,4 +318,157 @@ hipError_t launch_gemm_bf16_g(const BfGemmTask* tasks, GroupMap gm, int blocks, 
   if (blocks > 0) hipLaunchKernelGGL(k_gemm_bf16_nt_g, dim3(blocks), dim3(256), 0, s, tasks, gm);
   return hipGetLastError();
 }
+// ------------------------------------------------------------------------------------
+// Skinny sketch GEMM for the range finder (Alg. 3 "compute X Omega" and the power
+// iterations): C[M x N] = A[M x K] B[N x K]^T with M = l_pad <= 288 (the sketch width)
+// and N = K = d large.  A workgroup owns all M rows and 256 columns of C over one K slice,
+// so every element of F (B) is read once per slice and each 32-deep step issues 36 MFMAs
+// per wavefront for 13 LDS operand reads.  8 wavefronts as 2 (M) x 4 (N), each 144 x 64
+// (9 x 4 tiles of 16 x 16); BK = 64 with two LDS buffers.  K slices write fp32 partials
+// that a second launch sums in slice order.
+constexpr int SK_BN = 256, SK_MMAX = 288, SK_BK = 64, SK_SK = SK_BK + 8, SK_NT = 512;
+struct alignas(16) SkSmem {
+  uint16_t a[2][SK_MMAX][SK_SK];
+  uint16_t b[2][SK_BN][SK_SK];
+};
+constexpr int SK_VA = (SK_MMAX * SK_BK / 8 + SK_NT - 1) / SK_NT;   // 16-byte vectors per thread
+constexpr int SK_VB = SK_BN * SK_BK / 8 / SK_NT;
+
+__device__ __forceinline__ void skinny_body(const SkinnyTask& q, int bx, int by) {
+  __shared__ SkSmem sm;
+  const int tn = bx, ks = by;                        // grid width = tiles_n
+  const int n0 = tn * SK_BN;
+  const int M = q.M, N = q.N, K = q.K;
+  const int kchunk = ((K + q.ksplit - 1) / q.ksplit + SK_BK - 1) / SK_BK * SK_BK;
+  const int kb = ks * kchunk, ke = min(K, kb + kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int mt = (M + 15) / 16;                      // m tiles present
+  f32x4 acc[9][4];
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra[SK_VA], rb[SK_VB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < SK_VA; ++u) {
+      const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
+      ra[u] = (e < SK_MMAX * SK_BK / 8 && row < M) ? ld16(q.A, q.lda, row, M, k0 + kc, ke) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < SK_VB; ++u) {
+      const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
+      rb[u] = ld16(q.B, q.ldb, n0 + row, N, k0 + kc, ke);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < SK_VA; ++u) {
+      const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
+      if (e < SK_MMAX * SK_BK / 8) *(uint4*)&sm.a[buf][row][kc] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < SK_VB; ++u) {
+      const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
+      *(uint4*)&sm.b[buf][row][kc] = rb[u];
+    }
+  };
+  if (kb < ke) {
+    fetch(kb);
+    stash(0);
+    __syncthreads();
+  }
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += SK_BK) {
+    const bool more = k0 + SK_BK < ke;
+    if (more) fetch(k0 + SK_BK);
+#pragma unroll
+    for (int kk = 0; kk < SK_BK; kk += 32) {
+      const int kq = kk + (lane >> 4) * 8;
+      bf16x8 bfr[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bfr[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&sm.b[buf][wn * 64 + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        if (wm * 9 + i < mt) {                        // uniform: skip m tiles beyond M
+          const bf16x8 af = __builtin_bit_cast(bf16x8, *(const uint4*)&sm.a[buf][wm * 144 + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  const long ldp = (N + 3) / 4 * 4;                 // partial row pitch (16-byte rows)
+  float* out = (q.ksplit > 1) ? q.part + (long)ks * M * ldp : q.C;
+  const long ldo = (q.ksplit > 1) ? ldp : q.ldc;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm * 144 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (row < M && col < N) out[(long)row * ldo + col] = acc[i][j][r];
+      }
+}
+
+// Sum of the K-slice partials, in slice order: block = 256 threads x 4 consecutive columns
+// of one row (16-byte loads of the partials; the output row pitch is a multiple of 4).
+__device__ __forceinline__ void skinny_reduce_body(const SkinnyTask& q, int bx, int) {
+  const int N4 = (q.N + 3) / 4;
+  const long ldp = (long)N4 * 4;
+  const long total = (long)q.M * ldp;
+  const long g = (long)bx * 256 + threadIdx.x;       // group of 4 columns
+  if (g >= (long)q.M * N4) return;
+  const int row = (int)(g / N4), col = (int)(g % N4) * 4;
+  const float* p = q.part + (long)row * ldp + col;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int k = 0; k < q.ksplit; ++k) {             // pad columns >= N are summed, never stored
+    const float4 v = *(const float4*)(p + (long)k * total);
+    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+  }
+  float* c = q.C + (long)row * q.ldc + col;
+  c[0] = s.x;
+  if (col + 1 < q.N) c[1] = s.y;
+  if (col + 2 < q.N) c[2] = s.z;
+  if (col + 3 < q.N) c[3] = s.w;
+}
+
+__global__ __launch_bounds__(SK_NT) void k_skinny_bf16(SkinnyTask q) { skinny_body(q, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(256) void k_skinny_reduce(SkinnyTask q) { skinny_reduce_body(q, blockIdx.x, 0); }
+KFAC_GROUPED_KERNEL_XCD(k_skinny_bf16_g, skinny_body, SkinnyTask, SK_NT)
+KFAC_GROUPED_KERNEL(k_skinny_reduce_g, skinny_reduce_body, SkinnyTask, 256)
+
+int skinny_ksplit(int N, int K) {
+  const int tiles = (N + SK_BN - 1) / SK_BN;
+  int ks = (256 + tiles - 1) / tiles;                 // ~one workgroup per compute unit
+  ks = std::min(ks, std::max(1, K / 512));            // at least 512 k per slice
+  return std::max(1, std::min(ks, 16));
+}
+SkinnyTask make_skinny_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, float* C,
+                            long ldc, float* part, int ksplit) {
+  SkinnyTask q{M, N, K, A, lda, B, ldb, C, ldc, part, ksplit, (N + SK_BN - 1) / SK_BN};
+  return q;
+}
+int skinny_blocks(const SkinnyTask& q) { return q.tiles_n * q.ksplit; }
+int skinny_reduce_blocks(const SkinnyTask& q) { return (int)(((long)q.M * ((q.N + 3) / 4) + 255) / 256); }
+size_t skinny_part_bytes(int M, int N, int K) {
+  const int ks = skinny_ksplit(N, K);
+  return ks > 1 ? (size_t)ks * M * ((N + 3) / 4 * 4) * sizeof(float) : 0;
+}
+hipError_t launch_skinny_g(const SkinnyTask* t, GroupMap gm, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_skinny_bf16_g, dim3(blocks), dim3(SK_NT), 0, s, t, gm);
+  return hipGetLastError();
+}
+hipError_t launch_skinny_reduce_g(const SkinnyTask* t, GroupMap gm, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_skinny_reduce_g, dim3(blocks), dim3(256), 0, s, t, gm);
+  return hipGetLastError();
+}
+
 }  // namespace kfac

@@ -360,6 +360,137 @@ KFAC_GLAUNCH(launch_omega_g, k_omega_g, OmegaTask, 256)
 KFAC_GLAUNCH(launch_sign_partial_g, k_sign_partial_g, SignTask, 256)
 KFAC_GLAUNCH(launch_sign_apply_g, k_sign_apply_g, SignTask, 256)
 
+// Skinny fp32 GEMM for the Rayleigh-Ritz product W = F Q of Alg. 3 (stored transposed,
+// W^T = Q^T F): C[M x N] = A[M x K] B[K x N] with M <= 288 (the sketch width), A K-contiguous,
+// B N-contiguous.  A workgroup owns all M rows and 64 columns over the whole K, so F is read
+// once; 8 wavefronts as 2 (M) x 4 (N), each 144 x 16 (9 MFMA tiles); BK = 16, two LDS
+// buffers.
+constexpr int SF_M = 288, SF_BN = 64, SF_BK = 16, SF_NT = 512;
+constexpr int SF_SA = SF_M + lds_pad(SF_M), SF_SB = SF_BN + lds_pad(SF_BN);
+struct alignas(16) SfSmem {
+  float a[2][SF_BK][SF_SA];
+  float b[2][SF_BK][SF_SB];
+};
+constexpr int SF_GA = (SF_M * SF_BK / 4 + SF_NT - 1) / SF_NT;       // float4 groups per thread
+constexpr int SF_GB = (SF_BN * SF_BK / 4 + SF_NT - 1) / SF_NT;
+
+__device__ __forceinline__ void gemm_skinny_f32_body(const GemmP& p, int bx, int) {
+  __shared__ SfSmem sm;
+  const int n0 = bx * SF_BN;
+  const int M = p.M, N = p.N, K = p.K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int mt = (M + 15) / 16;
+  const bool va = ((p.lda & 3) == 0) && ((((uintptr_t)p.A) & 15) == 0);
+  const bool vb = ((p.ldb & 3) == 0) && ((((uintptr_t)p.B) & 15) == 0);
+  f32x4 acc[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // two register stages: the loads of k-step s+2 are issued while step s computes
+  float4 ra[2][SF_GA], rb[2][SF_GB];
+  auto fetch = [&](int k0, float4 (&xa)[SF_GA], float4 (&xb)[SF_GB]) {
+#pragma unroll
+    for (int u = 0; u < SF_GA; ++u) {
+      const int g = tid + u * SF_NT;
+      const int m = g / (SF_BK / 4), k = (g % (SF_BK / 4)) * 4, gk = k0 + k;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (g < SF_M * SF_BK / 4 && m < M) {
+        const float* src = p.A + (long)m * p.lda + gk;
+        if (va && gk + 4 <= K) v = *(const float4*)src;
+        else {
+          v.x = (gk < K) ? src[0] : 0.f; v.y = (gk + 1 < K) ? src[1] : 0.f;
+          v.z = (gk + 2 < K) ? src[2] : 0.f; v.w = (gk + 3 < K) ? src[3] : 0.f;
+        }
+      }
+      xa[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < SF_GB; ++u) {
+      const int g = tid + u * SF_NT;
+      const int k = g / (SF_BN / 4), n = (g % (SF_BN / 4)) * 4, gk = k0 + k, gn = n0 + n;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (g < SF_BN * SF_BK / 4 && gk < K) {
+        const float* src = p.B + (long)gk * p.ldb + gn;
+        if (vb && gn + 4 <= N) v = *(const float4*)src;
+        else {
+          v.x = (gn < N) ? src[0] : 0.f; v.y = (gn + 1 < N) ? src[1] : 0.f;
+          v.z = (gn + 2 < N) ? src[2] : 0.f; v.w = (gn + 3 < N) ? src[3] : 0.f;
+        }
+      }
+      xb[u] = v;
+    }
+  };
+  auto stash = [&](int buf, const float4 (&xa)[SF_GA], const float4 (&xb)[SF_GB]) {
+#pragma unroll
+    for (int u = 0; u < SF_GA; ++u) {
+      const int g = tid + u * SF_NT;
+      if (g >= SF_M * SF_BK / 4) continue;
+      const int m = g / (SF_BK / 4), k = (g % (SF_BK / 4)) * 4;
+      const int rot = (k >> 2) & 3;                  // spread one store over four k-rows
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = (i + rot) & 3;
+        sm.a[buf][k + j][m] = f4_elem(xa[u], j);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SF_GB; ++u) {
+      const int g = tid + u * SF_NT;
+      if (g >= SF_BN * SF_BK / 4) continue;
+      const int k = g / (SF_BN / 4), n = (g % (SF_BN / 4)) * 4;
+      *(float4*)&sm.b[buf][k][n] = xb[u];
+    }
+  };
+  const int nsteps = (K + SF_BK - 1) / SF_BK;
+  if (nsteps > 0) {
+    fetch(0, ra[0], rb[0]);
+    stash(0, ra[0], rb[0]);
+    if (nsteps > 1) fetch(SF_BK, ra[1], rb[1]);
+    __syncthreads();
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    const int cur = s & 1, nxt = cur ^ 1;
+    // registers [cur] held step s (already in LDS); reuse them for step s + 2
+    if (s + 2 < nsteps) {
+      if (cur == 0) fetch((s + 2) * SF_BK, ra[0], rb[0]);
+      else fetch((s + 2) * SF_BK, ra[1], rb[1]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < SF_BK; kk += 4) {
+      const int kq = kk + (lane >> 4);
+      const float bf = sm.b[cur][kq][wn * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        if (wm * 9 + i < mt) {                        // uniform: skip m tiles beyond M
+          const float af = sm.a[cur][kq][wm * 144 + i * 16 + (lane & 15)];
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc[i], 0, 0, 0);
+        }
+      }
+    }
+    // registers [nxt] hold step s + 1: into the other LDS buffer
+    if (s + 1 < nsteps) {
+      if (nxt == 0) stash(0, ra[0], rb[0]);
+      else stash(1, ra[1], rb[1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = wm * 144 + i * 16 + 4 * (lane >> 4) + r;
+      const int col = n0 + wn * 16 + (lane & 15);
+      if (row >= M || col >= N) continue;
+      float v = p.alpha * acc[i][r];
+      if (p.rowD) v *= damp_weight(p.rowD[row], p.lam);
+      if (p.colD) v *= damp_weight(p.colD[col], p.lam);
+      if (p.X) v += p.beta * p.X[(long)row * p.ldx + col];
+      p.C[(long)row * p.ldc + col] = v;
+      if (p.Cb) p.Cb[(long)row * p.ldcb + col] = f32_to_bf16_rne(v);
+    }
+}
+KFAC_GROUPED_KERNEL_XCD(k_gemm_skinny_f32_g, gemm_skinny_f32_body, GemmP, SF_NT)
+
 // Tile configurations of the grouped fp32 GEMM (BM x BN, 2 x 2 wavefronts, BK = 16).
 template <int BM, int BN>
 static void gemm_g_launch(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, hipStream_t s) {
@@ -369,7 +500,7 @@ static void gemm_g_launch(const GemmP* tasks, GroupMap gm, int blocks, bool ta, 
   else hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, true, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
 }
 
-static const int kGemmCfg[kGemmConfigs][2] = {{64, 64}, {128, 128}, {96, 128}, {128, 64}};
+static const int kGemmCfg[kGemmConfigs][2] = {{64, 64}, {128, 128}, {96, 128}, {128, 64}, {SF_M, SF_BN}};
 
 hipError_t launch_gemm_g(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, int cfg, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
@@ -377,6 +508,10 @@ hipError_t launch_gemm_g(const GemmP* tasks, GroupMap gm, int blocks, bool ta, b
     case 1: gemm_g_launch<128, 128>(tasks, gm, blocks, ta, tb, s); break;
     case 2: gemm_g_launch<96, 128>(tasks, gm, blocks, ta, tb, s); break;
     case 3: gemm_g_launch<128, 64>(tasks, gm, blocks, ta, tb, s); break;
+    case 4:   // skinny: no transposes, M <= 288 (checked by the caller)
+      if (ta || tb) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_gemm_skinny_f32_g, dim3(blocks), dim3(SF_NT), 0, s, tasks, gm);
+      break;
     default: gemm_g_launch<64, 64>(tasks, gm, blocks, ta, tb, s); break;
   }
   return hipGetLastError();

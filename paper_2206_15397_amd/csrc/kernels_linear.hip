@@ -14,7 +14,7 @@ namespace kfac {
 
 constexpr int LN_T = 128, LN_BK = 64, LN_SK = LN_BK + 8;
 
-struct LinSmem {
+struct alignas(16) LinSmem {
   union {
     struct {
       uint16_t a[2][LN_T][LN_SK];

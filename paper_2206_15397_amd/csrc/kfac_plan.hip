@@ -4,6 +4,7 @@
 // kfac_plan_launch only enqueues kernels, so it can be captured into a hipGraph.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -16,7 +17,7 @@ using namespace kfac;
 namespace {
 
 enum Kind {
-  K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRTRI, K_TRMM, K_TRIDIAG, K_PREP,
+  K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_SKINNY, K_SKINNY_R, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRTRI, K_TRMM, K_TRIDIAG, K_PREP,
   K_BISECT, K_SELECT, K_VEC, K_CLEAD, K_CLUSTER, K_BT, K_SIGN_P, K_SIGN_A
 };
 
@@ -26,8 +27,10 @@ struct LaunchRec {
   int ntasks, blocks;
   bool ta, tb;
   double flops, bytes;   // algorithmic work of the launch (all tasks)
-  int cfg;               // tile configuration (grouped fp32 GEMM)
+  int cfg;               // tile configuration (grouped fp32 GEMM) / kernel choice (bf16 sketch)
   int ord;               // ordinal among the tunable launches (-1: not tunable)
+  int ncfg;              // number of configurations of the tunable unit
+  int span;              // launches belonging to the tunable unit (a split-K reduction follows)
 };
 
 // Algorithmic work: flops of the operation as defined (padding and split-K excluded) and
@@ -59,6 +62,8 @@ struct Tables {
     r.bytes = w.bytes;
     r.cfg = 0;
     r.ord = -1;
+    r.ncfg = 1;
+    r.span = 1;
     r.ntasks = (int)tasks.size();
     r.ta = ta; r.tb = tb;
     r.tasks_off = align(sizeof(T) * tasks.size());
@@ -81,6 +86,7 @@ struct FactorInfo {
   int ea_ks;
   size_t ws_off, ws_bytes;   // EigWs region
   size_t ea_off, ea_bytes;   // EA split-K partials
+  size_t sk_off, sk_bytes;   // skinny sketch GEMM split-K partials
 };
 
 struct LayerInfo {
@@ -129,7 +135,10 @@ int default_gemm_cfg(const std::vector<GemmP>& g) {
 void add_gemm(kfac_plan* P, Tables& T, int& ord, const std::vector<GemmP>& g, bool ta, bool tb, Work w) {
   if (g.empty()) return;
   const int o = ord++;
+  bool skinny_ok = !ta && !tb;                    // the skinny tile: no transposes, M <= 288
+  for (const GemmP& q : g) skinny_ok = skinny_ok && q.M <= 288;
   int cfg = (o < (int)P->gemm_cfg.size() && P->gemm_cfg[o] >= 0) ? P->gemm_cfg[o] : default_gemm_cfg(g);
+  if (cfg == kGemmConfigs - 1 && !skinny_ok) cfg = default_gemm_cfg(g);
   std::vector<int> gx, nb;
   for (const GemmP& q : g) {
     gx.push_back(gemm_g_blocks_x(q, cfg));
@@ -140,6 +149,7 @@ void add_gemm(kfac_plan* P, Tables& T, int& ord, const std::vector<GemmP>& g, bo
   if (T.recs.size() > before) {
     T.recs.back().cfg = cfg;
     T.recs.back().ord = o;
+    T.recs.back().ncfg = skinny_ok ? kGemmConfigs : kGemmConfigs - 1;
   }
 }
 
@@ -216,16 +226,45 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           ws += bf ? Work{2 * l * d * d, 2 * d * d + 2 * l * d + 4 * l * d} : gemm_work(l, d, d, false);
         }
         if (bf) {
-          std::vector<BfGemmTask> g;
-          std::vector<int> gx2, nb2;
-          for (int i : act) {
-            const FactorInfo& I = P->fi[i];
-            const uint16_t* A = (it == 0) ? W[i].OmTb : W[i].Qtb;
-            float* out = (it == 0) ? basis[i] : spare[i];
-            BfGemmTask q = make_bf16_task(I.l_pad, I.d, I.d, A, I.ldt, P->f[i].F_bf16, P->f[i].ldfb, out, I.ldt);
-            g.push_back(q); gx2.push_back(bf16_task_blocks(q)); nb2.push_back(bf16_task_blocks(q));
+          // tunable unit: 0 = 96 x 128 tiles, 1 = skinny full-M tiles with split-K
+          const int o = gord++;
+          int dmax = 0;
+          for (int i : act) dmax = std::max(dmax, P->fi[i].d);
+          const int cfg = (o < (int)P->gemm_cfg.size() && P->gemm_cfg[o] >= 0) ? P->gemm_cfg[o] : (dmax >= 2048 ? 1 : 0);
+          const size_t before = T.recs.size();
+          if (cfg == 0) {
+            std::vector<BfGemmTask> g;
+            std::vector<int> gx2, nb2;
+            for (int i : act) {
+              const FactorInfo& I = P->fi[i];
+              const uint16_t* A = (it == 0) ? W[i].OmTb : W[i].Qtb;
+              float* out = (it == 0) ? basis[i] : spare[i];
+              BfGemmTask q = make_bf16_task(I.l_pad, I.d, I.d, A, I.ldt, P->f[i].F_bf16, P->f[i].ldfb, out, I.ldt);
+              g.push_back(q); gx2.push_back(bf16_task_blocks(q)); nb2.push_back(bf16_task_blocks(q));
+            }
+            T.add(K_BF16, g, gx2, nb2, false, false, ws);
+          } else {
+            std::vector<SkinnyTask> g, gr;
+            std::vector<int> gx2, nb2, gxr, nbr;
+            for (int i : act) {
+              const FactorInfo& I = P->fi[i];
+              const uint16_t* A = (it == 0) ? W[i].OmTb : W[i].Qtb;
+              float* out = (it == 0) ? basis[i] : spare[i];
+              SkinnyTask q = make_skinny_task(I.l_pad, I.d, I.d, A, I.ldt, P->f[i].F_bf16, P->f[i].ldfb, out, I.ldt,
+                                              (float*)wsp(I.sk_off), skinny_ksplit(I.d, I.d));
+              g.push_back(q); gx2.push_back(q.tiles_n); nb2.push_back(skinny_blocks(q));
+              if (q.ksplit > 1) { gr.push_back(q); gxr.push_back(skinny_reduce_blocks(q)); nbr.push_back(skinny_reduce_blocks(q)); }
+            }
+            T.add(K_SKINNY, g, gx2, nb2, false, false, ws);
+            T.add(K_SKINNY_R, gr, gxr, nbr);
           }
-          T.add(K_BF16, g, gx2, nb2, false, false, ws);
+          if (T.recs.size() > before) {
+            LaunchRec& r0 = T.recs[before];
+            r0.cfg = cfg;
+            r0.ord = o;
+            r0.ncfg = 2;
+            r0.span = (int)(T.recs.size() - before);
+          }
         } else {
           std::vector<GemmP> g;
           std::vector<int> gx2, nb2;
@@ -468,6 +507,8 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
     I.ea_ks = I.ea ? ea_choose_ksplit(I.d, F.n, xb) : 1;
     I.ea_bytes = (I.ea && I.ea_ks > 1) ? ea_workspace_bytes(I.d, F.n, xb) : 0;
     I.ea_off = take(I.ea_bytes + 16);
+    I.sk_bytes = (bf && !I.exact) ? skinny_part_bytes(I.l_pad, I.d, I.d) : 0;
+    I.sk_off = take(I.sk_bytes + 16);
     P->fi.push_back(I);
   }
   for (int l = 0; l < nl; ++l) {
@@ -478,11 +519,17 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
     I.off = take(I.bytes);
     P->li.push_back(I);
   }
-  // size the table head with every phase enabled
-  Tables T;
-  P->table_bytes = 0;
-  build_tables(P, nullptr, nullptr, T);
-  P->table_bytes = (T.bytes.size() + 2 * kAlign) / kAlign * kAlign;
+  // size the table head with every phase enabled, for either choice of the tunable kernels
+  size_t tb = 0;
+  for (int c = 0; c < 2; ++c) {
+    Tables T;
+    P->table_bytes = 0;
+    P->gemm_cfg.assign(256, c);
+    build_tables(P, nullptr, nullptr, T);
+    tb = std::max(tb, T.bytes.size());
+  }
+  P->gemm_cfg.clear();
+  P->table_bytes = (tb + 2 * kAlign) / kAlign * kAlign;
   P->ws_bytes = P->table_bytes + off + kAlign;
   *out = P;
   return KFAC_OK;
@@ -518,10 +565,12 @@ kfac_status kfac_plan_upload(kfac_plan* plan, void* workspace, size_t ws_bytes, 
 int kfac_plan_launch_count(const kfac_plan* plan) { return plan ? (int)plan->tab.recs.size() : 0; }
 
 const char* kfac_plan_launch_name(const kfac_plan* plan, int index) {
-  static const char* names[] = {"ea_tiles", "ea_finalize", "ea_tiles_bf16", "ea_finalize_bf16", "omega", "gemm_f32", "gemm_bf16", "gram_partial",
+  static const char* names[] = {"ea_tiles", "ea_finalize", "ea_tiles_bf16", "ea_finalize_bf16", "omega",
+                                "gemm_f32", "gemm_bf16", "gemm_bf16_skinny", "skinny_reduce", "gram_partial",
                                 "gram_reduce", "cholinv", "trtri_cols", "trmm", "tridiag", "tri_prep", "tri_bisect",
                                 "tri_select", "tri_vec", "tri_cluster_lead", "tri_cluster", "backtransform",
                                 "sign_partial", "sign_apply"};
+  static_assert(sizeof(names) / sizeof(names[0]) == K_SIGN_A + 1, "one name per launch kind");
   if (!plan || index < 0 || index >= (int)plan->tab.recs.size()) return nullptr;
   return names[plan->tab.recs[index].kind];
 }
@@ -551,6 +600,8 @@ kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, 
       case K_OMEGA: e = launch_omega_g((const OmegaTask*)tp, gm, r.blocks, s); break;
       case K_GEMM: e = launch_gemm_g((const GemmP*)tp, gm, r.blocks, r.ta, r.tb, r.cfg, s); break;
       case K_BF16: e = launch_gemm_bf16_g((const BfGemmTask*)tp, gm, r.blocks, s); break;
+      case K_SKINNY: e = launch_skinny_g((const SkinnyTask*)tp, gm, r.blocks, s); break;
+      case K_SKINNY_R: e = launch_skinny_reduce_g((const SkinnyTask*)tp, gm, r.blocks, s); break;
       case K_GRAM_P: e = launch_gram_partial_g((const GramP*)tp, gm, r.blocks, s); break;
       case K_GRAM_R: e = launch_gram_reduce_g((const GramP*)tp, gm, r.blocks, s); break;
       case K_CHOLINV: e = launch_cholinv_g((const CholInvTask*)tp, gm, r.blocks, s); break;
@@ -583,13 +634,20 @@ namespace {
 
 // Shape key of a grouped fp32 GEMM launch: layout flags and every task's (M, N, K), hashed.
 std::string gemm_key(const kfac_plan* P, const LaunchRec& r) {
-  const GemmP* t = (const GemmP*)(P->tab.bytes.data() + r.tasks_off);
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) { h ^= v; h *= 1099511628211ull; };
   mix((uint64_t)r.ta); mix((uint64_t)r.tb); mix((uint64_t)r.ntasks);
-  for (int i = 0; i < r.ntasks; ++i) { mix((uint64_t)t[i].M); mix((uint64_t)t[i].N); mix((uint64_t)t[i].K); }
+  const char* base = P->tab.bytes.data() + r.tasks_off;
+  const bool f32 = (r.kind == K_GEMM);
+  for (int i = 0; i < r.ntasks; ++i) {
+    int M, N, K;
+    if (f32) { const GemmP& t = ((const GemmP*)base)[i]; M = t.M; N = t.N; K = t.K; }
+    else if (r.kind == K_BF16) { const BfGemmTask& t = ((const BfGemmTask*)base)[i]; M = t.M; N = t.N; K = t.K; }
+    else { const SkinnyTask& t = ((const SkinnyTask*)base)[i]; M = t.M; N = t.N; K = t.K; }
+    mix((uint64_t)M); mix((uint64_t)N); mix((uint64_t)K);
+  }
   char buf[64];
-  std::snprintf(buf, sizeof(buf), "gemm_f32:%016llx", (unsigned long long)h);
+  std::snprintf(buf, sizeof(buf), "%s:%016llx", f32 ? "gemm_f32" : "sketch_bf16", (unsigned long long)h);
   return buf;
 }
 
@@ -602,7 +660,7 @@ std::map<std::string, int> read_cache(const char* path) {
   int cfg;
   double us;
   while (std::fscanf(f, "%127s %d %lf", key, &cfg, &us) == 3)
-    if (cfg >= 0 && cfg < kGemmConfigs) m[key] = cfg;
+    if (cfg >= 0 && cfg < 16) m[key] = cfg;
   std::fclose(f);
   return m;
 }
@@ -620,34 +678,39 @@ kfac_status kfac_plan_autotune(kfac_plan* plan, void* workspace, size_t ws_bytes
   plan->gemm_cfg.assign(nord, -1);
   std::map<std::string, int> cache = read_cache(cache_path);
   std::vector<std::string> lines;
+  const char* ev = std::getenv("KFAC_AUTOTUNE_VERBOSE");
+  const bool verbose = ev && ev[0] && ev[0] != '0';
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KFAC_EHIP;
   kfac_status result = KFAC_OK;
   for (int o = 0; o < nord && result == KFAC_OK; ++o) {
     // key of launch o with the configuration it currently has
+    // key (independent of the configuration: the shapes) and number of configurations
     std::string key;
+    int ncfg = 1;
     for (const LaunchRec& r : plan->tab.recs)
-      if (r.ord == o) key = gemm_key(plan, r);
+      if (r.ord == o) { key = gemm_key(plan, r); ncfg = r.ncfg; }
     auto hit = cache.find(key);
-    if (hit != cache.end()) { plan->gemm_cfg[o] = hit->second; continue; }
+    if (hit != cache.end() && hit->second < ncfg) { plan->gemm_cfg[o] = hit->second; continue; }
     int best = 0;
     float best_ms = 1e30f;
-    for (int c = 0; c < kGemmConfigs && result == KFAC_OK; ++c) {
+    for (int c = 0; c < ncfg && result == KFAC_OK; ++c) {
       plan->gemm_cfg[o] = c;
       if ((result = kfac_plan_upload(plan, workspace, ws_bytes, dev_status, stream)) != KFAC_OK) break;
-      int idx = -1;
+      int idx = -1, span = 1;
       for (size_t i = 0; i < plan->tab.recs.size(); ++i)
-        if (plan->tab.recs[i].ord == o) idx = (int)i;
+        if (plan->tab.recs[i].ord == o) { idx = (int)i; span = plan->tab.recs[i].span; }
       if (idx < 0) break;
       float tot = 0.f;
       for (int rep = 0; rep <= reps && result == KFAC_OK; ++rep) {   // rep 0 warms up
         if (hipEventRecord(e0, s) != hipSuccess) { result = KFAC_EHIP; break; }
-        if ((result = kfac_plan_launch_range(plan, idx, 1, stream)) != KFAC_OK) break;
+        if ((result = kfac_plan_launch_range(plan, idx, span, stream)) != KFAC_OK) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { result = KFAC_EHIP; break; }
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);
         if (rep > 0) tot += ms;
       }
+      if (result == KFAC_OK && verbose) std::fprintf(stderr, "kfac autotune %s cfg %d: %.1f us\n", key.c_str(), c, 1e3 * tot / reps);
       if (result == KFAC_OK && tot / reps < best_ms) { best_ms = tot / reps; best = c; }
     }
     plan->gemm_cfg[o] = best;
@@ -665,6 +728,24 @@ kfac_status kfac_plan_autotune(kfac_plan* plan, void* workspace, size_t ws_bytes
     }
   }
   return kfac_plan_upload(plan, workspace, ws_bytes, dev_status, stream);
+}
+
+kfac_status kfac_plan_force_config(kfac_plan* plan, int cfg_gemm_f32, int cfg_sketch_bf16) {
+  if (!plan || cfg_gemm_f32 < -1 || cfg_gemm_f32 >= kGemmConfigs || cfg_sketch_bf16 < -1 || cfg_sketch_bf16 > 1)
+    return KFAC_EINVAL;
+  // walk the launch list once with defaults to learn which ordinal is which kind
+  Tables T;
+  plan->gemm_cfg.clear();
+  build_tables(plan, nullptr, nullptr, T);
+  int nord = 0;
+  for (const LaunchRec& r : T.recs) nord = std::max(nord, r.ord + 1);
+  plan->gemm_cfg.assign(nord, -1);
+  for (const LaunchRec& r : T.recs) {
+    if (r.ord < 0) continue;
+    if (r.kind == K_GEMM && cfg_gemm_f32 >= 0 && cfg_gemm_f32 < r.ncfg) plan->gemm_cfg[r.ord] = cfg_gemm_f32;
+    if ((r.kind == K_BF16 || r.kind == K_SKINNY) && cfg_sketch_bf16 >= 0) plan->gemm_cfg[r.ord] = cfg_sketch_bf16;
+  }
+  return KFAC_OK;
 }
 
 int kfac_plan_launch_config(const kfac_plan* plan, int index) {

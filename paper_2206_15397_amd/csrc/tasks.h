@@ -38,6 +38,15 @@ struct BfGemmTask {      // C = A B^T, bf16 operands, K contiguous: block (flat 
   int tiles_m;
 };
 
+struct SkinnyTask {      // C[M x N] = A[M x K] B[N x K]^T, M <= 288, bf16: block (N tile, K slice)
+  int M, N, K;
+  const uint16_t* A; long lda;
+  const uint16_t* B; long ldb;
+  float* C; long ldc;
+  float* part;           // ksplit > 1: [ksplit][M][N] fp32 partial sums
+  int ksplit, tiles_n;
+};
+
 struct LinTask {         // K-FAC linear layer GEMMs on bf16 MFMA: block (flat tile)
   int M, N, K;
   const uint16_t* A; long lda;

@@ -259,6 +259,12 @@ class Plan:
                                                                _ptr(self.status), cp, int(reps), _stream()))
         return self
 
+    def force_config(self, gemm_f32=-1, sketch_bf16=-1):
+        """Fix the kernel configuration of every fp32 GEMM / bf16 sketch launch (-1: default);
+        re-uploads the tables."""
+        check("kfac_plan_force_config", self._L.kfac_plan_force_config(self._h, int(gemm_f32), int(sketch_bf16)))
+        return self.upload()
+
     def launch_configs(self):
         return [int(self._L.kfac_plan_launch_config(self._h, i)) for i in range(self.launch_count)]
 
