@@ -184,19 +184,22 @@ struct TileF32 {
     for (int k0 = kb; k0 < ke; k0 += BK) {
       const bool more = k0 + BK < ke;
       if (more) fetch(p, m0, n0, k0 + BK, ke, va, vb, ra, rb);
+      // all operand reads of the k-step first (one LDS latency per step), then the MFMAs
+      float af[BK / 4][FM], bf[BK / 4][FN];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        float af[FM], bf[FN];
+      for (int u = 0; u < BK / 4; ++u) {
 #pragma unroll
-        for (int i = 0; i < FM; ++i) af[i] = sm.a[buf][kk + kq][am + i * 16];
+        for (int i = 0; i < FM; ++i) af[u][i] = sm.a[buf][4 * u + kq][am + i * 16];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bf[j] = sm.b[buf][kk + kq][bn + j * 16];
+        for (int j = 0; j < FN; ++j) bf[u][j] = sm.b[buf][4 * u + kq][bn + j * 16];
+      }
+#pragma unroll
+      for (int u = 0; u < BK / 4; ++u)
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
-      }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[u][i], bf[u][j], acc[i][j], 0, 0, 0);
       if (more) stash(sm, buf ^ 1, ra, rb);
       __syncthreads();
       buf ^= 1;

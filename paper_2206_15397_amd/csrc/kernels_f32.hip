@@ -455,18 +455,21 @@ __device__ __forceinline__ void gemm_skinny_f32_body(const GemmP& p, int bx, int
       if (cur == 0) fetch((s + 2) * SF_BK, ra[0], rb[0]);
       else fetch((s + 2) * SF_BK, ra[1], rb[1]);
     }
+    // all operand reads of the k-step first (one LDS latency per step), then the MFMAs
+    float af[SF_BK / 4][9], bfv[SF_BK / 4];
 #pragma unroll
-    for (int kk = 0; kk < SF_BK; kk += 4) {
-      const int kq = kk + (lane >> 4);
-      const float bf = sm.b[cur][kq][wn * 16 + (lane & 15)];
+    for (int u = 0; u < SF_BK / 4; ++u) {
+      const int kq = 4 * u + (lane >> 4);
+      bfv[u] = sm.b[cur][kq][wn * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        if (wm * 9 + i < mt) {                        // uniform: skip m tiles beyond M
-          const float af = sm.a[cur][kq][wm * 144 + i * 16 + (lane & 15)];
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc[i], 0, 0, 0);
-        }
-      }
+      for (int i = 0; i < 9; ++i) af[u][i] = sm.a[cur][kq][wm * 144 + i * 16 + (lane & 15)];
     }
+#pragma unroll
+    for (int u = 0; u < SF_BK / 4; ++u)
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        if (wm * 9 + i < mt)                          // uniform: skip m tiles beyond M
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[u][i], bfv[u], acc[i], 0, 0, 0);
     // registers [nxt] hold step s + 1: into the other LDS buffer
     if (s + 1 < nsteps) {
       if (nxt == 0) stash(0, ra[0], rb[0]);
