@@ -294,10 +294,14 @@ def phase_times(plan, layers, reps, restore_fn=None):
 # Published MI355X peaks: HBM3E bandwidth and dense matrix / vector throughput.
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+# split-bf16 products of fp32 operands issue three bf16 MFMAs per product: their peak in
+# useful flops is a third of the bf16 one
+PEAK_TFLOPS["bf16x3"] = PEAK_TFLOPS["bf16"] / 3
 # arithmetic type and unit kind of each grouped launch: "mfma" for matrix-core kernels,
 # "alu" for the fp64 vector kernels (single-workgroup factorisations and eigensolver)
 KIND = {
     "ea_tiles_bf16": ("bf16", "mfma"), "gemm_bf16": ("bf16", "mfma"), "gemm_bf16_skinny": ("bf16", "mfma"),
+    "gemm_bf16x3": ("bf16x3", "mfma"),
     "ea_tiles": ("fp32", "mfma"), "gemm_f32": ("fp32", "mfma"),
     "gram_partial": ("fp64", "mfma"), "trmm": ("fp64", "mfma"),
     "cholinv": ("fp64", "alu"), "trtri_cols": ("fp64", "mfma"),
@@ -375,14 +379,19 @@ def cpu_baseline(target_seconds=15.0):
 
 def mfma_fraction(plan, names, times_ms):
     """Sum of GEMM flops over sum of (time x peak of the GEMM's arithmetic type), over the
-    sketch / power (bf16) and Rayleigh-Ritz / Ritz-vector (fp32) GEMM launches."""
-    fl, tp = 0.0, 0.0
+    sketch / power (bf16), Rayleigh-Ritz (fp32 or split-bf16) and Ritz-vector (fp32) GEMM
+    launches; a K-slice reduction counts with the GEMM it completes."""
+    gemm = {"gemm_bf16": "bf16", "gemm_bf16_skinny": "bf16", "gemm_bf16x3": "bf16x3", "gemm_f32": "fp32"}
+    fl, tp, last = 0.0, 0.0, None
     for i, (nm, t) in enumerate(zip(names, times_ms)):
-        if nm not in ("gemm_bf16", "gemm_bf16_skinny", "skinny_reduce", "gemm_f32"):
+        if nm in gemm:
+            last = gemm[nm]
+        elif nm != "slice_reduce" or last is None:
+            last = None
             continue
         f, _ = plan.launch_work(i)
         fl += f
-        tp += t * 1e-3 * PEAK_TFLOPS["fp32" if nm == "gemm_f32" else "bf16"] * 1e12
+        tp += t * 1e-3 * PEAK_TFLOPS[last] * 1e12
     return fl / tp if tp > 0 else None
 
 

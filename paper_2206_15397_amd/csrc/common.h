@@ -25,6 +25,36 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// All-ones or zero mask the compiler cannot see through: `load & mask` keeps the load
+// unconditional (from a clamped, valid address) instead of sinking it into a branch.
+__device__ __forceinline__ uint32_t opaque_mask(bool keep) {
+  uint32_t m = keep ? 0xffffffffu : 0u;
+  asm("" : "+v"(m));       // not volatile: no side effects, so memory is not re-read around it
+  return m;
+}
+// 16-byte load through a global-address-space pointer (a global_load, which unlike a
+// flat load does not hold back the LDS wait counter); p must be 16-byte aligned.
+__device__ __forceinline__ uint4 gload16(const void* p) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  typedef const u32x4 __attribute__((address_space(1)))* gp;
+  const u32x4 v = *(gp)__builtin_assume_aligned(p, 16);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t gload4(const void* p) {
+  typedef const uint32_t __attribute__((address_space(1)))* gp;
+  return *(gp)p;
+}
+__device__ __forceinline__ uint4 and_mask(uint4 v, uint32_t m) { return make_uint4(v.x & m, v.y & m, v.z & m, v.w & m); }
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// Two fp32 -> packed bf16 (a in the low half), round to nearest even: one
+// v_cvt_pk_bf16_f32 on gfx950.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  const f32x2 x = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2));
+}
+
 // Cross-lane moves on the DPP network (no LDS round trip).  Control codes of the GFX9
 // DPP encoding: quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E, row_mirror = 0x140,
 // row_half_mirror = 0x141, row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Lanes of rows

@@ -27,9 +27,11 @@ __device__ __forceinline__ void group_locate_at(const GroupMap& g, int b, int& t
     const int mid = (lo + hi + 1) >> 1;
     if (g.off[mid] <= b) lo = mid; else hi = mid - 1;
   }
-  t = lo;
-  const int local = b - g.off[t];
-  const int w = g.gx[t];
+  // every lane computed the same values: make them scalar, so the task record is read
+  // with scalar loads and kept in SGPRs
+  t = __builtin_amdgcn_readfirstlane(lo);
+  const int local = __builtin_amdgcn_readfirstlane(b - g.off[t]);
+  const int w = __builtin_amdgcn_readfirstlane(g.gx[t]);
   bx = local % w;
   by = local / w;
 }

@@ -80,10 +80,23 @@ int skinny_ksplit(int N, int K);
 SkinnyTask make_skinny_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, float* C,
                             long ldc, float* part, int ksplit);
 int skinny_blocks(const SkinnyTask& q);
-int skinny_reduce_blocks(const SkinnyTask& q);
 size_t skinny_part_bytes(int M, int N, int K);
 hipError_t launch_skinny_g(const SkinnyTask* t, GroupMap gm, int blocks, hipStream_t s);
-hipError_t launch_skinny_reduce_g(const SkinnyTask* t, GroupMap gm, int blocks, hipStream_t s);
+constexpr int kWholeWidthMaxM = 288;   // rows held by the whole-width (skinny / split) kernels
+// split-bf16 product of fp32 operands (hi*hi + hi*lo + lo*hi), same whole-width layout
+int split_ksplit(int N, int K);
+SplitTask make_split_task(int M, int N, int K, const float* A, long lda, const float* B, long ldb, float* C,
+                          long ldc, float* part, int ksplit);
+int split_blocks(const SplitTask& q);
+size_t split_part_bytes(int M, int N, int K);
+hipError_t launch_split_g(const SplitTask* t, GroupMap gm, int blocks, hipStream_t s);
+// K-slice reduction shared by both
+ReduceTask make_reduce_task(int M, int N, const float* part, float* C, long ldc, int ksplit);
+int reduce_blocks(const ReduceTask& q);
+hipError_t launch_reduce_g(const ReduceTask* t, GroupMap gm, int blocks, hipStream_t s);
+// single-factor forms (one group of one task)
+hipError_t launch_skinny(const SkinnyTask& q, hipStream_t s);
+hipError_t launch_split(const SplitTask& q, hipStream_t s);
 GramP make_gram_task(const float* A, long lda, const float* B, long ldb, int L, int K, int sym, double* part,
                      double* C, long ldc, int* status);
 int gram_tiles(int L, int sym);

@@ -334,14 +334,15 @@ struct alignas(16) SkSmem {
 constexpr int SK_VA = (SK_MMAX * SK_BK / 8 + SK_NT - 1) / SK_NT;   // 16-byte vectors per thread
 constexpr int SK_VB = SK_BN * SK_BK / 8 / SK_NT;
 
-__device__ __forceinline__ void skinny_body(const SkinnyTask& q, int bx, int by) {
+__device__ __forceinline__ void skinny_body(const SkinnyTask& task, int bx, int by) {
   __shared__ SkSmem sm;
+  const SkinnyTask q = task;                         // the record once, into registers
   const int tn = bx, ks = by;                        // grid width = tiles_n
   const int n0 = tn * SK_BN;
   const int M = q.M, N = q.N, K = q.K;
   const int kchunk = ((K + q.ksplit - 1) / q.ksplit + SK_BK - 1) / SK_BK * SK_BK;
   const int kb = ks * kchunk, ke = min(K, kb + kchunk);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 1, wn = wave >> 1;
   const int mt = (M + 15) / 16;                      // m tiles present
   f32x4 acc[9][4];
@@ -350,39 +351,56 @@ __device__ __forceinline__ void skinny_body(const SkinnyTask& q, int bx, int by)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   uint4 ra[SK_VA], rb[SK_VB];
+  uint32_t ma[SK_VA], mb[SK_VB];                     // applied at the stash, not at the load
+  // Full stages of 16-byte aligned rows load without element guards: a row outside the
+  // matrix reads a clamped valid address and is zeroed through the mask at the stash, so
+  // the loads stay in flight across the MFMAs.  The K tail and unaligned operands take the
+  // guarded ld16 in an unpipelined loop after the main one.
+  const bool al = (((q.lda | q.ldb) & 7) == 0) && (((uintptr_t)q.A | (uintptr_t)q.B) & 15) == 0;
+  const int kfull = al ? kb + (ke - kb) / SK_BK * SK_BK : kb;
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < SK_VA; ++u) {
       const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
+      const bool ok = e < SK_MMAX * SK_BK / 8 && row < M;
+      ra[u] = gload16(q.A + (ok ? (long)row * q.lda + k0 + kc : 0));
+      ma[u] = opaque_mask(ok);
+    }
+#pragma unroll
+    for (int u = 0; u < SK_VB; ++u) {
+      const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
+      const bool ok = n0 + row < N;
+      rb[u] = gload16(q.B + (ok ? (long)(n0 + row) * q.ldb + k0 + kc : 0));
+      mb[u] = opaque_mask(ok);
+    }
+  };
+  auto fetch_guarded = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < SK_VA; ++u) {
+      const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
       ra[u] = (e < SK_MMAX * SK_BK / 8 && row < M) ? ld16(q.A, q.lda, row, M, k0 + kc, ke) : make_uint4(0, 0, 0, 0);
+      ma[u] = 0xffffffffu;
     }
 #pragma unroll
     for (int u = 0; u < SK_VB; ++u) {
       const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
       rb[u] = ld16(q.B, q.ldb, n0 + row, N, k0 + kc, ke);
+      mb[u] = 0xffffffffu;
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < SK_VA; ++u) {
       const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
-      if (e < SK_MMAX * SK_BK / 8) *(uint4*)&sm.a[buf][row][kc] = ra[u];
+      if (e < SK_MMAX * SK_BK / 8) *(uint4*)&sm.a[buf][row][kc] = and_mask(ra[u], ma[u]);
     }
 #pragma unroll
     for (int u = 0; u < SK_VB; ++u) {
       const int e = tid + u * SK_NT, row = e >> 3, kc = (e & 7) * 8;
-      *(uint4*)&sm.b[buf][row][kc] = rb[u];
+      *(uint4*)&sm.b[buf][row][kc] = and_mask(rb[u], mb[u]);
     }
   };
-  if (kb < ke) {
-    fetch(kb);
-    stash(0);
-    __syncthreads();
-  }
-  int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += SK_BK) {
-    const bool more = k0 + SK_BK < ke;
-    if (more) fetch(k0 + SK_BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < SK_BK; kk += 32) {
       const int kq = kk + (lane >> 4) * 8;
@@ -399,9 +417,28 @@ __device__ __forceinline__ void skinny_body(const SkinnyTask& q, int bx, int by)
         }
       }
     }
-    if (more) stash(buf ^ 1);
+  };
+  int buf = 0;
+  if (kb < kfull) {
+    fetch(kb);
+    stash(0);
+    __syncthreads();
+  }
+  for (int k0 = kb; k0 < kfull; k0 += SK_BK) {
+    // the last full stage re-fetches itself into the idle buffer (never read)
+    fetch(k0 + SK_BK < kfull ? k0 + SK_BK : k0);
+    compute(buf);
+    __builtin_amdgcn_sched_barrier(0);               // keep the stash (and its load waits) after the MFMAs
+    stash(buf ^ 1);                                   // its last reads closed at the previous barrier
     __syncthreads();
     buf ^= 1;
+  }
+  for (int k0 = kfull; k0 < ke; k0 += SK_BK) {
+    fetch_guarded(k0);
+    stash(buf);
+    __syncthreads();
+    compute(buf);
+    __syncthreads();
   }
   const long ldp = (N + 3) / 4 * 4;                 // partial row pitch (16-byte rows)
   float* out = (q.ksplit > 1) ? q.part + (long)ks * M * ldp : q.C;
@@ -418,9 +455,198 @@ __device__ __forceinline__ void skinny_body(const SkinnyTask& q, int bx, int by)
       }
 }
 
+// ------------------------------------------------------------------------------------
+// The Rayleigh-Ritz product W = F Q (Alg. 3 "C = Q^T X Q") in the bf16-sketch precision
+// mode.  fp32 has 1/16 of bf16's MFMA rate on gfx950, so each fp32 operand enters as a
+// pair of bf16 values, hi = bf16(v) and lo = bf16(v - hi) (v - hi is exact in fp32), and
+// C = A_hi B_hi + A_hi B_lo + A_lo B_hi accumulates in fp32: each product keeps 16
+// significant bits per operand and drops only lo*lo (below 2^-16 relative).  The split is
+// done once per element while staging into LDS.  Same whole-width layout as the sketch
+// kernel: a workgroup owns all M <= 288 rows and 128 columns of C over one K slice, so F is
+// read from memory once; 8 wavefronts as 2 (M) x 4 (N), each 144 x 32 (9 x 2 tiles); BK =
+// 32 with two LDS buffers of hi and lo planes (130 KB).  K slices write fp32 partials.
+constexpr int SS_BN = 128, SS_BK = 32, SS_SK = SS_BK + 8, SS_NT = 512;
+struct alignas(16) SsSmem {
+  uint16_t ah[2][SK_MMAX][SS_SK], al[2][SK_MMAX][SS_SK];
+  uint16_t bh[2][SS_BN][SS_SK], bl[2][SS_BN][SS_SK];
+};
+constexpr int SS_NVA = SK_MMAX * SS_BK / 4, SS_NVB = SS_BN * SS_BK / 4;     // float4 per stage
+constexpr int SS_VA = (SS_NVA + SS_NT - 1) / SS_NT, SS_VB = SS_NVB / SS_NT;  // per thread
+static_assert(SS_NVB % SS_NT == 0, "B stage must divide evenly");
+
+// 4 consecutive fp32 of row `row` from column k (zeros outside rows < nrows, k < K).
+__device__ __forceinline__ float4 ld4f(const float* base, long ld, int row, int nrows, int k, int K) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (row < nrows) {
+    const float* p = base + (long)row * ld + k;
+    if (k + 4 <= K && (((uintptr_t)p) & 15) == 0) {
+      v = *(const float4*)p;
+    } else {
+      v.x = (k < K) ? p[0] : 0.f;
+      v.y = (k + 1 < K) ? p[1] : 0.f;
+      v.z = (k + 2 < K) ? p[2] : 0.f;
+      v.w = (k + 3 < K) ? p[3] : 0.f;
+    }
+  }
+  return v;
+}
+
+// hi / lo bf16 planes of 4 values, stored as one 8-byte word each (v - hi is exact in fp32)
+__device__ __forceinline__ void split_store(const float4 v, uint16_t* hi, uint16_t* lo) {
+  const uint32_t h0 = pack_bf16x2(v.x, v.y), h1 = pack_bf16x2(v.z, v.w);
+  const uint32_t l0 = pack_bf16x2(v.x - __uint_as_float(h0 << 16), v.y - __uint_as_float(h0 & 0xffff0000u));
+  const uint32_t l1 = pack_bf16x2(v.z - __uint_as_float(h1 << 16), v.w - __uint_as_float(h1 & 0xffff0000u));
+  *(uint2*)hi = make_uint2(h0, h1);
+  *(uint2*)lo = make_uint2(l0, l1);
+}
+
+template <bool AL>
+__device__ __forceinline__ void split_run(const SplitTask& q, SsSmem& sm, int bx, int by) {
+  const int tn = bx, ks = by;                        // grid width = tiles_n
+  const int n0 = tn * SS_BN;
+  const int M = q.M, N = q.N, K = q.K;
+  const int kchunk = ((K + q.ksplit - 1) / q.ksplit + SS_BK - 1) / SS_BK * SS_BK;
+  const int kb = ks * kchunk, ke = min(K, kb + kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 1, wn = wave >> 1;
+  const int mt = (M + 15) / 16;                      // m tiles present
+  f32x4 acc[9][2];
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra[SS_VA], rb[SS_VB];                        // fp32 bits
+  uint32_t ma[SS_VA], mb[SS_VB];                     // applied at the stash, not at the load
+  // Full stages load without element guards: a row outside the matrix reads a clamped valid
+  // address and is zeroed through the mask at the stash, so the loads stay in flight across
+  // the MFMAs.  AL: 16-byte aligned rows (one 16-byte load per 4 values), else four 4-byte
+  // loads.  The K tail takes the guarded ld4f in an unpipelined loop after the main one.
+  const int kfull = kb + (ke - kb) / SS_BK * SS_BK;
+  auto ld_full = [&](const float* p) -> uint4 {
+    if constexpr (AL) {
+      return gload16(p);
+    } else {
+      return make_uint4(gload4(p), gload4(p + 1), gload4(p + 2), gload4(p + 3));
+    }
+  };
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < SS_VA; ++u) {
+      const int e = tid + u * SS_NT, row = e >> 3, kc = (e & 7) * 4;
+      const bool ok = e < SS_NVA && row < M;
+      ra[u] = ld_full(q.A + (ok ? (long)row * q.lda + k0 + kc : 0));
+      ma[u] = opaque_mask(ok);
+    }
+#pragma unroll
+    for (int u = 0; u < SS_VB; ++u) {
+      const int e = tid + u * SS_NT, row = e >> 3, kc = (e & 7) * 4;
+      const bool ok = n0 + row < N;
+      rb[u] = ld_full(q.B + (ok ? (long)(n0 + row) * q.ldb + k0 + kc : 0));
+      mb[u] = opaque_mask(ok);
+    }
+  };
+  auto fetch_guarded = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < SS_VA; ++u) {
+      const int e = tid + u * SS_NT, row = e >> 3, kc = (e & 7) * 4;
+      ra[u] = __builtin_bit_cast(uint4, (e < SS_NVA) ? ld4f(q.A, q.lda, row, M, k0 + kc, ke)
+                                                      : make_float4(0.f, 0.f, 0.f, 0.f));
+      ma[u] = 0xffffffffu;
+    }
+#pragma unroll
+    for (int u = 0; u < SS_VB; ++u) {
+      const int e = tid + u * SS_NT, row = e >> 3, kc = (e & 7) * 4;
+      rb[u] = __builtin_bit_cast(uint4, ld4f(q.B, q.ldb, n0 + row, N, k0 + kc, ke));
+      mb[u] = 0xffffffffu;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < SS_VA; ++u) {
+      const int e = tid + u * SS_NT, row = e >> 3, kc = (e & 7) * 4;
+      if (e < SS_NVA)
+        split_store(__builtin_bit_cast(float4, and_mask(ra[u], ma[u])), &sm.ah[buf][row][kc], &sm.al[buf][row][kc]);
+    }
+#pragma unroll
+    for (int u = 0; u < SS_VB; ++u) {
+      const int e = tid + u * SS_NT, row = e >> 3, kc = (e & 7) * 4;
+      split_store(__builtin_bit_cast(float4, and_mask(rb[u], mb[u])), &sm.bh[buf][row][kc], &sm.bl[buf][row][kc]);
+    }
+  };
+  const int kq = (lane >> 4) * 8;
+  auto compute = [&](int buf) {
+    bf16x8 bh[2], bl[2], ah[9], al[9];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = wn * 32 + j * 16 + (lane & 15);
+      bh[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&sm.bh[buf][row][kq]);
+      bl[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&sm.bl[buf][row][kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int row = wm * 144 + i * 16 + (lane & 15);
+      ah[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&sm.ah[buf][row][kq]);
+      al[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&sm.al[buf][row][kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      if (wm * 9 + i < mt)                           // uniform: skip m tiles beyond M
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {                // small terms first
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+  };
+  int buf = 0;
+  if (kb < kfull) {
+    fetch(kb);
+    stash(0);
+    __syncthreads();
+  }
+  for (int k0 = kb; k0 < kfull; k0 += SS_BK) {
+    // the last full stage re-fetches itself into the idle buffer (never read)
+    fetch(k0 + SS_BK < kfull ? k0 + SS_BK : k0);
+    compute(buf);
+    __builtin_amdgcn_sched_barrier(0);               // keep the stash (and its load waits) after the MFMAs
+    stash(buf ^ 1);                                   // its last reads closed at the previous barrier
+    __syncthreads();
+    buf ^= 1;
+  }
+  for (int k0 = kfull; k0 < ke; k0 += SS_BK) {
+    fetch_guarded(k0);
+    stash(buf);
+    __syncthreads();
+    compute(buf);
+    __syncthreads();
+  }
+  const long ldp = (N + 3) / 4 * 4;                 // partial row pitch (16-byte rows)
+  float* out = (q.ksplit > 1) ? q.part + (long)ks * M * ldp : q.C;
+  const long ldo = (q.ksplit > 1) ? ldp : q.ldc;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm * 144 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (row < M && col < N) out[(long)row * ldo + col] = acc[i][j][r];
+      }
+}
+
+__device__ __forceinline__ void split_body(const SplitTask& task, int bx, int by) {
+  __shared__ SsSmem sm;
+  const SplitTask q = task;                          // the record once, into registers
+  if ((((q.lda | q.ldb) & 3) == 0) && (((uintptr_t)q.A | (uintptr_t)q.B) & 15) == 0)
+    split_run<true>(q, sm, bx, by);
+  else
+    split_run<false>(q, sm, bx, by);
+}
+
 // Sum of the K-slice partials, in slice order: block = 256 threads x 4 consecutive columns
-// of one row (16-byte loads of the partials; the output row pitch is a multiple of 4).
-__device__ __forceinline__ void skinny_reduce_body(const SkinnyTask& q, int bx, int) {
+// of one row (16-byte loads of the partials; the partial row pitch is a multiple of 4).
+__device__ __forceinline__ void reduce_body(const ReduceTask& q, int bx, int) {
   const int N4 = (q.N + 3) / 4;
   const long ldp = (long)N4 * 4;
   const long total = (long)q.M * ldp;
@@ -441,33 +667,73 @@ __device__ __forceinline__ void skinny_reduce_body(const SkinnyTask& q, int bx, 
 }
 
 __global__ __launch_bounds__(SK_NT) void k_skinny_bf16(SkinnyTask q) { skinny_body(q, blockIdx.x, blockIdx.y); }
-__global__ __launch_bounds__(256) void k_skinny_reduce(SkinnyTask q) { skinny_reduce_body(q, blockIdx.x, 0); }
+__global__ __launch_bounds__(SS_NT) void k_split_bf16x3(SplitTask q) { split_body(q, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(256) void k_slice_reduce(ReduceTask q) { reduce_body(q, blockIdx.x, 0); }
 KFAC_GROUPED_KERNEL_XCD(k_skinny_bf16_g, skinny_body, SkinnyTask, SK_NT)
-KFAC_GROUPED_KERNEL(k_skinny_reduce_g, skinny_reduce_body, SkinnyTask, 256)
+KFAC_GROUPED_KERNEL_XCD(k_split_bf16x3_g, split_body, SplitTask, SS_NT)
+KFAC_GROUPED_KERNEL(k_slice_reduce_g, reduce_body, ReduceTask, 256)
 
-int skinny_ksplit(int N, int K) {
-  const int tiles = (N + SK_BN - 1) / SK_BN;
-  int ks = (256 + tiles - 1) / tiles;                 // ~one workgroup per compute unit
-  ks = std::min(ks, std::max(1, K / 512));            // at least 512 k per slice
+// K slices for a whole-width kernel with `tiles` column tiles: about one workgroup per
+// compute unit, at least 512 k per slice, at most 16 slices.
+static int ksplit_for(int tiles, int K) {
+  int ks = (256 + tiles - 1) / tiles;
+  ks = std::min(ks, std::max(1, K / 512));
   return std::max(1, std::min(ks, 16));
 }
+int skinny_ksplit(int N, int K) { return ksplit_for((N + SK_BN - 1) / SK_BN, K); }
+int split_ksplit(int N, int K) { return ksplit_for((N + SS_BN - 1) / SS_BN, K); }
 SkinnyTask make_skinny_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, float* C,
                             long ldc, float* part, int ksplit) {
   SkinnyTask q{M, N, K, A, lda, B, ldb, C, ldc, part, ksplit, (N + SK_BN - 1) / SK_BN};
   return q;
 }
+SplitTask make_split_task(int M, int N, int K, const float* A, long lda, const float* B, long ldb, float* C,
+                          long ldc, float* part, int ksplit) {
+  SplitTask q{M, N, K, A, lda, B, ldb, C, ldc, part, ksplit, (N + SS_BN - 1) / SS_BN};
+  return q;
+}
+ReduceTask make_reduce_task(int M, int N, const float* part, float* C, long ldc, int ksplit) {
+  ReduceTask q{M, N, part, C, ldc, ksplit};
+  return q;
+}
 int skinny_blocks(const SkinnyTask& q) { return q.tiles_n * q.ksplit; }
-int skinny_reduce_blocks(const SkinnyTask& q) { return (int)(((long)q.M * ((q.N + 3) / 4) + 255) / 256); }
-size_t skinny_part_bytes(int M, int N, int K) {
-  const int ks = skinny_ksplit(N, K);
+int split_blocks(const SplitTask& q) { return q.tiles_n * q.ksplit; }
+int reduce_blocks(const ReduceTask& q) { return (int)(((long)q.M * ((q.N + 3) / 4) + 255) / 256); }
+static size_t part_bytes(int M, int N, int ks) {
   return ks > 1 ? (size_t)ks * M * ((N + 3) / 4 * 4) * sizeof(float) : 0;
 }
+size_t skinny_part_bytes(int M, int N, int K) { return part_bytes(M, N, skinny_ksplit(N, K)); }
+size_t split_part_bytes(int M, int N, int K) { return part_bytes(M, N, split_ksplit(N, K)); }
 hipError_t launch_skinny_g(const SkinnyTask* t, GroupMap gm, int blocks, hipStream_t s) {
   if (blocks > 0) hipLaunchKernelGGL(k_skinny_bf16_g, dim3(blocks), dim3(SK_NT), 0, s, t, gm);
   return hipGetLastError();
 }
-hipError_t launch_skinny_reduce_g(const SkinnyTask* t, GroupMap gm, int blocks, hipStream_t s) {
-  if (blocks > 0) hipLaunchKernelGGL(k_skinny_reduce_g, dim3(blocks), dim3(256), 0, s, t, gm);
+hipError_t launch_split_g(const SplitTask* t, GroupMap gm, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_split_bf16x3_g, dim3(blocks), dim3(SS_NT), 0, s, t, gm);
+  return hipGetLastError();
+}
+hipError_t launch_skinny(const SkinnyTask& q, hipStream_t s) {
+  if (q.M > SK_MMAX) return hipErrorInvalidValue;
+  if (q.M <= 0 || q.N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_skinny_bf16, dim3(q.tiles_n, q.ksplit), dim3(SK_NT), 0, s, q);
+  if (q.ksplit > 1) {
+    const ReduceTask r = make_reduce_task(q.M, q.N, q.part, q.C, q.ldc, q.ksplit);
+    hipLaunchKernelGGL(k_slice_reduce, dim3(reduce_blocks(r)), dim3(256), 0, s, r);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_split(const SplitTask& q, hipStream_t s) {
+  if (q.M > SK_MMAX) return hipErrorInvalidValue;
+  if (q.M <= 0 || q.N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_bf16x3, dim3(q.tiles_n, q.ksplit), dim3(SS_NT), 0, s, q);
+  if (q.ksplit > 1) {
+    const ReduceTask r = make_reduce_task(q.M, q.N, q.part, q.C, q.ldc, q.ksplit);
+    hipLaunchKernelGGL(k_slice_reduce, dim3(reduce_blocks(r)), dim3(256), 0, s, r);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_reduce_g(const ReduceTask* t, GroupMap gm, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_slice_reduce_g, dim3(blocks), dim3(256), 0, s, t, gm);
   return hipGetLastError();
 }
 

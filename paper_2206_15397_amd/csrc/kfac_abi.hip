@@ -114,8 +114,13 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
   // Omega^T (l_pad x d), rows >= l zero
   CK(launch_omega(dd, n, dd, L, seed, stream_id, inversion_index, w.OmT, ldt, bf ? w.OmTb : nullptr, nullptr,
                   0, nullptr, s));
+  // the whole-width kernels (all l_pad rows per workgroup) when l_pad fits them
+  const bool whole = bf && L <= kWholeWidthMaxM;
   auto f_times = [&](const float* At, const uint16_t* Atb, float* Out) -> hipError_t {
-    // Out^T = At^T... i.e. Out (L x d) = At (L x d) * F (d x d); F symmetric so this is (F A^T)^T.
+    // Out (L x d) = At (L x d) * F (d x d); F symmetric, so Out^T = F At^T.
+    if (whole && dd >= 2048)
+      return launch_skinny(make_skinny_task(L, dd, dd, Atb, ldt, F_bf16, ldfb, Out, ldt, w.skp,
+                                            skinny_ksplit(dd, dd)), s);
     if (bf) return launch_gemm_bf16_nt(L, dd, dd, Atb, ldt, F_bf16, ldfb, Out, ldt, s);
     GemmP g{};
     g.M = L; g.N = dd; g.K = dd;
@@ -157,8 +162,10 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
   }
   float* Qt = cur;
   float* Wt = (cur == w.Yt) ? w.Qt : w.Yt;
-  // Rayleigh-Ritz: W = F Q (fp32), C = Q^T W (fp64)
-  {
+  // Rayleigh-Ritz: W = F Q (fp32 tiles; split-bf16 in the bf16-sketch mode), C = Q^T W (fp64)
+  if (whole) {
+    CK(launch_split(make_split_task(L, dd, dd, Qt, ldt, F, ldf, Wt, ldt, w.skp, split_ksplit(dd, dd)), s));
+  } else {
     GemmP g{};
     g.M = L; g.N = dd; g.K = dd;
     g.A = Qt; g.lda = ldt; g.B = F; g.ldb = ldf;

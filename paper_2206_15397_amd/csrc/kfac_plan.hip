@@ -17,7 +17,7 @@ using namespace kfac;
 namespace {
 
 enum Kind {
-  K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_SKINNY, K_SKINNY_R, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRTRI, K_TRMM, K_TRIDIAG, K_PREP,
+  K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_SKINNY, K_SKINNY_R, K_SPLIT, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRTRI, K_TRMM, K_TRIDIAG, K_PREP,
   K_BISECT, K_SELECT, K_VEC, K_CLEAD, K_CLUSTER, K_BT, K_SIGN_P, K_SIGN_A
 };
 
@@ -86,7 +86,7 @@ struct FactorInfo {
   int ea_ks;
   size_t ws_off, ws_bytes;   // EigWs region
   size_t ea_off, ea_bytes;   // EA split-K partials
-  size_t sk_off, sk_bytes;   // skinny sketch GEMM split-K partials
+  size_t sk_off, sk_bytes;   // whole-width sketch / Rayleigh-Ritz split-K partials
 };
 
 struct LayerInfo {
@@ -244,7 +244,8 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             }
             T.add(K_BF16, g, gx2, nb2, false, false, ws);
           } else {
-            std::vector<SkinnyTask> g, gr;
+            std::vector<SkinnyTask> g;
+            std::vector<ReduceTask> gr;
             std::vector<int> gx2, nb2, gxr, nbr;
             for (int i : act) {
               const FactorInfo& I = P->fi[i];
@@ -253,7 +254,10 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
               SkinnyTask q = make_skinny_task(I.l_pad, I.d, I.d, A, I.ldt, P->f[i].F_bf16, P->f[i].ldfb, out, I.ldt,
                                               (float*)wsp(I.sk_off), skinny_ksplit(I.d, I.d));
               g.push_back(q); gx2.push_back(q.tiles_n); nb2.push_back(skinny_blocks(q));
-              if (q.ksplit > 1) { gr.push_back(q); gxr.push_back(skinny_reduce_blocks(q)); nbr.push_back(skinny_reduce_blocks(q)); }
+              if (q.ksplit > 1) {
+                const ReduceTask rq = make_reduce_task(q.M, q.N, q.part, q.C, q.ldc, q.ksplit);
+                gr.push_back(rq); gxr.push_back(reduce_blocks(rq)); nbr.push_back(reduce_blocks(rq));
+              }
             }
             T.add(K_SKINNY, g, gx2, nb2, false, false, ws);
             T.add(K_SKINNY_R, gr, gxr, nbr);
@@ -319,9 +323,12 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           T.add(K_TRMM, tm, gxt, nbt, false, false, wm);
         }
       }
-      // Rayleigh-Ritz: W = F Q (fp32) into spare, C = Q^T W (fp64) into G
+      // Rayleigh-Ritz: W = F Q into spare (fp32 tiles; split-bf16 in the bf16-sketch mode),
+      // C = Q^T W (fp64) into G
       std::vector<GemmP> g;
-      std::vector<int> gx2, nb2;
+      std::vector<SplitTask> gs;
+      std::vector<ReduceTask> gsr;
+      std::vector<int> gx2, nb2, gxs, nbs, gxsr, nbsr;
       std::vector<GramP> gp;
       std::vector<int> gxg, nbg, gxr, nbr;
       Work wrr, wg, wr;
@@ -331,18 +338,33 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
         wrr += gemm_work(l, d, d, false);
         wg += Work{2 * l * l * d, 8 * l * d};
         wr += Work{0, 8 * l * l};
-        GemmP q{};
-        q.M = I.l_pad; q.N = I.d; q.K = I.d;
-        q.A = basis[i]; q.lda = I.ldt; q.B = P->f[i].F; q.ldb = P->f[i].ldf;
-        q.C = spare[i]; q.ldc = I.ldt; q.alpha = 1.f; q.ones_col = -1;
-        g.push_back(q);
+        if (bf) {
+          const SplitTask q = make_split_task(I.l_pad, I.d, I.d, basis[i], I.ldt, P->f[i].F, P->f[i].ldf, spare[i],
+                                              I.ldt, (float*)wsp(I.sk_off), split_ksplit(I.d, I.d));
+          gs.push_back(q); gxs.push_back(q.tiles_n); nbs.push_back(split_blocks(q));
+          if (q.ksplit > 1) {
+            const ReduceTask rq = make_reduce_task(q.M, q.N, q.part, q.C, q.ldc, q.ksplit);
+            gsr.push_back(rq); gxsr.push_back(reduce_blocks(rq)); nbsr.push_back(reduce_blocks(rq));
+          }
+        } else {
+          GemmP q{};
+          q.M = I.l_pad; q.N = I.d; q.K = I.d;
+          q.A = basis[i]; q.lda = I.ldt; q.B = P->f[i].F; q.ldb = P->f[i].ldf;
+          q.C = spare[i]; q.ldc = I.ldt; q.alpha = 1.f; q.ones_col = -1;
+          g.push_back(q);
+        }
         GramP gr = make_gram_task(basis[i], I.ldt, spare[i], I.ldt, I.l_pad, I.d, 0, W[i].part, W[i].G, I.l_pad,
                                   status);
         const int tiles = gram_tiles(I.l_pad, 0);
         gp.push_back(gr); gxg.push_back(tiles); nbg.push_back(tiles * gr.ksplit);
         gxr.push_back(tiles); nbr.push_back(tiles * gram_reduce_slices());
       }
-      add_gemm(P, T, gord, g, false, false, wrr);
+      if (bf) {
+        T.add(K_SPLIT, gs, gxs, nbs, false, false, wrr);
+        T.add(K_SKINNY_R, gsr, gxsr, nbsr);
+      } else {
+        add_gemm(P, T, gord, g, false, false, wrr);
+      }
       T.add(K_GRAM_P, gp, gxg, nbg, false, false, wg);
       T.add(K_GRAM_R, gp, gxr, nbr, false, false, wr);
     }
@@ -507,7 +529,8 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
     I.ea_ks = I.ea ? ea_choose_ksplit(I.d, F.n, xb) : 1;
     I.ea_bytes = (I.ea && I.ea_ks > 1) ? ea_workspace_bytes(I.d, F.n, xb) : 0;
     I.ea_off = take(I.ea_bytes + 16);
-    I.sk_bytes = (bf && !I.exact) ? skinny_part_bytes(I.l_pad, I.d, I.d) : 0;
+    I.sk_bytes = (bf && !I.exact)
+                     ? std::max(skinny_part_bytes(I.l_pad, I.d, I.d), split_part_bytes(I.l_pad, I.d, I.d)) : 0;
     I.sk_off = take(I.sk_bytes + 16);
     P->fi.push_back(I);
   }
@@ -566,7 +589,7 @@ int kfac_plan_launch_count(const kfac_plan* plan) { return plan ? (int)plan->tab
 
 const char* kfac_plan_launch_name(const kfac_plan* plan, int index) {
   static const char* names[] = {"ea_tiles", "ea_finalize", "ea_tiles_bf16", "ea_finalize_bf16", "omega",
-                                "gemm_f32", "gemm_bf16", "gemm_bf16_skinny", "skinny_reduce", "gram_partial",
+                                "gemm_f32", "gemm_bf16", "gemm_bf16_skinny", "slice_reduce", "gemm_bf16x3", "gram_partial",
                                 "gram_reduce", "cholinv", "trtri_cols", "trmm", "tridiag", "tri_prep", "tri_bisect",
                                 "tri_select", "tri_vec", "tri_cluster_lead", "tri_cluster", "backtransform",
                                 "sign_partial", "sign_apply"};
@@ -601,7 +624,8 @@ kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, 
       case K_GEMM: e = launch_gemm_g((const GemmP*)tp, gm, r.blocks, r.ta, r.tb, r.cfg, s); break;
       case K_BF16: e = launch_gemm_bf16_g((const BfGemmTask*)tp, gm, r.blocks, s); break;
       case K_SKINNY: e = launch_skinny_g((const SkinnyTask*)tp, gm, r.blocks, s); break;
-      case K_SKINNY_R: e = launch_skinny_reduce_g((const SkinnyTask*)tp, gm, r.blocks, s); break;
+      case K_SKINNY_R: e = launch_reduce_g((const ReduceTask*)tp, gm, r.blocks, s); break;
+      case K_SPLIT: e = launch_split_g((const SplitTask*)tp, gm, r.blocks, s); break;
       case K_GRAM_P: e = launch_gram_partial_g((const GramP*)tp, gm, r.blocks, s); break;
       case K_GRAM_R: e = launch_gram_reduce_g((const GramP*)tp, gm, r.blocks, s); break;
       case K_CHOLINV: e = launch_cholinv_g((const CholInvTask*)tp, gm, r.blocks, s); break;

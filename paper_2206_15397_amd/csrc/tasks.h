@@ -47,6 +47,22 @@ struct SkinnyTask {      // C[M x N] = A[M x K] B[N x K]^T, M <= 288, bf16: bloc
   int ksplit, tiles_n;
 };
 
+struct SplitTask {       // C[M x N] = A[M x K] B[N x K]^T, M <= 288, fp32 inputs split into
+  int M, N, K;           // bf16 hi + lo pairs: block (N tile, K slice)
+  const float* A; long lda;
+  const float* B; long ldb;
+  float* C; long ldc;
+  float* part;           // ksplit > 1: [ksplit][M][N] fp32 partial sums
+  int ksplit, tiles_n;
+};
+
+struct ReduceTask {      // C = sum over k of part[k] (K-slice partials, in slice order)
+  int M, N;
+  const float* part;     // [ksplit][M][round_up(N, 4)]
+  float* C; long ldc;
+  int ksplit;
+};
+
 struct LinTask {         // K-FAC linear layer GEMMs on bf16 MFMA: block (flat tile)
   int M, N, K;
   const uint16_t* A; long lda;

@@ -31,6 +31,7 @@ struct EigWs {
   int* sidx;
   uint16_t *OmTb, *Qtb;
   double *G, *Wc, *Li, *part, *A, *V, *diag, *off, *Z, *scr, *Dd;
+  float* skp;            // bf16 mode, l_pad <= 288: split-K partials of the whole-width GEMMs
   int* fail;
   size_t bytes;
 
@@ -44,6 +45,7 @@ struct EigWs {
     OmT = Yt = Qt = P = nullptr;
     OmTb = Qtb = nullptr;
     G = Wc = Li = part = nullptr;
+    skp = nullptr;
     if (!exact) {
       OmT = b.take<float>(l_pad * ldt);
       Yt = b.take<float>(l_pad * ldt);
@@ -51,6 +53,11 @@ struct EigWs {
       if (bf16) {
         OmTb = b.take<uint16_t>(l_pad * ldt);
         Qtb = b.take<uint16_t>(l_pad * ldt);
+        if (l_pad <= kWholeWidthMaxM) {
+          const size_t pb = std::max(skinny_part_bytes((int)l_pad, (int)d, (int)d),
+                                     split_part_bytes((int)l_pad, (int)d, (int)d));
+          skp = b.take<float>(pb / sizeof(float) + 4);
+        }
       }
       G = b.take<double>(l_pad * l_pad);
       Wc = b.take<double>(l_pad * l_pad);

@@ -258,3 +258,24 @@ def test_rand_eig_bf16_sketch(d, r, p, q):
     So = O.precondition(J, Uo, Do, Ug_, Dg_, 0.1)
     Sg = O.precondition(J, to_np(U), to_np(D), Ug_, Dg_, 0.1)
     assert rel(Sg, So) <= 5e-3
+
+
+@pytest.mark.parametrize("d,k,r,p,q", [(700, 40, 32, 16, 1), (2000, 48, 32, 16, 1), (3000, 200, 128, 80, 1)])
+def test_rand_eig_bf16_sketch_rayleigh_ritz_at_fp32_accuracy(d, k, r, p, q):
+    """Rank-k factor with k <= r + p: the bf16 sketch still captures range(F), and after one
+    power iteration its rounding moves the Ritz values by about 1e-6 (second order in the
+    subspace angle; with q = 0 that term alone is near 1e-4), so e_lambda is set by the
+    Rayleigh-Ritz product W = F Q.  The split-bf16 product (hi*hi + hi*lo + lo*hi, fp32
+    accumulation) keeps it below 1e-5; a plain bf16 product would leave about 1e-4 (the
+    bf16 rounding of F and Q)."""
+    sig = np.zeros(d)
+    sig[:k] = np.exp(-2.0 * np.arange(k) / k)
+    F = synth.psd_factor(d, sig, 40 + d).astype(np.float32)
+    Ft = torch.from_numpy(F).to(DEV)
+    U, D, st = K().rand_eig(Ft, r, p, q, seed=0, sketch="bf16", F_bf16=Ft.to(torch.bfloat16))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    _, Do = O.srevd(F.astype(np.float64), r, p, q, 0)
+    assert e_lambda(to_np(D), Do) <= 1e-5, e_lambda(to_np(D), Do)
+    Ug = to_np(U)
+    assert np.abs(Ug.T @ Ug - np.eye(r)).max() < 1e-4

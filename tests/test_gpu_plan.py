@@ -261,37 +261,33 @@ def test_plan_autotune_keeps_results_bitwise(tmp_path):
 
 @pytest.mark.parametrize("f32_cfg", [0, 1, 2, 3, 4])
 def test_plan_every_gemm_config_matches(f32_cfg):
-    """Each fp32 GEMM tile configuration reproduces the default bit for bit (same k order);
-    the two bf16 sketch kernels (96 x 128 tiles; whole-width tiles with split-K) both meet
-    the bf16 gates against the oracle."""
+    """Each fp32 GEMM tile configuration reproduces the default bit for bit (same k order) on
+    the fp32-sketch plan, whose Rayleigh-Ritz product can take every configuration; the two
+    bf16 sketch kernels (96 x 128 tiles; whole-width tiles with split-K) both meet the bf16
+    gates against the oracle under each fp32 configuration."""
     facs, Js = make_problem(seed=6)
-    runs = {}
-    for bf_cfg in (0, 1):
+
+    def run(sketch, f32, bf):
         fd, ld = device_inputs(facs, Js)
-        plan = K().Plan(fd, ld, sketch="bf16")
+        plan = K().Plan(fd, ld, sketch=sketch)
         plan.set_scalars(RHO, LAM, SEED, INV).upload()
-        plan.force_config(gemm_f32=f32_cfg, sketch_bf16=bf_cfg)
-        cf = plan.launch_configs()
-        names = plan.launch_names()
-        assert any(n == ("gemm_bf16_skinny" if bf_cfg else "gemm_bf16") for n in names)
+        plan.force_config(gemm_f32=f32, sketch_bf16=bf)
         plan.launch()
         torch.cuda.synchronize()
         assert int(plan.status.item()) == 0
-        runs[bf_cfg] = (plan, cf, names)
+        return plan
+
+    ref, got = run("fp32", 0, -1), run("fp32", f32_cfg, -1)
+    assert any(n == "gemm_f32" and c == f32_cfg for n, c in zip(got.launch_names(), got.launch_configs()))
+    for a, b in zip(ref.factors, got.factors):
+        assert torch.equal(a["U"], b["U"]) and torch.equal(a["D"], b["D"])
+    for a, b in zip(ref.layers, got.layers):
+        assert torch.equal(a["S"], b["S"])
+    for bf_cfg in (0, 1):
+        plan = run("bf16", f32_cfg, bf_cfg)
+        names = plan.launch_names()
+        assert any(n == ("gemm_bf16_skinny" if bf_cfg else "gemm_bf16") for n in names)
+        assert "gemm_bf16x3" in names
         for i, f in enumerate(facs):
             Uo, Do = O.srevd(to_np(plan.factors[i]["F"]), f["r"], f["p"], f["q"], SEED, i, INV)
             assert e_lambda(to_np(plan.factors[i]["D"]), Do) <= 5e-3
-    # fp32 launches that could take the forced configuration did
-    plan, cf, names = runs[0]
-    assert any(n == "gemm_f32" and c == f32_cfg for n, c in zip(names, cf))
-    # and agree bit for bit with the default tiles (same sketch kernel)
-    fd, ld = device_inputs(facs, Js)
-    ref = K().Plan(fd, ld, sketch="bf16")
-    ref.set_scalars(RHO, LAM, SEED, INV).upload()
-    ref.force_config(gemm_f32=0, sketch_bf16=0)
-    ref.launch()
-    torch.cuda.synchronize()
-    for a, b in zip(ref.factors, plan.factors):
-        assert torch.equal(a["U"], b["U"]) and torch.equal(a["D"], b["D"])
-    for a, b in zip(ref.layers, plan.layers):
-        assert torch.equal(a["S"], b["S"])
