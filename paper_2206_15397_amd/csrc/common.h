@@ -48,6 +48,12 @@ __device__ __forceinline__ uint4 and_mask(uint4 v, uint32_t m) { return make_uin
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+// LDS writes of this wavefront visible to its own later LDS reads (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Two fp32 -> packed bf16 (a in the low half), round to nearest even: one
 // v_cvt_pk_bf16_f32 on gfx950.
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {

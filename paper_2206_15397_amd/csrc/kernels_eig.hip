@@ -459,7 +459,9 @@ __device__ __forceinline__ void tri_select_body(const EigTask& q, int, int) {
   }
   __threadfence_block();
   __syncthreads();
-  const double ctol = 1e-8 * m.scal[0];
+  // Twisted-factorisation vectors of eigenvalues a gap g apart lose orthogonality of about
+  // 2 eps ||T|| / g; below g = 1e-9 ||T|| (loss above ~5e-7) members take the cluster pass.
+  const double ctol = 1e-9 * m.scal[0];
   int any = 0;
   for (int k = tid; k < r; k += blockDim.x) {
     int s = 1;
@@ -543,91 +545,110 @@ __device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
 // ======================================================================================
 // 6. Tight clusters: inverse iteration on the block with Gram-Schmidt against the earlier
 // members (sequential over members, one workgroup).  Exits at once if there is none.
-// scratch: 5 * n doubles.
+// The block's tridiagonal, its LU factors and the iterate live in LDS: the two serial
+// sweeps (one thread) touch only LDS, the rest is spread over the workgroup.
 // ======================================================================================
 __device__ __forceinline__ void tri_cluster_body(const EigTask& q, int, int) {
-  const double* diag = q.diag; const int n = q.n, r = q.r; const TriMeta& m = q.m; double* Z = q.Z;
-  const long ldz = q.ldz; double* scratch = q.cl; int* status = q.status;
-  __shared__ double red[4];
+  const double* diag = q.diag; const int r = q.r; const TriMeta& m = q.m; double* Z = q.Z;
+  const long ldz = q.ldz; int* status = q.status;
+  __shared__ double red[16];
   __shared__ double sdot;
+  __shared__ double sd[KFAC_MAX_SKETCH], se[KFAC_MAX_SKETCH];        // block of T
+  __shared__ double lf[KFAC_MAX_SKETCH], rud[KFAC_MAX_SKETCH];       // multipliers, 1 / U diagonal
+  __shared__ double uu[KFAC_MAX_SKETCH], u2[KFAC_MAX_SKETCH];        // U super-diagonals
+  __shared__ double zc[KFAC_MAX_SKETCH];                              // the iterate
+  __shared__ unsigned char pv[KFAC_MAX_SKETCH];                        // row interchange at i
   if (m.scal[2] == 0.0) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nw = blockDim.x >> 6;
   const double tn = m.scal[0];
-  double* lf = scratch;
-  double* ud = scratch + n;
-  double* uu = scratch + 2L * n;
-  double* u2 = scratch + 3L * n;
-  double* pv = scratch + 4L * n;
+  auto block_sum = [&](double v) -> double {
+    v = wave_sum(v);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += red[w];
+      sdot = t;
+    }
+    __syncthreads();
+    const double t = sdot;
+    __syncthreads();                                   // red / sdot reusable
+    return t;
+  };
   for (int k = 1; k < r; ++k) {
     if (m.cstart[k]) continue;
     int k0 = k;
     while (k0 > 0 && !m.cstart[k0]) --k0;
     const int j = m.col_task[k];
-    const int b0 = m.blo[j], b1 = m.bhi[j];
+    const int b0 = m.blo[j], b1 = m.bhi[j], nb = b1 - b0;
     const double mu = m.lam[j] + (double)(k - k0) * 10.0 * kEps * tn;
+    for (int i = tid; i < nb; i += blockDim.x) {
+      sd[i] = diag[b0 + i] - mu;
+      se[i] = (i + 1 < nb) ? m.es[b0 + i] : 0.0;
+    }
+    __syncthreads();
     if (tid == 0) {
-      // LU with partial pivoting of the block of T - mu I
-      double cd = diag[b0] - mu, cu = (b0 + 1 < b1) ? m.es[b0] : 0.0;
-      for (int i = b0; i + 1 < b1; ++i) {
-        const double dl = m.es[i], nd = diag[i + 1] - mu, nu = (i + 2 < b1) ? m.es[i + 1] : 0.0;
+      // LU with partial pivoting of the block of T - mu I (U diagonal kept in rud)
+      double cd = sd[0], cu = (nb > 1) ? se[0] : 0.0;
+      for (int i = 0; i + 1 < nb; ++i) {
+        const double dl = se[i], nd = sd[i + 1], nu = (i + 2 < nb) ? se[i + 1] : 0.0;
         if (fabs(cd) >= fabs(dl)) {
           if (cd == 0.0) cd = kEps * tn;
           const double f = dl / cd;
-          lf[i] = f; ud[i] = cd; uu[i] = cu; u2[i] = 0.0; pv[i] = 0.0;
+          lf[i] = f; rud[i] = cd; uu[i] = cu; u2[i] = 0.0; pv[i] = 0;
           cd = nd - f * cu; cu = nu;
         } else {
           const double f = cd / dl;
-          lf[i] = f; ud[i] = dl; uu[i] = nd; u2[i] = nu; pv[i] = 1.0;
+          lf[i] = f; rud[i] = dl; uu[i] = nd; u2[i] = nu; pv[i] = 1;
           cd = cu - f * nd; cu = -f * nu;
         }
       }
-      ud[b1 - 1] = (cd == 0.0) ? kEps * tn : cd;
+      rud[nb - 1] = (cd == 0.0) ? kEps * tn : cd;
+      uu[nb - 1] = 0.0;
+      u2[nb - 1] = 0.0;
     }
+    __syncthreads();
+    for (int i = tid; i < nb; i += blockDim.x) rud[i] = 1.0 / rud[i];
+    for (int i = tid; i < nb; i += blockDim.x) zc[i] = Z[(long)(b0 + i) * ldz + k];
     __syncthreads();
     for (int iter = 0; iter < 3; ++iter) {
       if (tid == 0) {
-        double cur = Z[(long)b0 * ldz + k];
-        for (int i = b0; i + 1 < b1; ++i) {
-          const double nxt = Z[(long)(i + 1) * ldz + k];
-          if (pv[i] == 0.0) { Z[(long)i * ldz + k] = cur; cur = nxt - lf[i] * cur; }
-          else { Z[(long)i * ldz + k] = nxt; cur = cur - lf[i] * nxt; }
+        // forward: apply the interchanges and multipliers; backward: solve with U
+        double cur = zc[0];
+        for (int i = 0; i + 1 < nb; ++i) {
+          const double nxt = zc[i + 1];
+          if (pv[i] == 0) { zc[i] = cur; cur = nxt - lf[i] * cur; }
+          else { zc[i] = nxt; cur = cur - lf[i] * nxt; }
         }
-        Z[(long)(b1 - 1) * ldz + k] = cur;
+        zc[nb - 1] = cur;
         double x1 = 0.0, x2 = 0.0;
-        for (int i = b1 - 1; i >= b0; --i) {
-          double s = Z[(long)i * ldz + k];
-          if (i + 1 < b1) s -= uu[i] * x1;
-          if (i + 2 < b1) s -= u2[i] * x2;
-          const double xi = s / ud[i];
-          Z[(long)i * ldz + k] = xi;
+        for (int i = nb - 1; i >= 0; --i) {
+          const double xi = (zc[i] - uu[i] * x1 - u2[i] * x2) * rud[i];   // x1 = x2 = 0 past the end
+          zc[i] = xi;
           x2 = x1; x1 = xi;
         }
       }
       __syncthreads();
       for (int pass = 0; pass < 2; ++pass) {
-        for (int q = k0; q <= k; ++q) {
-          // normalise column q (q == k) or remove its component from column k (q < k)
+        for (int c = k0; c < k; ++c) {
+          // column c < k is final and unit-norm: remove its component
           double s = 0.0;
-          for (int i = b0 + tid; i < b1; i += blockDim.x)
-            s += Z[(long)i * ldz + q] * Z[(long)i * ldz + k];
-          s = wave_sum(s);
-          if ((tid & 63) == 0) red[tid >> 6] = s;
-          __syncthreads();
-          if (tid == 0) sdot = red[0] + red[1] + red[2] + red[3];
-          __syncthreads();
-          const double dt = sdot;
-          if (q < k) {
-            // column q < k is already unit-norm: remove its component from column k
-            for (int i = b0 + tid; i < b1; i += blockDim.x) Z[(long)i * ldz + k] -= dt * Z[(long)i * ldz + q];
-          } else {
-            const double sc = (dt > 0.0 && isfinite(dt)) ? 1.0 / sqrt(dt) : 0.0;
-            if (sc == 0.0 && tid == 0) atomicOr(status, KFAC_DS_EIG_NOCONV);
-            for (int i = b0 + tid; i < b1; i += blockDim.x) Z[(long)i * ldz + k] *= sc;
-          }
+          for (int i = tid; i < nb; i += blockDim.x) s += Z[(long)(b0 + i) * ldz + c] * zc[i];
+          const double dt = block_sum(s);
+          for (int i = tid; i < nb; i += blockDim.x) zc[i] -= dt * Z[(long)(b0 + i) * ldz + c];
           __syncthreads();
         }
+        double s = 0.0;
+        for (int i = tid; i < nb; i += blockDim.x) s += zc[i] * zc[i];
+        const double dt = block_sum(s);
+        const double sc = (dt > 0.0 && isfinite(dt)) ? 1.0 / sqrt(dt) : 0.0;
+        if (sc == 0.0 && tid == 0) atomicOr(status, KFAC_DS_EIG_NOCONV);
+        for (int i = tid; i < nb; i += blockDim.x) zc[i] *= sc;
+        __syncthreads();
       }
     }
+    for (int i = tid; i < nb; i += blockDim.x) Z[(long)(b0 + i) * ldz + k] = zc[i];
+    __syncthreads();
   }
 }
 

@@ -347,11 +347,6 @@ struct BcSmem {
   int fail;
 };
 
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // (a) for block K (wavefront 0 only).  Element (r, c) of the block is handled by lane
 // c + BC (r mod BC_RG) (slot r / BC_RG); pivots and columns are broadcast through LDS and
 // the loops over pivots stay rolled, so only BC_RT values per lane are live.
