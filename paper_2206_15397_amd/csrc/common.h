@@ -48,10 +48,11 @@ __device__ __forceinline__ uint4 and_mask(uint4 v, uint32_t m) { return make_uin
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-// LDS writes of this wavefront visible to its own later LDS reads (no workgroup barrier).
+// LDS writes of this wavefront visible to its own later LDS reads (no workgroup barrier):
+// wait for the wavefront's outstanding LDS operations only, so global stores keep flowing,
+// and keep the compiler from moving memory operations across.
 __device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
 // Two fp32 -> packed bf16 (a in the low half), round to nearest even: one

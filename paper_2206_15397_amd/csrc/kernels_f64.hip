@@ -341,108 +341,110 @@ static_assert(BC % 16 == 0 && BC_RT * BC_RG == BC, "block shape");
 struct BcSmem {
   double P[288][BC + 1];          // panel of block column K (absolute rows)
   double X[BC][BC + 1];           // inverse of the current diagonal block
-  double L[BC][BC + 1];           // the current diagonal block of L
-  double col[BC];                 // column broadcast inside the factoring wavefront
+  double D[BC][BC + 1];           // the next diagonal block after its update (look-ahead)
   double shift;
   int fail;
 };
 
-// (a) for block K (wavefront 0 only).  Element (r, c) of the block is handled by lane
-// c + BC (r mod BC_RG) (slot r / BC_RG); pivots and columns are broadcast through LDS and
-// the loops over pivots stay rolled, so only BC_RT values per lane are live.
-// Returns false on a non-positive or non-finite pivot (uniform over the wavefront).
-__device__ __forceinline__ bool bc_diag_block(double* G, long ldg, int n, int K, double* Xo, long ldx, BcSmem& sm) {
-  const int lane = threadIdx.x & 63;
-  const int k0 = K * BC;
-  // The lane split goes through an opaque move so that lane-dependent addresses and
-  // predicates are recomputed at each call instead of being hoisted out of the caller's
+// (a) for block K (wavefront 0 only).  Lane c (c = lane mod 16) holds the whole column c of
+// the symmetric block, so the multiplier l_cj of its own column is its own entry j; the
+// pivot and column j come from lane j by readlane (uniform values, no LDS round trip).
+// X = L_KK^{-1} follows by forward substitution on the columns of the identity (lane c:
+// column c of X) with the columns of L broadcast the same way.  The lane index fed to
+// each step's readlanes is passed through an empty asm that depends on the previous step,
+// so the broadcasts are issued step by step (hoisted, they would all be live at once).
+// The block's current values come from src (element (r, c) at src[r lds + c], lower
+// triangle read).  Rows / columns >= n are identity.  Returns false on a non-positive or
+// non-finite pivot.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// 1 / sqrt(x) for finite x > 0: the hardware estimate refined by two Newton steps
+// y <- y (3/2 - x y^2 / 2) (quadratic convergence from ~2^-22 to full fp64 precision).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+__device__ __forceinline__ bool bc_diag_block(double* G, long ldg, int n, int K, double* Xo, long ldx, BcSmem& sm,
+                                              const double* src, long lds) {
+  static_assert(BC == 16, "one lane per column of the diagonal block");
+  // The lane split goes through an opaque move so that lane-dependent predicates and
+  // constants are recomputed at each call instead of being hoisted out of the caller's
   // loop over K (hoisted, they stay live across the factorisation and spill).
-  int c, rg;
-  asm volatile("v_and_b32 %0, %2, %1" : "=v"(c) : "v"(lane), "i"(BC - 1));
-  asm volatile("v_lshrrev_b32 %0, %2, %1" : "=v"(rg) : "v"(lane), "i"(__builtin_ctz(BC)));
-  double d[BC_RT];                                    // d[t] = block element (rg + BC_RG t, c)
-  static_for<BC_RT>([&](auto T) {
-    constexpr int t = T;
-    const int r = rg + BC_RG * t;
+  int lane, c;
+  asm volatile("v_and_b32 %0, 63, %1" : "=v"(lane) : "v"((int)threadIdx.x));
+  asm volatile("v_and_b32 %0, 15, %1" : "=v"(c) : "v"(lane));
+  const int k0 = K * BC;
+  const bool cin = k0 + c < n;
+  double d[BC];
+#pragma unroll
+  for (int r = 0; r < BC; ++r) {
+    const int hi = r > c ? r : c, lo = r > c ? c : r;   // the lower-triangle copy of (r, c)
     double v = (r == c) ? 1.0 : 0.0;
-    if (c <= r && k0 + r < n && k0 + c < n) v = G[(long)(k0 + r) * ldg + k0 + c];
-    d[t] = v;
-  });
+    if (cin && k0 + r < n) v = src[(long)hi * lds + lo];
+    d[r] = v;
+  }
   bool ok = true;
+  double chain = 0.0;
+  double rdiag[BC];
+#pragma unroll
   for (int j = 0; j < BC; ++j) {
-    // publish column j, read the pivot
-    if (c == j) static_for<BC_RT>([&](auto T) { sm.col[rg + BC_RG * T] = d[T]; });
-    wave_lds_order();
-    const double piv = sm.col[j];
-    if (!(piv > 0.0) || !isfinite(piv)) { ok = false; break; }   // uniform
-    const double ljj = sqrt(piv), inv = 1.0 / ljj;
-    wave_lds_order();
-    // scale column j (one lane per row) and publish it
-    if (lane < BC) {
-      const double v = sm.col[lane];
-      const double l = (lane == j) ? ljj : ((lane > j) ? v * inv : 0.0);
-      wave_lds_order();
-      sm.col[lane] = l;
+    int src = j;
+    asm volatile("" : "+s"(src) : "v"(chain));
+    const double piv = readlane_f64(d[j], src);
+    ok = ok && piv > 0.0 && isfinite(piv);              // no early exit: one straight path
+    const double inv = rsqrt_nr(piv), ljj = piv * inv;
+    rdiag[j] = inv;
+    const double lc = (c > j) ? d[j] * inv : 0.0;       // l_cj (c > j); 0 leaves columns < j
+#pragma unroll
+    for (int r = j + 1; r < BC; ++r) {
+      const double lr = readlane_f64(d[r], src) * inv;  // column j of L
+      d[r] = (c == j) ? lr : d[r] - lr * lc;
     }
-    wave_lds_order();
-    const double lcj = sm.col[c];
-    double lrj[BC_RT];
-    static_for<BC_RT>([&](auto T) { lrj[T] = sm.col[rg + BC_RG * T]; });
-    static_for<BC_RT>([&](auto T) {
-      constexpr int t = T;
-      const int r = rg + BC_RG * t;
-      if (c == j) d[t] = lrj[t];                             // column j is final
-      else d[t] -= lrj[t] * ((c > j && r >= c) ? lcj : 0.0);
-    });
-    wave_lds_order();
+    if (c == j) d[j] = ljj;
+    chain = inv;
   }
   if (!ok) return false;
-  // L_KK to G (lower part) and to LDS; X = I in LDS
-  static_for<BC_RT>([&](auto T) {
-    constexpr int t = T;
-    const int r = rg + BC_RG * t;
-    if (c <= r && k0 + r < n && k0 + c < n) G[(long)(k0 + r) * ldg + k0 + c] = d[t];
-    sm.L[r][c] = (c <= r) ? d[t] : 0.0;
-    sm.X[r][c] = (r == c) ? 1.0 : 0.0;
-  });
-  wave_lds_order();
-  // X = L_KK^{-1} (solve L X = I one row of L at a time): X_k. /= l_kk, then
-  // X_r. -= l_rk X_k. for r > k
+  // X = L^{-1}: lane c solves L x = e_c
+  double x[BC];
+#pragma unroll
+  for (int r = 0; r < BC; ++r) x[r] = (r == c) ? 1.0 : 0.0;
+  double xk = 0.0;
+#pragma unroll
   for (int k = 0; k < BC; ++k) {
-    const double xk = sm.X[k][c] / sm.L[k][k];
-    double lrk[BC_RT], xr[BC_RT];
-    static_for<BC_RT>([&](auto T) {
-      lrk[T] = sm.L[rg + BC_RG * T][k];
-      xr[T] = sm.X[rg + BC_RG * T][c];
-    });
-    wave_lds_order();
-    if (rg == 0) sm.X[k][c] = xk;
-    static_for<BC_RT>([&](auto T) {
-      constexpr int t = T;
-      const int r = rg + BC_RG * t;
-      if (r > k) sm.X[r][c] = xr[t] - lrk[t] * xk;
-    });
-    wave_lds_order();
+    int src = k;
+    asm volatile("" : "+s"(src) : "v"(xk));
+    xk = x[k] * rdiag[k];
+    x[k] = xk;
+#pragma unroll
+    for (int r = k + 1; r < BC; ++r) x[r] -= readlane_f64(d[r], src) * xk;
   }
-  static_for<BC_RT>([&](auto T) {
-    constexpr int t = T;
-    const int r = rg + BC_RG * t;
-    const bool in = (k0 + r < n && k0 + c < n && c <= r);
-    Xo[(long)(k0 + r) * ldx + k0 + c] = in ? sm.X[r][c] : 0.0;     // zero outside n x n
-  });
-  wave_lds_order();
-  static_for<BC_RT>([&](auto T) {
-    constexpr int t = T;
-    const int r = rg + BC_RG * t;
-    if (!(k0 + r < n && k0 + c < n && c <= r)) sm.X[r][c] = 0.0;
-  });
+  if (lane < BC) {
+#pragma unroll
+    for (int r = 0; r < BC; ++r) {
+      const bool in = cin && k0 + r < n && r >= c;
+      if (in) G[(long)(k0 + r) * ldg + k0 + c] = d[r];
+      const double xr = in ? x[r] : 0.0;               // zero outside n x n
+      Xo[(long)(k0 + r) * ldx + k0 + c] = xr;
+      sm.X[r][c] = xr;
+    }
+  }
   return true;
 }
 
-// Lower-triangle tile t of a T x T grid of tiles, row-major over I >= J.
+// Lower-triangle tile t of a T x T grid of tiles, row-major over I >= J (closed form; t
+// is small, the float estimate is corrected by one step either way).
 __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
-  int i = 0;
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  if (i * (i + 1) / 2 > t) --i;
+  if ((i + 1) * (i + 2) / 2 <= t) ++i;
   I = i;
   J = t - i * (i + 1) / 2;
 }
@@ -481,13 +483,14 @@ __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
   }
   __syncthreads();
   constexpr int CT = BC / 16;                                  // 16-column tiles per block
+  if (wave == 0) {
+    const bool ok = bc_diag_block(G, ldg, n, 0, X, ldx, sm, G, ldg);
+    if (!ok && lane == 0) sm.fail = 1;
+  }
+  __syncthreads();
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
   for (int K = 0; K < NB; ++K) {
     const int k0 = K * BC, r0 = k0 + BC, m = l_pad - r0;
-    if (wave == 0) {
-      const bool ok = bc_diag_block(G, ldg, n, K, X, ldx, sm);
-      if (!ok && lane == 0) sm.fail = 1;
-    }
-    __syncthreads();
     if (sm.fail) break;                                       // uniform
     // (b) panel rows [r0, l_pad): L_iK = A_iK X_KK^T, 16 x 16 tiles
     const int ptiles = (m / 16) * CT;
@@ -513,37 +516,73 @@ __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
       }
     }
     __syncthreads();
-    // (c) trailing update of the lower triangle, 16 x 16 tiles; the next tile's values
-    // are loaded before the current tile's MFMAs
+    // (c) trailing update of the lower triangle, 16 x 16 tiles.  Look-ahead: wavefront 0
+    // updates the next diagonal tile first and factors it (block K + 1) while the other
+    // wavefronts update the remaining tiles, two per wavefront at a time (both tiles'
+    // loads in flight together, two independent MFMA chains).
     const int T16 = m / 16, utiles = T16 * (T16 + 1) / 2;
-    auto load_tile = [&](int t, f64x4& v) {
-      int ti, tj;
-      lower_tile(t, ti, tj);
-      const int i0 = r0 + ti * 16, j0 = r0 + tj * 16;
+    const bool ahead = K + 1 < NB;
+    if (ahead && wv == 0) {
+      f64x4 acc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = i0 + (lane >> 4) + 4 * r, col = j0 + (lane & 15);
-        v[r] = (row < n && col < n) ? G[(long)row * ldg + col] : 0.0;
+        const int row = r0 + (lane >> 4) + 4 * r, col = r0 + (lane & 15);
+        acc[r] = (row < n && col < n) ? G[(long)row * ldg + col] : 0.0;
       }
-    };
-    f64x4 nxt = {0, 0, 0, 0};
-    if (wave < utiles) load_tile(wave, nxt);
-    for (int t = wave; t < utiles; t += nw) {
-      f64x4 acc = nxt;
-      if (t + nw < utiles) load_tile(t + nw, nxt);
-      int ti, tj;
-      lower_tile(t, ti, tj);
-      const int i0 = r0 + ti * 16, j0 = r0 + tj * 16;
 #pragma unroll
-      for (int kk = 0; kk < BC; kk += 4) {
-        const int kc = kk + (lane >> 4);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sm.P[i0 + (lane & 15)][kc], sm.P[j0 + (lane & 15)][kc], acc,
+      for (int u = 0; u < BC / 4; ++u) {
+        const int kc = 4 * u + (lane >> 4);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sm.P[r0 + (lane & 15)][kc], sm.P[r0 + (lane & 15)][kc], acc,
                                                    0, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = i0 + (lane >> 4) + 4 * r, col = j0 + (lane & 15);
-        if (row < n && col < n && (ti != tj || col <= row)) G[(long)row * ldg + col] = acc[r];
+        const int lr = (lane >> 4) + 4 * r, lc = lane & 15, row = r0 + lr, col = r0 + lc;
+        if (row < n && col < n && col <= row) G[(long)row * ldg + col] = acc[r];
+        sm.D[lr][lc] = acc[r];
+      }
+      wave_lds_order();
+      const bool ok = bc_diag_block(G, ldg, n, K + 1, X, ldx, sm, &sm.D[0][0], BC + 1);
+      if (!ok && lane == 0) sm.fail = 1;
+    }
+    // the other tiles (tile 0 is the look-ahead tile when there is a next block)
+    const int w0 = ahead ? 1 : 0, nwu = nw - w0, first = ahead ? 1 : 0;
+    for (int base = first + (wv - w0); wv >= w0 && base < utiles; base += 2 * nwu) {
+      int ti[2], tj[2];
+      bool on[2];
+      f64x4 acc[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = base + h * nwu;
+        on[h] = t < utiles;
+        lower_tile(on[h] ? t : 0, ti[h], tj[h]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + ti[h] * 16 + (lane >> 4) + 4 * r, col = r0 + tj[h] * 16 + (lane & 15);
+          acc[h][r] = (on[h] && row < n && col < n) ? G[(long)row * ldg + col] : 0.0;
+        }
+      }
+      double pa[2][BC / 4], pb[2][BC / 4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int u = 0; u < BC / 4; ++u) {
+          const int kc = 4 * u + (lane >> 4);
+          pa[h][u] = -sm.P[r0 + ti[h] * 16 + (lane & 15)][kc];
+          pb[h][u] = sm.P[r0 + tj[h] * 16 + (lane & 15)][kc];
+        }
+#pragma unroll
+      for (int u = 0; u < BC / 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[h][u], pb[h][u], acc[h], 0, 0, 0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (!on[h]) continue;                                 // uniform
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + ti[h] * 16 + (lane >> 4) + 4 * r, col = r0 + tj[h] * 16 + (lane & 15);
+          if (row < n && col < n && (ti[h] != tj[h] || col <= row)) G[(long)row * ldg + col] = acc[h][r];
+        }
       }
     }
     __syncthreads();
