@@ -142,15 +142,17 @@ struct alignas(16) EbSmem {
   };
 };
 
-// Column c of the (row-major) 8 x 8 bf16 block held as v[row] (8 halves per uint4).
+// Column c of the (row-major) 8 x 8 bf16 block held as v[row] (8 halves per uint4): each
+// output word takes the same half of one word of rows 2w and 2w + 1 (one v_perm_b32; byte
+// selectors 0-3 address the second operand, 4-7 the first).
+__device__ __forceinline__ uint32_t word_of(const uint4& x, int i) { return i == 0 ? x.x : i == 1 ? x.y : i == 2 ? x.z : x.w; }
 __device__ __forceinline__ uint4 col_of_block(const uint4 v[8], int c) {
-  auto half = [&](int r) -> uint32_t {
-    const uint4& x = v[r];
-    const uint32_t w = (c >> 1) == 0 ? x.x : (c >> 1) == 1 ? x.y : (c >> 1) == 2 ? x.z : x.w;
-    return (c & 1) ? (w >> 16) : (w & 0xffffu);
-  };
-  return make_uint4(half(0) | (half(1) << 16), half(2) | (half(3) << 16), half(4) | (half(5) << 16),
-                    half(6) | (half(7) << 16));
+  const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
+  const int wi = c >> 1;
+  return make_uint4(__builtin_amdgcn_perm(word_of(v[1], wi), word_of(v[0], wi), sel),
+                    __builtin_amdgcn_perm(word_of(v[3], wi), word_of(v[2], wi), sel),
+                    __builtin_amdgcn_perm(word_of(v[5], wi), word_of(v[4], wi), sel),
+                    __builtin_amdgcn_perm(word_of(v[7], wi), word_of(v[6], wi), sel));
 }
 
 // Rows [k0, k0+8) x columns [c0, c0+8) of Xh (bf16, ones column appended at d_in when
@@ -188,7 +190,7 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
   int kb, ke;
   ea_slice(p.K, q.nks, by, EB_BK, kb, ke);
   const bool diag = (I == J);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 1, wn = wave >> 1;
   const int d = p.M, d_in = p.ones_col >= 0 ? p.ones_col : d;
   const bool ones = p.ones_col >= 0;
@@ -205,6 +207,17 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   uint4 v[8];
+  // a thread's 8 x 8 block lies inside the activations (no ones column, no padding): its
+  // 8 row loads of full 64-row stages go out unguarded
+  const bool inner = vec && (c0 + 8 <= d_in);
+  auto fetch = [&](int k0) {
+    if (inner && k0 + EB_BK <= ke) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = gload16(X + (long)(k0 + rg * 8 + r) * ldx + c0);
+    } else {
+      eb_load_block(X, ldx, d_in, d, ones, vec, k0 + rg * 8, ke, c0, v);
+    }
+  };
   auto stash = [&](int buf) {
     uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf] : sm.g.a[buf];
 #pragma unroll
@@ -212,7 +225,7 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
   };
   if (kb < ke) {
     if (loader) {
-      eb_load_block(X, ldx, d_in, d, ones, vec, kb + rg * 8, ke, c0, v);
+      fetch(kb);
       stash(0);
     }
     __syncthreads();
@@ -220,7 +233,7 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
   int buf = 0;
   for (int k0 = kb; k0 < ke; k0 += EB_BK) {
     const bool more = k0 + EB_BK < ke;
-    if (more && loader) eb_load_block(X, ldx, d_in, d, ones, vec, k0 + EB_BK + rg * 8, ke, c0, v);
+    if (more && loader) fetch(k0 + EB_BK);
     uint16_t (*A)[EB_SK] = sm.g.a[buf];
     uint16_t (*B)[EB_SK] = diag ? sm.g.a[buf] : sm.g.b[buf];
 #pragma unroll
@@ -239,6 +252,7 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
+    __builtin_amdgcn_sched_barrier(0);               // the stash (and its load waits) after the MFMAs
     if (more && loader) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
