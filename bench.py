@@ -42,9 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default GEMM tile configurations")
-    ap.add_argument("--config", choices=["vgg", "wide", "batched64"], default="vgg",
+    ap.add_argument("--config", choices=["vgg", "wide", "batched64", "copy"], default="vgg",
                     help="vgg: VGG16_bn factor set (default); wide: one d x d factor (--d); "
-                         "batched64: 64 factors of log-uniform sizes 64..8192")
+                         "batched64: 64 factors of log-uniform sizes 64..8192; copy: a plain 1 GiB "
+                         "device copy that calibrates the HBM byte counters of rocprofv3")
     ap.add_argument("--d", type=int, default=16384, help="factor size of --config wide")
     ap.add_argument("--full-eig", action="store_true", help="--config wide: also time torch.linalg.eigh")
     ap.add_argument("--check", action="store_true", help="check sampled outputs against the oracle")
@@ -309,7 +310,27 @@ KIND = {
 }
 
 
-def roofline(plan, names, times_ms):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes recorded in profiles/hbm_traffic.json (scaled by the counters' reading
+    for a plain copy of known size), or None when there is no record or the library was
+    built from other sources than the ones measured."""
+    try:
+        import paper_2206_15397_amd as K
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        src = K.lib().kfac_build_info().decode().rsplit(" src ", 1)[-1]
+        if rec.get("src_hash") != src:
+            return None
+        return rec["workloads"][workload][kernel]["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def roofline(plan, names, times_ms, workload=None):
     """Roofline of the kernel with the largest share of the step: algorithmic work of its
     launches (kfac_plan_launch_work) over their measured durations."""
     tot = {}
@@ -332,7 +353,8 @@ def roofline(plan, names, times_ms):
         ach = flops / (t_ms * 1e-3) / 1e12
         out = {"bound": unit_kind, "achieved": round(ach, 4), "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
                "frac": round(ach / PEAK_TFLOPS[dt], 6)}
-    out.update({"traffic": None, "kernel": nm, "dtype": dt, "launches_per_step": count,
+    out.update({"traffic": measured_traffic(workload, nm) if workload else None, "kernel": nm, "dtype": dt,
+                "launches_per_step": count,
                 "avg_launch_us": round(1e3 * t_ms / count, 2),
                 "flops_per_launch": flops / count, "bytes_per_launch": nbytes / count,
                 "share_of_step": round(t_ms / sum(times_ms), 4)})
@@ -475,7 +497,7 @@ def main_wide(args, dev):
            "dtype": "bf16+fp32+fp64", "data": "synthetic",
            "config": {"workload": f"wide_factor_d{d}_ea50_b512", "d": d, "r": r, "p": p, "q": q},
            "gemm_mfma_fraction": None if frac is None else round(frac, 4),
-           "roofline": roofline(plan, names, pt), "full_eig_ms": full_ms}
+           "roofline": roofline(plan, names, pt, f"wide_factor_d{d}_ea50_b512"), "full_eig_ms": full_ms}
     print(json.dumps(res), flush=True)
 
 
@@ -554,8 +576,22 @@ def main_batched64(args, dev):
                       "r": "min(256,d/2)", "p": 16, "q": 1, "lambda": 0.1},
            "plain_fp32_ms_per_step": plain_ms,
            "speedup_vs_plain_fp32": None if plain_ms is None else round(plain_ms / ms, 3),
-           "roofline": roofline(plan, names, pt)}
+           "roofline": roofline(plan, names, pt, "batched64_loguniform_64_8192")}
     print(json.dumps(res), flush=True)
+
+
+def main_copy(args):
+    """Counter calibration: a plain elementwise copy (1 GiB read, 1 GiB written per launch)."""
+    import torch
+    dev = torch.device("cuda:0")
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(max(1, args.steps)):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "elementwise copy", "bytes_read_per_launch": nbytes,
+                      "bytes_written_per_launch": nbytes, "launches": max(1, args.steps)}), flush=True)
 
 
 def main():
@@ -564,6 +600,8 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               "(multi-GPU sharding is design-only).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "copy":
+        return main_copy(args)
     if args.config != "vgg":
         import torch
         import paper_2206_15397_amd as K
@@ -588,7 +626,7 @@ def main():
     cfgs = plan.launch_configs()
     for i, (nm, t) in enumerate(zip(names, pt)):
         log(f"  [{i:2d}] {nm:18s} {t * 1e3:9.1f} us  {100 * t / tot:5.1f}%  cfg {cfgs[i]}")
-    roof = roofline(plan, names, pt)
+    roof = roofline(plan, names, pt, "vgg16_bn_cifar_b128_factor_set")
     log(f"roofline: {roof}")
     del gp
     plain_ms = None

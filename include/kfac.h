@@ -70,7 +70,8 @@ typedef void* kfac_stream_t; /* hipStream_t */
 /* Text for a status code (static storage, never NULL). */
 const char* kfac_status_string(kfac_status s);
 
-/* Library / device build information, e.g. "libkfac gfx950 hip 7.2".  Static string. */
+/* Library / device build information: target, kernel families and "src <hash>", a hash of
+ * the sources and build flags the library was compiled from.  Static string. */
 const char* kfac_build_info(void);
 
 /*

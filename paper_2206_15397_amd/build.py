@@ -23,11 +23,28 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+def source_hash() -> str:
+    """Hash of every device/host source and header the library is built from, and the
+    build flags: names the exact kernels a stored measurement was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    inc = os.path.join(ROOT, "include")
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    files += sorted(os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join([ARCH, "-O3"] + DEVICE_FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, jobs: int = 4) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     common = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-              "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"] + DEVICE_FLAGS
+              "-I", os.path.join(ROOT, "include"), "-Wno-unused-result",
+              f'-DKFAC_SRC_HASH="{source_hash()}"'] + DEVICE_FLAGS
     procs, objs = [], []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")

@@ -31,8 +31,11 @@ const char* kfac_status_string(kfac_status s) {
   return "unknown status";
 }
 
+#ifndef KFAC_SRC_HASH
+#define KFAC_SRC_HASH "unknown"
+#endif
 const char* kfac_build_info(void) {
-  return "libkfac gfx950 (fp32/bf16 MFMA GEMM, fp64 CholeskyQR2 + tridiagonal eigensolver)";
+  return "libkfac gfx950 (fp32/bf16 MFMA GEMM, fp64 CholeskyQR2 + tridiagonal eigensolver) src " KFAC_SRC_HASH;
 }
 
 kfac_status kfac_fill_identity(float* F, int64_t d, int64_t ldf, kfac_stream_t stream) {
