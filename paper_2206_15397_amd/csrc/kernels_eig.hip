@@ -676,31 +676,36 @@ __device__ __forceinline__ void tri_cluster_lead_body(const EigTask& q, int, int
 }
 
 // ======================================================================================
-// 7. Back-transformation P = H_0 ... H_{n-3} z for each of the first r columns (one
-// wavefront per column; the column is normalised first).  fp32 output, rows n..n_pad-1
-// zero.  grid = ceil(r / 4) blocks of 256 threads.
+// 7. Back-transformation P = H_0 ... H_{n-3} z for each of the first r columns (the column
+// is normalised first).  Each wavefront carries NC columns: every staged reflector is read
+// from LDS once for all of them and their NC dot-product reductions run side by side.
+// fp32 output, rows n..n_pad-1 zero.  grid = ceil(r / (4 NC)) blocks of 256 threads.
 // ======================================================================================
+template <int NC, int NMAX>
 __device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int) {
   const double* V = q.V; const double* Z = q.Z; const long ldz = q.ldz; const int n = q.n, n_pad = q.n_pad;
   const int r = q.r; float* P = q.P; const long ldp = q.ldp;
   constexpr int CH = 16;                      // reflectors staged per LDS chunk
-  __shared__ double vch[CH][KFAC_MAX_SKETCH];
+  constexpr int PER = (NMAX + 63) / 64;
+  __shared__ double vch[CH][PER * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = bx * 4 + wave;
-  const bool active = c < r;
-  constexpr int PER = KFAC_MAX_SKETCH / 64;
-  double z[PER];
-  double nn = 0.0;
+  const int c0 = (bx * 4 + wave) * NC;
+  double z[NC][PER];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int i = lane + 64 * u;
-    z[u] = (active && i < n) ? Z[(long)i * ldz + c] : 0.0;
-    nn += z[u] * z[u];
+  for (int j = 0; j < NC; ++j) {
+    const int c = c0 + j;
+    double nn = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = lane + 64 * u;
+      z[j][u] = (c < r && i < n) ? Z[(long)i * ldz + c] : 0.0;
+      nn += z[j][u] * z[j][u];
+    }
+    nn = wave_sum(nn);
+    const double sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) z[j][u] *= sc;
   }
-  nn = wave_sum(nn);
-  const double sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-#pragma unroll
-  for (int u = 0; u < PER; ++u) z[u] *= sc;
   for (int kt = n - 3; kt >= 0; kt -= CH) {
     const int klo = max(0, kt - CH + 1);
     const int cnt = kt - klo + 1;
@@ -713,23 +718,35 @@ __device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int
     for (int k = kt; k >= klo; --k) {
       const double* vk = vch[k - klo];
       double vv[PER];
-      double s = 0.0;
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
         const int i = lane + 64 * u;
         vv[u] = (i > k && i < n) ? vk[i] : 0.0;
-        s += vv[u] * z[u];
       }
-      s = 2.0 * wave_sum(s);
+      double s[NC];
 #pragma unroll
-      for (int u = 0; u < PER; ++u) z[u] -= s * vv[u];
+      for (int j = 0; j < NC; ++j) {
+        s[j] = 0.0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) s[j] += vv[u] * z[j][u];
+      }
+#pragma unroll
+      for (int j = 0; j < NC; ++j) s[j] = 2.0 * wave_sum(s[j]);
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+#pragma unroll
+        for (int u = 0; u < PER; ++u) z[j][u] -= s[j] * vv[u];
     }
   }
-  if (!active) return;
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int i = lane + 64 * u;
-    if (i < n_pad) P[(long)i * ldp + c] = (i < n) ? (float)z[u] : 0.f;
+  for (int j = 0; j < NC; ++j) {
+    const int c = c0 + j;
+    if (c >= r) continue;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = lane + 64 * u;
+      if (i < n_pad) P[(long)i * ldp + c] = (i < n) ? (float)z[j][u] : 0.f;
+    }
   }
 }
 
@@ -742,7 +759,9 @@ template <int NT, int NMAX>
 __global__ __launch_bounds__(NT) void k_tri_vec(EigTask q) { tri_vec_body<NT, NMAX>(q, blockIdx.x, 0); }
 __global__ __launch_bounds__(256) void k_tri_cluster_lead(EigTask q) { tri_cluster_lead_body(q, 0, 0); }
 __global__ __launch_bounds__(256) void k_tri_cluster(EigTask q) { tri_cluster_body(q, 0, 0); }
-__global__ __launch_bounds__(256) void k_backtransform(EigTask q) { backtransform_body(q, blockIdx.x, 0); }
+__global__ __launch_bounds__(256) void k_backtransform(EigTask q) {
+  backtransform_body<1, KFAC_MAX_SKETCH>(q, blockIdx.x, 0);
+}
 
 KFAC_GROUPED_KERNEL(k_tridiag_reg_g, tridiag_reg_body, EigTask, 1024)
 KFAC_GROUPED_KERNEL(k_tri_prep_g, tri_prep_body, EigTask, 512)
@@ -755,7 +774,8 @@ __global__ __launch_bounds__(32) void k_tri_vec_g(const EigTask* tasks, GroupMap
 }
 KFAC_GROUPED_KERNEL(k_tri_cluster_lead_g, tri_cluster_lead_body, EigTask, 256)
 KFAC_GROUPED_KERNEL(k_tri_cluster_g, tri_cluster_body, EigTask, 256)
-KFAC_GROUPED_KERNEL(k_backtransform_g, backtransform_body, EigTask, 256)
+KFAC_GROUPED_KERNEL(k_backtransform_g, (backtransform_body<1, kPlanMaxSketch>), EigTask, 256)
+KFAC_GROUPED_KERNEL(k_backtransform4_g, (backtransform_body<4, kPlanMaxSketch>), EigTask, 256)
 
 // ======================================================================================
 size_t small_eig_scratch_doubles(int n, int r) {
@@ -814,8 +834,12 @@ KFAC_GLAUNCH(launch_tri_select_g, k_tri_select_g, EigTask, 512)
 KFAC_GLAUNCH(launch_tri_vec_g, k_tri_vec_g, EigTask, 32)
 KFAC_GLAUNCH(launch_tri_cluster_lead_g, k_tri_cluster_lead_g, EigTask, 256)
 KFAC_GLAUNCH(launch_tri_cluster_g, k_tri_cluster_g, EigTask, 256)
-KFAC_GLAUNCH(launch_backtransform_g, k_backtransform_g, EigTask, 256)
+KFAC_GLAUNCH(launch_backtransform1_g, k_backtransform_g, EigTask, 256)
+KFAC_GLAUNCH(launch_backtransform4_g, k_backtransform4_g, EigTask, 256)
+hipError_t launch_backtransform_g(const EigTask* t, GroupMap gm, int blocks, int nc, hipStream_t s) {
+  return nc == 4 ? launch_backtransform4_g(t, gm, blocks, s) : launch_backtransform1_g(t, gm, blocks, s);
+}
 int tri_bisect_blocks(int n) { return (n + 15) / 16; }
 int tri_vec_blocks(int r) { return (r + 31) / 32; }
-int backtransform_blocks(int r) { return (r + 3) / 4; }
+int backtransform_blocks(int r, int nc) { return (r + 4 * nc - 1) / (4 * nc); }
 }  // namespace kfac

@@ -252,7 +252,10 @@ int ea_tiles_per_side(int d, bool bf) {
 int ea_choose_ksplit(int d, long n, bool bf) {
   int T = ea_tiles_per_side(d, bf);
   long tiles = (long)T * (T + 1) / 2;
-  long want = (1024 + tiles - 1) / tiles;           // aim for >= ~1024 workgroups
+  // aim for >= ~1024 workgroups (fp32) / ~512 (bf16: two per compute unit; fewer slices
+  // keep the split-K partial traffic down)
+  const long target = bf ? 512 : 1024;
+  long want = (target + tiles - 1) / tiles;
   const long rows = bf ? 1024 : 512;                // rows per slice at least
   long maxk = (n + rows - 1) / rows;
   long ks = std::min(want, maxk);
