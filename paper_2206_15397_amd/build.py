@@ -17,6 +17,10 @@ ROOT = os.path.dirname(HERE)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source code-generation options.  The bf16 kernels keep their MFMA accumulators in
+# ordinary VGPRs: the EA tile kernel's two register stages and its accumulators then fit
+# one register file without copies between VGPRs and AGPRs.
+FILE_FLAGS = {"kernels_bf16.hip": ["-mllvm", "--amdgpu-mfma-vgpr-form"]}
 
 
 def sources():
@@ -36,6 +40,8 @@ def source_hash() -> str:
         with open(f, "rb") as fh:
             h.update(fh.read())
     h.update(" ".join([ARCH, "-O3"] + DEVICE_FLAGS).encode())
+    for k in sorted(FILE_FLAGS):
+        h.update((k + " " + " ".join(FILE_FLAGS[k])).encode())
     return h.hexdigest()[:16]
 
 
@@ -49,7 +55,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = common + ["-c", src, "-o", obj]
+        cmd = common + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

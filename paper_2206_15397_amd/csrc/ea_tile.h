@@ -7,6 +7,33 @@
 
 namespace kfac {
 
+// (I, J) of the t-th upper tile of an EA factor with T tiles per side, in groups of
+// 8 x 8 tiles (row-major over the upper groups, row-major inside a group).  Consecutive
+// tiles, which run together on one XCD, then read 16 column panels of the activations
+// (8 on the diagonal) instead of a whole tile row's worth, and share them through that
+// XCD's L2.  Producers and the split-K finalize use the same order.
+__device__ __forceinline__ void ea_tile(int t, int T, int& I, int& J) {
+  constexpr int G = 8;
+  const int NG = (T + G - 1) / G;
+  int P = 0, Q = 0, rem = t;
+  for (;;) {
+    const int nr = min(G, T - P * G), nc = min(G, T - Q * G);
+    const int cnt = (P == Q) ? nr * (nr + 1) / 2 : nr * nc;
+    if (rem < cnt) {
+      if (P == Q) {
+        int i = 0;
+        while (rem >= nr - i) { rem -= nr - i; ++i; }
+        I = P * G + i; J = P * G + i + rem;
+      } else {
+        I = P * G + rem / nc; J = Q * G + rem % nc;
+      }
+      return;
+    }
+    rem -= cnt;
+    if (++Q == NG) { ++P; Q = P; }
+  }
+}
+
 // `t` holds the raw sums of upper tile (I, J) (rows of block I, columns of block J).
 template <int BT>
 __device__ void ea_store_tile_t(float (*t)[BT + 1], const EaOut& o, int I, int J) {
@@ -61,7 +88,7 @@ __device__ void ea_finalize_chunk(const EaTask& q, int bx, float (*v)[BT + 1]) {
   constexpr int NCH = BT / kEaChunk;
   const int tile = bx / NCH, a0 = (bx % NCH) * kEaChunk;
   int I, J;
-  upper_tile(tile, q.T, I, J);
+  ea_tile(tile, q.T, I, J);
   const EaOut& o = q.o;
   const int r0 = I * BT, c0 = J * BT, nks = q.nks;
   const float* base = q.g.part + (long)tile * nks * (BT * BT) + (long)a0 * BT;

@@ -44,6 +44,26 @@ __device__ __forceinline__ void group_locate_xcd(const GroupMap& g, int& t, int&
   group_locate_at(g, xcd_swizzle(blockIdx.x, gridDim.x), t, bx, by);
 }
 
+// Work-balanced XCD mapping for launches whose task block counts are multiples of 8:
+// every XCD takes one contiguous eighth of every task, so each XCD gets the same share
+// of each task's work while neighbouring blocks of a task still share its L2.  Block b
+// is the (b / 8)-th workgroup dispatched to XCD b % 8.
+__device__ __forceinline__ void group_locate_xcd8(const GroupMap& g, int& t, int& bx, int& by) {
+  const int x = blockIdx.x & 7, s = blockIdx.x >> 3;
+  int lo = 0, hi = g.ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.off[mid] <= 8 * s) lo = mid; else hi = mid - 1;
+  }
+  t = __builtin_amdgcn_readfirstlane(lo);
+  const int o = __builtin_amdgcn_readfirstlane(g.off[t]);
+  const int per = __builtin_amdgcn_readfirstlane((g.off[t + 1] - o) >> 3);
+  const int local = x * per + (s - (o >> 3));
+  const int w = __builtin_amdgcn_readfirstlane(g.gx[t]);
+  bx = local % w;
+  by = local / w;
+}
+
 #define KFAC_GROUPED_KERNEL(NAME, BODY, PARAMS, NT)                                   \
   __global__ __launch_bounds__(NT) void NAME(const PARAMS* tasks, GroupMap gm) {        \
     int t_, bx_, by_;                                                                   \

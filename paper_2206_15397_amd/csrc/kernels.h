@@ -19,6 +19,10 @@ hipError_t launch_gemm(const GemmP& p, bool ta, bool tb, hipStream_t s);
 int ea_tiles_per_side(int d, bool bf);
 int ea_choose_ksplit(int d, long n, bool bf);
 size_t ea_workspace_bytes(int d, long n, bool bf);
+size_t ea_partial_bytes(int d, int ks, bool bf);   // split-K partial sums of ks slices
+// split-K count of one factor inside a grouped EA launch whose factors together take
+// total_steps block steps (tiles x 64-row / 32-row steps) without splitting
+int ea_grouped_ksplit(int d, long n, bool bf, double total_steps);
 size_t ea_workspace_bytes(int d, long n);   // enough for either variant
 int ea_finalize_chunks(bool bf);             // finalize blocks per tile
 hipError_t launch_ea_f32(float* F, int d, long ldf, const float* X, int n, int d_in, long ldx, int ones,

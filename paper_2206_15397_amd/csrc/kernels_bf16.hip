@@ -128,9 +128,13 @@ __device__ __forceinline__ void gemm_bf16_body(const BfGemmTask& q, int bx, int)
 // X, which are strided in memory, so each thread loads an 8 (rows) x 8 (columns) block
 // with 16-byte row loads, transposes it in registers and stores 8 column vectors of 8
 // consecutive rows into LDS (column-major tiles, k contiguous).  Every MFMA operand is then
-// one 16-byte LDS read.  Two LDS buffers: one barrier per 64-row step.  The 144-byte LDS
-// row pitch keeps both the 16-lane column stores and the 16-lane operand reads on
-// distinct banks.
+// one 16-byte LDS read.  Two LDS buffers: one barrier per 64-row step.
+//   Loads: sixteen neighbouring lanes cover one 256-byte row segment of a panel, so each
+// load instruction touches few cache lines per lane group; full steps use buffer loads
+// with the row in the scalar offset and keep two steps in flight in registers.
+//   LDS: 144-byte column pitch plus an XOR swizzle of the 16-byte chunks (see sk below).
+//   Order: tiles in 8 x 8 groups, and per XCD one contiguous share of every factor
+// (ea_tile, group_locate_xcd8), so the panels of concurrently running tiles meet in L2.
 constexpr int EB_BT = kEaBf16Tile, EB_BK = 64, EB_SK = EB_BK + 8;
 struct alignas(16) EbSmem {
   union {
@@ -186,7 +190,7 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
   __shared__ EbSmem sm;
   const GemmP& p = q.g;
   int I, J;
-  upper_tile(bx, q.T, I, J);
+  ea_tile(bx, q.T, I, J);
   int kb, ke;
   ea_slice(p.K, q.nks, by, EB_BK, kb, ke);
   const bool diag = (I == J);
@@ -198,7 +202,12 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
   const long ldx = p.lda;
   const bool vec = ((ldx & 7) == 0) && ((((uintptr_t)X) & 15) == 0);
   // loader role: threads 0..127 fill the A tile (columns of block I), 128..255 the B tile
-  const int op = tid >> 7, tt = tid & 127, cg = tt >> 3, rg = tt & 7;
+  const int op = wave >> 1, tt = tid & 127, cg = tt & 15, rg = tt >> 4;   // op: wave-uniform
+  // LDS chunk of the thread's 8 rows: chunk rg of tile column cg * 8 + c sits at chunk
+  // rg ^ (cg & 7) of that 144-byte column.  LDS serves 16-byte accesses eight lanes at a
+  // time; eight lanes that store the same chunk of 8 columns 8 apart, and eight lanes
+  // that read one chunk of 8 neighbouring columns, then all land on distinct banks.
+  const int sk = rg ^ (cg & 7);
   const bool loader = !(diag && op == 1);
   const int c0 = (op ? J : I) * EB_BT + cg * 8;
   f32x4 acc[4][4];
@@ -221,41 +230,140 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
   auto stash = [&](int buf) {
     uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf] : sm.g.a[buf];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][rg * 8] = col_of_block(v, c);
+    for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][sk * 8] = col_of_block(v, c);
   };
-  if (kb < ke) {
-    if (loader) {
-      fetch(kb);
-      stash(0);
-    }
-    __syncthreads();
-  }
-  int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += EB_BK) {
-    const bool more = k0 + EB_BK < ke;
-    if (more && loader) fetch(k0 + EB_BK);
+  auto mfma_stage = [&](int buf) {
     uint16_t (*A)[EB_SK] = sm.g.a[buf];
     uint16_t (*B)[EB_SK] = diag ? sm.g.a[buf] : sm.g.b[buf];
 #pragma unroll
     for (int kk = 0; kk < EB_BK; kk += 32) {
-      const int kq = kk + (lane >> 4) * 8;
+      // logical 8-row chunk of the stage; column m of the tile keeps it at chunk
+      // q8 ^ ((m >> 3) & 7), and (m >> 3) & 7 = 2 i + bit 3 of the lane here
+      const int q8 = (kk >> 3) + (lane >> 4), h = (lane >> 3) & 1;
       bf16x8 af[4], bfr[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        af[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&A[wm * 64 + i * 16 + (lane & 15)][kq]);
+        af[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&A[wm * 64 + i * 16 + (lane & 15)][(q8 ^ (2 * i + h)) * 8]);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        bfr[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&B[wn * 64 + j * 16 + (lane & 15)][kq]);
+        bfr[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&B[wn * 64 + j * 16 + (lane & 15)][(q8 ^ (2 * j + h)) * 8]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
-    __builtin_amdgcn_sched_barrier(0);               // the stash (and its load waits) after the MFMAs
-    if (more && loader) stash(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+  };
+  // Both column panels of the tile hold no partial 8-column group (every group lies inside
+  // the activations or wholly beyond them), else the tile takes the guarded path.
+  auto panel_clean = [&](int P) {
+    const int lo = P * EB_BT, hi = lo + EB_BT;
+    return (d_in & 7) == 0 || d_in <= lo || d_in >= hi;
+  };
+  const bool piped = vec && d_in >= 8 && panel_clean(I) && panel_clean(J) &&
+                     (long)(ke - kb) * ldx * 2 < (1L << 31);
+  if (piped) {
+    // Full 64-row stages, two stages in flight in registers (va, vb) while the MFMAs run
+    // on the LDS stage loaded before them.  A thread whose 8 columns lie beyond the
+    // activations reads columns 0-7 of its rows instead and masks the values to zero, plus
+    // the ones column when it falls in its group: every thread issues the same 8 loads per
+    // stage.
+    const int nfull = (ke - kb) / EB_BK;
+    const bool in_x = c0 + 8 <= d_in;
+    // buffer loads over the block's row slice: one lane offset for every load, the row
+    // in the scalar offset
+    const int row_bytes = (int)ldx * 2;
+    const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(X + (long)kb * ldx), (short)0, (ke - kb) * row_bytes, 0x00020000);
+    const int vo = rg * 8 * row_bytes + (in_x ? c0 * 2 : 0);
+    const uint32_t m = opaque_mask(in_x);
+    uint4 o = make_uint4(0, 0, 0, 0);
+    if (ones && !in_x && d_in >= c0 && d_in < c0 + 8 && d_in < d) {
+      const int h = d_in - c0;                        // half index of the ones column
+      const uint32_t w1 = (h & 1) ? 0x3f800000u : 0x3f80u;
+      o = make_uint4(h >> 1 == 0 ? w1 : 0u, h >> 1 == 1 ? w1 : 0u, h >> 1 == 2 ? w1 : 0u, h >> 1 == 3 ? w1 : 0u);
+    }
+    uint4 va[8], vb[8];
+    auto fetch_full = [&](int k0, uint4 (&w)[8]) {
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      const int so = (k0 - kb) * row_bytes;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(xs, vo, so + r * row_bytes, 0);
+        w[r] = make_uint4(x.x, x.y, x.z, x.w);
+      }
+    };
+    // only a wave whose panel reaches past the activations has lanes to mask
+    const bool edge = (op ? J : I) * EB_BT + EB_BT > d_in;
+    auto stash_full = [&](uint4 (&w)[8], int buf) {
+      uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf] : sm.g.a[buf];
+      if (edge) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          w[r] = and_mask(w[r], m);
+          w[r] = make_uint4(w[r].x | o.x, w[r].y | o.y, w[r].z | o.z, w[r].w | o.w);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][sk * 8] = col_of_block(w, c);
+    };
+    // Every wave issues the same loads whether it stashes or not, and a stage past the
+    // last full one re-reads the last full one: the number of loads in flight is then the
+    // same on every path, and a stash waits only for its own register set.
+    auto stage_k = [&](int st) { return kb + (st < nfull ? st : nfull - 1) * EB_BK; };
+    if (nfull > 0) {
+      fetch_full(stage_k(0), va);
+      fetch_full(stage_k(1), vb);
+      if (loader) stash_full(va, 0);
+      __syncthreads();
+      fetch_full(stage_k(2), va);
+      int s = 0;
+      for (; s + 1 < nfull; s += 2) {
+        // stage s on buffer 0 while stage s + 1 (vb) goes to buffer 1
+        mfma_stage(0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (loader) stash_full(vb, 1);
+        __syncthreads();
+        fetch_full(stage_k(s + 3), vb);
+        // stage s + 1 on buffer 1 while stage s + 2 (va) goes to buffer 0; past the last
+        // full stage that copy is never read
+        mfma_stage(1);
+        __builtin_amdgcn_sched_barrier(0);
+        if (loader) stash_full(va, 0);
+        __syncthreads();
+        fetch_full(stage_k(s + 4), va);
+      }
+      if (s < nfull) mfma_stage(0);                   // odd count: the last stage is in buffer 0
+    }
+    const int kt = kb + nfull * EB_BK;
+    if (kt < ke) {
+      // ragged last stage with guarded loads; buffer nfull & 1 was last read two stages
+      // back, before a barrier
+      if (loader) {
+        eb_load_block(X, ldx, d_in, d, ones, vec, kt + rg * 8, ke, c0, v);
+        stash(nfull & 1);
+      }
+      __syncthreads();
+      mfma_stage(nfull & 1);
+    }
+  } else {
+    if (kb < ke) {
+      if (loader) {
+        fetch(kb);
+        stash(0);
+      }
+      __syncthreads();
+    }
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += EB_BK) {
+      const bool more = k0 + EB_BK < ke;
+      if (more && loader) fetch(k0 + EB_BK);
+      mfma_stage(buf);
+      __builtin_amdgcn_sched_barrier(0);             // the stash (and its load waits) after the MFMAs
+      if (more && loader) stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
   auto for_each = [&](auto&& fn) {
 #pragma unroll
@@ -282,9 +390,20 @@ __device__ __forceinline__ void ea_bf16_finalize_body(const EaTask& q, int bx, i
   ea_finalize_chunk<EB_BT>(q, bx, v);
 }
 
-__global__ __launch_bounds__(256) void k_ea_bf16_tiles(EaTask q) { ea_bf16_tiles_body(q, blockIdx.x, blockIdx.y); }
+// blocks spread over the XCDs so that consecutive tiles of one slice share an L2
+__global__ __launch_bounds__(256) void k_ea_bf16_tiles(EaTask q) {
+  const int l = xcd_swizzle(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  ea_bf16_tiles_body(q, l % gridDim.x, l / gridDim.x);
+}
 __global__ __launch_bounds__(256) void k_ea_bf16_finalize(EaTask q) { ea_bf16_finalize_body(q, blockIdx.x, 0); }
-KFAC_GROUPED_KERNEL_XCD(k_ea_bf16_tiles_g, ea_bf16_tiles_body<0>, EaTask, 256)
+// grouped EA tiles: per-task block counts padded to multiples of 8 (the padding blocks
+// have slice index >= nks and exit)
+__global__ __launch_bounds__(256) void k_ea_bf16_tiles_g(const EaTask* tasks, GroupMap gm) {
+  int t, bx, by;
+  group_locate_xcd8(gm, t, bx, by);
+  if (by >= tasks[t].nks) return;
+  ea_bf16_tiles_body(tasks[t], bx, by);
+}
 KFAC_GROUPED_KERNEL(k_ea_bf16_finalize_g, ea_bf16_finalize_body, EaTask, 256)
 
 hipError_t launch_ea_bf16_tiles(const EaTask& q, int tiles, int ks, hipStream_t s) {

@@ -67,7 +67,7 @@ __device__ __forceinline__ void ea_tiles_body(const EaTask& q, int bx, int by) {
   __shared__ EaSmem sm;
   const GemmP& p = q.g;
   int I, J;
-  upper_tile(bx, q.T, I, J);
+  ea_tile(bx, q.T, I, J);
   const int ks = by, nks = q.nks;
   int kb, ke;
   ea_slice(p.K, nks, ks, EA_BK, kb, ke);
@@ -95,9 +95,17 @@ __device__ __forceinline__ void ea_finalize_body(const EaTask& q, int bx, int) {
   ea_finalize_chunk<EA_BT>(q, bx, v);
 }
 
-__global__ __launch_bounds__(256) void k_ea_tiles(EaTask q) { ea_tiles_body(q, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(256) void k_ea_tiles(EaTask q) {
+  const int l = xcd_swizzle(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  ea_tiles_body(q, l % gridDim.x, l / gridDim.x);
+}
 __global__ __launch_bounds__(256) void k_ea_finalize(EaTask q) { ea_finalize_body(q, blockIdx.x, 0); }
-KFAC_GROUPED_KERNEL(k_ea_tiles_g, ea_tiles_body, EaTask, 256)
+__global__ __launch_bounds__(256) void k_ea_tiles_g(const EaTask* tasks, GroupMap gm) {
+  int t, bx, by;
+  group_locate_xcd8(gm, t, bx, by);
+  if (by >= tasks[t].nks) return;
+  ea_tiles_body(tasks[t], bx, by);
+}
 KFAC_GROUPED_KERNEL(k_ea_finalize_g, ea_finalize_body, EaTask, 256)
 
 // F <- rho F (n == 0), keeps the bf16 shadow in sync.
@@ -250,18 +258,44 @@ int ea_tiles_per_side(int d, bool bf) {
 }
 
 int ea_choose_ksplit(int d, long n, bool bf) {
-  int T = ea_tiles_per_side(d, bf);
-  long tiles = (long)T * (T + 1) / 2;
-  // aim for >= ~1024 workgroups (fp32) / ~512 (bf16: two per compute unit; fewer slices
-  // keep the split-K partial traffic down)
-  const long target = bf ? 512 : 1024;
-  long want = (target + tiles - 1) / tiles;
+  const int T = ea_tiles_per_side(d, bf);
+  const long tiles = (long)T * (T + 1) / 2;
+  // Split-K count from a simple cost model: the tiles run in rounds of `slots` resident
+  // workgroups (two per compute unit for bf16, four for fp32), a round lasting as long
+  // as one slice; each slice adds a tile of partial sums written and read back.
+  const long slots = bf ? 512 : 1024;
   const long rows = bf ? 1024 : 512;                // rows per slice at least
-  long maxk = (n + rows - 1) / rows;
-  long ks = std::min(want, maxk);
-  if (ks < 1) ks = 1;
-  if (ks > 64) ks = 64;
-  return (int)ks;
+  const long maxk = std::max<long>(1, std::min<long>(64, (n + rows - 1) / rows));
+  const double stage_us = bf ? 1.6 : 1.2;           // one 64- / 32-row step of a block
+  const double step_rows = bf ? 64.0 : 32.0;
+  const double tile_us = (double)(bf ? kEaBf16Tile : EA_BT) * (bf ? kEaBf16Tile : EA_BT) * 8.0 / 8e6;
+  long best = 1;
+  double best_cost = 0.0;
+  for (long ks = 1; ks <= maxk; ++ks) {
+    const long rounds = (tiles * ks + slots - 1) / slots;
+    double cost = (double)rounds * ((double)n / ks / step_rows) * stage_us;
+    if (ks > 1) cost += (double)(tiles * ks) * tile_us + 5.0;
+    if (ks == 1 || cost < best_cost) { best = ks; best_cost = cost; }
+  }
+  return (int)best;
+}
+
+size_t ea_partial_bytes(int d, int ks, bool bf) {
+  if (ks <= 1) return 0;
+  const long bt = bf ? kEaBf16Tile : EA_BT;
+  const long T = ea_tiles_per_side(d, bf);
+  return (size_t)(T * (T + 1) / 2) * ks * bt * bt * sizeof(float);
+}
+
+int ea_grouped_ksplit(int d, long n, bool bf, double total_steps) {
+  // In a grouped launch every slice of every factor is one workgroup of the same grid:
+  // slices only have to keep the longest workgroup well below the launch's length.
+  const double slots = bf ? 512.0 : 1024.0, step_rows = bf ? 64.0 : 32.0;
+  const double smax = std::max(32.0, total_steps / slots / 3.0);
+  const long rows = bf ? 1024 : 512;
+  const long maxk = std::max<long>(1, std::min<long>(64, (n + rows - 1) / rows));
+  const long ks = (long)std::ceil(std::ceil((double)n / step_rows) / smax);
+  return (int)std::max<long>(1, std::min<long>(ks, maxk));
 }
 
 size_t ea_workspace_bytes(int d, long n, bool bf) {

@@ -178,7 +178,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
                                 xb ? (const uint16_t*)F.X : nullptr, (int)F.n, (int)F.d_in, F.ldx,
                                 F.append_ones, P->rho, F.scale, F.F_bf16, F.ldfb, (float*)wsp(I.ea_off), I.ea_ks);
         const int tiles = q.T * (q.T + 1) / 2;
-        t.push_back(q); gx.push_back(tiles); nb.push_back(tiles * I.ea_ks);
+        t.push_back(q); gx.push_back(tiles); nb.push_back((tiles * I.ea_ks + 7) / 8 * 8);   // XCD eighths
         if (I.ea_ks > 1) {
           const int fb = tiles * ea_finalize_chunks(xb == 1);
           tf.push_back(q); gxf.push_back(fb); nbf.push_back(fb);
@@ -521,6 +521,15 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
   const bool bf = (prec == KFAC_SKETCH_BF16);
   size_t off = 0;
   auto take = [&](size_t bytes) { off = (off + kAlign - 1) / kAlign * kAlign; size_t o = off; off += bytes; return o; };
+  // block steps of the grouped EA launches (one per activation precision) without split-K
+  double ea_steps[2] = {0.0, 0.0};
+  for (int i = 0; i < nf; ++i) {
+    const kfac_factor_desc& F = factors[i];
+    if (F.X == nullptr) continue;
+    const int xb = (F.xtype == KFAC_BF16) ? 1 : 0;
+    const double T = ea_tiles_per_side((int)F.d, xb == 1);
+    ea_steps[xb] += T * (T + 1) / 2 * std::ceil((double)F.n / (xb ? 64.0 : 32.0));
+  }
   for (int i = 0; i < nf; ++i) {
     const kfac_factor_desc& F = factors[i];
     FactorInfo I{};
@@ -534,8 +543,8 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
     I.ws_bytes = w.bytes;
     I.ws_off = take(w.bytes);
     const bool xb = (F.xtype == KFAC_BF16);
-    I.ea_ks = I.ea ? ea_choose_ksplit(I.d, F.n, xb) : 1;
-    I.ea_bytes = (I.ea && I.ea_ks > 1) ? ea_workspace_bytes(I.d, F.n, xb) : 0;
+    I.ea_ks = I.ea ? ea_grouped_ksplit(I.d, F.n, xb, ea_steps[xb ? 1 : 0]) : 1;
+    I.ea_bytes = I.ea ? ea_partial_bytes(I.d, I.ea_ks, xb) : 0;
     I.ea_off = take(I.ea_bytes + 16);
     I.sk_bytes = (bf && !I.exact)
                      ? std::max(skinny_part_bytes(I.l_pad, I.d, I.d), split_part_bytes(I.l_pad, I.d, I.d)) : 0;

@@ -95,12 +95,14 @@ def test_ea_update_no_workspace_matches_split(dtype):
     assert torch.equal(F1, F3)   # deterministic: bitwise identical reruns
 
 
-@pytest.mark.parametrize("d_in,n,offset", [(576, 3000, 1), (1152, 777, 0), (27, 4100, 3), (64, 64, 8)])
-def test_ea_update_bf16_strided_views(d_in, n, offset):
+@pytest.mark.parametrize("d_in,n,offset,extra", [(576, 3000, 1, 5), (1152, 777, 0, 5), (27, 4100, 3, 5),
+                                                  (64, 64, 8, 5), (576, 3001, 8, 8), (1152, 2100, 0, 8)])
+def test_ea_update_bf16_strided_views(d_in, n, offset, extra):
     """bf16 activations given as column-offset views of a wider buffer: misaligned rows
-    take the element-wise load path, aligned ones the 16-byte path; same result."""
+    take the element-wise load path, 16-byte aligned ones (row pitch a multiple of 8) the
+    pipelined buffer-load path; same result."""
     rng = np.random.default_rng(d_in + n)
-    W = torch.from_numpy(rng.standard_normal((n, d_in + offset + 5)).astype(np.float32)).to(DEV)
+    W = torch.from_numpy(rng.standard_normal((n, d_in + offset + extra)).astype(np.float32)).to(DEV)
     Xv = W.to(torch.bfloat16)[:, offset:offset + d_in]
     d = d_in + 1
     F0 = synth.psd_factor(d, synth.power_spectrum(d), 4).astype(np.float32) + np.eye(d, dtype=np.float32)
