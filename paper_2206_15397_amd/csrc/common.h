@@ -84,22 +84,36 @@ __device__ __forceinline__ double dpp_t(double old, double src) { return dpp_f64
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ float dpp_t(float old, float src) { return dpp_f32<CTRL, ROW_MASK>(old, src); }
 
+// DPP moves whose lanes outside ROW_MASK are left undefined (no `old` value to set up
+// first): for reductions whose result is only read in the written lanes.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_any(double src) {
+  const long long v = __builtin_bit_cast(long long, src);
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_any(float src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, src), CTRL, ROW_MASK, 0xf, false));
+}
+
 // Sum over each row of 16 lanes; every lane of the row receives it.
 template <typename T>
 __device__ __forceinline__ T row16_sum(T v) {
-  v += dpp_t<0xB1>(T(0), v);
-  v += dpp_t<0x4E>(T(0), v);
-  v += dpp_t<0x141>(T(0), v);
-  v += dpp_t<0x140>(T(0), v);
+  v += dpp_any<0xB1>(v);
+  v += dpp_any<0x4E>(v);
+  v += dpp_any<0x141>(v);
+  v += dpp_any<0x140>(v);
   return v;
 }
 
 // Sum over each half wavefront (lanes 0-31, 32-63); the result is valid in lanes 16-31
-// and 48-63 (rows 1 and 3).
+// and 48-63 (rows 1 and 3) only.
 template <typename T>
 __device__ __forceinline__ T half_sum_hi(T v) {
   v = row16_sum(v);
-  v += dpp_t<0x142, 0xA>(T(0), v);
+  v += dpp_any<0x142, 0xA>(v);
   return v;
 }
 
@@ -117,7 +131,7 @@ __device__ __forceinline__ float readlane_t(float v, int lane) {
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   v = half_sum_hi(v);
-  v += dpp_t<0x143, 0xC>(T(0), v);      // row 3 now holds the total
+  v += dpp_any<0x143, 0xC>(v);          // row 3 now holds the total
   return readlane_t(v, 63);
 }
 

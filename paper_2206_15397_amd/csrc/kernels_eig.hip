@@ -1,7 +1,8 @@
 // fp64 symmetric eigensolver for the (r+p) x (r+p) Rayleigh-Ritz matrix of Alg. 3
 // ("Eigen_decomp(C)"), and for the factor itself when r+p >= d:
 //   1. Householder tridiagonalisation, one workgroup.  For n <= 288 the lower triangle
-//      lives in registers of 1024 threads (32 x 32 thread grid, 9 x 9 blocks of 32).
+//      lives in registers of 512 threads (16 x 32 thread grid, two rows per thread in
+//      each of the 9 x 9 blocks of 32) and the diagonal blocks in LDS.
 //   2. split of the tridiagonal T into unreduced blocks (|e_i| <= 2 eps ||T||);
 //   3. every eigenvalue of every block by 16-way multisection bisection on Sturm counts
 //      (one 16-lane group per eigenvalue, many workgroups);
@@ -19,151 +20,167 @@ constexpr double kEps = 2.2204460492503131e-16;
 constexpr double kTiny = 2.2250738585072014e-308;
 
 // ======================================================================================
-// 1a. Tridiagonalisation for n <= 288 with the matrix held on chip.
-// Thread t: tr = t / 32, tc = t % 32 owns A[32 I + tr][32 J + tc] of the lower triangle:
-// the 36 off-diagonal blocks (I > J) in registers (slot I (I - 1) / 2 + J), the 9
-// diagonal blocks in LDS (Ld[I][tr][tc], entries with tr >= tc).  Block columns are
-// processed by a template per block column so every register index is a constant.
+// 1a. Tridiagonalisation for n <= 288 with the matrix held on chip, 512 threads.
+// Thread t: tr = t / 32 (0..15), tc = t % 32 owns A[32 I + tr + 16 h][32 J + tc], h = 0, 1,
+// of the lower triangle: the 36 off-diagonal blocks (I > J) in registers (slot
+// I (I - 1) / 2 + J), the 9 diagonal blocks in LDS (Ld[I][row][col], row >= col).  Block
+// columns are processed by a template per block column so every register index is a
+// constant.  One Householder step costs three barriers:
+//   column k (rows > k) is in scol[k & 1]; every wave derives the reflector from it
+//   (same data, same reduction order, so the same bits in every wave) -> p = 2 A v,
+//   row sums reduced in the wave, column partials per wave -> barrier -> p reduced ->
+//   barrier -> K = v^T p (every wave), w = p - K v on the fly, rank-2 update, the owners
+//   of column k + 1 copy it into the other buffer -> barrier.
 // ======================================================================================
-constexpr int TB = 32, TNB = 9, TNMAX = TB * TNB;
+constexpr int TB = 32, TNB = 9, TNMAX = TB * TNB, TNT = 512, TNW = TNT / 64;
+// thread rows of the 32 x 32 block grid and rows per thread in each block
+constexpr int TTR = TNT / TB, THR = TB / TTR;
 
 __device__ __forceinline__ constexpr int toff(int I, int J) { return I * (I - 1) / 2 + J; }   // I > J
 
 struct TriSh {
   double (*Ld)[TB][TB + 1];
-  double* sv;
-  double* sw;
-  double (*spr)[TB];
-  double (*spc)[TNB][TB];
-  double* sscal;
+  double (*scol)[TNMAX];    // two column buffers
+  double* sp;               // p = 2 A v, zero on rows <= k
+  double (*spr)[TB];        // row sums
+  double (*spc)[TNB][TB];   // column partials per wave
 };
 
+// Column kn of the working matrix (rows >= kn) into dst by its owners (tc == kn % 32, block
+// column JN): entries they hold themselves, already updated, so no barrier is needed first.
+template <int JN>
+__device__ __forceinline__ void tri_copy_col(const double (&a)[36][THR], const TriSh& S, int n, int kn, double* dst) {
+  if constexpr (JN < TNB) {
+    const int t = threadIdx.x, tr = t >> 5, tc = t & 31;
+    if (tc != (kn & 31)) return;
+#pragma unroll
+    for (int h = 0; h < THR; ++h) {
+      const int rr = tr + TTR * h;
+      {
+        const int i = TB * JN + rr;
+        if (rr >= tc && i < n) dst[i] = S.Ld[JN][rr][tc];
+      }
+#pragma unroll
+      for (int I = JN + 1; I < TNB; ++I) {
+        const int i = TB * I + rr;
+        if (i < n) dst[i] = a[toff(I, JN)][h];
+      }
+    }
+  }
+}
+
 template <int J0>
-__device__ __forceinline__ void tri_block_col(double (&a)[36], const TriSh& S, int n, double* V, double* diag,
+__device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh& S, int n, double* V, double* diag,
                                               double* off) {
-  const int t = threadIdx.x, tr = t >> 5, tc = t & 31, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, tr = t >> 5, tc = t & 31, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   double (*Ld)[TB][TB + 1] = S.Ld;
-  double* sv = S.sv;
-  double* sw = S.sw;
   if (TB * J0 + 2 >= n) return;                       // uniform
   for (int c0 = 0; c0 < TB; ++c0) {
     const int k = TB * J0 + c0;
     if (k + 2 >= n) break;                            // uniform
     const int kb = (k + 1) >> 5;                      // first block with rows/cols > k
-    // (1) column k (rows >= k) into sw
-    if (tc == c0) {
-      {
-        const int i = TB * J0 + tr;
-        if (i >= k && i < n) sw[i] = Ld[J0][tr][tc];
-      }
-#pragma unroll
-      for (int I = J0 + 1; I < TNB; ++I) {
-        const int i = TB * I + tr;
-        if (i < n) sw[i] = a[toff(I, J0)];
-      }
-    }
-    __syncthreads();
-    // (2) Householder vector (H = I - 2 v v^T, |v| = 1) by wave 0
+    const double* col = S.scol[k & 1];
+    // (1) reflector H = I - 2 v v^T (|v| = 1) from column k, in every wave
+    double s2 = 0.0;
+    for (int i = k + 1 + lane; i < n; i += 64) { const double x = col[i]; s2 += x * x; }
+    s2 = wave_sum(s2);
+    const double x0 = col[k + 1];
+    const double nrm = sqrt(s2);
+    const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+    const double vn2 = s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+    const double inv = (s2 > 0.0 && vn2 > 0.0) ? 1.0 / sqrt(vn2) : 0.0;
+    const double v1 = (x0 - alpha) * inv;
+    auto vval = [&](int i) {
+      const double x = col[i];
+      return (i > k + 1) ? x * inv : (i == k + 1 ? v1 : 0.0);
+    };
     if (wave == 0) {
-      double s2 = 0.0;
-      for (int i = k + 1 + lane; i < n; i += 64) { const double x = sw[i]; s2 += x * x; }
-      s2 = wave_sum(s2);
-      const double x0 = sw[k + 1];
-      const double nrm = sqrt(s2);
-      const double alpha = (x0 >= 0.0) ? -nrm : nrm;
-      const double vn2 = s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
-      const double inv = (s2 > 0.0 && vn2 > 0.0) ? 1.0 / sqrt(vn2) : 0.0;
-      for (int i = lane; i < n; i += 64) {
-        double vi = 0.0;
-        if (i > k + 1) vi = sw[i] * inv;
-        else if (i == k + 1) vi = (x0 - alpha) * inv;
-        sv[i] = vi;
-        V[(long)k * n + i] = vi;
-      }
+      for (int i = lane; i < n; i += 64) V[(long)k * n + i] = vval(i);
       if (lane == 0) {
-        diag[k] = sw[k];
+        diag[k] = col[k];
         off[k] = (inv > 0.0) ? alpha : x0;
-        S.sscal[0] = inv;
       }
     }
-    __syncthreads();
-    if (S.sscal[0] == 0.0) continue;                  // column already reduced (uniform)
-    // (3) p = 2 A v.  Row partials pr[I] (reduced over tc inside the wave), column
-    //     partials per wave in LDS.
-    double pr[TNB];
+    if (inv != 0.0) {                                 // uniform: same value in every wave
+      // (2) p = 2 A v: v at the thread's columns once, at its rows once per block row
+      double vc[TNB], pc[TNB];
 #pragma unroll
-    for (int I = 0; I < TNB; ++I) pr[I] = 0.0;
+      for (int J = J0; J < TNB; ++J) { vc[J] = (J >= kb) ? vval(TB * J + tc) : 0.0; pc[J] = 0.0; }
 #pragma unroll
-    for (int J = J0; J < TNB; ++J) {
-      if (J >= kb) {
-        const double vj = sv[TB * J + tc];
-        double pc = 0.0;
-        {   // diagonal block J
-          const double aij = (tr >= tc) ? Ld[J][tr][tc] : 0.0;
-          pr[J] += aij * vj;
-          pc += (tr != tc) ? aij * sv[TB * J + tr] : 0.0;
+      for (int I = J0; I < TNB; ++I) {
+        if (I >= kb) {
+#pragma unroll
+          for (int h = 0; h < THR; ++h) {
+            const int rr = tr + TTR * h;
+            const double vi = vval(TB * I + rr);
+            double pr = 0.0;
+#pragma unroll
+            for (int J = J0; J < I; ++J) {
+              if (J >= kb) {
+                const double aij = a[toff(I, J)][h];
+                pr += aij * vc[J];
+                pc[J] += aij * vi;
+              }
+            }
+            const double aii = (rr >= tc) ? Ld[I][rr][tc] : 0.0;   // diagonal block I
+            pr += aii * vc[I];
+            pc[I] += (rr != tc) ? aii * vi : 0.0;
+            const double x = half_sum_hi(pr);        // sum over tc, valid in tc >= 16
+            if (tc == 16) S.spr[I][rr] = x;
+          }
         }
-#pragma unroll
-        for (int I = J + 1; I < TNB; ++I) {
-          const double aij = a[toff(I, J)];
-          pr[I] += aij * vj;
-          pc += aij * sv[TB * I + tr];
-        }
-        pc += __shfl_xor(pc, 32, 64);
-        if (lane < 32) S.spc[wave][J][tc] = pc;
       }
-    }
 #pragma unroll
-    for (int I = J0; I < TNB; ++I) {
-      if (I >= kb) {
-        const double x = half_sum_hi(pr[I]);          // sum over tc, valid in tc >= 16
-        if (tc == 16) S.spr[I][tr] = x;
-      }
-    }
-    __syncthreads();
-    if (t > k && t < n) {
-      const int I = t >> 5, c = t & 31;
-      double p = S.spr[I][c];
-#pragma unroll
-      for (int w2 = 0; w2 < 16; ++w2) p += S.spc[w2][I][c];
-      sw[t] = 2.0 * p;
-    }
-    __syncthreads();
-    // (4) w = p - (v^T p) v  (zero on rows <= k)
-    if (wave == 0) {
-      double s2 = 0.0;
-      for (int i = k + 1 + lane; i < n; i += 64) s2 += sv[i] * sw[i];
-      s2 = wave_sum(s2);
-      if (lane == 0) S.sscal[1] = s2;
-    }
-    __syncthreads();
-    {
-      const double K = S.sscal[1];
-      if (t < n) sw[t] = (t > k) ? sw[t] - K * sv[t] : 0.0;
-    }
-    __syncthreads();
-    // (5) A <- A - v w^T - w v^T on the active blocks
-#pragma unroll
-    for (int J = J0; J < TNB; ++J) {
-      if (J >= kb) {
-        const double vj = sv[TB * J + tc], wj = sw[TB * J + tc];
-        if (tr >= tc) {
-          const double vi = sv[TB * J + tr], wi = sw[TB * J + tr];
-          Ld[J][tr][tc] -= vi * wj + wi * vj;
+      for (int J = J0; J < TNB; ++J) {
+        if (J >= kb) {
+          const double y = pc[J] + __shfl_xor(pc[J], 32, 64);
+          if (lane < 32) S.spc[wave][J][tc] = y;
         }
+      }
+      __syncthreads();
+      if (t < TNMAX) {
+        double p = 0.0;
+        if (t > k && t < n) {
+          const int I = t >> 5, c = t & 31;
+          p = S.spr[I][c];
 #pragma unroll
-        for (int I = J + 1; I < TNB; ++I) {
-          const double vi = sv[TB * I + tr], wi = sw[TB * I + tr];
-          a[toff(I, J)] -= vi * wj + wi * vj;
+          for (int w2 = 0; w2 < TNW; ++w2) p += S.spc[w2][I][c];
+        }
+        S.sp[t] = 2.0 * p;
+      }
+      __syncthreads();
+      // (3) K = v^T p in every wave; w = p - K v (zero on rows <= k); A -= v w^T + w v^T
+      double kp = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) kp += vval(i) * S.sp[i];
+      const double K = wave_sum(kp);
+      double wc[TNB];
+#pragma unroll
+      for (int J = J0; J < TNB; ++J) wc[J] = (J >= kb) ? S.sp[TB * J + tc] - K * vc[J] : 0.0;
+#pragma unroll
+      for (int I = J0; I < TNB; ++I) {
+        if (I >= kb) {
+#pragma unroll
+          for (int h = 0; h < THR; ++h) {
+            const int rr = tr + TTR * h;
+            const double vi = vval(TB * I + rr), wi = S.sp[TB * I + rr] - K * vi;
+#pragma unroll
+            for (int J = J0; J < I; ++J)
+              if (J >= kb) a[toff(I, J)][h] -= vi * wc[J] + wi * vc[J];
+            if (rr >= tc) Ld[I][rr][tc] -= vi * wc[I] + wi * vc[I];
+          }
         }
       }
     }
+    // (4) column k + 1 into the other buffer (its owners updated it just now)
+    if (c0 + 1 < TB) tri_copy_col<J0>(a, S, n, k + 1, S.scol[(k + 1) & 1]);
+    else tri_copy_col<J0 + 1>(a, S, n, k + 1, S.scol[(k + 1) & 1]);
     __syncthreads();
   }
 }
 
 template <int... Js>
-__device__ __forceinline__ void tri_all_cols(std::integer_sequence<int, Js...>, double (&a)[36], const TriSh& S,
+__device__ __forceinline__ void tri_all_cols(std::integer_sequence<int, Js...>, double (&a)[36][THR], const TriSh& S,
                                              int n, double* V, double* diag, double* off) {
   (tri_block_col<Js>(a, S, n, V, diag, off), ...);
 }
@@ -172,13 +189,12 @@ __device__ __forceinline__ void tridiag_reg_body(const EigTask& q, int, int) {
   const double* C = q.C; const long ldc = q.ldc; const float* Cf = q.Cf; const long ldcf = q.ldcf;
   const int n = q.n; double* V = q.V; double* diag = q.diag; double* off = q.off; int* status = q.status;
   __shared__ double Ld[TNB][TB][TB + 1];
-  __shared__ double sv[TNMAX];
-  __shared__ double sw[TNMAX];
+  __shared__ double scol[2][TNMAX];
+  __shared__ double sp[TNMAX];
   __shared__ double spr[TNB][TB];
-  __shared__ double spc[16][TNB][TB];
-  __shared__ double sscal[2];
+  __shared__ double spc[TNW][TNB][TB];
   const int t = threadIdx.x, tr = t >> 5, tc = t & 31;
-  double a[36];
+  double a[36][THR];
   bool bad = false;
   auto sym = [&](int i, int j) -> double {
     double x, y;
@@ -190,39 +206,44 @@ __device__ __forceinline__ void tridiag_reg_body(const EigTask& q, int, int) {
   };
 #pragma unroll
   for (int I = 0; I < TNB; ++I) {
-    const int i = TB * I + tr;
-    {
-      const int j = TB * I + tc;
-      Ld[I][tr][tc] = (i < n && j < n && tr >= tc) ? sym(i, j) : 0.0;
-    }
 #pragma unroll
-    for (int J = 0; J < I; ++J) {
-      const int j = TB * J + tc;
-      a[toff(I, J)] = (i < n && j < n) ? sym(i, j) : 0.0;
+    for (int h = 0; h < THR; ++h) {
+      const int rr = tr + TTR * h, i = TB * I + rr;
+      {
+        const int j = TB * I + tc;
+        Ld[I][rr][tc] = (i < n && j < n && rr >= tc) ? sym(i, j) : 0.0;
+      }
+#pragma unroll
+      for (int J = 0; J < I; ++J) {
+        const int j = TB * J + tc;
+        a[toff(I, J)][h] = (i < n && j < n) ? sym(i, j) : 0.0;
+      }
     }
   }
   if (bad) atomicOr(status, KFAC_DS_NONFINITE);
-  for (int i = t; i < TNMAX; i += 1024) { sv[i] = 0.0; sw[i] = 0.0; }
+  for (int i = t; i < TNMAX; i += TNT) { scol[0][i] = 0.0; scol[1][i] = 0.0; sp[i] = 0.0; }
   __syncthreads();
-  TriSh S{Ld, sv, sw, spr, spc, sscal};
+  TriSh S{Ld, scol, sp, spr, spc};
+  tri_copy_col<0>(a, S, n, 0, scol[0]);
+  __syncthreads();
   tri_all_cols(std::make_integer_sequence<int, TNB>{}, a, S, n, V, diag, off);
   // trailing 2 x 2 (or 1 x 1) block
   __syncthreads();
   if (t == 0) {
-    auto at = [&](int i, int j) { return Ld[i >> 5][i & 31][j & 31]; };   // valid when i, j share a block
     if (n >= 2) diag[n - 2] = Ld[(n - 2) >> 5][(n - 2) & 31][(n - 2) & 31];
     diag[n - 1] = Ld[(n - 1) >> 5][(n - 1) & 31][(n - 1) & 31];
-    (void)at;
   }
   if (n >= 2) {
     const int i = n - 1, j = n - 2;
     if ((i >> 5) == (j >> 5)) {
       if (t == 0) off[n - 2] = Ld[i >> 5][i & 31][j & 31];
     } else {
-      // (n-1, n-2) lies in the off-diagonal block (I, I-1): owner tr = i & 31, tc = j & 31
+      // (n-1, n-2) lies in the off-diagonal block (I, I-1): owner row i & 31, column j & 31
 #pragma unroll
       for (int I = 1; I < TNB; ++I)
-        if (I == (i >> 5) && tr == (i & 31) && tc == (j & 31)) off[n - 2] = a[toff(I, I - 1)];
+#pragma unroll
+        for (int h = 0; h < THR; ++h)
+          if (I == (i >> 5) && tr + TTR * h == (i & 31) && tc == (j & 31)) off[n - 2] = a[toff(I, I - 1)][h];
     }
   }
 }
@@ -751,7 +772,7 @@ __device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int
 }
 
 // single-task and grouped entry points of the eigensolver phases
-__global__ __launch_bounds__(1024) void k_tridiag_reg(EigTask q) { tridiag_reg_body(q, 0, 0); }
+__global__ __launch_bounds__(TNT) void k_tridiag_reg(EigTask q) { tridiag_reg_body(q, 0, 0); }
 __global__ __launch_bounds__(512) void k_tri_prep(EigTask q) { tri_prep_body(q, 0, 0); }
 __global__ __launch_bounds__(256) void k_tri_bisect(EigTask q) { tri_bisect_body(q, blockIdx.x, 0); }
 __global__ __launch_bounds__(512) void k_tri_select(EigTask q) { tri_select_body(q, 0, 0); }
@@ -763,7 +784,7 @@ __global__ __launch_bounds__(256) void k_backtransform(EigTask q) {
   backtransform_body<1, KFAC_MAX_SKETCH>(q, blockIdx.x, 0);
 }
 
-KFAC_GROUPED_KERNEL(k_tridiag_reg_g, tridiag_reg_body, EigTask, 1024)
+KFAC_GROUPED_KERNEL(k_tridiag_reg_g, tridiag_reg_body, EigTask, TNT)
 KFAC_GROUPED_KERNEL(k_tri_prep_g, tri_prep_body, EigTask, 512)
 KFAC_GROUPED_KERNEL(k_tri_bisect_g, tri_bisect_body, EigTask, 256)
 KFAC_GROUPED_KERNEL(k_tri_select_g, tri_select_body, EigTask, 512)
@@ -809,7 +830,7 @@ hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldc
                             double* A, double* V, double* diag, double* off, double* Z, double* scratch,
                             float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s) {
   EigTask q = make_eig_task(C, ldc, Cf, ldcf, n, n_pad, r, A, V, diag, off, Z, scratch, P, ldp, D, Dd, status);
-  if (n <= TNMAX) hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(1024), 0, s, q);
+  if (n <= TNMAX) hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(TNT), 0, s, q);
   else hipLaunchKernelGGL(k_tridiag_gmem, dim3(1), dim3(1024), 0, s, q);
   hipLaunchKernelGGL(k_tri_prep, dim3(1), dim3(512), 0, s, q);
   hipLaunchKernelGGL(k_tri_bisect, dim3((n + 15) / 16), dim3(256), 0, s, q);
@@ -827,7 +848,7 @@ hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldc
     if (blocks > 0) hipLaunchKernelGGL(KER, dim3(blocks), dim3(NT), 0, s, tasks, gm);      \
     return hipGetLastError();                                                              \
   }
-KFAC_GLAUNCH(launch_tridiag_g, k_tridiag_reg_g, EigTask, 1024)
+KFAC_GLAUNCH(launch_tridiag_g, k_tridiag_reg_g, EigTask, TNT)
 KFAC_GLAUNCH(launch_tri_prep_g, k_tri_prep_g, EigTask, 512)
 KFAC_GLAUNCH(launch_tri_bisect_g, k_tri_bisect_g, EigTask, 256)
 KFAC_GLAUNCH(launch_tri_select_g, k_tri_select_g, EigTask, 512)
