@@ -135,6 +135,16 @@ __device__ __forceinline__ T wave_sum(T v) {
   return readlane_t(v, 63);
 }
 
+// 1 / sqrt(x) for normal x > 0: the hardware estimate refined by two Newton steps
+// y <- y (3/2 - x y^2 / 2) (quadratic convergence from ~2^-22 to full fp64 precision).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32 Philox
 // bijection; multipliers M0, M1 and Weyl key increments W0, W1.
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {

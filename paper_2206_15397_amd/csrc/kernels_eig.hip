@@ -23,7 +23,8 @@ constexpr double kTiny = 2.2250738585072014e-308;
 // 1a. Tridiagonalisation for n <= 288 with the matrix held on chip, 512 threads.
 // Thread t: tr = t / 32 (0..15), tc = t % 32 owns A[32 I + tr + 16 h][32 J + tc], h = 0, 1,
 // of the lower triangle: the 36 off-diagonal blocks (I > J) in registers (slot
-// I (I - 1) / 2 + J), the 9 diagonal blocks in LDS (Ld[I][row][col], row >= col).  Block
+// I (I - 1) / 2 + J), the 9 diagonal blocks in LDS in full (Ld[I][row][col], both
+// triangles, each updated by the same rank-2 formula; the lower one is read out).  Block
 // columns are processed by a template per block column so every register index is a
 // constant.  One Householder step costs three barriers:
 //   column k (rows > k) is in scol[k & 1]; every wave derives the reflector from it
@@ -41,8 +42,9 @@ __device__ __forceinline__ constexpr int toff(int I, int J) { return I * (I - 1)
 struct TriSh {
   double (*Ld)[TB][TB + 1];
   double (*scol)[TNMAX];    // two column buffers
+  double* sv;               // v of the current step (written by every wave, same values)
   double* sp;               // p = 2 A v, zero on rows <= k
-  double (*spr)[TB];        // row sums
+  double (*spr)[TB][4];     // row partials, one per 8 columns of a block
   double (*spc)[TNB][TB];   // column partials per wave
 };
 
@@ -86,22 +88,26 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
     for (int i = k + 1 + lane; i < n; i += 64) { const double x = col[i]; s2 += x * x; }
     s2 = wave_sum(s2);
     const double x0 = col[k + 1];
-    const double nrm = sqrt(s2);
+    // |x|, alpha = -sign(x0) |x| and 1 / |x - alpha e1| with |x - alpha e1|^2 =
+    // 2 |x| (|x| + |x0|), by Newton-refined reciprocal square roots (short dependency chain)
+    const double nrm = (s2 > 0.0) ? s2 * rsqrt_nr(s2) : 0.0;
     const double alpha = (x0 >= 0.0) ? -nrm : nrm;
-    const double vn2 = s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
-    const double inv = (s2 > 0.0 && vn2 > 0.0) ? 1.0 / sqrt(vn2) : 0.0;
+    const double vn2 = 2.0 * nrm * (nrm + fabs(x0));
+    const double inv = (s2 > 0.0 && vn2 > 0.0) ? rsqrt_nr(vn2) : 0.0;
     const double v1 = (x0 - alpha) * inv;
-    auto vval = [&](int i) {
+    // v into LDS by every wave (identical values; the wave's own stores precede its
+    // loads in LDS order, and the previous step's readers are past the last barrier)
+    for (int i = lane; i < TNMAX; i += 64) {
       const double x = col[i];
-      return (i > k + 1) ? x * inv : (i == k + 1 ? v1 : 0.0);
-    };
-    if (wave == 0) {
-      for (int i = lane; i < n; i += 64) V[(long)k * n + i] = vval(i);
-      if (lane == 0) {
-        diag[k] = col[k];
-        off[k] = (inv > 0.0) ? alpha : x0;
-      }
+      const double vi = (i > k + 1 && i < n) ? x * inv : (i == k + 1 ? v1 : 0.0);
+      S.sv[i] = vi;
+      if (wave == 0 && i < n) V[(long)k * n + i] = vi;
     }
+    if (wave == 0 && lane == 0) {
+      diag[k] = col[k];
+      off[k] = (inv > 0.0) ? alpha : x0;
+    }
+    auto vval = [&](int i) { return S.sv[i]; };
     if (inv != 0.0) {                                 // uniform: same value in every wave
       // (2) p = 2 A v: v at the thread's columns once, at its rows once per block row
       double vc[TNB], pc[TNB];
@@ -123,11 +129,11 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
                 pc[J] += aij * vi;
               }
             }
-            const double aii = (rr >= tc) ? Ld[I][rr][tc] : 0.0;   // diagonal block I
-            pr += aii * vc[I];
-            pc[I] += (rr != tc) ? aii * vi : 0.0;
-            const double x = half_sum_hi(pr);        // sum over tc, valid in tc >= 16
-            if (tc == 16) S.spr[I][rr] = x;
+            pr += Ld[I][rr][tc] * vc[I];             // diagonal block I, held in full
+            pr += dpp_any<0xB1>(pr);                 // sum over 8 neighbouring columns
+            pr += dpp_any<0x4E>(pr);
+            pr += dpp_any<0x141>(pr);
+            S.spr[I][rr][tc >> 3] = pr;              // the 8 lanes store the same value
           }
         }
       }
@@ -143,7 +149,7 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
         double p = 0.0;
         if (t > k && t < n) {
           const int I = t >> 5, c = t & 31;
-          p = S.spr[I][c];
+          p = (S.spr[I][c][0] + S.spr[I][c][1]) + (S.spr[I][c][2] + S.spr[I][c][3]);
 #pragma unroll
           for (int w2 = 0; w2 < TNW; ++w2) p += S.spc[w2][I][c];
         }
@@ -166,8 +172,8 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
             const double vi = vval(TB * I + rr), wi = S.sp[TB * I + rr] - K * vi;
 #pragma unroll
             for (int J = J0; J < I; ++J)
-              if (J >= kb) a[toff(I, J)][h] -= vi * wc[J] + wi * vc[J];
-            if (rr >= tc) Ld[I][rr][tc] -= vi * wc[I] + wi * vc[I];
+              if (J >= kb) a[toff(I, J)][h] = fma(-wi, vc[J], fma(-vi, wc[J], a[toff(I, J)][h]));
+            Ld[I][rr][tc] = fma(-wi, vc[I], fma(-vi, wc[I], Ld[I][rr][tc]));
           }
         }
       }
@@ -190,8 +196,9 @@ __device__ __forceinline__ void tridiag_reg_body(const EigTask& q, int, int) {
   const int n = q.n; double* V = q.V; double* diag = q.diag; double* off = q.off; int* status = q.status;
   __shared__ double Ld[TNB][TB][TB + 1];
   __shared__ double scol[2][TNMAX];
+  __shared__ double sv[TNMAX];
   __shared__ double sp[TNMAX];
-  __shared__ double spr[TNB][TB];
+  __shared__ double spr[TNB][TB][4];
   __shared__ double spc[TNW][TNB][TB];
   const int t = threadIdx.x, tr = t >> 5, tc = t & 31;
   double a[36][THR];
@@ -211,7 +218,7 @@ __device__ __forceinline__ void tridiag_reg_body(const EigTask& q, int, int) {
       const int rr = tr + TTR * h, i = TB * I + rr;
       {
         const int j = TB * I + tc;
-        Ld[I][rr][tc] = (i < n && j < n && rr >= tc) ? sym(i, j) : 0.0;
+        Ld[I][rr][tc] = (i < n && j < n) ? sym(i, j) : 0.0;
       }
 #pragma unroll
       for (int J = 0; J < I; ++J) {
@@ -221,9 +228,9 @@ __device__ __forceinline__ void tridiag_reg_body(const EigTask& q, int, int) {
     }
   }
   if (bad) atomicOr(status, KFAC_DS_NONFINITE);
-  for (int i = t; i < TNMAX; i += TNT) { scol[0][i] = 0.0; scol[1][i] = 0.0; sp[i] = 0.0; }
+  for (int i = t; i < TNMAX; i += TNT) { scol[0][i] = 0.0; scol[1][i] = 0.0; sv[i] = 0.0; sp[i] = 0.0; }
   __syncthreads();
-  TriSh S{Ld, scol, sp, spr, spc};
+  TriSh S{Ld, scol, sv, sp, spr, spc};
   tri_copy_col<0>(a, S, n, 0, scol[0]);
   __syncthreads();
   tri_all_cols(std::make_integer_sequence<int, TNB>{}, a, S, n, V, diag, off);

@@ -362,16 +362,6 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
-// 1 / sqrt(x) for finite x > 0: the hardware estimate refined by two Newton steps
-// y <- y (3/2 - x y^2 / 2) (quadratic convergence from ~2^-22 to full fp64 precision).
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
-}
-
 __device__ __forceinline__ bool bc_diag_block(double* G, long ldg, int n, int K, double* Xo, long ldx, BcSmem& sm,
                                               const double* src, long lds) {
   static_assert(BC == 16, "one lane per column of the diagonal block");
