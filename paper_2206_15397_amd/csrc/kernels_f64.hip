@@ -11,50 +11,80 @@ namespace kfac {
 // ======================================================================================
 // Gram / projection: C[a][b] = sum_k A[a][k] * B[b][k]   (fp32 inputs, fp64 accumulate)
 // ======================================================================================
-constexpr int GR_T = 64, GR_BK = 16;
+constexpr int GR_T = 64;
 
 __device__ __forceinline__ void tile_of(int t, int T, int sym, int& I, int& J) {
   if (sym) { upper_tile(t, T, I, J); }
   else { I = t / T; J = t % T; }
 }
 
-// block (tile, K slice), 256 threads = 2 x 2 waves of 32 x 32.
+// block (tile, K slice), 256 threads = 2 x 2 waves of 32 x 32, 32-wide K steps.  The
+// next step's operands are loaded into registers (16-byte row loads when the rows are
+// 16-byte aligned) while the MFMAs run on the current one.
+constexpr int GP_BK = 32;
 __device__ __forceinline__ void gram_partial_body(const GramP& p, int bx, int by) {
-  __shared__ double sa[GR_BK][GR_T + 2];
-  __shared__ double sb[GR_BK][GR_T + 2];
+  __shared__ double sa[GP_BK][GR_T + 2];
+  __shared__ double sb[GP_BK][GR_T + 2];
   const int T = (p.L + GR_T - 1) / GR_T;
   int I, J;
   tile_of(bx, T, p.sym, I, J);
   const int a0 = I * GR_T, b0 = J * GR_T;
   const int ks = by, nks = p.ksplit;
-  const int kchunk = ((p.K + nks - 1) / nks + GR_BK - 1) / GR_BK * GR_BK;
+  const int kchunk = ((p.K + nks - 1) / nks + GP_BK - 1) / GP_BK * GP_BK;
   const int kb = ks * kchunk, ke = min(p.K, kb + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
+  // loader: thread -> rows lr and lr + 32, k lk .. lk + 3 of the step
+  const int lr = tid >> 3, lk = (tid & 7) * 4;
+  const bool vec = ((p.lda & 3) == 0) && ((p.ldb & 3) == 0) && ((((uintptr_t)p.A) & 15) == 0) &&
+                   ((((uintptr_t)p.B) & 15) == 0);
   f64x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
-  for (int k0 = kb; k0 < ke; k0 += GR_BK) {
-    __syncthreads();
-    // 64 rows x 16 k for each operand: 4 elements per thread, consecutive threads -> k
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int e = tid + u * 256;
-      int row = e / GR_BK, k = e % GR_BK;
-      int gk = k0 + k;
-      float va = 0.f, vb = 0.f;
-      if (gk < ke) {
-        if (a0 + row < p.L) va = p.A[(long)(a0 + row) * p.lda + gk];
-        if (b0 + row < p.L) vb = p.B[(long)(b0 + row) * p.ldb + gk];
+  float4 ra[2], rb[2];
+  auto load_row = [&](const float* X, long ldx, int r0, int k0, int u) {
+    const int row = r0 + lr + 32 * u, gk = k0 + lk;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row < p.L) {
+      const float* q = X + (long)row * ldx + gk;
+      if (vec && gk + 4 <= ke) {
+        v = *(const float4*)q;
+      } else {
+        if (gk + 0 < ke) v.x = q[0];
+        if (gk + 1 < ke) v.y = q[1];
+        if (gk + 2 < ke) v.z = q[2];
+        if (gk + 3 < ke) v.w = q[3];
       }
-      sa[k][row] = (double)va;
-      sb[k][row] = (double)vb;
     }
-    __syncthreads();
+    return v;
+  };
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int kk = 0; kk < GR_BK; kk += 4) {
+    for (int u = 0; u < 2; ++u) {
+      ra[u] = load_row(p.A, p.lda, a0, k0, u);
+      rb[u] = load_row(p.B, p.ldb, b0, k0, u);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int row = lr + 32 * u;
+      sa[lk + 0][row] = (double)ra[u].x; sa[lk + 1][row] = (double)ra[u].y;
+      sa[lk + 2][row] = (double)ra[u].z; sa[lk + 3][row] = (double)ra[u].w;
+      sb[lk + 0][row] = (double)rb[u].x; sb[lk + 1][row] = (double)rb[u].y;
+      sb[lk + 2][row] = (double)rb[u].z; sb[lk + 3][row] = (double)rb[u].w;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += GP_BK) {
+    __syncthreads();                                 // the previous step's reads are done
+    store();
+    __syncthreads();
+    if (k0 + GP_BK < ke) load(k0 + GP_BK);           // in flight during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < GP_BK; kk += 4) {
       double af[2], bf[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) af[i] = sa[kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
@@ -671,8 +701,8 @@ __device__ __forceinline__ void trmm_body(const TrmmTask& q, int bx, int by) {
   const double* Li = q.Li; const long ldl = q.ldl; const int n = q.n;
   const float* Yt = q.Yt; const long ldy = q.ldy; const int ncols = q.ncols;
   float* Qt = q.Qt; const long ldq = q.ldq; uint16_t* Qtb = q.Qtb; const long ldqb = q.ldqb; const int l_pad = q.l_pad;
-  __shared__ double sa[GR_BK][GR_T + 2];
-  __shared__ double sb[GR_BK][GR_T + 2];
+  __shared__ double sa[GP_BK][GR_T + 2];
+  __shared__ double sb[GP_BK][GR_T + 2];
   const int a0 = by * GR_T, c0 = bx * GR_T;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -682,29 +712,54 @@ __device__ __forceinline__ void trmm_body(const TrmmTask& q, int bx, int by) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
   const int kend = min(n, a0 + GR_T);
-  for (int k0 = 0; k0 < kend; k0 += GR_BK) {
-    __syncthreads();
+  // loaders, 32-wide K steps with the next step in registers during the MFMAs:
+  //   L^{-1}: rows lr, lr + 32, k lk .. lk + 3;  Y^T: k rows kr, kr + 16, columns cc .. cc + 3
+  const int lr = tid >> 3, lk = (tid & 7) * 4, kr = tid >> 4, cc = (tid & 15) * 4;
+  const bool yvec = ((ldy & 3) == 0) && ((((uintptr_t)Yt) & 15) == 0);
+  double ra[2][4];
+  float4 rb[2];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + u * 256;
-      // A: 64 rows x 16 k (k contiguous in memory)
-      {
-        const int row = e / GR_BK, kk = e % GR_BK;
-        double v = 0.0;
-        if (a0 + row < n && k0 + kk < kend) v = Li[(long)(a0 + row) * ldl + k0 + kk];
-        sa[kk][row] = v;
+    for (int u = 0; u < 2; ++u) {
+      const int row = a0 + lr + 32 * u;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + lk + i;
+        ra[u][i] = (row < n && k < kend) ? Li[(long)row * ldl + k] : 0.0;
       }
-      // B: 16 k x 64 columns (columns contiguous)
-      {
-        const int kk = e / GR_T, col = e % GR_T;
-        double v = 0.0;
-        if (k0 + kk < kend && c0 + col < ncols) v = (double)Yt[(long)(k0 + kk) * ldy + c0 + col];
-        sb[kk][col] = v;
+      const int k = k0 + kr + 16 * u, col = c0 + cc;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (k < kend) {
+        const float* y = Yt + (long)k * ldy + col;
+        if (yvec && col + 4 <= ncols) {
+          v = *(const float4*)y;
+        } else {
+          if (col + 0 < ncols) v.x = y[0];
+          if (col + 1 < ncols) v.y = y[1];
+          if (col + 2 < ncols) v.z = y[2];
+          if (col + 3 < ncols) v.w = y[3];
+        }
       }
+      rb[u] = v;
     }
-    __syncthreads();
+  };
+  auto store = [&]() {
 #pragma unroll
-    for (int kk = 0; kk < GR_BK; kk += 4) {
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sa[lk + i][lr + 32 * u] = ra[u][i];
+      double* d = &sb[kr + 16 * u][cc];
+      d[0] = (double)rb[u].x; d[1] = (double)rb[u].y; d[2] = (double)rb[u].z; d[3] = (double)rb[u].w;
+    }
+  };
+  if (kend > 0) load(0);
+  for (int k0 = 0; k0 < kend; k0 += GP_BK) {
+    __syncthreads();                                 // the previous step's reads are done
+    store();
+    __syncthreads();
+    if (k0 + GP_BK < kend) load(k0 + GP_BK);         // in flight during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < GP_BK; kk += 4) {
       double af[2], bf[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) af[i] = sa[kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
