@@ -408,7 +408,7 @@ def mfma_fraction(plan, names, times_ms):
     for i, (nm, t) in enumerate(zip(names, times_ms)):
         if nm in gemm:
             last = gemm[nm]
-        elif nm != "slice_reduce" or last is None:
+        elif nm not in ("slice_reduce", "gemm_f32_reduce") or last is None:
             last = None
             continue
         f, _ = plan.launch_work(i)

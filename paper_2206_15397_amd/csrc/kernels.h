@@ -118,6 +118,10 @@ int backtransform_blocks(int r, int nc);   // nc columns per wavefront (1 or 4)
 constexpr int kGemmConfigs = 5;
 int gemm_g_blocks_x(const GemmP& p, int cfg);
 int gemm_g_blocks_y(const GemmP& p, int cfg);
+int gemm_slice_blocks(const GemmP& p);                // split-K finish blocks (0 if ksplit <= 1)
+hipError_t launch_gemm_slices_g(const GemmP* t, GroupMap gm, int blocks, hipStream_t s);
+// K slices of the precondition's T1 = J U_a diag(f_a) product
+int precondition_ksplit(int64_t d_g, int64_t d_a, int64_t r_a);
 
 hipError_t launch_ea_tiles_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_ea_finalize_g(const EaTask* t, GroupMap gm, int blocks, hipStream_t s);
@@ -129,7 +133,8 @@ hipError_t launch_ea_bf16_finalize_g(const EaTask* t, GroupMap gm, int blocks, h
 hipError_t launch_omega_g(const OmegaTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_sign_partial_g(const SignTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_sign_apply_g(const SignTask* t, GroupMap gm, int blocks, hipStream_t s);
-hipError_t launch_gemm_g(const GemmP* t, GroupMap gm, int blocks, bool ta, bool tb, int cfg, hipStream_t s);
+// split: the launch holds split-K tasks (ksplit > 1; no transposes, cfg != 4)
+hipError_t launch_gemm_g(const GemmP* t, GroupMap gm, int blocks, bool ta, bool tb, int cfg, bool split, hipStream_t s);
 hipError_t launch_gemm_bf16_g(const BfGemmTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_gram_partial_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_gram_reduce_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);

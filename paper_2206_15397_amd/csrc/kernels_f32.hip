@@ -16,21 +16,38 @@ __global__ void k_fill_identity(float* F, int d, long ldf) {
 }
 
 // ------------------------------------------------------------------------------------
-// Generic GEMM: block (bx, by) computes C[by*BM : , bx*BN : ].
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+// Generic GEMM: block (bx, by) computes C[by*BM : , bx*BN : ].  With ksplit > 1, by also
+// names the K slice (by = slice * tile rows + tile row) and the raw tile goes to slice
+// `slice` of the partial sums (ksplit x M x N, row-major), to be finished by
+// gemm_slices_body.
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT = false>
 __device__ __forceinline__ void gemm_body(const GemmP& p, int bx, int by) {
   using T = TileF32<BM, BN, BK, WM, WN, TA, TB>;
   __shared__ typename T::Smem sm;
+  int kb = 0, ke = p.K, slice = 0;
+  if constexpr (SPLIT) {
+    if (p.ksplit > 1) {
+      const int ty = (p.M + BM - 1) / BM;
+      slice = by / ty;
+      by -= slice * ty;
+      const int kc = ((p.K + p.ksplit - 1) / p.ksplit + BK - 1) / BK * BK;
+      kb = min(p.K, slice * kc);
+      ke = min(p.K, kb + kc);
+    }
+  }
   const int m0 = by * BM, n0 = bx * BN;
   f32x4 acc[T::FM][T::FN];
 #pragma unroll
   for (int i = 0; i < T::FM; ++i)
 #pragma unroll
     for (int j = 0; j < T::FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  T::run(p, m0, n0, 0, p.K, sm, acc);
+  T::run(p, m0, n0, kb, ke, sm, acc);
+  const bool split = SPLIT && p.ksplit > 1;
+  float* part = p.part + (long)slice * p.M * p.N;
   T::for_each(acc, [&](int r, int c, float v) {
     int i = m0 + r, j = n0 + c;
     if (i >= p.M || j >= p.N) return;
+    if (split) { part[(long)i * p.N + j] = v; return; }
     float s = p.alpha * v;
     if (p.rowD) s *= damp_weight(p.rowD[i], p.lam);
     if (p.colD) s *= damp_weight(p.colD[j], p.lam);
@@ -40,16 +57,37 @@ __device__ __forceinline__ void gemm_body(const GemmP& p, int bx, int by) {
   });
 }
 
+// Split-K finish: 1024 consecutive elements of C per block; slices summed in index order,
+// then the GEMM's epilogue.
+constexpr int kGemmSliceChunk = 1024;
+__device__ __forceinline__ void gemm_slices_body(const GemmP& p, int bx, int) {
+  const long total = (long)p.M * p.N;
+  for (int u = 0; u < kGemmSliceChunk / 256; ++u) {
+    const long e = (long)bx * kGemmSliceChunk + u * 256 + threadIdx.x;
+    if (e >= total) return;
+    float v = 0.f;
+    for (int sl = 0; sl < p.ksplit; ++sl) v += p.part[(long)sl * total + e];
+    const int i = (int)(e / p.N), j = (int)(e % p.N);
+    float s = p.alpha * v;
+    if (p.rowD) s *= damp_weight(p.rowD[i], p.lam);
+    if (p.colD) s *= damp_weight(p.colD[j], p.lam);
+    if (p.X) s += p.beta * p.X[(long)i * p.ldx + j];
+    p.C[(long)i * p.ldc + j] = s;
+    if (p.Cb) p.Cb[(long)i * p.ldcb + j] = f32_to_bf16_rne(s);
+  }
+}
+KFAC_GROUPED_KERNEL(k_gemm_slices_g, gemm_slices_body, GemmP, 256)
+
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmP p) {
   gemm_body<BM, BN, BK, WM, WN, TA, TB>(p, blockIdx.x, blockIdx.y);
 }
 
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT = false>
 __global__ __launch_bounds__(WM * WN * 64) void k_gemm_g(const GemmP* tasks, GroupMap gm) {
   int t, bx, by;
   group_locate(gm, t, bx, by);
-  gemm_body<BM, BN, BK, WM, WN, TA, TB>(tasks[t], bx, by);
+  gemm_body<BM, BN, BK, WM, WN, TA, TB, SPLIT>(tasks[t], bx, by);
 }
 
 // ------------------------------------------------------------------------------------
@@ -533,8 +571,9 @@ KFAC_GROUPED_KERNEL_XCD(k_gemm_skinny_f32_g, gemm_skinny_f32_body, GemmP, SF_NT)
 
 // Tile configurations of the grouped fp32 GEMM (BM x BN, 2 x 2 wavefronts, BK = 16).
 template <int BM, int BN>
-static void gemm_g_launch(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, hipStream_t s) {
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, false, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+static void gemm_g_launch(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, bool split, hipStream_t s) {
+  if (split) hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, false, false, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
+  else if (!ta && !tb) hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, false, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
   else if (!ta && tb) hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, false, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
   else if (ta && !tb) hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, true, false>), dim3(blocks), dim3(256), 0, s, tasks, gm);
   else hipLaunchKernelGGL((k_gemm_g<BM, BN, 16, 2, 2, true, true>), dim3(blocks), dim3(256), 0, s, tasks, gm);
@@ -542,22 +581,39 @@ static void gemm_g_launch(const GemmP* tasks, GroupMap gm, int blocks, bool ta, 
 
 static const int kGemmCfg[kGemmConfigs][2] = {{64, 64}, {128, 128}, {96, 128}, {128, 64}, {SF_M, SF_BN}};
 
-hipError_t launch_gemm_g(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, int cfg, hipStream_t s) {
+hipError_t launch_gemm_g(const GemmP* tasks, GroupMap gm, int blocks, bool ta, bool tb, int cfg, bool split,
+                         hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
+  if (split && (ta || tb || cfg == 4)) return hipErrorInvalidValue;   // split-K: plain layouts, square tiles
   switch (cfg) {
-    case 1: gemm_g_launch<128, 128>(tasks, gm, blocks, ta, tb, s); break;
-    case 2: gemm_g_launch<96, 128>(tasks, gm, blocks, ta, tb, s); break;
-    case 3: gemm_g_launch<128, 64>(tasks, gm, blocks, ta, tb, s); break;
+    case 1: gemm_g_launch<128, 128>(tasks, gm, blocks, ta, tb, split, s); break;
+    case 2: gemm_g_launch<96, 128>(tasks, gm, blocks, ta, tb, split, s); break;
+    case 3: gemm_g_launch<128, 64>(tasks, gm, blocks, ta, tb, split, s); break;
     case 4:   // skinny: no transposes, M <= 288 (checked by the caller)
       if (ta || tb) return hipErrorInvalidValue;
       hipLaunchKernelGGL(k_gemm_skinny_f32_g, dim3(blocks), dim3(SF_NT), 0, s, tasks, gm);
       break;
-    default: gemm_g_launch<64, 64>(tasks, gm, blocks, ta, tb, s); break;
+    default: gemm_g_launch<64, 64>(tasks, gm, blocks, ta, tb, split, s); break;
   }
   return hipGetLastError();
 }
 int gemm_g_blocks_x(const GemmP& p, int cfg) { return (p.N + kGemmCfg[cfg][1] - 1) / kGemmCfg[cfg][1]; }
-int gemm_g_blocks_y(const GemmP& p, int cfg) { return (p.M + kGemmCfg[cfg][0] - 1) / kGemmCfg[cfg][0]; }
+int gemm_g_blocks_y(const GemmP& p, int cfg) {
+  return (p.M + kGemmCfg[cfg][0] - 1) / kGemmCfg[cfg][0] * (p.ksplit > 1 ? p.ksplit : 1);
+}
+int gemm_slice_blocks(const GemmP& p) {
+  return p.ksplit > 1 ? (int)(((long)p.M * p.N + kGemmSliceChunk - 1) / kGemmSliceChunk) : 0;
+}
+hipError_t launch_gemm_slices_g(const GemmP* tasks, GroupMap gm, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_gemm_slices_g, dim3(blocks), dim3(256), 0, s, tasks, gm);
+  return hipGetLastError();
+}
+int precondition_ksplit(int64_t d_g, int64_t d_a, int64_t r_a) {
+  // T1 = J U_a diag(f_a) (d_g x r_a, contraction over d_a): few 64 x 64 tiles, long K
+  const int64_t tiles = ((d_g + 63) / 64) * ((r_a + 63) / 64);
+  const int64_t want = (256 + tiles - 1) / tiles, maxk = (d_a + 511) / 512;
+  return (int)std::max<int64_t>(1, std::min<int64_t>({want, maxk, (int64_t)16}));
+}
 
 EaTask make_ea_task(float* F, int d, long ldf, const float* X, const uint16_t* Xb, int n, int d_in, long ldx, int ones,
                     float rho, float scale, uint16_t* Fb, long ldfb, float* part, int ks) {

@@ -18,7 +18,7 @@ namespace {
 
 enum Kind {
   K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_SKINNY, K_SKINNY_R, K_SPLIT, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRTRI, K_TRMM, K_TRIDIAG, K_PREP,
-  K_BISECT, K_SELECT, K_VEC, K_CLEAD, K_CLUSTER, K_BT, K_SIGN_P, K_SIGN_A
+  K_BISECT, K_SELECT, K_VEC, K_CLEAD, K_CLUSTER, K_BT, K_SIGN_P, K_SIGN_A, K_GEMM_SL
 };
 
 struct LaunchRec {
@@ -31,6 +31,7 @@ struct LaunchRec {
   int ord;               // ordinal among the tunable launches (-1: not tunable)
   int ncfg;              // number of configurations of the tunable unit
   int span;              // launches belonging to the tunable unit (a split-K reduction follows)
+  bool split;            // fp32 GEMM launch with split-K tasks
 };
 
 // Algorithmic work: flops of the operation as defined (padding and split-K excluded) and
@@ -136,7 +137,7 @@ void add_gemm(kfac_plan* P, Tables& T, int& ord, const std::vector<GemmP>& g, bo
   if (g.empty()) return;
   const int o = ord++;
   bool skinny_ok = !ta && !tb;                    // the skinny tile: no transposes, M <= 288
-  for (const GemmP& q : g) skinny_ok = skinny_ok && q.M <= 288;
+  for (const GemmP& q : g) skinny_ok = skinny_ok && q.M <= 288 && q.ksplit <= 1;
   int cfg = (o < (int)P->gemm_cfg.size() && P->gemm_cfg[o] >= 0) ? P->gemm_cfg[o] : default_gemm_cfg(g);
   if (cfg == kGemmConfigs - 1 && !skinny_ok) cfg = default_gemm_cfg(g);
   std::vector<int> gx, nb;
@@ -146,11 +147,20 @@ void add_gemm(kfac_plan* P, Tables& T, int& ord, const std::vector<GemmP>& g, bo
   }
   const size_t before = T.recs.size();
   T.add(K_GEMM, g, gx, nb, ta, tb, w);
+  // split-K tasks: slices summed and the epilogue applied by a second launch
+  std::vector<GemmP> gs;
+  std::vector<int> gxs, nbs;
+  for (const GemmP& q : g)
+    if (q.ksplit > 1) { gs.push_back(q); gxs.push_back(gemm_slice_blocks(q)); nbs.push_back(gemm_slice_blocks(q)); }
   if (T.recs.size() > before) {
-    T.recs.back().cfg = cfg;
-    T.recs.back().ord = o;
-    T.recs.back().ncfg = skinny_ok ? kGemmConfigs : kGemmConfigs - 1;
+    LaunchRec& r = T.recs.back();
+    r.cfg = cfg;
+    r.ord = o;
+    r.ncfg = skinny_ok ? kGemmConfigs : kGemmConfigs - 1;
+    r.split = !gs.empty();
+    r.span = gs.empty() ? 1 : 2;
   }
+  if (!gs.empty()) T.add(K_GEMM_SL, gs, gxs, nbs);
 }
 
 // Build all task tables for workspace base `base` (null: sizes only) and status pointer.
@@ -460,6 +470,8 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       float* T1 = b.take<float>((size_t)dg * ra);
       float* M = b.take<float>((size_t)dg * da);
       float* T2 = b.take<float>((size_t)rg * da);
+      const int ks1 = precondition_ksplit(dg, da, ra);
+      float* T1p = ks1 > 1 ? b.take<float>((size_t)ks1 * dg * ra) : nullptr;
       auto push = [&](std::vector<GemmP>& v, std::vector<int>& gx, std::vector<int>& nb, const GemmP& q) {
         v.push_back(q); (void)gx; (void)nb;
       };
@@ -467,6 +479,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       q.ones_col = -1; q.alpha = 1.f; q.lam = P->lam;
       GemmP a = q;  // T1 = J U_a diag(f_a)
       a.M = dg; a.N = ra; a.K = da; a.A = L.J; a.lda = L.ldj; a.B = A.U; a.ldb = A.ldu; a.C = T1; a.ldc = ra; a.colD = A.D;
+      if (ks1 > 1) { a.ksplit = ks1; a.part = T1p; }
       push(g1, x1, n1, a);
       GemmP m = q;  // M = T1 U_a^T + J / lambda
       m.M = dg; m.N = da; m.K = ra; m.A = T1; m.lda = ra; m.B = A.U; m.ldb = A.ldu; m.C = M; m.ldc = da;
@@ -555,7 +568,8 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
     const kfac_layer_desc& L = layers[l];
     const int64_t dg = factors[L.fg].d, da = factors[L.fa].d, ra = factors[L.fa].r, rg = factors[L.fg].r;
     LayerInfo I{};
-    I.bytes = kfac_precondition_workspace(dg, da, ra, rg);
+    const int ks1 = precondition_ksplit(dg, da, ra);
+    I.bytes = kfac_precondition_workspace(dg, da, ra, rg) + (ks1 > 1 ? (size_t)ks1 * dg * ra * sizeof(float) + kAlign : 0);
     I.off = take(I.bytes);
     P->li.push_back(I);
   }
@@ -609,8 +623,8 @@ const char* kfac_plan_launch_name(const kfac_plan* plan, int index) {
                                 "gemm_f32", "gemm_bf16", "gemm_bf16_skinny", "slice_reduce", "gemm_bf16x3", "gram_partial",
                                 "gram_reduce", "cholinv", "trtri_cols", "trmm", "tridiag", "tri_prep", "tri_bisect",
                                 "tri_select", "tri_vec", "tri_cluster_lead", "tri_cluster", "backtransform",
-                                "sign_partial", "sign_apply"};
-  static_assert(sizeof(names) / sizeof(names[0]) == K_SIGN_A + 1, "one name per launch kind");
+                                "sign_partial", "sign_apply", "gemm_f32_reduce"};
+  static_assert(sizeof(names) / sizeof(names[0]) == K_GEMM_SL + 1, "one name per launch kind");
   if (!plan || index < 0 || index >= (int)plan->tab.recs.size()) return nullptr;
   return names[plan->tab.recs[index].kind];
 }
@@ -638,7 +652,8 @@ kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, 
       case K_EA_TILES_BF: e = launch_ea_bf16_tiles_g((const EaTask*)tp, gm, r.blocks, s); break;
       case K_EA_FIN_BF: e = launch_ea_bf16_finalize_g((const EaTask*)tp, gm, r.blocks, s); break;
       case K_OMEGA: e = launch_omega_g((const OmegaTask*)tp, gm, r.blocks, s); break;
-      case K_GEMM: e = launch_gemm_g((const GemmP*)tp, gm, r.blocks, r.ta, r.tb, r.cfg, s); break;
+      case K_GEMM: e = launch_gemm_g((const GemmP*)tp, gm, r.blocks, r.ta, r.tb, r.cfg, r.split, s); break;
+      case K_GEMM_SL: e = launch_gemm_slices_g((const GemmP*)tp, gm, r.blocks, s); break;
       case K_BF16: e = launch_gemm_bf16_g((const BfGemmTask*)tp, gm, r.blocks, s); break;
       case K_SKINNY: e = launch_skinny_g((const SkinnyTask*)tp, gm, r.blocks, s); break;
       case K_SKINNY_R: e = launch_reduce_g((const ReduceTask*)tp, gm, r.blocks, s); break;
