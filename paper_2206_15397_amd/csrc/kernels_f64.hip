@@ -640,14 +640,33 @@ __device__ __forceinline__ void trtri_cols_body(const CholInvTask& q, int bx, in
   for (int e = tid; e < BC * BC; e += TT_NT) sm.Xc[k0 + e / BC][e % BC] = X[(long)(k0 + e / BC) * ldx + k0 + e % BC];
   const int tile = wave % NTILE, ks = wave / NTILE;
   const int rt = tile % CT, ct = tile / CT;
+  // block row I's operands (L_I,[K, I) and X_II) are loaded into registers one step
+  // ahead, while the MFMAs of the previous row run
+  constexpr int RL = BC * 288 / TT_NT;
+  static_assert(BC * BC == TT_NT, "one element of X_II per thread");
+  double rl[RL], rx = 0.0;
+  auto load = [&](int I) {
+    const int i0 = I * BC, w = i0 - k0;
+#pragma unroll
+    for (int u = 0; u < RL; ++u) {
+      const int e = tid + u * TT_NT;
+      const int r = e / w, cc = e - r * w;
+      rl[u] = (e < BC * w && i0 + r < n && k0 + cc < n) ? L[(long)(i0 + r) * ldg + k0 + cc] : 0.0;
+    }
+    rx = X[(long)(i0 + tid / BC) * ldx + i0 + tid % BC];
+  };
+  if (K + 1 < NB) load(K + 1);
   for (int I = K + 1; I < NB; ++I) {
     const int i0 = I * BC, w = i0 - k0;
-    for (int e = tid; e < BC * w; e += TT_NT) {
-      const int r = e / w, cc = e % w;
-      sm.Lr[r][cc] = (i0 + r < n && k0 + cc < n) ? L[(long)(i0 + r) * ldg + k0 + cc] : 0.0;
+#pragma unroll
+    for (int u = 0; u < RL; ++u) {
+      const int e = tid + u * TT_NT;
+      const int r = e / w, cc = e - r * w;
+      if (e < BC * w) sm.Lr[r][cc] = rl[u];
     }
-    for (int e = tid; e < BC * BC; e += TT_NT) sm.Xd[e / BC][e % BC] = X[(long)(i0 + e / BC) * ldx + i0 + e % BC];
+    sm.Xd[tid / BC][tid % BC] = rx;
     __syncthreads();
+    if (I + 1 < NB) load(I + 1);
     {
       f64x4 acc = {0, 0, 0, 0};
       for (int kk = 4 * ks; kk < w; kk += 4 * KS) {
