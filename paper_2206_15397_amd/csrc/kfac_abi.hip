@@ -135,13 +135,16 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
   // product).  For l <= 288 the Cholesky also forms L^{-1} and the product is a plain
   // fp64 MFMA GEMM (out of place, so the basis ends in *cur); larger l uses blocked
   // forward substitution in place.  `cur` points at the buffer holding Q afterwards.
+  // The orthonormalisations inside the power iteration take one pass (CholeskyQR): their
+  // basis only has to span the same range with full rank, and the next product and the
+  // final two-pass orthonormalisation restore orthonormality.
   float* cur = nullptr;
-  auto cholqr = [&](float* Yt, float* other, uint16_t* Qtb) -> hipError_t {
+  auto cholqr = [&](float* Yt, float* other, uint16_t* Qtb, int npass) -> hipError_t {
     hipError_t x;
     float* src = Yt;
     float* dst = other;
-    for (int pass = 0; pass < 2; ++pass) {
-      uint16_t* qb = (pass == 1) ? Qtb : nullptr;
+    for (int pass = 0; pass < npass; ++pass) {
+      uint16_t* qb = (pass == npass - 1) ? Qtb : nullptr;
       if ((x = launch_gram(src, ldt, src, ldt, L, dd, 1, w.part, w.G, L, st, s)) != hipSuccess) return x;
       if (L <= kCholInvMax) {
         if ((x = launch_cholinv(w.G, L, n, dd, w.Wc, L, L, w.Li, st, w.fail, s)) != hipSuccess) return x;
@@ -157,11 +160,11 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
   };
   // sketch Y = F Omega, then orthonormalise
   CK(f_times(w.OmT, w.OmTb, w.Yt));
-  CK(cholqr(w.Yt, w.Qt, bf ? w.Qtb : nullptr));
+  CK(cholqr(w.Yt, w.Qt, bf ? w.Qtb : nullptr, q > 0 ? 1 : 2));
   for (int it = 0; it < q; ++it) {
     float* spare = (cur == w.Yt) ? w.Qt : w.Yt;
     CK(f_times(cur, w.Qtb, spare));
-    CK(cholqr(spare, cur, bf ? w.Qtb : nullptr));
+    CK(cholqr(spare, cur, bf ? w.Qtb : nullptr, it + 1 < q ? 1 : 2));
   }
   float* Qt = cur;
   float* Wt = (cur == w.Yt) ? w.Qt : w.Yt;

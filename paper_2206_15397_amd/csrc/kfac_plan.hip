@@ -295,21 +295,28 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           add_gemm(P, T, gord, g, false, false, ws);
         }
         if (it > 0) for (int i : act) std::swap(basis[i], spare[i]);
-        // CholeskyQR2 on basis[i]: pass 0 basis -> spare, pass 1 spare -> basis
-        for (int pass = 0; pass < 2; ++pass) {
+        // CholeskyQR2 on basis[i] for the final basis (pass 0 basis -> spare, pass 1 spare ->
+        // basis); inside the power iteration one pass, basis -> spare, then swapped: the
+        // next product and the final two passes restore orthonormality
+        auto npass_of = [&](int i) { return it < P->fi[i].q ? 1 : 2; };
+        int npass_max = 1;
+        for (int i : act) npass_max = std::max(npass_max, npass_of(i));
+        for (int pass = 0; pass < npass_max; ++pass) {
           std::vector<GramP> gp;
           std::vector<CholInvTask> ch;
           std::vector<TrmmTask> tm;
           std::vector<int> gxg, nbg, gxr, nbr, gxc, nbc, gxt, nbt, gxi, nbi;
           Work wg, wr, wc, wi, wm;
           for (int i : act) {
+            const int npass = npass_of(i);
+            if (pass >= npass) continue;
             const FactorInfo& I = P->fi[i];
             const double l = I.l, d = I.d;
             wg += Work{l * (l + 1) * d, 4 * l * d};
             wr += Work{0, 8 * l * l};
             wc += Work{l * l * l / 3, 16 * l * l};       // Cholesky
             wi += Work{l * l * l / 3, 16 * l * l};       // triangular inverse
-            wm += Work{l * (l + 1) * d, 8 * l * d + 8 * l * l / 2 + ((bf && pass == 1) ? 2 * l * d : 0)};
+            wm += Work{l * (l + 1) * d, 8 * l * d + 8 * l * l / 2 + ((bf && pass == npass - 1) ? 2 * l * d : 0)};
             float* src = pass == 0 ? basis[i] : spare[i];
             float* dst = pass == 0 ? spare[i] : basis[i];
             GramP g = make_gram_task(src, I.ldt, src, I.ldt, I.l_pad, I.d, 1, W[i].part, W[i].G, I.l_pad, status);
@@ -320,7 +327,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             ch.push_back(c); gxc.push_back(1); nbc.push_back(1);
             gxi.push_back(trtri_col_blocks(I.l_pad)); nbi.push_back(trtri_col_blocks(I.l_pad));
             TrmmTask tt{W[i].Wc, I.l_pad, I.l, src, I.ldt, I.d, dst, I.ldt,
-                        (bf && pass == 1) ? W[i].Qtb : nullptr, I.ldt, I.l_pad};
+                        (bf && pass == npass - 1) ? W[i].Qtb : nullptr, I.ldt, I.l_pad};
             const int bx = trmm_blocks_x(I.d), by = trmm_blocks_y(I.l_pad);
             tm.push_back(tt); gxt.push_back(bx); nbt.push_back(bx * by);
           }
@@ -332,6 +339,8 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           T.add(K_TRTRI, ch, gxi, nbi, false, false, wi);
           T.add(K_TRMM, tm, gxt, nbt, false, false, wm);
         }
+        for (int i : act)
+          if (npass_of(i) == 1) std::swap(basis[i], spare[i]);   // the one-pass basis is in spare
       }
       // Rayleigh-Ritz: W = F Q into spare (fp32 tiles; split-bf16 in the bf16-sketch mode),
       // C = Q^T W (fp64) into G
