@@ -388,7 +388,8 @@ __device__ __forceinline__ void tri_prep_body(const EigTask& q, int, int) {
 
 // ======================================================================================
 // 3. Bisection.  Task j (one per row) = eigenvalue number j - blo[j] (ascending) of its
-// block; 16 lanes evaluate the Sturm count at 16 interior points of the bracket.
+// block; 16 lanes evaluate the Sturm count at 16 interior points of the bracket.  The
+// counts are monotone in the point, so one ballot locates the new bracket.
 // ======================================================================================
 __device__ __forceinline__ double fast_div(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);          // ~2^-26 relative, refined twice
@@ -439,24 +440,19 @@ __device__ __forceinline__ void tri_bisect_body(const EigTask& q, int bx, int) {
   const double pad = 4.0 * kEps * tn * (hi_i - lo_i) + 2.0 * pivmin;
   lo -= pad; hi += pad;
   const int base = (threadIdx.x & 63) & ~(BIS_LANES - 1);
+  // point p of the bracket; the bracket update evaluates the same expression
+  auto point = [&](double l, double wd, int p) { return l + wd * (double)(p + 1) / (double)(BIS_LANES + 1); };
   for (int it = 0; it < 40; ++it) {
     const double w = hi - lo;
     const bool done = !(w > 2.0 * kEps * (fabs(lo) + fabs(hi)) + 1e-3 * kEps * tn + 4.0 * pivmin);
-    const double x = lo + w * (double)(sub + 1) / (double)(BIS_LANES + 1);
+    const double x = point(lo, w, sub);
     const int c = (active && !done) ? sturm_block(d, e2, lo_i, hi_i, x, pivmin) : 0;
-    double nlo = lo, nhi = hi;
-#pragma unroll
-    for (int s = 0; s < BIS_LANES; ++s) {
-      const double xs = __shfl(x, base + s, 64);
-      const int cs = __shfl(c, base + s, 64);
-      if (cs <= target) nlo = xs;
-    }
-#pragma unroll
-    for (int s = BIS_LANES - 1; s >= 0; --s) {
-      const double xs = __shfl(x, base + s, 64);
-      const int cs = __shfl(c, base + s, 64);
-      if (cs >= target + 1) nhi = xs;
-    }
+    // the counts grow with the point: the number P of points with count <= target (one
+    // ballot) gives the new bracket [point P - 1, point P]
+    const unsigned long long bl = __ballot(c <= target);
+    const int P = __popcll((bl >> base) & ((1ull << BIS_LANES) - 1));
+    const double nlo = (P > 0) ? point(lo, w, P - 1) : lo;
+    const double nhi = (P < BIS_LANES) ? point(lo, w, P) : hi;
     if (__all(done || !active)) break;
     if (!done) { lo = nlo; hi = nhi; }
   }
