@@ -57,10 +57,13 @@ hipError_t launch_gram(const float* A, long lda, const float* B, long ldb, int L
 hipError_t launch_cholesky(const double* G, long ldg, int n, long m_rows, double* W, long ldw, double* Li,
                            int* status, int* fail_flag, hipStream_t s);
 constexpr int kCholInvMax = 288;   // blocked Cholesky-inverse path handles l_pad <= this
+// Second pass of CholeskyQR2 (skip != null): the pass is kept out (*skip = 1, Q copied by
+// launch_trmm) when the Gram of the first pass's basis is within kQrKeepTol of I.
+constexpr double kQrKeepTol = 5.9604644775390625e-08;   // 2^-24
 hipError_t launch_cholinv(double* G, long ldg, int n, long m_rows, double* Linv, long ldl, int l_pad, double* dsave,
-                          int* status, int* fail_flag, hipStream_t s);
+                          int* status, int* fail_flag, hipStream_t s, int* skip = nullptr, double tol = 0.0);
 hipError_t launch_trmm(const double* Li, long ldl, int n, const float* Yt, long ldy, int ncols, float* Qt, long ldq,
-                       uint16_t* Qtb, long ldqb, int l_pad, hipStream_t s);
+                       uint16_t* Qtb, long ldqb, int l_pad, hipStream_t s, const int* skip = nullptr);
 hipError_t launch_trsm(const double* W, long ldw, const double* Li, int n, int l_pad, const float* Yt,
                        long ldy, int ncols, float* Qt, long ldq, uint16_t* Qtb, long ldqb, hipStream_t s);
 size_t small_eig_scratch_doubles(int n, int r);

@@ -476,6 +476,25 @@ __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
   const int attempt = q.attempt;
   if (attempt == 1 && *q.fail_flag == 0) return;             // uniform
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = BC_NT / 64;
+  if (attempt == 0 && q.skip) {
+    // second pass of CholeskyQR2: the first pass's basis is kept when its Gram is I to tol
+    __shared__ int s_far;
+    if (tid == 0) s_far = 0;
+    __syncthreads();
+    bool far = false;
+    for (int e = tid; e < n * n; e += BC_NT) {
+      const int i = e / n, j = e % n;
+      if (i >= j && !(fabs(G[(long)i * ldg + j] - (i == j ? 1.0 : 0.0)) <= q.tol)) far = true;
+    }
+    if (far) s_far = 1;                                       // benign race: same value
+    __syncthreads();
+    const bool keep = (s_far == 0);
+    if (tid == 0) {
+      *q.skip = keep ? 1 : 0;
+      if (keep) *q.fail_flag = 0;
+    }
+    if (keep) return;                                         // uniform
+  }
   const int NB = l_pad / BC;
   // ---- set-up: save the diagonal (attempt 0) or restore G and shift it (attempt 1)
   if (attempt == 0) {
@@ -635,6 +654,7 @@ __device__ __forceinline__ void trtri_cols_body(const CholInvTask& q, int bx, in
   static_assert(NTILE * KS == 4, "four wavefronts");
   const int NB = l_pad / BC, K = bx;
   if (K >= NB - 1) return;                                     // uniform
+  if (q.skip && *q.skip) return;                               // pass kept (see cholinv)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int k0 = K * BC;
   for (int e = tid; e < BC * BC; e += TT_NT) sm.Xc[k0 + e / BC][e % BC] = X[(long)(k0 + e / BC) * ldx + k0 + e % BC];
@@ -725,6 +745,17 @@ __device__ __forceinline__ void trmm_body(const TrmmTask& q, int bx, int by) {
   const int a0 = by * GR_T, c0 = bx * GR_T;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
+  if (q.skip && *q.skip) {                                     // pass kept: Q^T = Y^T
+    for (int e = tid; e < GR_T * GR_T; e += 256) {
+      const int row = a0 + e / GR_T, col = c0 + e % GR_T;
+      if (row < l_pad && col < ncols) {
+        const float v = (row < n) ? Yt[(long)row * ldy + col] : 0.f;
+        Qt[(long)row * ldq + col] = v;
+        if (Qtb) Qtb[(long)row * ldqb + col] = f32_to_bf16_rne(v);
+      }
+    }
+    return;
+  }
   f64x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -857,8 +888,8 @@ hipError_t launch_cholesky(const double* G, long ldg, int n, long m_rows, double
 }
 
 hipError_t launch_cholinv(double* G, long ldg, int n, long m_rows, double* Linv, long ldl, int l_pad, double* dsave,
-                          int* status, int* fail_flag, hipStream_t s) {
-  CholInvTask q{G, ldg, n, m_rows, Linv, ldl, l_pad, dsave, status, fail_flag, 0};
+                          int* status, int* fail_flag, hipStream_t s, int* skip, double tol) {
+  CholInvTask q{G, ldg, n, m_rows, Linv, ldl, l_pad, dsave, status, fail_flag, 0, skip, tol};
   hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(BC_NT), 0, s, q);
   q.attempt = 1;
   hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(BC_NT), 0, s, q);
@@ -867,8 +898,8 @@ hipError_t launch_cholinv(double* G, long ldg, int n, long m_rows, double* Linv,
 }
 
 hipError_t launch_trmm(const double* Li, long ldl, int n, const float* Yt, long ldy, int ncols, float* Qt, long ldq,
-                       uint16_t* Qtb, long ldqb, int l_pad, hipStream_t s) {
-  TrmmTask q{Li, ldl, n, Yt, ldy, ncols, Qt, ldq, Qtb, ldqb, l_pad};
+                       uint16_t* Qtb, long ldqb, int l_pad, hipStream_t s, const int* skip) {
+  TrmmTask q{Li, ldl, n, Yt, ldy, ncols, Qt, ldq, Qtb, ldqb, l_pad, skip};
   dim3 grid((ncols + GR_T - 1) / GR_T, (l_pad + GR_T - 1) / GR_T);
   hipLaunchKernelGGL(k_trmm_f64, grid, dim3(256), 0, s, q);
   return hipGetLastError();

@@ -147,8 +147,10 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
       uint16_t* qb = (pass == npass - 1) ? Qtb : nullptr;
       if ((x = launch_gram(src, ldt, src, ldt, L, dd, 1, w.part, w.G, L, st, s)) != hipSuccess) return x;
       if (L <= kCholInvMax) {
-        if ((x = launch_cholinv(w.G, L, n, dd, w.Wc, L, L, w.Li, st, w.fail, s)) != hipSuccess) return x;
-        if ((x = launch_trmm(w.Wc, L, n, src, ldt, dd, dst, ldt, qb, ldt, L, s)) != hipSuccess) return x;
+        int* keep = (pass == 1) ? w.fail + 1 : nullptr;     // second pass: kept out when not needed
+        if ((x = launch_cholinv(w.G, L, n, dd, w.Wc, L, L, w.Li, st, w.fail, s, keep, kQrKeepTol)) != hipSuccess)
+          return x;
+        if ((x = launch_trmm(w.Wc, L, n, src, ldt, dd, dst, ldt, qb, ldt, L, s, keep)) != hipSuccess) return x;
         std::swap(src, dst);
       } else {
         if ((x = launch_cholesky(w.G, L, n, dd, w.Wc, L, w.Li, st, w.fail, s)) != hipSuccess) return x;

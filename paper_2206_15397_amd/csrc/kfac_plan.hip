@@ -323,11 +323,14 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             const int tiles = gram_tiles(I.l_pad, 1);
             gp.push_back(g); gxg.push_back(tiles); nbg.push_back(tiles * g.ksplit);
             gxr.push_back(tiles); nbr.push_back(tiles * gram_reduce_slices());
-            CholInvTask c{W[i].G, I.l_pad, I.l, I.d, W[i].Wc, I.l_pad, I.l_pad, W[i].Li, status, W[i].fail, 0};
+            // the second pass may be kept out (first pass already orthonormal to 2^-24)
+            int* keep = (pass == 1) ? W[i].fail + 1 : nullptr;
+            CholInvTask c{W[i].G, I.l_pad, I.l, I.d, W[i].Wc, I.l_pad, I.l_pad, W[i].Li, status, W[i].fail, 0,
+                          keep, kQrKeepTol};
             ch.push_back(c); gxc.push_back(1); nbc.push_back(1);
             gxi.push_back(trtri_col_blocks(I.l_pad)); nbi.push_back(trtri_col_blocks(I.l_pad));
             TrmmTask tt{W[i].Wc, I.l_pad, I.l, src, I.ldt, I.d, dst, I.ldt,
-                        (bf && pass == npass - 1) ? W[i].Qtb : nullptr, I.ldt, I.l_pad};
+                        (bf && pass == npass - 1) ? W[i].Qtb : nullptr, I.ldt, I.l_pad, keep};
             const int bx = trmm_blocks_x(I.d), by = trmm_blocks_y(I.l_pad);
             tm.push_back(tt); gxt.push_back(bx); nbt.push_back(bx * by);
           }

@@ -93,12 +93,16 @@ struct CholInvTask {     // blocked Cholesky + inverse of the l x l Gram (one bl
   double* Linv; long ldl; int l_pad;
   double* dsave;                             // n doubles: diagonal of G for the retry
   int* status; int* fail_flag; int attempt;
+  // second pass of CholeskyQR2: when the Gram is within tol of I (max entry deviation), set
+  // *skip and leave the first pass's basis as it is (null: always factor)
+  int* skip; double tol;
 };
 
 struct TrmmTask {        // Q^T = L^{-1} Y^T: block (column tile, row tile)
   const double* Li; long ldl; int n;
   const float* Yt; long ldy; int ncols;
   float* Qt; long ldq; uint16_t* Qtb; long ldqb; int l_pad;
+  const int* skip;       // set by the Cholesky of this pass: Q^T = Y^T (copy)
 };
 
 struct TriMeta {         // tridiagonal eigensolver state (see kernels_eig.hip)
