@@ -232,26 +232,31 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
 #pragma unroll
     for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][sk * 8] = col_of_block(v, c);
   };
-  auto mfma_stage = [&](int buf) {
+  // the 8 fragment reads of one 32-row half h2 of stage buffer buf
+  auto read_frags = [&](int buf, int h2, bf16x8 (&af)[2][4], bf16x8 (&bfr)[2][4]) {
     uint16_t (*A)[EB_SK] = sm.g.a[buf];
     uint16_t (*B)[EB_SK] = diag ? sm.g.a[buf] : sm.g.b[buf];
+    // logical 8-row chunk of the stage; column m of the tile keeps it at chunk
+    // q8 ^ ((m >> 3) & 7), and (m >> 3) & 7 = 2 i + bit 3 of the lane here
+    const int q8 = h2 * 4 + (lane >> 4), h = (lane >> 3) & 1;
 #pragma unroll
-    for (int kk = 0; kk < EB_BK; kk += 32) {
-      // logical 8-row chunk of the stage; column m of the tile keeps it at chunk
-      // q8 ^ ((m >> 3) & 7), and (m >> 3) & 7 = 2 i + bit 3 of the lane here
-      const int q8 = (kk >> 3) + (lane >> 4), h = (lane >> 3) & 1;
-      bf16x8 af[4], bfr[4];
+    for (int i = 0; i < 4; ++i)
+      af[h2][i] = __builtin_bit_cast(bf16x8, *(const uint4*)&A[wm * 64 + i * 16 + (lane & 15)][(q8 ^ (2 * i + h)) * 8]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        af[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&A[wm * 64 + i * 16 + (lane & 15)][(q8 ^ (2 * i + h)) * 8]);
+    for (int j = 0; j < 4; ++j)
+      bfr[h2][j] = __builtin_bit_cast(bf16x8, *(const uint4*)&B[wn * 64 + j * 16 + (lane & 15)][(q8 ^ (2 * j + h)) * 8]);
+  };
+  auto mfma_one = [&](const bf16x8 (&af)[2][4], const bf16x8 (&bfr)[2][4], int t) {
+    const int h2 = t >> 4, i = (t >> 2) & 3, j = t & 3;
+    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h2][i], bfr[h2][j], acc[i][j], 0, 0, 0);
+  };
+  auto mfma_stage = [&](int buf) {
+    bf16x8 af[2][4], bfr[2][4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bfr[j] = __builtin_bit_cast(bf16x8, *(const uint4*)&B[wn * 64 + j * 16 + (lane & 15)][(q8 ^ (2 * j + h)) * 8]);
+    for (int h2 = 0; h2 < 2; ++h2) {
+      read_frags(buf, h2, af, bfr);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      for (int t = 16 * h2; t < 16 * h2 + 16; ++t) mfma_one(af, bfr, t);
     }
   };
   // Both column panels of the tile hold no partial 8-column group (every group lies inside
@@ -264,26 +269,21 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
                      (long)(ke - kb) * ldx * 2 < (1L << 31);
   if (piped) {
     // Full 64-row stages, two stages in flight in registers (va, vb) while the MFMAs run
-    // on the LDS stage loaded before them.  A thread whose 8 columns lie beyond the
-    // activations reads columns 0-7 of its rows instead and masks the values to zero, plus
-    // the ones column when it falls in its group: every thread issues the same 8 loads per
-    // stage.
+    // on the LDS stage loaded before them.  Every thread issues the same 8 loads per stage
+    // and runs the same branch-free code: a thread whose 8 columns lie beyond the
+    // activations gets zeros from the buffer range check (its lane offset is past the
+    // end of the buffer), and the ones column, which then starts a group of its own
+    // (panel_clean), is set in the first transposed column of its thread.
     const int nfull = (ke - kb) / EB_BK;
     const bool in_x = c0 + 8 <= d_in;
     // buffer loads over the block's row slice: one lane offset for every load, the row
-    // in the scalar offset
+    // in the scalar offset; 2^31 is past the range (< 2^31 bytes), so those loads read 0
     const int row_bytes = (int)ldx * 2;
     const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(X + (long)kb * ldx), (short)0, (ke - kb) * row_bytes, 0x00020000);
-    const int vo = rg * 8 * row_bytes + (in_x ? c0 * 2 : 0);
-    const uint32_t m = opaque_mask(in_x);
-    uint4 o = make_uint4(0, 0, 0, 0);
-    if (ones && !in_x && d_in >= c0 && d_in < c0 + 8 && d_in < d) {
-      const int h = d_in - c0;                        // half index of the ones column
-      const uint32_t w1 = (h & 1) ? 0x3f800000u : 0x3f80u;
-      o = make_uint4(h >> 1 == 0 ? w1 : 0u, h >> 1 == 1 ? w1 : 0u, h >> 1 == 2 ? w1 : 0u, h >> 1 == 3 ? w1 : 0u);
-    }
-    uint4 va[8], vb[8];
+    const int vo = in_x ? rg * 8 * row_bytes + c0 * 2 : (int)0x80000000u;
+    const uint32_t w1 = (ones && c0 == d_in && d_in < d) ? 0x3f803f80u : 0u;
+    const uint4 o = make_uint4(w1, w1, w1, w1);
     auto fetch_full = [&](int k0, uint4 (&w)[8]) {
       typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
       const int so = (k0 - kb) * row_bytes;
@@ -293,43 +293,69 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
         w[r] = make_uint4(x.x, x.y, x.z, x.w);
       }
     };
-    // only a wave whose panel reaches past the activations has lanes to mask
-    const bool edge = (op ? J : I) * EB_BT + EB_BT > d_in;
-    auto stash_full = [&](uint4 (&w)[8], int buf) {
+    auto column = [&](const uint4 (&w)[8], int c) {
+      uint4 x = col_of_block(w, c);
+      if (c == 0) x = make_uint4(x.x | o.x, x.y | o.y, x.z | o.z, x.w | o.w);
+      return x;
+    };
+    // Every wave stashes (on a diagonal tile waves 2-3 fill the unused B buffer).
+    auto stash_full = [&](const uint4 (&w)[8], int buf) {
       uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf] : sm.g.a[buf];
-      if (edge) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          w[r] = and_mask(w[r], m);
-          w[r] = make_uint4(w[r].x | o.x, w[r].y | o.y, w[r].z | o.z, w[r].w | o.w);
+      for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][sk * 8] = column(w, c);
+    };
+    // One stage's MFMAs on buffer buf with the next stage (w) transposed into buffer
+    // buf ^ 1 between them, in an order that scheduling fences keep, so that the VALU and
+    // LDS work issues while the matrix core runs: the first half's 8 fragment reads; its
+    // 16 MFMAs with the v_perm of the transpose between them and the second half's reads
+    // behind the 12th (the fragments of rows 0-47 of the wave tile are dead by then); the
+    // second half's 16 MFMAs with the 8 LDS stores between them (after every read of the
+    // stage, which the compiler cannot prove disjoint from them).
+    auto stage_stash = [&](int buf, const uint4 (&w)[8]) {
+      bf16x8 af[2][4], bfr[2][4];
+      uint4 col[8];
+      read_frags(buf, 0, af, bfr);
+      uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf ^ 1] : sm.g.a[buf ^ 1];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        mfma_one(af, bfr, 2 * c);
+        mfma_one(af, bfr, 2 * c + 1);
+        col[c] = column(w, c);
+        if (c == 5) {
+          __builtin_amdgcn_sched_barrier(0);
+          read_frags(buf, 1, af, bfr);
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
-      for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][sk * 8] = col_of_block(w, c);
+      for (int c = 0; c < 8; ++c) {
+        mfma_one(af, bfr, 16 + 2 * c);
+        mfma_one(af, bfr, 16 + 2 * c + 1);
+        *(uint4*)&dst[cg * 8 + c][sk * 8] = col[c];
+        __builtin_amdgcn_sched_barrier(0);
+      }
     };
-    // Every wave issues the same loads whether it stashes or not, and a stage past the
-    // last full one re-reads the last full one: the number of loads in flight is then the
-    // same on every path, and a stash waits only for its own register set.
+    // A stage past the last full one re-reads the last full one: the number of loads in
+    // flight is then the same on every path, and a stash waits only for its own register
+    // set.
     auto stage_k = [&](int st) { return kb + (st < nfull ? st : nfull - 1) * EB_BK; };
     if (nfull > 0) {
+      uint4 va[8], vb[8];
       fetch_full(stage_k(0), va);
       fetch_full(stage_k(1), vb);
-      if (loader) stash_full(va, 0);
+      stash_full(va, 0);
       __syncthreads();
       fetch_full(stage_k(2), va);
       int s = 0;
       for (; s + 1 < nfull; s += 2) {
         // stage s on buffer 0 while stage s + 1 (vb) goes to buffer 1
-        mfma_stage(0);
-        __builtin_amdgcn_sched_barrier(0);
-        if (loader) stash_full(vb, 1);
+        stage_stash(0, vb);
         __syncthreads();
         fetch_full(stage_k(s + 3), vb);
         // stage s + 1 on buffer 1 while stage s + 2 (va) goes to buffer 0; past the last
         // full stage that copy is never read
-        mfma_stage(1);
-        __builtin_amdgcn_sched_barrier(0);
-        if (loader) stash_full(va, 0);
+        stage_stash(1, va);
         __syncthreads();
         fetch_full(stage_k(s + 4), va);
       }
