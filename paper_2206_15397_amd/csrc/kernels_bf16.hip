@@ -125,38 +125,45 @@ __device__ __forceinline__ void gemm_bf16_body(const BfGemmTask& q, int bx, int)
 // ------------------------------------------------------------------------------------
 // EA update from bf16 activations on bf16 MFMA: F <- rho F + c * Xh^T Xh (Alg. 1 EA lines),
 // upper 128 x 128 tiles, 4 waves of 64 x 64.  The contraction runs over the batch rows of
-// X, which are strided in memory, so each thread loads an 8 (rows) x 8 (columns) block
-// with 16-byte row loads, transposes it in registers and stores 8 column vectors of 8
-// consecutive rows into LDS (column-major tiles, k contiguous).  Every MFMA operand is then
-// one 16-byte LDS read.  Two LDS buffers: one barrier per 64-row step.
+// X, which are strided in memory: each thread loads an 8 (rows) x 8 (columns) block with
+// 16-byte row loads and stores the rows unchanged into LDS (row-major stage, 64 rows of
+// the tile's column panel); the MFMA operands, which need 8 consecutive rows of one
+// column per lane, come from gfx950's transposing LDS read (ds_read_b64_tr_b16: in each
+// group of 16 lanes, lanes 4r..4r+3 address row r of a 4 x 16 block and lane j receives
+// its column j), two per operand.  Two LDS buffers: one barrier per 64-row step.
 //   Loads: sixteen neighbouring lanes cover one 256-byte row segment of a panel, so each
 // load instruction touches few cache lines per lane group; full steps use buffer loads
 // with the row in the scalar offset and keep two steps in flight in registers.
-//   LDS: 144-byte column pitch plus an XOR swizzle of the 16-byte chunks (see sk below).
+//   LDS: 288-byte row pitch, so the four 32-byte row pieces of one transposing read land
+// on distinct banks; row stores are contiguous 256-byte segments.
 //   Order: tiles in 8 x 8 groups, and per XCD one contiguous share of every factor
 // (ea_tile, group_locate_xcd8), so the panels of concurrently running tiles meet in L2.
-constexpr int EB_BT = kEaBf16Tile, EB_BK = 64, EB_SK = EB_BK + 8;
+//   Two workgroups share a compute unit; each one's MFMAs fill the other's barrier and
+// load waits (one 8-wave workgroup on 256 x 128 pair tiles, which halves the L2 bytes per
+// flop, measured slower for that reason).
+constexpr int EB_BT = kEaBf16Tile, EB_BK = 64, EB_RP = EB_BT + 16;
 struct alignas(16) EbSmem {
   union {
     struct {
-      uint16_t a[2][EB_BT][EB_SK];
-      uint16_t b[2][EB_BT][EB_SK];
+      uint16_t a[2][EB_BK][EB_RP];
+      uint16_t b[2][EB_BK][EB_RP];
     } g;
     float t[EB_BT][EB_BT + 1];
   };
 };
 
-// Column c of the (row-major) 8 x 8 bf16 block held as v[row] (8 halves per uint4): each
-// output word takes the same half of one word of rows 2w and 2w + 1 (one v_perm_b32; byte
-// selectors 0-3 address the second operand, 4-7 the first).
-__device__ __forceinline__ uint32_t word_of(const uint4& x, int i) { return i == 0 ? x.x : i == 1 ? x.y : i == 2 ? x.z : x.w; }
-__device__ __forceinline__ uint4 col_of_block(const uint4 v[8], int c) {
-  const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
-  const int wi = c >> 1;
-  return make_uint4(__builtin_amdgcn_perm(word_of(v[1], wi), word_of(v[0], wi), sel),
-                    __builtin_amdgcn_perm(word_of(v[3], wi), word_of(v[2], wi), sel),
-                    __builtin_amdgcn_perm(word_of(v[5], wi), word_of(v[4], wi), sel),
-                    __builtin_amdgcn_perm(word_of(v[7], wi), word_of(v[6], wi), sel));
+typedef short eb_s4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) eb_s4 eb_lds_s4;
+// 8 consecutive rows (k0 .. k0+7 for lane group g = lane / 16) of column m0 + lane % 16 of
+// a row-major LDS stage, as one MFMA operand: two transposing reads of 4 rows each.
+__device__ __forceinline__ bf16x8 eb_tr_frag(const uint16_t (*P)[EB_RP], int k0, int m0, int lane) {
+  const int g = lane >> 4, r = (lane >> 2) & 3, q = lane & 3;
+  const uint16_t* p = &P[k0 + 8 * g + r][m0 + 4 * q];
+  const eb_s4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((eb_lds_s4*)p);
+  const eb_s4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((eb_lds_s4*)(p + 4 * EB_RP));
+  typedef short s8 __attribute__((ext_vector_type(8)));
+  const s8 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(bf16x8, v);
 }
 
 // Rows [k0, k0+8) x columns [c0, c0+8) of Xh (bf16, ones column appended at d_in when
@@ -201,13 +208,9 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
   const uint16_t* X = p.Ab;
   const long ldx = p.lda;
   const bool vec = ((ldx & 7) == 0) && ((((uintptr_t)X) & 15) == 0);
-  // loader role: threads 0..127 fill the A tile (columns of block I), 128..255 the B tile
+  // loader role: threads 0..127 fill the A panel (columns of block I), 128..255 the B
+  // panel; thread (cg, rg) holds rows rg*8 .. rg*8+7 of columns cg*8 .. cg*8+7
   const int op = wave >> 1, tt = tid & 127, cg = tt & 15, rg = tt >> 4;   // op: wave-uniform
-  // LDS chunk of the thread's 8 rows: chunk rg of tile column cg * 8 + c sits at chunk
-  // rg ^ (cg & 7) of that 144-byte column.  LDS serves 16-byte accesses eight lanes at a
-  // time; eight lanes that store the same chunk of 8 columns 8 apart, and eight lanes
-  // that read one chunk of 8 neighbouring columns, then all land on distinct banks.
-  const int sk = rg ^ (cg & 7);
   const bool loader = !(diag && op == 1);
   const int c0 = (op ? J : I) * EB_BT + cg * 8;
   f32x4 acc[4][4];
@@ -228,23 +231,18 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
     }
   };
   auto stash = [&](int buf) {
-    uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf] : sm.g.a[buf];
+    uint16_t (*dst)[EB_RP] = op ? sm.g.b[buf] : sm.g.a[buf];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][sk * 8] = col_of_block(v, c);
+    for (int r = 0; r < 8; ++r) *(uint4*)&dst[rg * 8 + r][cg * 8] = v[r];
   };
-  // the 8 fragment reads of one 32-row half h2 of stage buffer buf
+  // the 8 operand reads of one 32-row half h2 of stage buffer buf
   auto read_frags = [&](int buf, int h2, bf16x8 (&af)[2][4], bf16x8 (&bfr)[2][4]) {
-    uint16_t (*A)[EB_SK] = sm.g.a[buf];
-    uint16_t (*B)[EB_SK] = diag ? sm.g.a[buf] : sm.g.b[buf];
-    // logical 8-row chunk of the stage; column m of the tile keeps it at chunk
-    // q8 ^ ((m >> 3) & 7), and (m >> 3) & 7 = 2 i + bit 3 of the lane here
-    const int q8 = h2 * 4 + (lane >> 4), h = (lane >> 3) & 1;
+    const uint16_t (*A)[EB_RP] = sm.g.a[buf];
+    const uint16_t (*B)[EB_RP] = diag ? sm.g.a[buf] : sm.g.b[buf];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      af[h2][i] = __builtin_bit_cast(bf16x8, *(const uint4*)&A[wm * 64 + i * 16 + (lane & 15)][(q8 ^ (2 * i + h)) * 8]);
+    for (int i = 0; i < 4; ++i) af[h2][i] = eb_tr_frag(A, h2 * 32, wm * 64 + i * 16, lane);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      bfr[h2][j] = __builtin_bit_cast(bf16x8, *(const uint4*)&B[wn * 64 + j * 16 + (lane & 15)][(q8 ^ (2 * j + h)) * 8]);
+    for (int j = 0; j < 4; ++j) bfr[h2][j] = eb_tr_frag(B, h2 * 32, wn * 64 + j * 16, lane);
   };
   auto mfma_one = [&](const bf16x8 (&af)[2][4], const bf16x8 (&bfr)[2][4], int t) {
     const int h2 = t >> 4, i = (t >> 2) & 3, j = t & 3;
@@ -282,8 +280,9 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
     const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(X + (long)kb * ldx), (short)0, (ke - kb) * row_bytes, 0x00020000);
     const int vo = in_x ? rg * 8 * row_bytes + c0 * 2 : (int)0x80000000u;
-    const uint32_t w1 = (ones && c0 == d_in && d_in < d) ? 0x3f803f80u : 0u;
-    const uint4 o = make_uint4(w1, w1, w1, w1);
+    // the ones column, when it starts this thread's (otherwise zero) group: the first
+    // half of every row
+    const uint32_t o1 = (ones && c0 == d_in && d_in < d) ? 0x3f80u : 0u;
     auto fetch_full = [&](int k0, uint4 (&w)[8]) {
       typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
       const int so = (k0 - kb) * row_bytes;
@@ -293,35 +292,27 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
         w[r] = make_uint4(x.x, x.y, x.z, x.w);
       }
     };
-    auto column = [&](const uint4 (&w)[8], int c) {
-      uint4 x = col_of_block(w, c);
-      if (c == 0) x = make_uint4(x.x | o.x, x.y | o.y, x.z | o.z, x.w | o.w);
-      return x;
-    };
     // Every wave stashes (on a diagonal tile waves 2-3 fill the unused B buffer).
     auto stash_full = [&](const uint4 (&w)[8], int buf) {
-      uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf] : sm.g.a[buf];
+      uint16_t (*dst)[EB_RP] = op ? sm.g.b[buf] : sm.g.a[buf];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) *(uint4*)&dst[cg * 8 + c][sk * 8] = column(w, c);
+      for (int r = 0; r < 8; ++r) *(uint4*)&dst[rg * 8 + r][cg * 8] = make_uint4(w[r].x | o1, w[r].y, w[r].z, w[r].w);
     };
-    // One stage's MFMAs on buffer buf with the next stage (w) transposed into buffer
-    // buf ^ 1 between them, in an order that scheduling fences keep, so that the VALU and
-    // LDS work issues while the matrix core runs: the first half's 8 fragment reads; its
-    // 16 MFMAs with the v_perm of the transpose between them and the second half's reads
-    // behind the 12th (the fragments of rows 0-47 of the wave tile are dead by then); the
-    // second half's 16 MFMAs with the 8 LDS stores between them (after every read of the
-    // stage, which the compiler cannot prove disjoint from them).
+    // One stage's MFMAs on buffer buf with the next stage (w) stored into buffer buf ^ 1
+    // between them, in an order that scheduling fences keep: the first half's 8 operand
+    // reads; its 16 MFMAs with the second half's reads behind the 12th (the operands of
+    // rows 0-47 of the wave tile are dead by then); the second half's 16 MFMAs with the 8
+    // row stores between them (after every read of the stage, which the compiler cannot
+    // prove disjoint from them).
     auto stage_stash = [&](int buf, const uint4 (&w)[8]) {
       bf16x8 af[2][4], bfr[2][4];
-      uint4 col[8];
       read_frags(buf, 0, af, bfr);
-      uint16_t (*dst)[EB_SK] = op ? sm.g.b[buf ^ 1] : sm.g.a[buf ^ 1];
+      uint16_t (*dst)[EB_RP] = op ? sm.g.b[buf ^ 1] : sm.g.a[buf ^ 1];
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         mfma_one(af, bfr, 2 * c);
         mfma_one(af, bfr, 2 * c + 1);
-        col[c] = column(w, c);
         if (c == 5) {
           __builtin_amdgcn_sched_barrier(0);
           read_frags(buf, 1, af, bfr);
@@ -329,10 +320,10 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        mfma_one(af, bfr, 16 + 2 * c);
-        mfma_one(af, bfr, 16 + 2 * c + 1);
-        *(uint4*)&dst[cg * 8 + c][sk * 8] = col[c];
+      for (int r = 0; r < 8; ++r) {
+        mfma_one(af, bfr, 16 + 2 * r);
+        mfma_one(af, bfr, 16 + 2 * r + 1);
+        *(uint4*)&dst[rg * 8 + r][cg * 8] = make_uint4(w[r].x | o1, w[r].y, w[r].z, w[r].w);
         __builtin_amdgcn_sched_barrier(0);
       }
     };
