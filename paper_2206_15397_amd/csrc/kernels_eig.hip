@@ -391,9 +391,11 @@ __device__ __forceinline__ void tri_prep_body(const EigTask& q, int, int) {
 // block; 16 lanes evaluate the Sturm count at 16 interior points of the bracket.  The
 // counts are monotone in the point, so one ballot locates the new bracket.
 // ======================================================================================
+// a / b from the hardware reciprocal (about 2^-26 relative) and one Newton step (relative
+// error then about 2^-52 plus rounding): a Sturm count only needs each pivot to a few ulps,
+// which perturbs the tridiagonal matrix by as much (backward stable recurrence)
 __device__ __forceinline__ double fast_div(double a, double b) {
-  double r = __builtin_amdgcn_rcp(b);          // ~2^-26 relative, refined twice
-  r = r * fma(-b, r, 2.0);
+  double r = __builtin_amdgcn_rcp(b);
   r = r * fma(-b, r, 2.0);
   return a * r;
 }
@@ -403,6 +405,7 @@ __device__ int sturm_block(const double* d, const double* e2, int lo, int hi, do
   double q = d[lo] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += (q < 0.0);
+#pragma unroll 4
   for (int i = lo + 1; i < hi; ++i) {
     q = (d[i] - x) - fast_div(e2[i - 1], q);
     if (fabs(q) < pivmin) q = -pivmin;
