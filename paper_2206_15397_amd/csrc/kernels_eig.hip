@@ -714,7 +714,27 @@ __device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int
   const int r = q.r; float* P = q.P; const long ldp = q.ldp;
   constexpr int CH = 16;                      // reflectors staged per LDS chunk
   constexpr int PER = (NMAX + 63) / 64;
-  __shared__ double vch[CH][PER * 64];
+  // A chunk (reflectors klo .. klo + cnt - 1) is one contiguous run of cnt * n doubles of V:
+  // it is copied flat (row pitch n in LDS), every thread's loads in flight together, and
+  // the next chunk's loads go out before the current chunk is applied.
+  constexpr int CPT = (CH * NMAX + 255) / 256;
+  __shared__ double vch[CH * NMAX];
+  double pre[CPT];
+  auto load_chunk = [&](int klo, int cnt) {
+    const double* src = V + (long)klo * n;
+#pragma unroll
+    for (int t = 0; t < CPT; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      pre[t] = (e < cnt * n) ? src[e] : 0.0;
+    }
+  };
+  auto store_chunk = [&](int cnt) {
+#pragma unroll
+    for (int t = 0; t < CPT; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      if (e < cnt * n) vch[e] = pre[t];
+    }
+  };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c0 = (bx * 4 + wave) * NC;
   double z[NC][PER];
@@ -733,17 +753,19 @@ __device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int
 #pragma unroll
     for (int u = 0; u < PER; ++u) z[j][u] *= sc;
   }
+  if (n - 3 >= 0) load_chunk(max(0, n - 3 - CH + 1), n - 3 - max(0, n - 3 - CH + 1) + 1);
   for (int kt = n - 3; kt >= 0; kt -= CH) {
     const int klo = max(0, kt - CH + 1);
     const int cnt = kt - klo + 1;
+    __syncthreads();                          // the previous chunk's readers are done
+    store_chunk(cnt);
     __syncthreads();
-    for (int e = threadIdx.x; e < cnt * n; e += blockDim.x) {
-      const int rr = e / n, ii = e % n;
-      vch[rr][ii] = V[(long)(klo + rr) * n + ii];
+    if (kt - CH >= 0) {
+      const int nlo = max(0, kt - CH - CH + 1);
+      load_chunk(nlo, kt - CH - nlo + 1);
     }
-    __syncthreads();
     for (int k = kt; k >= klo; --k) {
-      const double* vk = vch[k - klo];
+      const double* vk = vch + (k - klo) * n;
       double vv[PER];
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
