@@ -529,11 +529,15 @@ __device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
   double* L = sL[tid];
   double* Dp = sD[tid];
   // forward
+  // divisions by the pivots: hardware reciprocal + one Newton step (about 2^-52 relative,
+  // a rounding-sized perturbation of each pivot); loops unrolled so that the loads of d
+  // and e go out ahead of the dependent recurrence
   double dp = diag[b0] - lam;
+#pragma unroll 4
   for (int i = b0; i + 1 < b1; ++i) {
     if (fabs(dp) < tiny) dp = (dp < 0.0) ? -tiny : tiny;
     const double e = m.es[i];
-    const double l = e / dp;
+    const double l = fast_div(e, dp);
     L[i - b0] = l;
     Dp[i - b0] = dp;
     dp = (diag[i + 1] - lam) - l * e;
@@ -543,10 +547,11 @@ __device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
   double dm = diag[b1 - 1] - lam;
   double best = fabs(dp);   // gamma_{b1-1} = D+_{b1-1}
   int kstar = b1 - 1;
+#pragma unroll 4
   for (int i = b1 - 2; i >= b0; --i) {
     if (fabs(dm) < tiny) dm = (dm < 0.0) ? -tiny : tiny;
     const double e = m.es[i];
-    const double u = e / dm;
+    const double u = fast_div(e, dm);
     const double dmi = (diag[i] - lam) - u * e;
     const double g = Dp[i - b0] + dmi - (diag[i] - lam);
     Dp[i - b0] = u;           // slot i now holds U_i
@@ -558,11 +563,13 @@ __device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
   for (int i = b1; i < n; ++i) Z[(long)i * ldz + k] = 0.0;
   double z = 1.0;
   Z[(long)kstar * ldz + k] = 1.0;
+#pragma unroll 4
   for (int i = kstar - 1; i >= b0; --i) {
     z = -L[i - b0] * z;
     Z[(long)i * ldz + k] = z;
   }
   z = 1.0;
+#pragma unroll 4
   for (int i = kstar; i + 1 < b1; ++i) {
     z = -Dp[i - b0] * z;
     Z[(long)(i + 1) * ldz + k] = z;
