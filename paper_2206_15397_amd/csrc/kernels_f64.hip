@@ -481,10 +481,18 @@ __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
     __shared__ int s_far;
     if (tid == 0) s_far = 0;
     __syncthreads();
+    // lower triangle, a row per wave and a column per lane, the loads of several rows in
+    // flight together (n <= kCholInvMax)
     bool far = false;
-    for (int e = tid; e < n * n; e += BC_NT) {
-      const int i = e / n, j = e % n;
-      if (i >= j && !(fabs(G[(long)i * ldg + j] - (i == j ? 1.0 : 0.0)) <= q.tol)) far = true;
+    constexpr int PERC = (kCholInvMax + 63) / 64;
+#pragma unroll 3
+    for (int i = wave; i < n; i += nw) {
+      const double* row = G + (long)i * ldg;
+#pragma unroll
+      for (int u = 0; u < PERC; ++u) {
+        const int j = lane + 64 * u;
+        if (j <= i && !(fabs(row[j] - (i == j ? 1.0 : 0.0)) <= q.tol)) far = true;
+      }
     }
     if (far) s_far = 1;                                       // benign race: same value
     __syncthreads();
