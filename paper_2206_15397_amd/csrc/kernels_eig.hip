@@ -369,20 +369,33 @@ __device__ __forceinline__ void tri_prep_body(const EigTask& q, int, int) {
   }
   __syncthreads();
   const double tn = ssh[0];
-  for (int i = tid; i < n; i += blockDim.x) {
-    double e = (i + 1 < n) ? off[i] : 0.0;
-    if (fabs(e) <= 2.0 * kEps * tn) e = 0.0;
-    m.es[i] = e;
+  // unreduced blocks: row i ends a block when i = n - 1 or its (negligible) off-diagonal
+  // was set to zero.  The end flags go into 64-bit words (one ballot per wavefront), and
+  // every row finds the nearest ends below and at or above it a word at a time.
+  __shared__ unsigned long long wend[(KFAC_MAX_SKETCH + 63) / 64];
+  for (int i0 = 0; i0 < n; i0 += blockDim.x) {               // uniform: ballots
+    const int i = i0 + tid;
+    bool f = false;
+    if (i < n) {
+      double e = (i + 1 < n) ? off[i] : 0.0;
+      if (fabs(e) <= 2.0 * kEps * tn) e = 0.0;
+      m.es[i] = e;
+      f = (i == n - 1 || e == 0.0);
+    }
+    const unsigned long long b = __ballot(f);
+    if (lane == 0 && i0 + 64 * wave < n) wend[(i0 >> 6) + wave] = b;
   }
   __syncthreads();
-  if (tid == 0) {
-    int lo = 0;
-    for (int i = 0; i < n; ++i) {
-      if (i == n - 1 || m.es[i] == 0.0) {
-        for (int j = lo; j <= i; ++j) { m.blo[j] = lo; m.bhi[j] = i + 1; }
-        lo = i + 1;
-      }
-    }
+  for (int i = tid; i < n; i += blockDim.x) {
+    int w = i >> 6;
+    unsigned long long mk = wend[w] & ((1ull << (i & 63)) - 1);   // ends before row i
+    while (mk == 0 && w > 0) mk = wend[--w];
+    const int lo = mk ? 64 * w + 64 - __clzll(mk) : 0;
+    w = i >> 6;
+    mk = wend[w] & ~((1ull << (i & 63)) - 1);                     // ends at or after row i
+    while (mk == 0) mk = wend[++w];                               // row n - 1 ends the last
+    m.blo[i] = lo;
+    m.bhi[i] = 64 * w + __ffsll((long long)mk);
   }
 }
 

@@ -172,6 +172,32 @@ def test_rand_eig_repeated_eigenvalues_exact_regime():
     np.testing.assert_allclose(Ug[:, :6] @ Ug[:, :6].T, R[:, :6] @ R[:, :6].T, atol=1e-5)
 
 
+@pytest.mark.parametrize("sizes", [[1] * 200, [70, 70, 60], [64, 1, 63, 72]])
+def test_rand_eig_exact_regime_split_tridiagonal(sizes):
+    """F = blockdiag(B_1, ..., B_m) in the exact regime (l = d): the Householder reduction
+    keeps the blocks apart, so the tridiagonal splits into unreduced blocks at the block
+    boundaries (every row for the diagonal case, and boundaries on both sides of the 64-row
+    words the block search works in).  Eigenvalues against LAPACK, orthonormal vectors and
+    the eigen-residual."""
+    d = sum(sizes)
+    rng = np.random.default_rng(7)
+    F = np.zeros((d, d))
+    o = 0
+    for i, b in enumerate(sizes):
+        F[o:o + b, o:o + b] = synth.psd_factor(b, rng.uniform(0.5, 2.0, b), 11 + i)
+        o += b
+    F = F.astype(np.float32)
+    r = d - 10
+    U, D, st = K().rand_eig(torch.from_numpy(F).to(DEV), r, 10, 0, seed=0)
+    torch.cuda.synchronize()
+    Ug, Dg = to_np(U).astype(np.float64), to_np(D).astype(np.float64)
+    ref = np.sort(np.linalg.eigvalsh(F.astype(np.float64)))[::-1][:r]
+    np.testing.assert_allclose(Dg, ref, rtol=1e-5)
+    assert np.abs(Ug.T @ Ug - np.eye(r)).max() < 1e-5
+    res = F.astype(np.float64) @ Ug - Ug * Dg
+    assert np.linalg.norm(res) <= 1e-5 * np.linalg.norm(F.astype(np.float64)) * np.sqrt(r)
+
+
 @pytest.mark.parametrize("d,k,p,q", [(300, 20, 22, 1), (700, 37, 50, 0), (100, 5, 90, 1)])
 def test_rand_eig_rank_deficient_takes_shifted_retry(d, k, p, q):
     """F = blockdiag(A_k, 0): the sketch has exactly k nonzero rows, so every Gram in
