@@ -208,6 +208,7 @@ __device__ __forceinline__ void sign_partial_body(const SignTask& q, int bx, int
   float best = -1.f, bval = 0.f;
   int bidx = 0x7fffffff;
   if (c < r) {
+#pragma unroll 8
     for (int i = r0 + rg; i < r1; i += 4) {
       const float v = U[(long)i * ldu + c];
       if (fabsf(v) > best) { best = fabsf(v); bval = v; bidx = i; }
@@ -251,6 +252,7 @@ __device__ __forceinline__ void sign_apply_body(const SignTask& q, int bx, int b
   __syncthreads();
   if (c >= r || ssgn[cl] > 0.f) return;
   const int r0 = chunk * SG_ROWS, r1 = min(d, r0 + SG_ROWS);
+#pragma unroll 8
   for (int i = r0 + rg; i < r1; i += 4) U[(long)i * ldu + c] = -U[(long)i * ldu + c];
 }
 
