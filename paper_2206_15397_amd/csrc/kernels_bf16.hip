@@ -139,8 +139,8 @@ __device__ __forceinline__ void gemm_bf16_body(const BfGemmTask& q, int bx, int)
 //   Order: tiles in 8 x 8 groups, and per XCD one contiguous share of every factor
 // (ea_tile, group_locate_xcd8), so the panels of concurrently running tiles meet in L2.
 //   Two workgroups share a compute unit; each one's MFMAs fill the other's barrier and
-// load waits (one 8-wave workgroup on 256 x 128 pair tiles, which halves the L2 bytes per
-// flop, measured slower for that reason).
+// load waits (one 8-wave workgroup on 256 x 128 pair tiles, which reads a quarter fewer L2
+// bytes per flop, measured slower for that reason).
 constexpr int EB_BT = kEaBf16Tile, EB_BK = 64, EB_RP = EB_BT + 16;
 struct alignas(16) EbSmem {
   union {
