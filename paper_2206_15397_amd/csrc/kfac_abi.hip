@@ -162,11 +162,12 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
   };
   // sketch Y = F Omega, then orthonormalise
   CK(f_times(w.OmT, w.OmTb, w.Yt));
-  CK(cholqr(w.Yt, w.Qt, bf ? w.Qtb : nullptr, q > 0 ? 1 : 2));
+  // the bf16 copy of Q only where another bf16 product follows
+  CK(cholqr(w.Yt, w.Qt, (bf && q > 0) ? w.Qtb : nullptr, q > 0 ? 1 : 2));
   for (int it = 0; it < q; ++it) {
     float* spare = (cur == w.Yt) ? w.Qt : w.Yt;
     CK(f_times(cur, w.Qtb, spare));
-    CK(cholqr(spare, cur, bf ? w.Qtb : nullptr, it + 1 < q ? 1 : 2));
+    CK(cholqr(spare, cur, (bf && it + 1 < q) ? w.Qtb : nullptr, it + 1 < q ? 1 : 2));
   }
   float* Qt = cur;
   float* Wt = (cur == w.Yt) ? w.Qt : w.Yt;

@@ -316,7 +316,10 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             wr += Work{0, 8 * l * l};
             wc += Work{l * l * l / 3, 16 * l * l};       // Cholesky
             wi += Work{l * l * l / 3, 16 * l * l};       // triangular inverse
-            wm += Work{l * (l + 1) * d, 8 * l * d + 8 * l * l / 2 + ((bf && pass == npass - 1) ? 2 * l * d : 0)};
+            // the bf16 copy of Q only where a bf16 power-iteration product follows (the
+            // Rayleigh-Ritz product and U = QP take the fp32 basis)
+            const bool qb = bf && pass == npass - 1 && it < I.q;
+            wm += Work{l * (l + 1) * d, 8 * l * d + 8 * l * l / 2 + (qb ? 2 * l * d : 0)};
             float* src = pass == 0 ? basis[i] : spare[i];
             float* dst = pass == 0 ? spare[i] : basis[i];
             GramP g = make_gram_task(src, I.ldt, src, I.ldt, I.l_pad, I.d, 1, W[i].part, W[i].G, I.l_pad, status);
@@ -330,7 +333,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
             ch.push_back(c); gxc.push_back(1); nbc.push_back(1);
             gxi.push_back(trtri_col_blocks(I.l_pad)); nbi.push_back(trtri_col_blocks(I.l_pad));
             TrmmTask tt{W[i].Wc, I.l_pad, I.l, src, I.ldt, I.d, dst, I.ldt,
-                        (bf && pass == npass - 1) ? W[i].Qtb : nullptr, I.ldt, I.l_pad, keep};
+                        qb ? W[i].Qtb : nullptr, I.ldt, I.l_pad, keep};
             const int bx = trmm_blocks_x(I.d), by = trmm_blocks_y(I.l_pad);
             tm.push_back(tt); gxt.push_back(bx); nbt.push_back(bx * by);
           }
