@@ -215,9 +215,10 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       Work wo;
       for (int i : rnd) {
         const FactorInfo& I = P->fi[i];
-        wo += Work{0, (double)I.l * I.d * (bf ? 6 : 4)};
-        OmegaTask q = make_omega_task(I.d, I.l, I.d, I.l_pad, P->seed, P->f[i].stream_id, P->inv, W[i].OmT, I.ldt,
-                                      bf ? W[i].OmTb : nullptr, nullptr, 0, nullptr);
+        // bf16-sketch mode: the sketch reads only the bf16 copy of Omega^T
+        wo += Work{0, (double)I.l * I.d * (bf ? 2 : 4)};
+        OmegaTask q = make_omega_task(I.d, I.l, I.d, I.l_pad, P->seed, P->f[i].stream_id, P->inv,
+                                      bf ? nullptr : W[i].OmT, I.ldt, bf ? W[i].OmTb : nullptr, nullptr, 0, nullptr);
         dim3 g = omega_grid(q);
         om.push_back(q); gx.push_back((int)g.x); nb.push_back((int)(g.x * g.y));
       }
