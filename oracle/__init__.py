@@ -10,7 +10,7 @@ Randomized Numerical Linear Algebra", arXiv 2206.15397):
 * the exponential-average K-factor update (Algorithm 1, forward and backward EA lines;
   matrix form of Section 3),
 * the Gaussian test matrix, range finder with power iterations, SREVD (Algorithm 3) and
-  RSVD (Algorithm 2, using the V factor as Section 2.3.1 recommends),
+  RSVD (Algorithm 2, using the V factor as Section 2.2.2 recommends),
 * the damped low-rank inverse application (Section 4.1, the identity for
   (U D U^T + lambda I)^{-1} V, used by Algorithms 4 and 5),
 * a cyclic Jacobi full eigendecomposition (plain C, ``jacobi.c``).

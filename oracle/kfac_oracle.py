@@ -8,7 +8,7 @@ Section / algorithm references are to Puiu, arXiv 2206.15397:
   Alg. 3   symmetric randomized EVD (SREVD)
   Alg. 4/5 RS-KFAC / SRE-KFAC per-layer loops
   Sec. 2.2 power iterations ("n_pwr-it")
-  Sec. 2.3.1 use of the V factor of RSVD for symmetric PSD matrices
+  Sec. 2.2.2 use of the V factor of RSVD for symmetric PSD matrices
   Sec. 3   matrix form of the EA and Proposition 3.1
   Sec. 4.1 identity (U D U^T + lam I)^{-1} V = U[(D + lam I)^{-1} - I/lam]U^T V + V/lam
 """
@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "philox4x32_10", "uniforms_from_words", "gaussian_test_matrix", "ea_update",
-    "philox_words_for", "householder_qr", "jacobi_eig", "jacobi_svd", "sign_normalize", "range_finder",
+    "philox_words_for", "philox_words_at", "householder_qr", "jacobi_eig", "jacobi_svd", "sign_normalize", "range_finder",
     "srevd", "rsvd", "damping_weights", "precondition", "exact_precondition",
     "prop31_r_eps", "prop31_max_modes", "full_eig", "kfactor_step", "oracle_library_path",
     "linear_forward", "linear_backward",
@@ -87,11 +87,7 @@ def philox4x32_10(ctr: np.ndarray, key) -> np.ndarray:
 
     One round maps (c0, c1, c2, c3) to (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2),
     hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)); between rounds the key is bumped by the Weyl
-    constants (W0, W1).
-
-    Parity unpinned against the generator's published known-answer vectors (none are
-    available offline): the words are pinned by CPU/GPU bit equality, counter
-    separation and the moment / distribution tests of the Gaussians built from them."""
+    constants (W0, W1).  Pinned to the generator's published known-answer vectors."""
     c = np.array(ctr, dtype=np.uint64) & _MASK32
     k0 = np.uint64(int(key[0]) & _MASK32)
     k1 = np.uint64(int(key[1]) & _MASK32)
@@ -114,18 +110,25 @@ def uniforms_from_words(w: np.ndarray) -> np.ndarray:
     return ((w.astype(np.uint64) >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
 
 
-def philox_words_for(d: int, l: int, seed: int, stream_id: int, inversion_index: int) -> np.ndarray:
-    """Raw 32-bit words for rows 0..d-1 and column groups 0..ceil(l/4)-1: (d, G, 4)."""
-    groups = (l + 3) // 4
-    i = np.arange(d, dtype=np.uint64)[:, None]
-    g = np.arange(groups, dtype=np.uint64)[None, :]
-    ctr = np.zeros((d, groups, 4), dtype=np.uint64)
+def philox_words_at(rows, groups, seed: int, stream_id: int, inversion_index: int) -> np.ndarray:
+    """Raw 32-bit words of Omega's draw for the given row indices and column groups
+    (a group is four consecutive columns): (len(rows), len(groups), 4).  The counter of
+    (row i, group g) is (i, g, stream_id mod 2^32, inversion_index) and the key is
+    (seed mod 2^32, seed >> 32)."""
+    i = np.asarray(rows, dtype=np.uint64).reshape(-1)[:, None]
+    g = np.asarray(groups, dtype=np.uint64).reshape(-1)[None, :]
+    ctr = np.zeros((i.shape[0], g.shape[1], 4), dtype=np.uint64)
     ctr[..., 0] = i
     ctr[..., 1] = g
     ctr[..., 2] = np.uint64(int(stream_id) & _MASK32)
     ctr[..., 3] = np.uint64(int(inversion_index) & _MASK32)
     key = (int(seed) & _MASK32, (int(seed) >> 32) & _MASK32)
     return philox4x32_10(ctr, key)
+
+
+def philox_words_for(d: int, l: int, seed: int, stream_id: int, inversion_index: int) -> np.ndarray:
+    """Raw 32-bit words for rows 0..d-1 and column groups 0..ceil(l/4)-1: (d, G, 4)."""
+    return philox_words_at(np.arange(d), np.arange((l + 3) // 4), seed, stream_id, inversion_index)
 
 
 def gaussian_test_matrix(d: int, l: int, seed: int, stream_id: int = 0,
@@ -304,7 +307,7 @@ def rsvd(F: np.ndarray, r: int, p: int, q: int, seed: int, stream_id: int = 0,
 
     B = Q^T F (l x d); the SVD of B^T = F Q (d x l) gives B = U_B Sigma_B V_B^T; the
     returned factor is V~ = V_B[:, :r] (the more accurate one for symmetric PSD
-    matrices, Sec. 2.3.1) with D = Sigma_B[:r]."""
+    matrices, Sec. 2.2.2) with D = Sigma_B[:r]."""
     F = np.asarray(F, dtype=np.float64)
     d = F.shape[0]
     l = _sketch_width(d, r, p)

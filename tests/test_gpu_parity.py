@@ -49,6 +49,21 @@ def test_omega_words_bitexact_and_values(d, l, seed, sid, inv):
     assert np.abs(to_np(Om) - Oo).max() <= 2e-6 * max(1.0, np.abs(Oo).max())
 
 
+def test_omega_first_words_are_the_published_known_answer():
+    # seed 0, stream 0, inversion 0: row 0's first column group is Philox4x32-10 of the
+    # all-zero counter under the all-zero key, a published known-answer vector
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.json")
+    with open(path) as fh:
+        kat = json.load(fh)["cases"][0]
+    assert kat["ctr"] == ["00000000"] * 4 and kat["key"] == ["00000000"] * 2
+    _, words = K().gaussian_omega(3, 8, 0, 0, 0, device=DEV, want_words=True)
+    torch.cuda.synchronize()
+    w = words.cpu().numpy().view(np.uint32)
+    assert [int(v) for v in w[0, 0]] == [int(x, 16) for x in kat["out"]]
+
+
 # --------------------------------------------------------------------------------------
 EA_CASES = [(257, 128, True), (128, 128, False), (1, 5, False), (63, 1000, False), (65, 7, True),
             (200, 5000, True), (577, 4096, True), (130, 0, False)]

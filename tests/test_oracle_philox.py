@@ -1,12 +1,51 @@
 """Pins for the oracle's Gaussian test matrix (Alg. 2/3 "Sample Gaussian Matrix").
 
-Philox4x32-10 parity against published known-answer vectors is UNPINNED (no KAT data is
-available here); what the method needs -- i.i.d. N(0,1) entries reproducible from
-(seed, stream, inversion index) -- is pinned statistically and structurally below."""
+The generator itself is pinned to the known-answer vectors published with Philox4x32-10
+(Salmon, Moraes, Dror, Shaw, SC'11; tests/golden/philox4x32_10_kat.json); what the method
+needs from it -- i.i.d. N(0,1) entries reproducible from (seed, stream, inversion index) --
+is pinned statistically and structurally below."""
+import json
+import os
+
 import numpy as np
 from scipy import stats
 
 import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.json")
+
+
+def _kat_cases():
+    with open(GOLDEN) as fh:
+        return json.load(fh)["cases"]
+
+
+def test_philox_known_answer_vectors():
+    cases = _kat_cases()
+    assert len(cases) == 3
+    for c in cases:
+        ctr = np.array([int(x, 16) for x in c["ctr"]], dtype=np.uint64)
+        key = tuple(int(x, 16) for x in c["key"])
+        out = O.philox4x32_10(ctr, key)
+        assert [int(v) for v in out] == [int(x, 16) for x in c["out"]], c
+
+
+def test_philox_known_answer_through_omega_counter_layout():
+    # Row 0, column group 0, stream 0, inversion 0 under seed 0 is the all-zero counter and
+    # key: the first four words of Omega's draw are the first known-answer vector.
+    c = _kat_cases()[0]
+    w = O.philox_words_for(1, 4, seed=0, stream_id=0, inversion_index=0)
+    assert [int(v) for v in w[0, 0]] == [int(x, 16) for x in c["out"]]
+    # seed -> key: (seed mod 2^32, seed >> 32); stream/inversion -> counter words 2 and 3
+    c3 = _kat_cases()[2]
+    ctr = [int(x, 16) for x in c3["ctr"]]
+    key = [int(x, 16) for x in c3["key"]]
+    seed = key[0] | (key[1] << 32)
+    w = O.philox_words_at([ctr[0]], [ctr[1]], seed, ctr[2], ctr[3])
+    assert [int(v) for v in w[0, 0]] == [int(x, 16) for x in c3["out"]]
+    # the row/group form agrees with the full-matrix form on a block of rows and groups
+    np.testing.assert_array_equal(O.philox_words_at(np.arange(5, 9), np.arange(2, 4), 77, 3, 1),
+                                  O.philox_words_for(9, 16, 77, 3, 1)[5:9, 2:4])
 
 
 def test_uniform_grid_and_range():

@@ -55,10 +55,80 @@ def test_ritz_interlacing_residual_orthonormality(q):
         res = F @ U[:, i] - D[i] * U[:, i]
         proj = F @ U[:, i] - Q @ (Q.T @ (F @ U[:, i]))
         assert abs(np.linalg.norm(res) - np.linalg.norm(proj)) < 1e-12
-    # more power iterations -> better Ritz values (monotone in expectation; here, gapped)
+    # every column of U has its largest-magnitude entry positive (the sign convention)
+    cols = np.arange(U.shape[1])
+    assert np.all(U[np.argmax(np.abs(U), axis=0), cols] > 0)
     # RSVD singular values sit between SREVD Ritz values and the true eigenvalues.
     V, S = O.rsvd(F, r=12, p=6, q=q, seed=9)
     assert np.all(D <= S + 1e-12) and np.all(S <= lam[:12] + 1e-12)
+
+
+def _sin_largest_angle(Q1, Q2):
+    """sin of the largest principal angle between span(Q1) and span(Q2) (orthonormal)."""
+    return np.linalg.norm(Q2 - Q1 @ (Q1.T @ Q2), 2)
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_range_finder_spans_power_of_factor_times_omega(q):
+    # q power iterations (Sec. 2.2): span(Q) = span(F^{q+1} Omega).  F is well conditioned
+    # (spectrum in [1, 3]) so F^{q+1} Omega has full rank in fp64; the spans of different
+    # powers are far apart, so one multiply too many or too few fails the check.
+    d, l = 40, 10
+    F = factor(d, np.linspace(3.0, 1.0, d), 31)
+    omega = O.gaussian_test_matrix(d, l, seed=5, stream_id=1)
+    Q = O.range_finder(F, omega, q)
+    assert Q.shape == (d, l) and np.abs(Q.T @ Q - np.eye(l)).max() < 1e-13
+    for m in range(4):
+        ref, _ = np.linalg.qr(np.linalg.matrix_power(F, m) @ omega)
+        s = _sin_largest_angle(Q, ref)
+        if m == q + 1:
+            assert s <= 1e-10, (q, m, s)
+        else:
+            assert s > 1e-3, (q, m, s)
+
+
+def test_power_iterations_reduce_projection_error_on_gapped_spectrum():
+    # On a spectrum with a gap after k modes, each power iteration raises the decay of the
+    # tail relative to the head, so the range error ||(I - QQ^T) F|| falls strictly.
+    d, k, l = 120, 10, 12
+    sig = np.concatenate([np.linspace(1.0, 0.5, k), np.linspace(0.1, 0.01, d - k)])
+    F = factor(d, sig, 41)
+    omega = O.gaussian_test_matrix(d, l, seed=3)
+    err = []
+    for q in range(3):
+        Q = O.range_finder(F, omega, q)
+        err.append(np.linalg.norm(F - Q @ (Q.T @ F), 2))
+    assert err[1] < 0.5 * err[0] and err[2] < err[1], err
+    assert err[2] >= sig[l] * (1 - 1e-12)       # never below the rank-l truncation floor
+
+
+def test_kfactor_step_draws_omega_from_stream_2l_and_2l_plus_1():
+    # One K-factor step over two layers equals the per-layer steps it is made of, with the
+    # Omega stream of layer l's A factor 2l and of its G factor 2l+1 (and not swapped).
+    rng = np.random.default_rng(17)
+    rho, lam, r_cap, p, q, seed = 0.9, 0.1, 6, 3, 1, 11
+    layers = []
+    for li, (m, dg, n) in enumerate([(12, 9, 20), (10, 14, 25)]):
+        layers.append({"A": np.eye(m + 1), "G": np.eye(dg), "a": rng.standard_normal((n, m)),
+                       "g": rng.standard_normal((n, dg)), "bias": True,
+                       "J": rng.standard_normal((dg, m + 1))})
+    out = O.kfactor_step(layers, rho, lam, r_cap, p, q, seed)
+    for li, (L, o) in enumerate(zip(layers, out)):
+        n = L["a"].shape[0]
+        A = O.ea_update(L["A"], L["a"], rho, 1.0 / n, append_ones=True)
+        G = O.ea_update(L["G"], L["g"], rho, 1.0 / n)
+        np.testing.assert_array_equal(o["A"], A)
+        np.testing.assert_array_equal(o["G"], G)
+        Ua, Da = O.srevd(A, r_cap, p, q, seed, 2 * li)
+        Ug, Dg = O.srevd(G, r_cap, p, q, seed, 2 * li + 1)
+        np.testing.assert_array_equal(o["U_a"], Ua)
+        np.testing.assert_array_equal(o["D_a"], Da)
+        np.testing.assert_array_equal(o["U_g"], Ug)
+        np.testing.assert_array_equal(o["D_g"], Dg)
+        np.testing.assert_array_equal(o["S"], O.precondition(L["J"], Ua, Da, Ug, Dg, lam))
+        # the other stream gives a different draw, hence different Ritz values
+        _, Da_other = O.srevd(A, r_cap, p, q, seed, 2 * li + 1)
+        assert np.abs(Da_other - Da).max() > 1e-8
 
 
 def _hmt_spectral_bound(sig, k, p, m):
@@ -91,7 +161,7 @@ def test_hmt_average_bounds(q):
 
 
 def test_rsvd_projection_error_not_worse_than_srevd():
-    # RSVD keeps V~ (Sec. 2.3.1), whose projection error is smaller than SREVD's (Sec. 2.4).
+    # RSVD keeps V~ (Sec. 2.2.2), whose projection error is smaller than SREVD's (Sec. 2.3).
     d, r, p = 100, 10, 3
     F = factor(d, synth.power_spectrum(d, 1.0), 4)
     lam, V0 = np.linalg.eigh(F)
