@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "philox4x32_10", "uniforms_from_words", "gaussian_test_matrix", "ea_update",
-    "philox_words_for", "philox_words_at", "householder_qr", "jacobi_eig", "jacobi_svd", "sign_normalize", "range_finder",
+    "philox_words_for", "philox_words_at", "householder_qr", "thin_qr", "jacobi_eig", "jacobi_svd", "sign_normalize", "range_finder",
     "srevd", "rsvd", "damping_weights", "precondition", "exact_precondition",
     "prop31_r_eps", "prop31_max_modes", "full_eig", "kfactor_step", "oracle_library_path",
     "linear_forward", "linear_backward",
@@ -205,6 +205,16 @@ def householder_qr(Y: np.ndarray):
     return Q * sgn[None, :], R * sgn[:, None]
 
 
+def thin_qr(Y: np.ndarray):
+    """The same thin QR as householder_qr (diag(R) >= 0), computed by LAPACK's blocked
+    Householder routines: the range finder's QR at full sizes, where the reflector loop
+    above would dominate the oracle's run time.  Any thin QR serves the range finder, whose
+    downstream results depend only on span(Q) (Sec. 2.2 leaves the QR method open)."""
+    Q, R = np.linalg.qr(np.asarray(Y, dtype=np.float64), mode="reduced")
+    sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return Q * sgn[None, :], R * sgn[:, None]
+
+
 # ----------------------------------------------------------------------------------------
 # Dense symmetric eigendecomposition (Alg. 1 "eig", Alg. 3 "Eigen_decomp") and thin SVD
 # (Alg. 2) by Jacobi rotations in plain C.
@@ -263,10 +273,14 @@ def sign_normalize(U: np.ndarray) -> np.ndarray:
 # (Sec. 2.2).  One power iteration is one more multiply by F followed by a fresh thin QR,
 # so span(Q) = span(F^{q+1} Omega).
 # ----------------------------------------------------------------------------------------
-def range_finder(F: np.ndarray, omega: np.ndarray, q: int) -> np.ndarray:
-    Q, _ = householder_qr(F @ omega)
+def range_finder(F: np.ndarray, omega: np.ndarray, q: int, F_sketch: np.ndarray = None) -> np.ndarray:
+    """Q with span(Q) = span(F^{q+1} Omega).  F_sketch, when given, is the matrix the
+    sketch and power-iteration products multiply by (the bf16 copy of F on a path whose
+    sketch runs in bf16); the method is otherwise unchanged."""
+    Fs = F if F_sketch is None else np.asarray(F_sketch, dtype=np.float64)
+    Q, _ = thin_qr(Fs @ omega)
     for _ in range(q):
-        Q, _ = householder_qr(F @ Q)
+        Q, _ = thin_qr(Fs @ Q)
     return Q
 
 
@@ -275,13 +289,14 @@ def _sketch_width(d: int, r: int, p: int) -> int:
 
 
 def srevd(F: np.ndarray, r: int, p: int, q: int, seed: int, stream_id: int = 0,
-          inversion_index: int = 0, return_all: bool = False):
+          inversion_index: int = 0, return_all: bool = False, F_sketch: np.ndarray = None):
     """Symmetric randomized EVD, Alg. 3: top-r eigenpairs (U d x r, D r) of PSD F.
 
     Steps: Omega (d x l, l = min(r+p, d)); Y = F Omega; Q = thin-QR(Y); q power
     iterations; C = Q^T F Q (symmetrised); C = P diag(D_C) P^T sorted descending;
     U = Q P[:, :r], D = D_C[:r]; columns of U sign-normalised.  When l = d the sketch
-    spans everything and Q = I (the randomized result equals the full eig)."""
+    spans everything and Q = I (the randomized result equals the full eig).  F_sketch: see
+    range_finder (the Rayleigh-Ritz product W = F Q always takes F)."""
     F = np.asarray(F, dtype=np.float64)
     d = F.shape[0]
     l = _sketch_width(d, r, p)
@@ -289,7 +304,7 @@ def srevd(F: np.ndarray, r: int, p: int, q: int, seed: int, stream_id: int = 0,
         Q = np.eye(d)
     else:
         omega = gaussian_test_matrix(d, l, seed, stream_id, inversion_index)
-        Q = range_finder(F, omega, q)
+        Q = range_finder(F, omega, q, F_sketch)
     W = F @ Q
     C = Q.T @ W
     C = 0.5 * (C + C.T)
@@ -302,12 +317,12 @@ def srevd(F: np.ndarray, r: int, p: int, q: int, seed: int, stream_id: int = 0,
 
 
 def rsvd(F: np.ndarray, r: int, p: int, q: int, seed: int, stream_id: int = 0,
-         inversion_index: int = 0, return_all: bool = False):
+         inversion_index: int = 0, return_all: bool = False, F_sketch: np.ndarray = None):
     """Randomized SVD of a symmetric PSD factor, Alg. 2, returning (V~, Sigma~).
 
     B = Q^T F (l x d); the SVD of B^T = F Q (d x l) gives B = U_B Sigma_B V_B^T; the
     returned factor is V~ = V_B[:, :r] (the more accurate one for symmetric PSD
-    matrices, Sec. 2.2.2) with D = Sigma_B[:r]."""
+    matrices, Sec. 2.2.2) with D = Sigma_B[:r].  F_sketch: see range_finder."""
     F = np.asarray(F, dtype=np.float64)
     d = F.shape[0]
     l = _sketch_width(d, r, p)
@@ -315,7 +330,7 @@ def rsvd(F: np.ndarray, r: int, p: int, q: int, seed: int, stream_id: int = 0,
         Q = np.eye(d)
     else:
         omega = gaussian_test_matrix(d, l, seed, stream_id, inversion_index)
-        Q = range_finder(F, omega, q)
+        Q = range_finder(F, omega, q, F_sketch)
     Bt = F @ Q
     Vb, s, Ub = jacobi_svd(Bt)
     V = sign_normalize(Vb[:, :r])

@@ -22,6 +22,18 @@ def test_householder_qr_definition_and_lapack(m, k):
     np.testing.assert_allclose(Q, Ql * s, atol=1e-12)
 
 
+@pytest.mark.parametrize("m,k", [(40, 7), (9, 9), (300, 42)])
+def test_thin_qr_equals_householder_qr(m, k):
+    # the range finder's library-backed thin QR is the same factorisation as the reflector
+    # loop above (positive diagonal of R makes the thin QR of a full-rank Y unique)
+    rng = np.random.default_rng(m * 7 + k)
+    Y = rng.standard_normal((m, k))
+    Q, R = O.thin_qr(Y)
+    Qh, Rh = O.householder_qr(Y)
+    np.testing.assert_allclose(Q, Qh, atol=1e-12)
+    np.testing.assert_allclose(R, Rh, atol=1e-12 * np.abs(Rh).max())
+
+
 def test_jacobi_tridiagonal_toeplitz_closed_form():
     # tridiag(b, a, b) of size n has eigenvalues a + 2 b cos(k pi / (n + 1)), k = 1..n,
     # with eigenvectors sin(i k pi / (n+1)).

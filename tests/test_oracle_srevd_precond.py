@@ -253,3 +253,22 @@ def test_jacobi_on_rayleigh_ritz_matrix_matches_lapack():
     U, D, aux = O.srevd(F, 32, 10, 1, 0, return_all=True)
     ref = np.sort(np.linalg.eigvalsh(aux["C"]))[::-1]
     np.testing.assert_allclose(aux["lam"], ref, atol=1e-13)
+
+
+def test_sketch_operand_enters_only_the_range_finder():
+    # F_sketch replaces F in the sketch and power-iteration products only: with F_sketch = F
+    # the result is unchanged, and with a rank-k F_sketch whose range holds F's top-k
+    # eigenvectors the range finder returns exactly that span while the Rayleigh-Ritz step
+    # still projects F itself (Ritz values = F's top-k eigenvalues).
+    d, k = 60, 8
+    sig = np.concatenate([np.geomspace(4.0, 1.0, k), np.geomspace(0.5, 0.05, d - k)])
+    F = factor(d, sig, 61)
+    U1, D1 = O.srevd(F, 6, 4, 1, 3, 2)
+    U2, D2 = O.srevd(F, 6, 4, 1, 3, 2, F_sketch=F.copy())
+    np.testing.assert_array_equal(D1, D2)
+    np.testing.assert_array_equal(U1, U2)
+    Uf = synth.haar_orthogonal(d, 61, d)[:, :k]
+    Fs = (Uf * np.linspace(2.0, 1.0, k)[None, :]) @ Uf.T
+    U3, D3, aux = O.srevd(F, k - 2, 2, 1, 3, 2, F_sketch=Fs, return_all=True)
+    np.testing.assert_allclose(D3, sig[:k - 2], rtol=1e-12)
+    assert _sin_largest_angle(aux["Q"], Uf) < 1e-10
