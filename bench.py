@@ -9,10 +9,17 @@ from I (rho 0.95) during untimed setup.  One timed step = EA step 11 for all 32 
 the randomized eigendecomposition (SREVD, r=min(256,d), p=16, q=1) of all 32 factors and
 the damped inverse (lambda 0.1) for all 16 layer gradients -- with inputs resident in HBM.
 
+Oracle leg (skipped with --no-check): after the timings the FP64 CPU oracle runs the full
+step from the GPU's own pre-step factors and the step's activations (EA, SREVD with the same
+Omega, damped inverse); its wall time is the `cpu_baseline` and its outputs give the
+`parity` object (EA error, e_lambda, e_S per path against the 5e-3 / 1e-4 gates).
+
 Paths measured on the same GPU:
   plan    : the grouped plan (kfac_plan_*): every phase of all 32 factors / 16 layers in one
-            launch, bf16 activations and bf16 sketch, captured once in a hipGraph and
-            replayed -- this is the reported `value` (32 factors / median step time);
+            launch, bf16 activations and the split-bf16 sketch (fp32 factors as bf16 hi/lo
+            pairs on bf16 MFMA), captured once in a hipGraph and replayed -- this is the
+            reported `value` (32 factors / median step time);
+  plan bf16: the same plan with the sketch on the bf16 shadow of the factors;
   plain   : per-layer entry-point calls on one stream, fp32 activations and fp32 sketch;
   streams : (optional, --streams N) per-factor calls spread over N streams in a hipGraph.
 After the timed replays the plan's launches are replayed eagerly with a HIP event between
@@ -39,7 +46,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--streams", type=int, default=0,
                     help="also time per-factor calls spread over this many streams (0: skip)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--branches", type=int, default=1,
+                    help="concurrent branches (streams) of the grouped plan, 1..4")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the oracle leg (CPU baseline timing and parity of the timed outputs)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default GEMM tile configurations")
     ap.add_argument("--config", choices=["vgg", "wide", "batched64", "copy"], default="vgg",
@@ -48,7 +58,6 @@ def parse():
                          "device copy that calibrates the HBM byte counters of rocprofv3")
     ap.add_argument("--d", type=int, default=16384, help="factor size of --config wide")
     ap.add_argument("--full-eig", action="store_true", help="--config wide: also time torch.linalg.eigh")
-    ap.add_argument("--check", action="store_true", help="check sampled outputs against the oracle")
     return ap.parse_args()
 
 
@@ -219,19 +228,23 @@ def run_batched(wl, layers, steps, warmup, nstreams):
     return g, times
 
 
-def make_plan(wl, layers, sketch="bf16", autotune=True):
-    """All 32 factors and 16 layers of the step in one grouped plan (bf16 activations, bf16
-    sketch): factor 2i is layer i's A factor, 2i+1 its G factor."""
+def make_plan(wl, layers, sketch="bf16", autotune=True, branches=1):
+    """All 32 factors and 16 layers of the step in one grouped plan (bf16 activations; sketch
+    "split": split-bf16 products of the fp32 factors, "bf16": products of the bf16 shadow,
+    which the EA phase refreshes): factor 2i is layer i's A factor, 2i+1 its G factor."""
     import paper_2206_15397_amd as K
     fd, ld = [], []
+    sh = sketch == "bf16"
     for li, L in enumerate(layers):
-        fd.append(dict(F=L.A, F_bf16=L.Ab, X=L.a, append_ones=L.shape.bias, scale=1.0 / L.n, r=L.ra, p=wl.p,
-                       q=wl.q, stream_id=2 * li, U=L.Ua, D=L.Da))
-        fd.append(dict(F=L.G, F_bf16=L.Gb, X=L.g, append_ones=False, scale=1.0 / L.n, r=L.rg, p=wl.p,
-                       q=wl.q, stream_id=2 * li + 1, U=L.Ug, D=L.Dg))
+        fd.append(dict(F=L.A, F_bf16=L.Ab if sh else None, X=L.a, append_ones=L.shape.bias, scale=1.0 / L.n, r=L.ra,
+                       p=wl.p, q=wl.q, stream_id=2 * li, U=L.Ua, D=L.Da))
+        fd.append(dict(F=L.G, F_bf16=L.Gb if sh else None, X=L.g, append_ones=False, scale=1.0 / L.n, r=L.rg,
+                       p=wl.p, q=wl.q, stream_id=2 * li + 1, U=L.Ug, D=L.Dg))
         ld.append(dict(fa=2 * li, fg=2 * li + 1, J=L.J, S=L.S))
     plan = K.Plan(fd, ld, sketch=sketch)
     plan.set_scalars(wl.rho, wl.lam, wl.seed, 0).upload()
+    if branches > 1:
+        plan.set_branches(branches)
     if autotune:
         import tempfile
         restore(layers)
@@ -240,9 +253,9 @@ def make_plan(wl, layers, sketch="bf16", autotune=True):
     return plan
 
 
-def run_plan(wl, layers, steps, warmup, autotune=True):
+def run_plan(wl, layers, steps, warmup, autotune=True, sketch="bf16", branches=1):
     import torch
-    plan = make_plan(wl, layers, autotune=autotune)
+    plan = make_plan(wl, layers, sketch=sketch, autotune=autotune, branches=branches)
     restore(layers)
     plan.launch()                       # first-launch paths outside the capture
     torch.cuda.synchronize()
@@ -330,11 +343,100 @@ def measured_traffic(workload, kernel):
         return None
 
 
-def roofline(plan, names, times_ms, workload=None):
-    """Roofline of the kernel with the largest share of the step: algorithmic work of its
-    launches (kfac_plan_launch_work) over their measured durations."""
+# Kernel families of the step (SURVEY-independent names): the launch sequence is walked in
+# order, since a gemm_f32 / slice_reduce launch belongs to the phase it sits in.
+A8 = {"tridiag", "tri_prep", "tri_bisect", "tri_select", "tri_vec", "tri_cluster_lead", "tri_cluster",
+      "backtransform"}
+
+
+def families(names):
+    """Family of every launch: ea, omega, sketch (sketch and power-iteration products),
+    cholqr (Gram, Cholesky, triangular inverse and product), rr (Rayleigh-Ritz product),
+    eig (the small eigensolver), ritz (U = QP and column signs), precondition."""
+    fam = []
+    for nm in names:
+        if nm.startswith("ea_"):
+            fam.append("ea")
+        elif nm == "omega":
+            fam.append("omega")
+        elif nm in ("gemm_bf16", "gemm_bf16_skinny"):
+            fam.append("sketch")
+        elif nm == "gemm_bf16x3":
+            fam.append(None)            # split-bf16 products: sketch / power or Rayleigh-Ritz
+        elif nm in ("gram_partial", "gram_reduce", "cholinv", "trtri_cols", "trmm"):
+            fam.append("cholqr")
+        elif nm in A8:
+            fam.append("eig")
+        elif nm.startswith("sign_"):
+            fam.append("ritz")
+        else:
+            fam.append(None)            # fp32 GEMMs and K-slice reductions: by position
+    eig = [i for i, f in enumerate(fam) if f == "eig"]
+    first_eig, last_eig = (eig[0], eig[-1]) if eig else (len(names), -1)
+    # the Rayleigh-Ritz product is the last product before the eigensolver
+    prods = [i for i in range(first_eig) if names[i] in ("gemm_f32", "gemm_bf16x3", "gemm_bf16", "gemm_bf16_skinny")]
+    rr_at = prods[-1] if prods else None
+    seen_ritz = False
+    for i, nm in enumerate(names):
+        if fam[i] is not None:
+            continue
+        if nm in ("slice_reduce", "gemm_f32_reduce"):
+            fam[i] = fam[i - 1] if i > 0 else "other"
+        elif i < first_eig:
+            fam[i] = "rr" if i == rr_at else "sketch"
+        elif i > last_eig and eig and not seen_ritz:
+            fam[i] = "ritz"
+            seen_ritz = True
+        else:
+            fam[i] = "precondition"
+    return fam
+
+
+# arithmetic type each family's roofline is taken against (the EA is priced on HBM bytes)
+FAMILY_BOUND = {"sketch": ("bf16", "mfma"), "rr": ("bf16x3", "mfma"), "cholqr": ("fp64", "mfma"),
+                "ritz": ("fp32", "mfma"), "precondition": ("fp32", "mfma"), "ea": (None, "hbm"),
+                "omega": (None, "hbm")}
+
+
+def roofline(plan, names, times_ms, workload=None, precondition_dtype="fp32"):
+    """Roofline of the step, per kernel family and for the dominant kernel.
+
+    by_family: time per step of each family and its achieved fraction of the roofline that
+    bounds it (EA and Omega: HBM on their algorithmic bytes; products: MFMA peak of their
+    arithmetic type); the small eigensolver is reported in absolute microseconds only.
+    The returned top-level object is the dominant kernel outside the small eigensolver:
+    algorithmic work of its launches (kfac_plan_launch_work) over their measured time."""
+    fam = families(names)
+    bound = dict(FAMILY_BOUND)
+    for f in ("sketch", "rr"):            # priced on the arithmetic of the family's product kernel
+        ks = [nm for nm, fa in zip(names, fam) if fa == f and nm in KIND]
+        if ks:
+            bound[f] = (KIND[ks[0]][0], "mfma")
+    bound["precondition"] = (precondition_dtype, "mfma")
+    byf = {}
+    for i, (nm, t) in enumerate(zip(names, times_ms)):
+        f, b = plan.launch_work(i)
+        a = byf.setdefault(fam[i], [0.0, 0.0, 0.0])
+        a[0] += t
+        a[1] += f
+        a[2] += b
+    by_family = {}
+    for k, (t_ms, fl, nb) in byf.items():
+        e = {"us_per_step": round(1e3 * t_ms, 1)}
+        if k in bound and t_ms > 0:
+            dt, kind = bound[k]
+            if kind == "hbm":
+                ach = nb / (t_ms * 1e-3) / 1e9
+                e.update({"bound": "hbm", "achieved_GBs": round(ach, 1), "frac": round(ach / PEAK_HBM_GBS, 4)})
+            else:
+                ach = fl / (t_ms * 1e-3) / 1e12
+                e.update({"bound": "mfma", "dtype": dt, "achieved_TFLOPs": round(ach, 2),
+                          "frac": round(ach / PEAK_TFLOPS[dt], 4)})
+        by_family[k] = e
     tot = {}
     for i, (nm, t) in enumerate(zip(names, times_ms)):
+        if nm in A8:
+            continue
         f, b = plan.launch_work(i)
         a = tot.setdefault(nm, [0.0, 0.0, 0.0, 0])
         a[0] += t
@@ -344,8 +446,10 @@ def roofline(plan, names, times_ms, workload=None):
     nm = max(tot, key=lambda k: tot[k][0])
     t_ms, flops, nbytes, count = tot[nm]
     dt, unit_kind = KIND.get(nm, ("fp32", "hbm"))
+    if nm.startswith("gemm_f32") and fam[names.index(nm)] == "precondition":
+        dt = precondition_dtype
     peak_f = PEAK_TFLOPS[dt] * 1e12
-    if unit_kind == "hbm" or nbytes / (PEAK_HBM_GBS * 1e9) >= flops / peak_f:
+    if unit_kind == "hbm" or nm.startswith("ea_") or nbytes / (PEAK_HBM_GBS * 1e9) >= flops / peak_f:
         ach = nbytes / (t_ms * 1e-3) / 1e9
         out = {"bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                "frac": round(ach / PEAK_HBM_GBS, 5)}
@@ -353,11 +457,15 @@ def roofline(plan, names, times_ms, workload=None):
         ach = flops / (t_ms * 1e-3) / 1e12
         out = {"bound": unit_kind, "achieved": round(ach, 4), "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
                "frac": round(ach / PEAK_TFLOPS[dt], 6)}
-    out.update({"traffic": measured_traffic(workload, nm) if workload else None, "kernel": nm, "dtype": dt,
+    traffic = measured_traffic(workload, nm) if workload else None
+    out.update({"traffic": traffic, "kernel": nm, "dtype": dt,
                 "launches_per_step": count,
                 "avg_launch_us": round(1e3 * t_ms / count, 2),
                 "flops_per_launch": flops / count, "bytes_per_launch": nbytes / count,
-                "share_of_step": round(t_ms / sum(times_ms), 4)})
+                "traffic_over_algorithmic": None if traffic is None else round(traffic / (nbytes / count), 3),
+                "share_of_step": round(t_ms / sum(times_ms), 4),
+                "small_eigensolver_us_per_step": round(1e3 * sum(t for n_, t in zip(names, times_ms) if n_ in A8), 1),
+                "by_family": by_family})
     return out
 
 
@@ -366,37 +474,128 @@ def median(xs):
     return s[len(s) // 2]
 
 
-def cpu_baseline(target_seconds=15.0):
-    """The FP64 oracle on a bounded sample of the same workload (the FC head and the last
-    conv block: EA step, SREVD of both factors, damped inverse per layer)."""
+def snapshot(layers, status=None):
+    """Host copies of one step of every layer: the pre-step factors and the step's inputs
+    (exactly the values the GPU consumed) and every output of the step.  status: the device
+    status word of the path (default: the per-layer words of the entry-point calls)."""
+    out = []
+    for L in layers:
+        out.append({k: getattr(L, k).detach().cpu() for k in
+                    ("A0", "G0", "a", "g", "J", "A", "G", "Ua", "Da", "Ug", "Dg", "S")})
+        out[-1].update(name=L.shape.name, bias=L.shape.bias, n=L.n, ra=L.ra, rg=L.rg,
+                       status=int(L.st.abs().sum().item()) if status is None else 0)
+    if status is not None and out:
+        out[0]["status"] = int(status)
+    return out
+
+
+GATES = {"plan_bf16": 5e-3, "plan_split": 5e-3, "plain_fp32": 1e-4}
+
+
+def cpu_baseline(wl, snaps):
+    """The FP64 oracle on the full step of the same workload, timed on the host cores: for
+    every layer the EA of both factors from the GPU's own pre-step factors and the step's
+    activations, the randomized eigendecomposition (SREVD, same Omega) of the GPU's post-EA
+    factors, and the damped inverse.  snaps: {path: snapshot}, the first being the reported
+    path, whose oracle step is the one timed.  The oracle's outputs also give the parity of
+    every path (the eigendecompositions are repeated, untimed, from each other path's own
+    post-EA factors): EA error, e_lambda (top-r relative eigenvalue error), e_S (relative
+    Frobenius error of the preconditioned gradient), the damped inverse applied to the
+    GPU's own (U, D) (stage error), the damping-aware eigenvalue error |dD| / (D + lambda)
+    and the relative gap of the oracle's Ritz values at the rank cut."""
     import numpy as np
     import oracle as O
-    from paper_2206_15397_amd import synth
-    wl = synth.vgg16_bn_workload()
-    order = [15, 14, 13, 12, 11, 10]      # fc3, fc2, fc1, conv13, conv12, conv11
-    t0 = time.perf_counter()
-    factors = 0
-    done = []
-    for li in order:
-        s = wl.layers[li]
-        Ra = synth.haar_orthogonal(s.m_a, synth.SEED_ROT_A + li)
-        Rg = synth.haar_orthogonal(s.d_g, synth.SEED_ROT_G + li)
-        a = synth.activation_batch(s.n, Ra, synth.power_spectrum(s.m_a), synth.SEED_ACT_A + li, 0)
-        g = synth.activation_batch(s.n, Rg, synth.power_spectrum(s.d_g), synth.SEED_ACT_G + li, 0)
-        t_l = time.perf_counter()
-        L = {"A": np.eye(s.d_a), "G": np.eye(s.d_g), "a": a, "g": g, "bias": True,
-             "J": g.T @ np.concatenate([a, np.ones((s.n, 1))], 1) / s.n}
-        O.kfactor_step([L], wl.rho, wl.lam, wl.r_cap, wl.p, wl.q, wl.seed)
-        factors += 2
-        done.append(s.name)
-        if time.perf_counter() - t0 > target_seconds:
-            break
-    el = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(factors / el, 4), "unit": "K-factor eig-inversions/s", "cores": threads,
+
+    def f64(t):
+        return t.double().numpy()
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+    def eig(F, r, sid):
+        U, D, aux = O.srevd(F, r, wl.p, wl.q, wl.seed, sid, return_all=True)
+        lam = aux["lam"]
+        return U, D, float((lam[r - 1] - lam[r]) / lam[r - 1]) if r < len(lam) else float("inf")
+
+    def layer_errors(s, A, G, oa, og, So):
+        Da, Dg = f64(s["Da"]), f64(s["Dg"])
+        S = f64(s["S"])
+        st = O.precondition(f64(s["J"]), f64(s["Ua"]), Da, f64(s["Ug"]), Dg, wl.lam)
+        return {"e_ea": max(rel(f64(s["A"]), A), rel(f64(s["G"]), G)),
+                "e_lambda": float(max(np.max(np.abs(Da - oa[1]) / oa[1]), np.max(np.abs(Dg - og[1]) / og[1]))),
+                "e_S": rel(S, So), "e_S_stage": rel(S, st),
+                "dD_damped": float(max(np.max(np.abs(Da - oa[1]) / (oa[1] + wl.lam)),
+                                       np.max(np.abs(Dg - og[1]) / (og[1] + wl.lam)))),
+                "cut_gap": min(oa[2], og[2])}
+
+    names = list(snaps)
+    first = snaps[names[0]]
+    t = {"ea": 0.0, "eig": 0.0, "precondition": 0.0}
+    per = {k: [] for k in names}
+    t_all = time.perf_counter()
+    for li, s in enumerate(first):
+        n = s["n"]
+        t0 = time.perf_counter()
+        A = O.ea_update(f64(s["A0"]), f64(s["a"]), wl.rho, 1.0 / n, append_ones=s["bias"])
+        G = O.ea_update(f64(s["G0"]), f64(s["g"]), wl.rho, 1.0 / n)
+        t["ea"] += time.perf_counter() - t0
+        for k, name in enumerate(names):
+            q = snaps[name][li]
+            t1 = time.perf_counter()
+            oa = eig(f64(q["A"]), q["ra"], 2 * li)
+            og = eig(f64(q["G"]), q["rg"], 2 * li + 1)
+            t2 = time.perf_counter()
+            So = O.precondition(f64(q["J"]), oa[0], oa[1], og[0], og[1], wl.lam)
+            t3 = time.perf_counter()
+            per[name].append(layer_errors(q, A, G, oa, og, So))
+            if k == 0:
+                t["eig"] += t2 - t1
+                t["precondition"] += t3 - t2
+                # conditioning of S: the oracle's own S moves by this much when its input
+                # factors are perturbed entrywise at fp32 rounding (relative 2^-24, symmetric)
+                rng = np.random.default_rng(1000 + li)
+
+                def pert(F):
+                    E = rng.uniform(-1.0, 1.0, F.shape)
+                    return F * (1.0 + 2.0 ** -24 * (E + E.T) / 2)
+                pa = eig(pert(f64(q["A"])), q["ra"], 2 * li)
+                pg = eig(pert(f64(q["G"])), q["rg"], 2 * li + 1)
+                per[name][-1]["e_S_floor_fp32_input"] = rel(
+                    O.precondition(f64(q["J"]), pa[0], pa[1], pg[0], pg[1], wl.lam), So)
+        log(f"  oracle {s['name']}: " + "; ".join(
+            f"{nm} e_lambda {per[nm][-1]['e_lambda']:.1e} e_S {per[nm][-1]['e_S']:.1e}" for nm in names))
+    t_step = t["ea"] + t["eig"] + t["precondition"]
+    nfac = 2 * len(first)
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:       # pragma: no cover
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    base = {"value": round(nfac / t_step, 4), "unit": "K-factor eig-inversions/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"FP64 oracle K-factor step (EA + SREVD of both factors + damped inverse) for layers "
-                      f"{','.join(done)} = {factors} factors in {el:.1f}s; host nproc={os.cpu_count()}"}
+            "sample": f"the full step (all {len(first)} layers / {nfac} factors): FP64 oracle EA "
+                      f"{t['ea']:.1f}s + SREVD {t['eig']:.1f}s + damped inverse {t['precondition']:.1f}s = "
+                      f"{t_step:.1f}s; its products and QR run in the host BLAS/LAPACK ({threads} threads), "
+                      f"its Jacobi sweeps on one core; host nproc={os.cpu_count()}"}
+    parity = {}
+    for name in names:
+        rows = per[name]
+        gate = GATES.get(name, 5e-3)
+        mx = {k: max(r[k] for r in rows) for k in rows[0] if k not in ("cut_gap", "e_S_floor_fp32_input")}
+        sep = [r["cut_gap"] >= 1e-2 for r in rows]
+        parity[name] = {"gate": gate, **{k + "_max": float(f"{v:.4g}") for k, v in mx.items()},
+                        "e_S_per_layer": [float(f"{r['e_S']:.3g}") for r in rows],
+                        "separated_cut_per_layer": sep,
+                        **({"e_S_floor_fp32_input_per_layer": [float(f"{r['e_S_floor_fp32_input']:.3g}") for r in rows]}
+                           if "e_S_floor_fp32_input" in rows[0] else {}),
+                        "e_S_max_separated_cuts": max([r["e_S"] for r, ok in zip(rows, sep) if ok] or [0.0]),
+                        "status": sum(sn["status"] for sn in snaps[name]),
+                        "pass_e_lambda": bool(mx["e_lambda"] <= gate), "pass_e_S": bool(mx["e_S"] <= gate),
+                        "pass_e_S_separated_cuts": bool(max([r["e_S"] for r, ok in zip(rows, sep) if ok] or [0.0])
+                                                        <= gate),
+                        "pass_ea": bool(mx["e_ea"] <= 1e-5)}
+    log(f"  oracle step {time.perf_counter() - t_all:.1f}s")
+    return base, parity
 
 
 def mfma_fraction(plan, names, times_ms):
@@ -443,29 +642,46 @@ def graph_times(plan, steps, warmup, restore_fn):
     return g, times
 
 
-def main_wide(args, dev):
-    """One wide factor: d x d built by 50 EA steps (batch 512, bf16 activations with an
-    e^(-i/40) spectrum on a thin Haar basis of 2048 columns); randomized eig with r = 256,
-    p = 16, q = 2 through a one-factor plan (eig phases only)."""
-    import tempfile
+WIDE_N, WIDE_EA_STEPS, WIDE_R, WIDE_P, WIDE_Q = 512, 50, 256, 16, 2
+
+
+def build_wide(d, dev, keep_last_input=False):
+    """The wide-factor workload: d x d factor built from I by 50 EA steps (rho 0.95) of 512
+    bf16 activation rows whose covariance has the spectrum e^(-i/40) on a thin Haar basis of
+    min(d, 2048) columns; the bf16 shadow is refreshed by the last step.  Returns (F, F_bf16)
+    or, with keep_last_input, (F, F_bf16, F before the last step, the last step's rows)."""
     import torch
     import paper_2206_15397_amd as K
     from paper_2206_15397_amd import synth
-    d, n, ea_steps = args.d, 512, 50
+    n, ea_steps = WIDE_N, WIDE_EA_STEPS
     k = min(d, 2048)
-    log(f"building d={d} factor ({ea_steps} EA steps of {n} rows) ...")
-    t0 = time.time()
     U = synth.torch_haar_orthogonal(d, 301, dev, k)
     spec = torch.exp(-torch.arange(k, device=dev, dtype=torch.float32) / 40.0)
     F = K.fill_identity(torch.empty((d, d), device=dev))
     Fb = K.bf16_shadow(F)
+    prev = a = None
     for st in range(ea_steps):
         a = synth.torch_activation_batch(n, U, spec, 302, st, dev, out_dtype=torch.bfloat16)
+        if keep_last_input and st == ea_steps - 1:
+            prev = F.clone()
         K.ea_update(F, a, 0.95, 1.0 / n, F_bf16=Fb)
     torch.cuda.synchronize()
     del U
+    return (F, Fb, prev, a) if keep_last_input else (F, Fb)
+
+
+def main_wide(args, dev):
+    """One wide factor (build_wide); randomized eig with r = 256, p = 16, q = 2 through a
+    one-factor plan (eig phases only)."""
+    import tempfile
+    import torch
+    import paper_2206_15397_amd as K
+    d = args.d
+    log(f"building d={d} factor ({WIDE_EA_STEPS} EA steps of {WIDE_N} rows) ...")
+    t0 = time.time()
+    F, Fb = build_wide(d, dev)
     log(f"  setup {time.time() - t0:.1f}s")
-    r, p, q = 256, 16, 2
+    r, p, q = WIDE_R, WIDE_P, WIDE_Q
     plan = K.Plan([dict(F=F, F_bf16=Fb, r=r, p=p, q=q, stream_id=0)], [], sketch="bf16")
     plan.set_scalars(0.95, 0.1, 0, 0, do_ea=False, do_eig=True, do_precondition=False).upload()
     if not args.no_autotune:
@@ -501,17 +717,17 @@ def main_wide(args, dev):
     print(json.dumps(res), flush=True)
 
 
-def main_batched64(args, dev):
+BATCHED64_SKETCH = "split"
+
+
+def build_batched64(dev):
     """64 factors of log-uniform sizes 64..8192 with e^(-j/40) spectra (built in fp64 on a thin
-    Haar basis, rounded to fp32 + bf16 shadow); r = min(256, d/2), p = 16, q = 1, lambda 0.1;
-    32 layers pair (F_2j, F_2j+1) with J ~ N(0, 1).  No EA in the step (factors are given)."""
-    import tempfile
+    Haar basis, rounded to fp32 + bf16 shadow); r = min(256, d/2), p = 16, q = 1; 32 layers
+    pair (F_2j, F_2j+1) with J ~ N(0, 1).  Returns (factor descriptors, layer descriptors)."""
     import torch
     import paper_2206_15397_amd as K
     from paper_2206_15397_amd import synth
     sizes = synth.c5_factor_sizes(64, 64, 8192)
-    log("building 64 factors ...")
-    t0 = time.time()
     facs = []
     for i, d in enumerate(sizes):
         k = min(d, 2048)
@@ -527,17 +743,32 @@ def main_batched64(args, dev):
         dg, da = sizes[2 * j], sizes[2 * j + 1]
         lays.append(dict(fg=2 * j, fa=2 * j + 1, J=torch.randn((dg, da), generator=gen, device=dev)))
     torch.cuda.synchronize()
+    return facs, lays
+
+
+def main_batched64(args, dev):
+    """The 64-factor workload (build_batched64), lambda 0.1.  No EA in the step (factors are
+    given)."""
+    import tempfile
+    import torch
+    import paper_2206_15397_amd as K
+    log("building 64 factors ...")
+    t0 = time.time()
+    facs, lays = build_batched64(dev)
     log(f"  setup {time.time() - t0:.1f}s")
-    plan = K.Plan(facs, lays, sketch="bf16")
-    plan.set_scalars(0.95, 0.1, 0, 0, do_ea=False).upload()
-    if not args.no_autotune:
-        plan.autotune(cache_path=os.path.join(tempfile.gettempdir(), "kfac_autotune_cache.txt"), reps=3)
     nothing = lambda: None
-    g, times = graph_times(plan, args.steps, args.warmup, nothing)
-    ms = median(times)
+    alt_ms = {}
+    for sk in ("bf16", BATCHED64_SKETCH):          # the reported sketch last (its plan is kept)
+        plan = K.Plan(facs, lays, sketch=sk)
+        plan.set_scalars(0.95, 0.1, 0, 0, do_ea=False).upload()
+        if not args.no_autotune:
+            plan.autotune(cache_path=os.path.join(tempfile.gettempdir(), "kfac_autotune_cache.txt"), reps=3)
+        g, times = graph_times(plan, args.steps, args.warmup, nothing)
+        alt_ms[sk] = median(times)
+        log(f"batched64 {sk} sketch: median {alt_ms[sk]:.3f} ms, status={int(plan.status.item())}")
+        del g
+    ms = alt_ms[BATCHED64_SKETCH]
     names, pt = phase_times(plan, None, max(3, args.steps // 2), restore_fn=nothing)
-    log(f"batched64: median {ms:.3f} ms, status={int(plan.status.item())}")
-    del g
     plain_ms = None
     if not args.no_plain:
         Fs = [f["F"] for f in facs]
@@ -573,7 +804,8 @@ def main_batched64(args, dev):
            "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16+fp32+fp64", "data": "synthetic",
            "config": {"workload": "batched64_loguniform_64_8192", "factors": 64, "layers": 32,
-                      "r": "min(256,d/2)", "p": 16, "q": 1, "lambda": 0.1},
+                      "r": "min(256,d/2)", "p": 16, "q": 1, "lambda": 0.1, "sketch": BATCHED64_SKETCH},
+           "bf16_sketch_ms_per_step": round(alt_ms["bf16"], 4),
            "plain_fp32_ms_per_step": plain_ms,
            "speedup_vs_plain_fp32": None if plain_ms is None else round(plain_ms / ms, 3),
            "roofline": roofline(plan, names, pt, "batched64_loguniform_64_8192")}
@@ -617,10 +849,13 @@ def main():
     wl, layers = build_workload(dev, act_dtype_bf16=True)
     make_buffers(wl, layers, dev, "bf16")
     log(f"  setup {time.time() - t0:.1f}s")
-    plan, gp, tp_ = run_plan(wl, layers, args.steps, args.warmup, autotune=not args.no_autotune)
+    snaps = {}
+    # the reported path: the grouped plan with the bf16-shadow sketch
+    plan, gp, tp_ = run_plan(wl, layers, args.steps, args.warmup, autotune=not args.no_autotune, sketch="bf16",
+                             branches=args.branches)
     ms_b = median(tp_)
-    log(f"plan bf16 ({plan.launch_count} grouped launches): median {ms_b:.3f} ms  (min {min(tp_):.3f}, "
-        f"max {max(tp_):.3f}) status={int(plan.status.item())}")
+    log(f"plan bf16 sketch ({plan.launch_count} grouped launches, {args.branches} branches): median {ms_b:.3f} ms  "
+        f"(min {min(tp_):.3f}, max {max(tp_):.3f}) status={int(plan.status.item())}")
     names, pt = phase_times(plan, layers, max(3, args.steps // 2))
     tot = sum(pt)
     cfgs = plan.launch_configs()
@@ -629,6 +864,23 @@ def main():
     roof = roofline(plan, names, pt, "vgg16_bn_cifar_b128_factor_set")
     log(f"roofline: {roof}")
     del gp
+    # the step's outputs (the eager replay above ran one whole step from the restored factors)
+    if not args.no_check:
+        snaps["plan_bf16"] = snapshot(layers, int(plan.status.item()))
+    launches = plan.launch_count
+    del plan
+    # the same plan with the split-bf16 sketch (fp32-class products)
+    plan_b, gb, tb_ = run_plan(wl, layers, max(3, args.steps // 2), 1, autotune=not args.no_autotune, sketch="split",
+                               branches=args.branches)
+    ms_sp = median(tb_)
+    log(f"plan split-bf16 sketch: median {ms_sp:.3f} ms status={int(plan_b.status.item())}")
+    del gb
+    if not args.no_check:
+        restore(layers)
+        plan_b.launch()
+        torch.cuda.synchronize()
+        snaps["plan_split"] = snapshot(layers, int(plan_b.status.item()))
+    del plan_b
     plain_ms = None
     if args.streams > 0:
         g, tb = run_batched(wl, layers, args.steps, args.warmup, args.streams)
@@ -640,11 +892,12 @@ def main():
         for L in layers:
             for n in ("a", "g"):
                 setattr(L, n, getattr(L, n).float())
-        wsz = [L.ws_a.numel() for L in layers]
         make_buffers(wl, layers, dev, "fp32")
         tp = run_plain(wl, layers, max(3, args.steps // 4), 1)
         plain_ms = median(tp)
         log(f"plain fp32: median {plain_ms:.3f} ms")
+        if not args.no_check:
+            snaps["plain_fp32"] = snapshot(layers)
     nfac = 2 * len(layers)
     res = {
         "metric": "K-factor eig-inversions/s + K-FAC step ms vs plain FP32 at <=1e-4/<=5e-3 err",
@@ -657,14 +910,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "vgg16_bn_cifar_b128_factor_set", "factors": nfac, "layers": len(layers),
                    "r": "min(256,d)", "p": wl.p, "q": wl.q, "rho": wl.rho, "lambda": wl.lam,
-                   "path": "grouped plan (%d launches), bf16 sketch, hipGraph" % plan.launch_count},
+                   "path": "grouped plan (%d launches, %d branches), bf16 sketch, hipGraph" % (launches, args.branches)},
         "plain_fp32_ms_per_step": None if plain_ms is None else round(plain_ms, 4),
         "speedup_vs_plain_fp32": None if plain_ms is None else round(plain_ms / ms_b, 3),
+        "split_sketch_plan_ms_per_step": round(ms_sp, 4),
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline()
+    if not args.no_check:
+        log("oracle: full step, timed (cpu_baseline) and compared with the GPU outputs (parity) ...")
+        base, parity = cpu_baseline(wl, snaps)
+        res["cpu_baseline"] = base
+        res["parity"] = parity
     print(json.dumps(res), flush=True)
 
 

@@ -43,18 +43,34 @@ typedef enum {
 
 typedef enum { KFAC_FP32 = 0, KFAC_BF16 = 1 } kfac_dtype;
 
-/* Which randomized decomposition.  SREVD is Alg. 3 (Rayleigh-Ritz on Q^T F Q), used by
- * SRE-KFAC (Alg. 5).  RSVD (Alg. 2, Alg. 4) is reserved and currently returns
- * KFAC_EUNSUPPORTED. */
+/* Which randomized decomposition of the symmetric PSD factor F, after the same range
+ * finder (Omega, sketch, power iterations, orthonormal Q):
+ *  KFAC_SREVD  Alg. 3 (used by SRE-KFAC, Alg. 5): C = Q^T F Q, C = P Lambda P^T,
+ *              U = Q P[:, :r], D = Lambda[:r].
+ *  KFAC_RSVD   Alg. 2 (used by RS-KFAC, Alg. 4) returning the V factor, which Sec. 2.2.2
+ *              prescribes for PSD factors: B = Q^T F, B^T = F Q = V_B Sigma U_B^T (thin
+ *              SVD), U = V_B[:, :r], D = Sigma[:r].  The SVD is taken through the fp64
+ *              eigendecomposition of the l x l Gram (FQ)^T (FQ) = U_B Sigma^2 U_B^T,
+ *              V_B = F Q U_B Sigma^{-1}; columns with Sigma_k = 0 come out zero. */
 typedef enum { KFAC_SREVD = 0, KFAC_RSVD = 1 } kfac_variant;
 
 /* Precision of the sketch and power-iteration products F*Omega, F*Q (Alg. 3 "Compute
- * X Omega" and the power iterations of Sec. 2.2).  KFAC_SKETCH_FP32: fp32 operands on
- * fp32 MFMA.  KFAC_SKETCH_BF16: bf16 operands (a bf16 copy of F supplied by the caller,
- * e.g. the shadow written by kfac_ea_update) with fp32 accumulation.  In both cases the
- * Gram matrices, Cholesky factors and the (r+p)x(r+p) Rayleigh-Ritz eigensolve are fp64
- * and the Rayleigh-Ritz product F*Q is fp32. */
-typedef enum { KFAC_SKETCH_FP32 = 0, KFAC_SKETCH_BF16 = 1 } kfac_precision;
+ * X Omega" and the power iterations of Sec. 2.2).
+ *  KFAC_SKETCH_FP32   fp32 operands on fp32 MFMA.
+ *  KFAC_SKETCH_BF16   bf16 operands (a bf16 copy of F supplied by the caller, e.g. the
+ *                     shadow written by kfac_ea_update, and bf16 Omega / Q) with fp32
+ *                     accumulation.  Rounding F to bf16 perturbs it by about 2^-9 ||F||,
+ *                     which moves the Ritz values near the rank cut by up to that much
+ *                     relative to lambda_r: accurate to the 5e-3 gate only where
+ *                     lambda_r >> 2^-9 ||F|| (e.g. EA factors with the identity floor).
+ *  KFAC_SKETCH_SPLIT  fp32 F and fp32 Omega / Q, each entering bf16 MFMAs as a pair
+ *                     hi = bf16(v), lo = bf16(v - hi); three bf16 MFMAs per product
+ *                     (hi*hi + hi*lo + lo*hi) with fp32 accumulation: fp32-class accuracy
+ *                     at bf16-MFMA speed, no bf16 copy of F needed.
+ * In every mode the Gram matrices, Cholesky factors and the (r+p)x(r+p) eigensolve are
+ * fp64; the Rayleigh-Ritz product F*Q is fp32 MFMA (FP32 mode) or split-bf16 (the two
+ * bf16 modes). */
+typedef enum { KFAC_SKETCH_FP32 = 0, KFAC_SKETCH_BF16 = 1, KFAC_SKETCH_SPLIT = 2 } kfac_precision;
 
 #define KFAC_MAX_SKETCH 512   /* largest l = min(r+p, d) handled by the fp64 eigensolver */
 
@@ -122,14 +138,16 @@ kfac_status kfac_gaussian_omega(float* Omega, int64_t d, int64_t l, int64_t ldo,
                                 uint32_t* words, kfac_stream_t stream);
 
 /*
- * kfac_rand_eig -- randomized symmetric eigendecomposition of one K-factor (SREVD,
- * Alg. 3, with the power iterations of Sec. 2.2), replacing the cubic full eig of
- * Alg. 1:
+ * kfac_rand_eig -- randomized low-rank eigendecomposition of one K-factor (SREVD, Alg. 3,
+ * or RSVD, Alg. 2, see kfac_variant; with the power iterations of Sec. 2.2), replacing the
+ * cubic full eig of Alg. 1:
  *   l = min(r + p, d).  If l < d: Y = F Omega (d x l); Q = orth(Y) by CholeskyQR2
  *   (fp64 Gram and Cholesky); q times: Y = F Q, Q = orth(Y).  If l == d: Q = I.
- *   C = Q^T F Q (fp64, symmetrised); C = P diag(Lambda) P^T (fp64, descending);
- *   U = Q P[:, :r], D = Lambda[:r]; each column of U is signed so that its
- *   largest-magnitude entry is positive (ties: lowest row).
+ *   SREVD: C = Q^T F Q (fp64, symmetrised); C = P diag(Lambda) P^T (fp64, descending);
+ *   U = Q P[:, :r], D = Lambda[:r].  RSVD: W = F Q, W^T W = P diag(Sigma^2) P^T (fp64),
+ *   U = W P[:, :r] Sigma^{-1}, D = Sigma[:r] (at l == d both are the eig of F).  Each
+ *   column of U is signed so that its largest-magnitude entry is positive (ties: lowest
+ *   row).
  *  F        d x d fp32 symmetric PSD factor (ldf >= d).
  *  F_bf16   bf16 copy of F (ldfb >= d); required iff prec == KFAC_SKETCH_BF16.
  *  r        target rank, 1 <= r <= d.  p >= 0 oversampling.  0 <= q <= 16 power its.
@@ -241,6 +259,7 @@ typedef struct {
   const void* X; kfac_dtype xtype;     /* EA input (n x d_in, ldx); X == NULL: no EA update */
   int64_t n, d_in, ldx; int append_ones; float scale;
   float* U; int64_t ldu; float* D;     /* outputs: U d x r, D r                             */
+  kfac_variant variant;                /* SREVD (Alg. 3) or RSVD (Alg. 2), see kfac_variant  */
 } kfac_factor_desc;
 
 typedef struct {
@@ -284,6 +303,22 @@ kfac_status kfac_plan_launch_work(const kfac_plan* plan, int index, double* flop
  */
 kfac_status kfac_plan_autotune(kfac_plan* plan, void* workspace, size_t ws_bytes, int32_t* dev_status,
                                const char* cache_path, int reps, kfac_stream_t stream);
+/*
+ * Concurrent branches: the plan's layers (each with its two factors) and unused factors are
+ * split into nbranch groups (1..4) that run on separate streams: kfac_plan_launch records
+ * an event on the caller's stream, makes nbranch - 1 plan-owned streams wait for it,
+ * enqueues every group's launches on its own stream (group 0 on the caller's) and joins
+ * them back into the caller's stream, so a capture of kfac_plan_launch holds parallel
+ * branches.  The layers with the largest EA work form the last group and the rest are
+ * balanced over the others, so the latency-bound eigensolver phases of one group (a few
+ * workgroups each) overlap the streaming phases of another.  Results are identical to
+ * nbranch = 1 (the default).  Streams and events are created here (default priority);
+ * takes effect at the next kfac_plan_upload and resets the autotuned configurations.
+ * kfac_plan_launch_branch gives the group of launch `index` (-1 out of range; nbranch
+ * marks layers preconditioned after the join because their factors sit in two groups).
+ */
+kfac_status kfac_plan_set_branches(kfac_plan* plan, int nbranch);
+int kfac_plan_launch_branch(const kfac_plan* plan, int index);
 /* Sets every fp32 GEMM launch to configuration cfg_gemm_f32 (0..4; 4, the whole-sketch-width
  * tile, only where it applies) and every bf16 sketch launch to cfg_sketch_bf16 (0..1); -1
  * keeps the default.  Takes effect at the next kfac_plan_upload.  For tests and experiments. */

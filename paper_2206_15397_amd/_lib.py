@@ -11,7 +11,7 @@ _SO = os.path.join(HERE, "libkfac.so")
 KFAC_OK, KFAC_EINVAL, KFAC_EWORKSPACE, KFAC_EHIP, KFAC_EUNSUPPORTED = 0, 1, 2, 3, 4
 KFAC_FP32, KFAC_BF16 = 0, 1
 KFAC_SREVD, KFAC_RSVD = 0, 1
-KFAC_SKETCH_FP32, KFAC_SKETCH_BF16 = 0, 1
+KFAC_SKETCH_FP32, KFAC_SKETCH_BF16, KFAC_SKETCH_SPLIT = 0, 1, 2
 STATUS_BITS = {1: "CHOL_SHIFTED", 2: "CHOL_FAILED", 4: "NONFINITE", 8: "EIG_NOCONV"}
 
 # Every function exported by include/kfac.h, with (restype, argtypes).
@@ -45,6 +45,8 @@ SIGNATURES = {
     "kfac_plan_autotune": (_i, [_p, _p, _sz, _p, ctypes.c_char_p, _i, _p]),
     "kfac_plan_force_config": (_i, [_p, _i, _i]),
     "kfac_plan_launch_config": (_i, [_p, _i]),
+    "kfac_plan_set_branches": (_i, [_p, _i]),
+    "kfac_plan_launch_branch": (_i, [_p, _i]),
     "kfac_plan_destroy": (None, [_p]),
 }
 
@@ -54,7 +56,7 @@ class FactorDesc(ctypes.Structure):
     _fields_ = [("F", _p), ("d", _i64), ("ldf", _i64), ("F_bf16", _p), ("ldfb", _i64),
                 ("r", _i64), ("p", _i64), ("q", _i), ("stream_id", _u64),
                 ("X", _p), ("xtype", _i), ("n", _i64), ("d_in", _i64), ("ldx", _i64),
-                ("append_ones", _i), ("scale", _f), ("U", _p), ("ldu", _i64), ("D", _p)]
+                ("append_ones", _i), ("scale", _f), ("U", _p), ("ldu", _i64), ("D", _p), ("variant", _i)]
 
 
 class LayerDesc(ctypes.Structure):

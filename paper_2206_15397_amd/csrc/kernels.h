@@ -69,7 +69,8 @@ hipError_t launch_trsm(const double* W, long ldw, const double* Li, int n, int l
 size_t small_eig_scratch_doubles(int n, int r);
 hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r,
                             double* A, double* V, double* diag, double* off, double* Z, double* scratch,
-                            float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s);
+                            float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s,
+                            int svd = 0);
 
 
 // ---- grouped launches (one launch covers one phase of many tasks) -----------------------

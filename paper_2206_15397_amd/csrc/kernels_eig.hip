@@ -494,7 +494,7 @@ __device__ __forceinline__ void tri_select_body(const EigTask& q, int, int) {
     if (rank < r) {
       m.col_task[rank] = j;
       Dd[rank] = lj;
-      D[rank] = (float)lj;
+      D[rank] = q.svd ? (float)sqrt(fmax(lj, 0.0)) : (float)lj;
     }
   }
   __threadfence_block();
@@ -769,7 +769,11 @@ __device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int
       nn += z[j][u] * z[j][u];
     }
     nn = wave_sum(nn);
-    const double sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+    double sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+    if (q.svd && c < r) {               // left singular vectors: W p_k / sigma_k
+      const double lk = q.Dd[c];
+      sc = (lk > 0.0) ? sc / sqrt(lk) : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < PER; ++u) z[j][u] *= sc;
   }
@@ -871,13 +875,15 @@ EigTask make_eig_task(const double* C, long ldc, const float* Cf, long ldcf, int
   q.m.cstart = ip; ip += r;
   q.cl = (double*)(((uintptr_t)ip + 15) & ~(uintptr_t)15);
   q.P = P; q.ldp = ldp; q.D = D; q.Dd = Dd; q.status = status;
+  q.svd = 0;
   return q;
 }
 
 hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldcf, int n, int n_pad, int r,
                             double* A, double* V, double* diag, double* off, double* Z, double* scratch,
-                            float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s) {
+                            float* P, long ldp, float* D, double* Dd, int* status, hipStream_t s, int svd) {
   EigTask q = make_eig_task(C, ldc, Cf, ldcf, n, n_pad, r, A, V, diag, off, Z, scratch, P, ldp, D, Dd, status);
+  q.svd = svd;
   if (n <= TNMAX) hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(TNT), 0, s, q);
   else hipLaunchKernelGGL(k_tridiag_gmem, dim3(1), dim3(1024), 0, s, q);
   hipLaunchKernelGGL(k_tri_prep, dim3(1), dim3(512), 0, s, q);

@@ -81,7 +81,8 @@ kfac_status kfac_gaussian_omega(float* Omega, int64_t d, int64_t l, int64_t ldo,
 size_t kfac_rand_eig_workspace(int64_t d, int64_t r, int64_t p, int q, kfac_variant v, kfac_precision prec) {
   if (d < 1 || r < 1 || r > d || p < 0 || q < 0) return 0;
   (void)v;
-  EigWs w(d, r, p, prec == KFAC_SKETCH_BF16, nullptr);
+  if (prec != KFAC_SKETCH_FP32 && prec != KFAC_SKETCH_BF16 && prec != KFAC_SKETCH_SPLIT) return 0;
+  EigWs w(d, r, p, (int)prec, nullptr);
   return w.bytes;
 }
 
@@ -92,35 +93,39 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
                           kfac_stream_t stream) {
   if (!F || !U || !D || !dev_status || !workspace) return KFAC_EINVAL;
   if (d < 1 || ldf < d || r < 1 || r > d || p < 0 || q < 0 || q > 16 || ldu < r) return KFAC_EINVAL;
-  if (prec != KFAC_SKETCH_FP32 && prec != KFAC_SKETCH_BF16) return KFAC_EINVAL;
+  if (prec != KFAC_SKETCH_FP32 && prec != KFAC_SKETCH_BF16 && prec != KFAC_SKETCH_SPLIT) return KFAC_EINVAL;
   if (v != KFAC_SREVD && v != KFAC_RSVD) return KFAC_EINVAL;
   if (prec == KFAC_SKETCH_BF16 && (!F_bf16 || ldfb < d)) return KFAC_EINVAL;
-  if (v == KFAC_RSVD) return KFAC_EUNSUPPORTED;
+  const bool rsvd = (v == KFAC_RSVD);
   const int64_t l = std::min<int64_t>(r + p, d);
   if (l > KFAC_MAX_SKETCH || d > (1 << 28)) return KFAC_EUNSUPPORTED;
-  EigWs w(d, r, p, prec == KFAC_SKETCH_BF16, workspace);
+  EigWs w(d, r, p, (int)prec, workspace);
   if (ws_bytes < w.bytes) return KFAC_EWORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   int* st = (int*)dev_status;
   hipError_t e = hipSuccess;
 #define CK(x) do { e = (x); if (e != hipSuccess) return KFAC_EHIP; } while (0)
   if (w.exact) {
-    // l == d: the sketch spans R^d, Q = I; eigendecompose F itself, U = P[:, :r].
+    // l == d: the sketch spans R^d, Q = I; eigendecompose F itself, U = P[:, :r] (for the
+    // RSVD variant this is also the SVD of B^T = F, F being symmetric PSD).
     CK(launch_small_eig(nullptr, 0, F, ldf, (int)d, (int)d, (int)r, w.A, w.V, w.diag, w.off, w.Z, w.scr, U,
                         ldu, D, w.Dd, st, s));
     CK(launch_sign_normalize(U, ldu, (int)d, (int)r, w.sval, w.sidx, s));
     return KFAC_OK;
   }
   const bool bf = (prec == KFAC_SKETCH_BF16);
+  const bool sp = (prec == KFAC_SKETCH_SPLIT);
   const int L = (int)w.l_pad, n = (int)w.l, dd = (int)d;
   const long ldt = w.ldt;
   // Omega^T (l_pad x d), rows >= l zero
   CK(launch_omega(dd, n, dd, L, seed, stream_id, inversion_index, w.OmT, ldt, bf ? w.OmTb : nullptr, nullptr,
                   0, nullptr, s));
   // the whole-width kernels (all l_pad rows per workgroup) when l_pad fits them
-  const bool whole = bf && L <= kWholeWidthMaxM;
+  const bool whole = (bf || sp) && L <= kWholeWidthMaxM;
   auto f_times = [&](const float* At, const uint16_t* Atb, float* Out) -> hipError_t {
     // Out (L x d) = At (L x d) * F (d x d); F symmetric, so Out^T = F At^T.
+    if (sp && whole)
+      return launch_split(make_split_task(L, dd, dd, At, ldt, F, ldf, Out, ldt, w.skp, split_ksplit(dd, dd)), s);
     if (whole && dd >= 2048)
       return launch_skinny(make_skinny_task(L, dd, dd, Atb, ldt, F_bf16, ldfb, Out, ldt, w.skp,
                                             skinny_ksplit(dd, dd)), s);
@@ -181,14 +186,20 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf, const uint16_t
     g.C = Wt; g.ldc = ldt; g.alpha = 1.f; g.ones_col = -1;
     CK(launch_gemm(g, false, false, s));
   }
-  CK(launch_gram(Qt, ldt, Wt, ldt, L, dd, 0, w.part, w.G, L, st, s));
+  // SREVD (Alg. 3): C = Q^T W, eig(C) = P Lambda P^T, U = Q P[:, :r], D = Lambda[:r].
+  // RSVD (Alg. 2, returning V as Sec. 2.2.2 prescribes for PSD factors): B^T = F Q = W; its
+  // thin SVD W = V Sigma P^T from the eigendecomposition of the Gram W^T W = P Sigma^2 P^T
+  // (fp64), V = W P Sigma^{-1}; U = V[:, :r], D = Sigma[:r].
+  if (rsvd) CK(launch_gram(Wt, ldt, Wt, ldt, L, dd, 1, w.part, w.G, L, st, s));
+  else CK(launch_gram(Qt, ldt, Wt, ldt, L, dd, 0, w.part, w.G, L, st, s));
   CK(launch_small_eig(w.G, L, nullptr, 0, n, L, (int)r, w.A, w.V, w.diag, w.off, w.Z, w.scr, w.P, r, D, w.Dd,
-                      st, s));
-  // U = Q P[:, :r]  (A = Q^T stored l_pad x d, i.e. K x M)
+                      st, s, rsvd ? 1 : 0));
+  // U = Q P[:, :r] (SREVD) or W P[:, :r] Sigma^{-1} (RSVD; P already scaled); the left
+  // operand is stored transposed (l_pad x d, i.e. K x M)
   {
     GemmP g{};
     g.M = dd; g.N = (int)r; g.K = n;
-    g.A = Qt; g.lda = ldt; g.B = w.P; g.ldb = r;
+    g.A = rsvd ? Wt : Qt; g.lda = ldt; g.B = w.P; g.ldb = r;
     g.C = U; g.ldc = ldu; g.alpha = 1.f; g.ones_col = -1;
     CK(launch_gemm(g, true, false, s));
   }

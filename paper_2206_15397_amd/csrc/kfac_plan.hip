@@ -16,6 +16,8 @@ using namespace kfac;
 
 namespace {
 
+constexpr int kMaxBranches = 4;     // the caller's stream plus three (four hardware queues)
+
 enum Kind {
   K_EA_TILES, K_EA_FIN, K_EA_TILES_BF, K_EA_FIN_BF, K_OMEGA, K_GEMM, K_BF16, K_SKINNY, K_SKINNY_R, K_SPLIT, K_GRAM_P, K_GRAM_R, K_CHOLINV, K_TRTRI, K_TRMM, K_TRIDIAG, K_PREP,
   K_BISECT, K_SELECT, K_VEC, K_CLEAD, K_CLUSTER, K_BT, K_SIGN_P, K_SIGN_A, K_GEMM_SL
@@ -32,6 +34,7 @@ struct LaunchRec {
   int ncfg;              // number of configurations of the tunable unit
   int span;              // launches belonging to the tunable unit (a split-K reduction follows)
   bool split;            // fp32 GEMM launch with split-K tasks
+  int branch;            // concurrent branch (stream) the launch belongs to
 };
 
 // Algorithmic work: flops of the operation as defined (padding and split-K excluded) and
@@ -48,6 +51,7 @@ inline Work gemm_work(double M, double N, double K, bool extra) {
 struct Tables {
   std::vector<char> bytes;
   std::vector<LaunchRec> recs;
+  int cur_branch = 0;    // branch of the launches being added
   size_t align(size_t n) {
     size_t o = (bytes.size() + 255) / 256 * 256;
     bytes.resize(o + n);
@@ -67,6 +71,7 @@ struct Tables {
     r.span = 1;
     r.ntasks = (int)tasks.size();
     r.ta = ta; r.tb = tb;
+    r.branch = cur_branch;
     r.tasks_off = align(sizeof(T) * tasks.size());
     std::memcpy(bytes.data() + r.tasks_off, tasks.data(), sizeof(T) * tasks.size());
     r.off_off = align(sizeof(int) * (tasks.size() + 1));
@@ -111,6 +116,13 @@ struct kfac_plan {
   Tables tab;                  // built by upload
   std::vector<int> gemm_cfg;   // tuned tile configuration per fp32 GEMM launch (-1: default)
   char* dev = nullptr;         // uploaded workspace base
+  // concurrent branches: every layer (with its two factors) and every factor no layer uses
+  // belongs to one branch; branch b > 0 runs on stream[b - 1], forked from and joined into
+  // the caller's stream around the launch sequence
+  int nbranch = 1;
+  std::vector<int> fbranch, lbranch;
+  hipStream_t stream[kMaxBranches - 1] = {};
+  hipEvent_t fork = nullptr, join[kMaxBranches - 1] = {};
 };
 
 namespace {
@@ -163,15 +175,23 @@ void add_gemm(kfac_plan* P, Tables& T, int& ord, const std::vector<GemmP>& g, bo
   if (!gs.empty()) T.add(K_GEMM_SL, gs, gxs, nbs);
 }
 
-// Build all task tables for workspace base `base` (null: sizes only) and status pointer.
-void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
+// Task tables of branch `br` (its factors and layers) for workspace base `base` (null:
+// sizes only) and status pointer, appended to T; gord numbers the tunable launches.
+void build_branch(kfac_plan* P, char* base, int* status, Tables& T, int br, int& gord) {
   const bool bf = (P->prec == KFAC_SKETCH_BF16);
-  int gord = 0;                 // ordinal of the next fp32 GEMM launch
+  const bool sp = (P->prec == KFAC_SKETCH_SPLIT);
+  T.cur_branch = br;
+  auto in_f = [&](size_t i) { return P->fbranch.empty() ? br == 0 : P->fbranch[i] == br; };
+  // branch nbranch: the layers whose two factors sit in different branches, after the join
+  auto in_l = [&](size_t l) {
+    if (P->lbranch.empty()) return br == 0;
+    return br == P->nbranch ? P->lbranch[l] == -1 : P->lbranch[l] == br;
+  };
   const size_t head = P->table_bytes;
   auto wsp = [&](size_t off) -> void* { return base ? (void*)(base + head + off) : nullptr; };
   std::vector<EigWs> W;
   for (size_t i = 0; i < P->f.size(); ++i)
-    W.emplace_back(P->fi[i].d, P->fi[i].r, P->f[i].p, bf, wsp(P->fi[i].ws_off));
+    W.emplace_back(P->fi[i].d, P->fi[i].r, P->f[i].p, (int)P->prec, wsp(P->fi[i].ws_off));
 
   // ---- EA --------------------------------------------------------------------------
   if (P->do_ea) {
@@ -183,7 +203,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       for (size_t i = 0; i < P->f.size(); ++i) {
         const kfac_factor_desc& F = P->f[i];
         const FactorInfo& I = P->fi[i];
-        if (!I.ea || (F.xtype == KFAC_BF16) != (xb == 1)) continue;
+        if (!in_f(i) || !I.ea || (F.xtype == KFAC_BF16) != (xb == 1)) continue;
         EaTask q = make_ea_task(F.F, I.d, F.ldf, xb ? nullptr : (const float*)F.X,
                                 xb ? (const uint16_t*)F.X : nullptr, (int)F.n, (int)F.d_in, F.ldx,
                                 F.append_ones, P->rho, F.scale, F.F_bf16, F.ldfb, (float*)wsp(I.ea_off), I.ea_ks);
@@ -207,7 +227,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
     // ---- randomized range finder with CholeskyQR2 -----------------------------------
     std::vector<int> rnd;
     for (size_t i = 0; i < P->f.size(); ++i)
-      if (!P->fi[i].exact) rnd.push_back((int)i);
+      if (in_f(i) && !P->fi[i].exact) rnd.push_back((int)i);
     std::vector<float*> basis(P->f.size(), nullptr), spare(P->f.size(), nullptr);
     if (!rnd.empty()) {
       std::vector<OmegaTask> om;
@@ -236,7 +256,26 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           const double l = P->fi[i].l, d = P->fi[i].d;
           ws += bf ? Work{2 * l * d * d, 2 * d * d + 2 * l * d + 4 * l * d} : gemm_work(l, d, d, false);
         }
-        if (bf) {
+        if (sp) {
+          // split-bf16 products of the fp32 operands (whole sketch width per workgroup)
+          std::vector<SplitTask> g;
+          std::vector<ReduceTask> gr;
+          std::vector<int> gx2, nb2, gxr, nbr;
+          for (int i : act) {
+            const FactorInfo& I = P->fi[i];
+            const float* A = (it == 0) ? W[i].OmT : basis[i];
+            float* out = (it == 0) ? basis[i] : spare[i];
+            const SplitTask q = make_split_task(I.l_pad, I.d, I.d, A, I.ldt, P->f[i].F, P->f[i].ldf, out, I.ldt,
+                                                (float*)wsp(I.sk_off), split_ksplit(I.d, I.d));
+            g.push_back(q); gx2.push_back(q.tiles_n); nb2.push_back(split_blocks(q));
+            if (q.ksplit > 1) {
+              const ReduceTask rq = make_reduce_task(q.M, q.N, q.part, q.C, q.ldc, q.ksplit);
+              gr.push_back(rq); gxr.push_back(reduce_blocks(rq)); nbr.push_back(reduce_blocks(rq));
+            }
+          }
+          T.add(K_SPLIT, g, gx2, nb2, false, false, ws);
+          T.add(K_SKINNY_R, gr, gxr, nbr);
+        } else if (bf) {
           // tunable unit: 0 = 96 x 128 tiles, 1 = skinny full-M tiles with split-K
           const int o = gord++;
           int dmax = 0;
@@ -362,9 +401,9 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
         const FactorInfo& I = P->fi[i];
         const double l = I.l, d = I.d;
         wrr += gemm_work(l, d, d, false);
-        wg += Work{2 * l * l * d, 8 * l * d};
+        wg += P->f[i].variant == KFAC_RSVD ? Work{l * (l + 1) * d, 4 * l * d} : Work{2 * l * l * d, 8 * l * d};
         wr += Work{0, 8 * l * l};
-        if (bf) {
+        if (bf || sp) {
           const SplitTask q = make_split_task(I.l_pad, I.d, I.d, basis[i], I.ldt, P->f[i].F, P->f[i].ldf, spare[i],
                                               I.ldt, (float*)wsp(I.sk_off), split_ksplit(I.d, I.d));
           gs.push_back(q); gxs.push_back(q.tiles_n); nbs.push_back(split_blocks(q));
@@ -379,13 +418,17 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
           q.C = spare[i]; q.ldc = I.ldt; q.alpha = 1.f; q.ones_col = -1;
           g.push_back(q);
         }
-        GramP gr = make_gram_task(basis[i], I.ldt, spare[i], I.ldt, I.l_pad, I.d, 0, W[i].part, W[i].G, I.l_pad,
-                                  status);
-        const int tiles = gram_tiles(I.l_pad, 0);
+        // SREVD: C = Q^T W; RSVD: the Gram W^T W of B^T = W = F Q
+        const int sv = P->f[i].variant == KFAC_RSVD ? 1 : 0;
+        GramP gr = sv ? make_gram_task(spare[i], I.ldt, spare[i], I.ldt, I.l_pad, I.d, 1, W[i].part, W[i].G,
+                                       I.l_pad, status)
+                      : make_gram_task(basis[i], I.ldt, spare[i], I.ldt, I.l_pad, I.d, 0, W[i].part, W[i].G,
+                                       I.l_pad, status);
+        const int tiles = gram_tiles(I.l_pad, sv);
         gp.push_back(gr); gxg.push_back(tiles); nbg.push_back(tiles * gr.ksplit);
         gxr.push_back(tiles); nbr.push_back(tiles * gram_reduce_slices());
       }
-      if (bf) {
+      if (bf || sp) {
         T.add(K_SPLIT, gs, gxs, nbs, false, false, wrr);
         T.add(K_SKINNY_R, gsr, gxsr, nbsr);
       } else {
@@ -400,6 +443,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
     int bt4 = 0;
     Work wtri, wbt;
     for (size_t i = 0; i < P->f.size(); ++i) {
+      if (!in_f(i)) continue;
       const FactorInfo& I = P->fi[i];
       const kfac_factor_desc& F = P->f[i];
       const double n = I.l, r = I.r;
@@ -412,6 +456,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       else
         q = make_eig_task(W[i].G, I.l_pad, nullptr, 0, I.l, I.l_pad, I.r, W[i].A, W[i].V, W[i].diag, W[i].off,
                           W[i].Z, W[i].scr, W[i].P, I.r, F.D, W[i].Dd, status);
+      q.svd = (!I.exact && F.variant == KFAC_RSVD) ? 1 : 0;
       et.push_back(q);
       one.push_back(1); onen.push_back(1);
       gxb.push_back(tri_bisect_blocks(q.n)); nbb.push_back(tri_bisect_blocks(q.n));
@@ -443,7 +488,8 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
         wu += gemm_work(I.d, I.r, I.l, false);
         GemmP q{};
         q.M = I.d; q.N = I.r; q.K = I.l;
-        q.A = basis[i]; q.lda = I.ldt; q.B = W[i].P; q.ldb = I.r;
+        // SREVD: U = Q P; RSVD: U = W P Sigma^{-1} (the eigensolver scaled P)
+        q.A = P->f[i].variant == KFAC_RSVD ? spare[i] : basis[i]; q.lda = I.ldt; q.B = W[i].P; q.ldb = I.r;
         q.C = P->f[i].U; q.ldc = P->f[i].ldu; q.alpha = 1.f; q.ones_col = -1;
         g.push_back(q);
       }
@@ -455,6 +501,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
       std::vector<int> gx2, nb2;
       Work wsp, wsa;
       for (size_t i = 0; i < P->f.size(); ++i) {
+        if (!in_f(i)) continue;
         const FactorInfo& I = P->fi[i];
         wsp += Work{0, 4.0 * I.d * I.r};
         wsa += Work{0, 8.0 * I.d * I.r};
@@ -474,6 +521,7 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
     Work w1, w2, w3, w4;
     const float inv_lam = 1.0f / P->lam;
     for (size_t l = 0; l < P->lyr.size(); ++l) {
+      if (!in_l(l)) continue;
       const kfac_layer_desc& L = P->lyr[l];
       const kfac_factor_desc& A = P->f[L.fa];
       const kfac_factor_desc& G = P->f[L.fg];
@@ -517,6 +565,92 @@ void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
   }
 }
 
+// All task tables, branch after branch (each branch's launches are in stream order).
+void build_tables(kfac_plan* P, char* base, int* status, Tables& T) {
+  int gord = 0;                 // ordinal of the next tunable launch
+  for (int b = 0; b < P->nbranch; ++b) build_branch(P, base, status, T, b, gord);
+  bool post = false;
+  for (int lb : P->lbranch) post = post || lb == -1;
+  if (post && P->nbranch > 1) build_branch(P, base, status, T, P->nbranch, gord);
+  T.cur_branch = 0;
+}
+
+// Work estimate of one factor's share of the step (EA products, sketch / power / Rayleigh-
+// Ritz products): the quantity branches are balanced on.
+double factor_cost(const kfac_plan* P, size_t i) {
+  const kfac_factor_desc& F = P->f[i];
+  const double d = (double)F.d, l = std::min<double>((double)(F.r + F.p), d);
+  double c = 2.0 * d * d * l * (F.q + 2);
+  if (F.X) c += (double)F.n * d * d;
+  return c;
+}
+
+// Layers (with their factors) and unused factors to branches: the layers with the largest
+// EA work go to branch nb - 1, the others are spread over the branches by longest-
+// processing-time on factor_cost.  A branch whose EA is light starts its eigensolver
+// phases (latency-bound, few workgroups each) while the heavy-EA branch still streams its
+// activations, and its preconditioner overlaps the other branch's eigensolver.
+void assign_branches(kfac_plan* P, int nb) {
+  const size_t nf = P->f.size(), nl = P->lyr.size();
+  P->fbranch.assign(nf, -1);
+  P->lbranch.assign(nl, 0);
+  if (nb <= 1) { P->fbranch.assign(nf, 0); return; }
+  struct Unit { std::vector<int> f; int l; double cost, ea; };
+  std::vector<Unit> units;
+  std::vector<char> used(nf, 0);
+  for (size_t l = 0; l < nl; ++l) {
+    Unit u{{}, (int)l, 0.0, 0.0};
+    for (int fi : {P->lyr[l].fa, P->lyr[l].fg})
+      if (!used[fi]) {
+        used[fi] = 1;
+        u.f.push_back(fi);
+        u.cost += factor_cost(P, fi);
+        if (P->f[fi].X) u.ea += (double)P->f[fi].n * P->f[fi].d * P->f[fi].d;
+      }
+    units.push_back(u);
+  }
+  for (size_t i = 0; i < nf; ++i)
+    if (!used[i]) {
+      const double ea = P->f[i].X ? (double)P->f[i].n * P->f[i].d * P->f[i].d : 0.0;
+      units.push_back(Unit{{(int)i}, -1, factor_cost(P, i), ea});
+    }
+  // heavy-EA units: the largest EA works that together hold at least half of the EA
+  std::vector<size_t> ord(units.size());
+  for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+  std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return units[a].ea > units[b].ea; });
+  double ea_tot = 0.0, ea_acc = 0.0;
+  for (const Unit& u : units) ea_tot += u.ea;
+  std::vector<int> br(units.size(), -1);
+  for (size_t k : ord) {
+    if (ea_tot <= 0.0 || ea_acc >= 0.5 * ea_tot) break;
+    br[k] = nb - 1;
+    ea_acc += units[k].ea;
+  }
+  // the rest by LPT over branches 0 .. nb - 2 (all branches if nothing is heavy)
+  const int nlight = (ea_acc > 0.0) ? nb - 1 : nb;
+  std::vector<double> load(nb, 0.0);
+  std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return units[a].cost > units[b].cost; });
+  for (size_t k : ord) {
+    if (br[k] >= 0) { load[br[k]] += units[k].cost; continue; }
+    int best = 0;
+    for (int b = 1; b < nlight; ++b) if (load[b] < load[best]) best = b;
+    br[k] = best;
+    load[best] += units[k].cost;
+  }
+  for (size_t k = 0; k < units.size(); ++k) {
+    for (int fi : units[k].f) P->fbranch[fi] = br[k];
+    if (units[k].l >= 0) P->lbranch[units[k].l] = br[k];
+  }
+  // a factor shared with a layer of another branch stays where it was placed first; the
+  // other branch then reads its (U, D) only after the join, so such layers run in branch of
+  // their first factor's owner
+  for (size_t l = 0; l < nl; ++l) {
+    const int a = P->fbranch[P->lyr[l].fa], g = P->fbranch[P->lyr[l].fg];
+    if (a != g) P->lbranch[l] = -1;   // precondition after the join (see kfac_plan_launch)
+    else P->lbranch[l] = a;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -524,12 +658,13 @@ extern "C" {
 kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac_layer_desc* layers, int nl,
                              kfac_precision prec, kfac_plan** out) {
   if (!out || nf < 1 || (nl > 0 && !layers) || !factors) return KFAC_EINVAL;
-  if (prec != KFAC_SKETCH_FP32 && prec != KFAC_SKETCH_BF16) return KFAC_EINVAL;
+  if (prec != KFAC_SKETCH_FP32 && prec != KFAC_SKETCH_BF16 && prec != KFAC_SKETCH_SPLIT) return KFAC_EINVAL;
   *out = nullptr;
   for (int i = 0; i < nf; ++i) {
     const kfac_factor_desc& F = factors[i];
     if (!F.F || F.d < 1 || F.ldf < F.d || F.r < 1 || F.r > F.d || F.p < 0 || F.q < 0 || F.q > 16) return KFAC_EINVAL;
     if (!F.U || F.ldu < F.r || !F.D) return KFAC_EINVAL;
+    if (F.variant != KFAC_SREVD && F.variant != KFAC_RSVD) return KFAC_EINVAL;
     if (prec == KFAC_SKETCH_BF16 && (!F.F_bf16 || F.ldfb < F.d)) return KFAC_EINVAL;
     if (F.X) {
       if (F.n < 1 || F.d != F.d_in + (F.append_ones ? 1 : 0) || F.ldx < F.d_in || !(F.scale > 0.f)) return KFAC_EINVAL;
@@ -548,6 +683,7 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
   if (nl > 0) P->lyr.assign(layers, layers + nl);
   P->prec = prec;
   const bool bf = (prec == KFAC_SKETCH_BF16);
+  const bool sp = (prec == KFAC_SKETCH_SPLIT);
   size_t off = 0;
   auto take = [&](size_t bytes) { off = (off + kAlign - 1) / kAlign * kAlign; size_t o = off; off += bytes; return o; };
   // block steps of the grouped EA launches (one per activation precision) without split-K
@@ -568,14 +704,14 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
     I.ldt = round_up(F.d, 8);
     I.exact = (I.l == I.d);
     I.ea = (F.X != nullptr);
-    EigWs w(F.d, F.r, F.p, bf, nullptr);
+    EigWs w(F.d, F.r, F.p, (int)prec, nullptr);
     I.ws_bytes = w.bytes;
     I.ws_off = take(w.bytes);
     const bool xb = (F.xtype == KFAC_BF16);
     I.ea_ks = I.ea ? ea_grouped_ksplit(I.d, F.n, xb, ea_steps[xb ? 1 : 0]) : 1;
     I.ea_bytes = I.ea ? ea_partial_bytes(I.d, I.ea_ks, xb) : 0;
     I.ea_off = take(I.ea_bytes + 16);
-    I.sk_bytes = (bf && !I.exact)
+    I.sk_bytes = ((bf || sp) && !I.exact)
                      ? std::max(skinny_part_bytes(I.l_pad, I.d, I.d), split_part_bytes(I.l_pad, I.d, I.d)) : 0;
     I.sk_off = take(I.sk_bytes + 16);
     P->fi.push_back(I);
@@ -590,14 +726,21 @@ kfac_status kfac_plan_create(const kfac_factor_desc* factors, int nf, const kfac
     P->li.push_back(I);
   }
   // size the table head with every phase enabled, for either choice of the tunable kernels
+  // and every branch count
   size_t tb = 0;
-  for (int c = 0; c < 2; ++c) {
-    Tables T;
-    P->table_bytes = 0;
-    P->gemm_cfg.assign(256, c);
-    build_tables(P, nullptr, nullptr, T);
-    tb = std::max(tb, T.bytes.size());
+  for (int nb = 1; nb <= kMaxBranches; ++nb) {
+    P->nbranch = nb;
+    assign_branches(P, nb);
+    for (int c = 0; c < 2; ++c) {
+      Tables T;
+      P->table_bytes = 0;
+      P->gemm_cfg.assign(256, c);
+      build_tables(P, nullptr, nullptr, T);
+      tb = std::max(tb, T.bytes.size());
+    }
   }
+  P->nbranch = 1;
+  assign_branches(P, 1);
   P->gemm_cfg.clear();
   P->table_bytes = (tb + 2 * kAlign) / kAlign * kAlign;
   P->ws_bytes = P->table_bytes + off + kAlign;
@@ -652,13 +795,11 @@ kfac_status kfac_plan_launch_work(const kfac_plan* plan, int index, double* flop
   return KFAC_OK;
 }
 
-kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, kfac_stream_t stream) {
-  if (!plan || !plan->dev || first < 0 || count < 0 || first + count > (int)plan->tab.recs.size())
-    return KFAC_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
+namespace {
+// Enqueues launch record r of the plan on stream s.
+hipError_t launch_rec(const kfac_plan* plan, const LaunchRec& r, hipStream_t s) {
   char* d = plan->dev;
-  for (int i = first; i < first + count; ++i) {
-    const LaunchRec& r = plan->tab.recs[i];
+  {
     GroupMap gm{(const int*)(d + r.off_off), (const int*)(d + r.gx_off), r.ntasks};
     const void* tp = d + r.tasks_off;
     hipError_t e = hipSuccess;
@@ -689,16 +830,68 @@ kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, 
       case K_BT: e = launch_backtransform_g((const EigTask*)tp, gm, r.blocks, r.cfg == 1 ? 4 : 1, s); break;
       case K_SIGN_P: e = launch_sign_partial_g((const SignTask*)tp, gm, r.blocks, s); break;
       case K_SIGN_A: e = launch_sign_apply_g((const SignTask*)tp, gm, r.blocks, s); break;
-      default: return KFAC_EINVAL;
+      default: return hipErrorInvalidValue;
     }
-    if (e != hipSuccess) return KFAC_EHIP;
+    return e;
   }
+}
+}  // namespace
+
+kfac_status kfac_plan_launch_range(const kfac_plan* plan, int first, int count, kfac_stream_t stream) {
+  if (!plan || !plan->dev || first < 0 || count < 0 || first + count > (int)plan->tab.recs.size())
+    return KFAC_EINVAL;
+  for (int i = first; i < first + count; ++i)
+    if (launch_rec(plan, plan->tab.recs[i], (hipStream_t)stream) != hipSuccess) return KFAC_EHIP;
   return KFAC_OK;
 }
 
 kfac_status kfac_plan_launch(const kfac_plan* plan, kfac_stream_t stream) {
   if (!plan || !plan->dev) return KFAC_EINVAL;
-  return kfac_plan_launch_range(plan, 0, (int)plan->tab.recs.size(), stream);
+  const int nb = plan->nbranch;
+  if (nb <= 1) return kfac_plan_launch_range(plan, 0, (int)plan->tab.recs.size(), stream);
+  // fork: branches 1.. wait for everything enqueued on the caller's stream so far
+  hipStream_t s = (hipStream_t)stream;
+  if (hipEventRecord(plan->fork, s) != hipSuccess) return KFAC_EHIP;
+  for (int b = 1; b < nb; ++b)
+    if (hipStreamWaitEvent(plan->stream[b - 1], plan->fork, 0) != hipSuccess) return KFAC_EHIP;
+  // enqueue the branches' launches round-robin (each stream keeps its own order)
+  std::vector<std::vector<const LaunchRec*>> per(nb + 1);
+  for (const LaunchRec& r : plan->tab.recs) per[std::min(r.branch, nb)].push_back(&r);
+  size_t longest = 0;
+  for (int b = 0; b < nb; ++b) longest = std::max(longest, per[b].size());
+  for (size_t k = 0; k < longest; ++k)
+    for (int b = 0; b < nb; ++b)
+      if (k < per[b].size() && launch_rec(plan, *per[b][k], b == 0 ? s : plan->stream[b - 1]) != hipSuccess)
+        return KFAC_EHIP;
+  // join, then the layers whose factors sit in different branches
+  for (int b = 1; b < nb; ++b) {
+    if (hipEventRecord(plan->join[b - 1], plan->stream[b - 1]) != hipSuccess) return KFAC_EHIP;
+    if (hipStreamWaitEvent(s, plan->join[b - 1], 0) != hipSuccess) return KFAC_EHIP;
+  }
+  for (const LaunchRec* r : per[nb])
+    if (launch_rec(plan, *r, s) != hipSuccess) return KFAC_EHIP;
+  return KFAC_OK;
+}
+
+kfac_status kfac_plan_set_branches(kfac_plan* plan, int nbranch) {
+  if (!plan || nbranch < 1 || nbranch > kMaxBranches) return KFAC_EINVAL;
+  for (int b = 1; b < nbranch; ++b) {
+    if (!plan->stream[b - 1] && hipStreamCreateWithFlags(&plan->stream[b - 1], hipStreamNonBlocking) != hipSuccess)
+      return KFAC_EHIP;
+    if (!plan->join[b - 1] && hipEventCreateWithFlags(&plan->join[b - 1], hipEventDisableTiming) != hipSuccess)
+      return KFAC_EHIP;
+  }
+  if (nbranch > 1 && !plan->fork && hipEventCreateWithFlags(&plan->fork, hipEventDisableTiming) != hipSuccess)
+    return KFAC_EHIP;
+  plan->nbranch = nbranch;
+  assign_branches(plan, nbranch);
+  plan->gemm_cfg.clear();       // the tunable launches are numbered anew
+  return KFAC_OK;
+}
+
+int kfac_plan_launch_branch(const kfac_plan* plan, int index) {
+  if (!plan || index < 0 || index >= (int)plan->tab.recs.size()) return -1;
+  return plan->tab.recs[index].branch;
 }
 
 // ---- autotuner ---------------------------------------------------------------------------
@@ -825,6 +1018,14 @@ int kfac_plan_launch_config(const kfac_plan* plan, int index) {
   return plan->tab.recs[index].cfg;
 }
 
-void kfac_plan_destroy(kfac_plan* plan) { delete plan; }
+void kfac_plan_destroy(kfac_plan* plan) {
+  if (!plan) return;
+  for (int b = 0; b < kMaxBranches - 1; ++b) {
+    if (plan->stream[b]) (void)hipStreamDestroy(plan->stream[b]);
+    if (plan->join[b]) (void)hipEventDestroy(plan->join[b]);
+  }
+  if (plan->fork) (void)hipEventDestroy(plan->fork);
+  delete plan;
+}
 
 }  // extern "C"

@@ -126,6 +126,9 @@ struct EigTask {         // one small symmetric eigenproblem
   float* P; long ldp;             // fp32 eigenvectors (n_pad x r)
   float* D; double* Dd;
   int* status;
+  int svd;                        // 1: the input is a Gram W^T W; D gets sqrt(lambda) and
+                                  // column k of P is scaled by 1 / sqrt(lambda_k), so that
+                                  // W P holds W's leading left singular vectors
 };
 
 }  // namespace kfac

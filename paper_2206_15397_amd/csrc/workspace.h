@@ -26,7 +26,7 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Layout of the kfac_rand_eig workspace; with base == nullptr it only measures.
 struct EigWs {
   int64_t d, r, l, l_pad, ldt;
-  bool exact, bf16;
+  bool exact, bf16, split;
   float *OmT, *Yt, *Qt, *P, *sval;
   int* sidx;
   uint16_t *OmTb, *Qtb;
@@ -35,7 +35,9 @@ struct EigWs {
   int* fail;
   size_t bytes;
 
-  EigWs(int64_t d_, int64_t r_, int64_t p_, bool bf16_, void* base) : d(d_), r(r_), bf16(bf16_) {
+  // prec: KFAC_SKETCH_FP32 / _BF16 (bf16 copies of Omega^T and Q^T) / _SPLIT (fp32 only)
+  EigWs(int64_t d_, int64_t r_, int64_t p_, int prec, void* base)
+      : d(d_), r(r_), bf16(prec == KFAC_SKETCH_BF16), split(prec == KFAC_SKETCH_SPLIT) {
     l = std::min<int64_t>(r + p_, d);
     exact = (l == d);
     l_pad = round_up(l, 32);
@@ -53,6 +55,8 @@ struct EigWs {
       if (bf16) {
         OmTb = b.take<uint16_t>(l_pad * ldt);
         Qtb = b.take<uint16_t>(l_pad * ldt);
+      }
+      if (bf16 || split) {
         if (l_pad <= kWholeWidthMaxM) {
           const size_t pb = std::max(skinny_part_bytes((int)l_pad, (int)d, (int)d),
                                      split_part_bytes((int)l_pad, (int)d, (int)d));

@@ -71,18 +71,38 @@ def gaussian_omega(d: int, l: int, seed: int, stream_id: int = 0, inversion_inde
     return (Om, words) if want_words else Om
 
 
-def rand_eig_workspace_bytes(d, r, p, q, sketch="fp32") -> int:
-    prec = _lib.KFAC_SKETCH_BF16 if sketch == "bf16" else _lib.KFAC_SKETCH_FP32
-    return int(lib().kfac_rand_eig_workspace(d, r, p, q, _lib.KFAC_SREVD, prec))
+def _prec(sketch) -> int:
+    """Sketch / power-iteration product precision: "fp32", "bf16" (bf16 copy of F) or
+    "split" (fp32 operands as bf16 hi/lo pairs on bf16 MFMA)."""
+    try:
+        return {"fp32": _lib.KFAC_SKETCH_FP32, "bf16": _lib.KFAC_SKETCH_BF16, "split": _lib.KFAC_SKETCH_SPLIT}[sketch]
+    except KeyError:
+        raise ValueError(f"sketch must be 'fp32', 'bf16' or 'split', not {sketch!r}") from None
+
+
+def _variant(v) -> int:
+    if v in ("srevd", _lib.KFAC_SREVD):
+        return _lib.KFAC_SREVD
+    if v in ("rsvd", _lib.KFAC_RSVD):
+        return _lib.KFAC_RSVD
+    raise ValueError(f"variant must be 'srevd' or 'rsvd', not {v!r}")
+
+
+def rand_eig_workspace_bytes(d, r, p, q, sketch="fp32", variant="srevd") -> int:
+    prec = _prec(sketch)
+    return int(lib().kfac_rand_eig_workspace(d, r, p, q, _variant(variant), prec))
 
 
 def rand_eig(F: torch.Tensor, r: int, p: int, q: int, seed: int, stream_id: int = 0,
              inversion_index: int = 0, sketch: str = "fp32", F_bf16: torch.Tensor = None,
-             U: torch.Tensor = None, D: torch.Tensor = None, workspace=None, status=None):
-    """SREVD of the symmetric PSD factor F: returns (U d x r, D r descending, status int32)."""
+             U: torch.Tensor = None, D: torch.Tensor = None, workspace=None, status=None,
+             variant: str = "srevd"):
+    """Randomized low-rank eigendecomposition of the symmetric PSD factor F (variant
+    "srevd": Alg. 3; "rsvd": Alg. 2 returning its V factor): returns (U d x r, D r
+    descending, status int32)."""
     _require_cuda(F, F_bf16)
     d = F.shape[0]
-    prec = _lib.KFAC_SKETCH_BF16 if sketch == "bf16" else _lib.KFAC_SKETCH_FP32
+    prec = _prec(sketch)
     if prec == _lib.KFAC_SKETCH_BF16 and F_bf16 is None:
         F_bf16 = bf16_shadow(F)
     if U is None:
@@ -92,11 +112,12 @@ def rand_eig(F: torch.Tensor, r: int, p: int, q: int, seed: int, stream_id: int 
     if status is None:
         status = torch.zeros((1,), dtype=torch.int32, device=F.device)
     L = lib()
+    v = _variant(variant)
     if workspace is None:
-        workspace = _workspace(L.kfac_rand_eig_workspace(d, r, p, q, _lib.KFAC_SREVD, prec), F.device)
+        workspace = _workspace(L.kfac_rand_eig_workspace(d, r, p, q, v, prec), F.device)
     check("kfac_rand_eig", L.kfac_rand_eig(
         _ptr(F), d, F.stride(0), _ptr(F_bf16), 0 if F_bf16 is None else F_bf16.stride(0),
-        int(r), int(p), int(q), int(seed), int(stream_id), int(inversion_index), _lib.KFAC_SREVD, prec,
+        int(r), int(p), int(q), int(seed), int(stream_id), int(inversion_index), v, prec,
         _ptr(U), U.stride(0), _ptr(D), _ptr(workspace), workspace.numel(), _ptr(status), _stream()))
     return U, D, status
 
@@ -177,7 +198,8 @@ class Plan:
     """Grouped K-factor step over many factors and layers (kfac_plan_* in the C ABI).
 
     factors: list of dicts with keys F (d x d fp32), r, p, q, stream_id, and optionally
-             F_bf16, X (n x d_in, fp32 or bf16), append_ones, scale, U, D.
+             F_bf16, X (n x d_in, fp32 or bf16), append_ones, scale, U, D, variant ("srevd" or
+             "rsvd").
     layers:  list of dicts with keys fa, fg (factor indices), J (d_g x d_a); S optional.
     The plan owns its workspace and status tensors; launch() only enqueues kernels and may
     be captured in a CUDA/HIP graph after upload()."""
@@ -189,7 +211,7 @@ class Plan:
         self.factors = [dict(f) for f in factors]
         self.layers = [dict(l) for l in layers]
         dev = device or self.factors[0]["F"].device
-        prec = _lib.KFAC_SKETCH_BF16 if sketch == "bf16" else _lib.KFAC_SKETCH_FP32
+        prec = _prec(sketch)
         fds = (_lib.FactorDesc * len(self.factors))()
         for i, f in enumerate(self.factors):
             F = f["F"]
@@ -213,6 +235,7 @@ class Plan:
                 fd.append_ones = 1 if f.get("append_ones") else 0
                 fd.scale = float(f.get("scale", 1.0 / x.shape[0]))
             fd.U, fd.ldu, fd.D = f["U"].data_ptr(), f["U"].stride(0), f["D"].data_ptr()
+            fd.variant = _variant(f.get("variant", "srevd"))
         lds = (_lib.LayerDesc * max(1, len(self.layers)))()
         for k, l in enumerate(self.layers):
             J = l["J"]
@@ -264,6 +287,14 @@ class Plan:
         re-uploads the tables."""
         check("kfac_plan_force_config", self._L.kfac_plan_force_config(self._h, int(gemm_f32), int(sketch_bf16)))
         return self.upload()
+
+    def set_branches(self, nbranch):
+        """Run the plan's layer groups on `nbranch` concurrent streams (1..4); re-uploads."""
+        check("kfac_plan_set_branches", self._L.kfac_plan_set_branches(self._h, int(nbranch)))
+        return self.upload()
+
+    def launch_branches(self):
+        return [int(self._L.kfac_plan_launch_branch(self._h, i)) for i in range(self.launch_count)]
 
     def launch_configs(self):
         return [int(self._L.kfac_plan_launch_config(self._h, i)) for i in range(self.launch_count)]

@@ -88,7 +88,7 @@ def test_rand_eig_validation(L):
     assert call(st=P(0)) == 1
     assert call(prec=1) == 1                 # bf16 sketch without a bf16 copy of F
     assert call(wsb=ws - 1) == 2
-    assert call(v=1) == 4                    # RSVD variant not built
+    assert call(v=2) == 1                    # unknown variant
     assert call(r=400, p=200, d=1000, ldf=1000, ldu=400) == 4   # sketch wider than supported
 
 

@@ -157,6 +157,27 @@ def test_rand_eig_fp32(d, r, p, q):
     assert proj_err(Ug[:, :k], Uo[:, :k]) < 1e-3
 
 
+@pytest.mark.parametrize("d,r,p,q,spec", [(257, 32, 10, 1, "pow"), (1100, 40, 24, 1, "pow"), (2305, 256, 16, 1, "pow"),
+                                          (753, 256, 16, 1, "exp"), (4778, 256, 16, 1, "exp"), (600, 100, 16, 2, "exp")])
+def test_rand_eig_split_sketch(d, r, p, q, spec):
+    """Split-bf16 sketch (fp32 operands as bf16 hi/lo pairs, three bf16 MFMAs per product):
+    fp32-class, so the fp32 gate e_lambda <= 1e-4 holds, including the e^(-j/40) factors
+    without an identity floor, where rounding F to bf16 moves the Ritz values near the cut by
+    percents (lambda_256 / lambda_1 = e^-6.4 against the 2^-9 relative rounding of F)."""
+    if spec == "pow":
+        F = built_factor(d - 1, 128, 10, True, d)
+    else:
+        F = synth.psd_factor(d, synth.exp_spectrum(min(d, 2048)), 400 + d).astype(np.float32)
+    Ft = torch.from_numpy(F).to(DEV)
+    U, D, st = K().rand_eig(Ft, r, p, q, seed=0, stream_id=5, inversion_index=0, sketch="split")
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    Uo, Do = O.srevd(F.astype(np.float64), r, p, q, 0, 5, 0)
+    Ug = to_np(U)
+    assert e_lambda(to_np(D), Do) <= 1e-4, e_lambda(to_np(D), Do)
+    assert np.abs(Ug.T @ Ug - np.eye(r)).max() < 1e-5
+
+
 @pytest.mark.parametrize("d,r,p", [(24, 20, 8), (64, 64, 16), (256, 240, 16), (272, 256, 16), (10, 10, 0),
                                    (300, 280, 30), (1, 1, 0), (2, 1, 3)])
 def test_rand_eig_exact_regime(d, r, p):
