@@ -38,7 +38,8 @@ typedef enum {
   KFAC_EINVAL = 1,
   KFAC_EWORKSPACE = 2,
   KFAC_EHIP = 3,
-  KFAC_EUNSUPPORTED = 4
+  KFAC_EUNSUPPORTED = 4,
+  KFAC_ESCRATCH = 5     /* the allocation-free entry point's static scratch is too small */
 } kfac_status;
 
 typedef enum { KFAC_FP32 = 0, KFAC_BF16 = 1 } kfac_dtype;
@@ -166,6 +167,27 @@ kfac_status kfac_rand_eig(const float* F, int64_t d, int64_t ldf,
                           float* U, int64_t ldu, float* D,
                           void* workspace, size_t ws_bytes, int32_t* dev_status,
                           kfac_stream_t stream);
+
+/*
+ * kfac_rand_eig_noalloc -- kfac_rand_eig with no workspace argument and no allocation,
+ * for callers that cannot allocate device memory: code under hipGraph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same operation, arguments, outputs and
+ * errors as kfac_rand_eig; the scratch is a static device array of
+ * KFAC_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds until the process
+ * ends (its address is looked up once per device, on the first call with that device
+ * current).  Returns KFAC_ESCRATCH, before enqueueing anything, when
+ * kfac_rand_eig_workspace(d, r, p, q, v, prec) exceeds that size (e.g. d above ~8192 with
+ * the bf16 sketch at l = 272).  All calls on one GPU share the array: calls that overlap
+ * in time (different streams, host threads) race; calls on one stream are ordered.
+ */
+#define KFAC_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+kfac_status kfac_rand_eig_noalloc(const float* F, int64_t d, int64_t ldf,
+                                  const uint16_t* F_bf16, int64_t ldfb,
+                                  int64_t r, int64_t p, int q,
+                                  uint64_t seed, uint64_t stream_id, uint32_t inversion_index,
+                                  kfac_variant v, kfac_precision prec,
+                                  float* U, int64_t ldu, float* D,
+                                  int32_t* dev_status, kfac_stream_t stream);
 
 /*
  * kfac_precondition -- damped low-rank inverse application (Sec. 4.1 identity, the M and

@@ -8,7 +8,8 @@ import threading
 HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(HERE, "libkfac.so")
 
-KFAC_OK, KFAC_EINVAL, KFAC_EWORKSPACE, KFAC_EHIP, KFAC_EUNSUPPORTED = 0, 1, 2, 3, 4
+KFAC_OK, KFAC_EINVAL, KFAC_EWORKSPACE, KFAC_EHIP, KFAC_EUNSUPPORTED, KFAC_ESCRATCH = 0, 1, 2, 3, 4, 5
+NOALLOC_SCRATCH_BYTES = 128 << 20
 KFAC_FP32, KFAC_BF16 = 0, 1
 KFAC_SREVD, KFAC_RSVD = 0, 1
 KFAC_SKETCH_FP32, KFAC_SKETCH_BF16, KFAC_SKETCH_SPLIT = 0, 1, 2
@@ -27,6 +28,8 @@ SIGNATURES = {
     "kfac_rand_eig_workspace": (_sz, [_i64, _i64, _i64, _i, _i, _i]),
     "kfac_rand_eig": (_i, [_p, _i64, _i64, _p, _i64, _i64, _i64, _i, _u64, _u64, _u32, _i, _i,
                            _p, _i64, _p, _p, _sz, _p, _p]),
+    "kfac_rand_eig_noalloc": (_i, [_p, _i64, _i64, _p, _i64, _i64, _i64, _i, _u64, _u64, _u32, _i, _i,
+                                   _p, _i64, _p, _p, _p]),
     "kfac_precondition_workspace": (_sz, [_i64, _i64, _i64, _i64]),
     "kfac_precondition": (_i, [_p, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _f,
                                _p, _i64, _p, _sz, _p]),

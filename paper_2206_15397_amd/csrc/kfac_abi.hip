@@ -27,6 +27,7 @@ const char* kfac_status_string(kfac_status s) {
     case KFAC_EWORKSPACE: return "workspace too small";
     case KFAC_EHIP: return "HIP launch error";
     case KFAC_EUNSUPPORTED: return "unsupported configuration";
+    case KFAC_ESCRATCH: return "problem needs more scratch than the allocation-free entry point's static buffer holds";
   }
   return "unknown status";
 }

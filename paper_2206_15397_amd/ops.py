@@ -122,6 +122,27 @@ def rand_eig(F: torch.Tensor, r: int, p: int, q: int, seed: int, stream_id: int 
     return U, D, status
 
 
+def rand_eig_noalloc(F: torch.Tensor, r: int, p: int, q: int, seed: int, stream_id: int = 0,
+                     inversion_index: int = 0, sketch: str = "fp32", F_bf16: torch.Tensor = None,
+                     U: torch.Tensor = None, D: torch.Tensor = None, status=None):
+    """rand_eig through kfac_rand_eig_noalloc: no workspace, the library's static scratch.
+    U, D and status must be given by callers that allocate nothing during the call."""
+    _require_cuda(F, F_bf16, U, D, status)
+    d = F.shape[0]
+    prec = _prec(sketch)
+    if U is None:
+        U = torch.empty((d, r), dtype=torch.float32, device=F.device)
+    if D is None:
+        D = torch.empty((r,), dtype=torch.float32, device=F.device)
+    if status is None:
+        status = torch.zeros((1,), dtype=torch.int32, device=F.device)
+    check("kfac_rand_eig_noalloc", lib().kfac_rand_eig_noalloc(
+        _ptr(F), d, F.stride(0), _ptr(F_bf16), 0 if F_bf16 is None else F_bf16.stride(0),
+        int(r), int(p), int(q), int(seed), int(stream_id), int(inversion_index), _lib.KFAC_SREVD, prec,
+        _ptr(U), U.stride(0), _ptr(D), _ptr(status), _stream()))
+    return U, D, status
+
+
 def precondition_workspace_bytes(d_g, d_a, r_a, r_g) -> int:
     return int(lib().kfac_precondition_workspace(d_g, d_a, r_a, r_g))
 

@@ -92,6 +92,24 @@ def test_rand_eig_validation(L):
     assert call(r=400, p=200, d=1000, ldf=1000, ldu=400) == 4   # sketch wider than supported
 
 
+def test_rand_eig_noalloc_validation(L):
+    # validation and the scratch-size check happen on the host, before any device call
+    def call(**kw):
+        a = dict(F=FAKE, d=100, ldf=100, Fb=P(0), ldfb=0, r=10, p=5, q=1, v=0, prec=0, U=FAKE, ldu=10, D=FAKE,
+                 st=FAKE)
+        a.update(kw)
+        return L.kfac_rand_eig_noalloc(a["F"], a["d"], a["ldf"], a["Fb"], a["ldfb"], a["r"], a["p"], a["q"], 0,
+                                       0, 0, a["v"], a["prec"], a["U"], a["ldu"], a["D"], a["st"], P(0))
+    assert call(r=0) == 1
+    assert call(r=101) == 1
+    assert call(p=-1) == 1
+    from paper_2206_15397_amd import _lib
+    big = L.kfac_rand_eig_workspace(16384, 256, 16, 2, 0, 1)
+    assert big > _lib.NOALLOC_SCRATCH_BYTES
+    assert call(d=16384, ldf=16384, Fb=FAKE, ldfb=16384, r=256, p=16, q=2, prec=1, ldu=256) == _lib.KFAC_ESCRATCH
+    assert b"scratch" in L.kfac_status_string(_lib.KFAC_ESCRATCH)
+
+
 def test_precondition_validation(L):
     ws = L.kfac_precondition_workspace(8, 9, 3, 2)
     assert ws > 0
