@@ -46,16 +46,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--streams", type=int, default=0,
                     help="also time per-factor calls spread over this many streams (0: skip)")
-    ap.add_argument("--branches", type=int, default=1,
+    ap.add_argument("--branches", type=int, default=4,
                     help="concurrent branches (streams) of the grouped plan, 1..4")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the oracle leg (CPU baseline timing and parity of the timed outputs)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default GEMM tile configurations")
-    ap.add_argument("--config", choices=["vgg", "wide", "batched64", "copy"], default="vgg",
+    ap.add_argument("--config", choices=["vgg", "wide", "batched64", "copy", "vgg_ea"], default="vgg",
                     help="vgg: VGG16_bn factor set (default); wide: one d x d factor (--d); "
                          "batched64: 64 factors of log-uniform sizes 64..8192; copy: a plain 1 GiB "
-                         "device copy that calibrates the HBM byte counters of rocprofv3")
+                         "device copy that calibrates the HBM byte counters of rocprofv3; vgg_ea: the "
+                         "VGG16_bn EA phase alone (counter harness)")
     ap.add_argument("--d", type=int, default=16384, help="factor size of --config wide")
     ap.add_argument("--full-eig", action="store_true", help="--config wide: also time torch.linalg.eigh")
     return ap.parse_args()
@@ -812,6 +813,37 @@ def main_batched64(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def main_vgg_ea(args):
+    """Counter harness for the EA phase: the VGG16_bn factor set's EA inputs (bf16 activation
+    rows of the real shapes, drawn on the host with numpy: no device linear-algebra library
+    runs during setup) in a plan with only its EA phase, launched --steps times.  Traffic
+    counters do not depend on the values, so these stand in for the benchmark's inputs."""
+    import numpy as np
+    import torch
+    import paper_2206_15397_amd as K
+    from paper_2206_15397_amd import synth
+    dev = torch.device("cuda:0")
+    wl = synth.vgg16_bn_workload()
+    rng = np.random.default_rng(7)
+    fd, keep = [], []
+    for li, s_ in enumerate(wl.layers):
+        for d, din, bias in ((s_.d_a, s_.m_a, s_.bias), (s_.d_g, s_.d_g, False)):
+            F = K.fill_identity(torch.empty((d, d), device=dev))
+            X = torch.from_numpy(rng.standard_normal((s_.n, din), dtype=np.float32)).to(dev).to(torch.bfloat16)
+            keep += [F, X]
+            fd.append(dict(F=F, F_bf16=K.bf16_shadow(F), X=X, append_ones=bias, scale=1.0 / s_.n,
+                           r=min(wl.r_cap, d), p=wl.p, q=wl.q, stream_id=len(fd)))
+    plan = K.Plan(fd, [], sketch="bf16")
+    plan.set_scalars(wl.rho, wl.lam, wl.seed, 0, do_ea=True, do_eig=False, do_precondition=False).upload()
+    names = plan.launch_names()
+    for _ in range(max(1, args.steps)):
+        plan.launch()
+    torch.cuda.synchronize()
+    print(json.dumps({"harness": "vgg16_bn EA phase", "launches": names, "steps": max(1, args.steps),
+                      "work": [plan.launch_work(i) for i in range(len(names))],
+                      "src": K.lib().kfac_build_info().decode().rsplit(" src ", 1)[-1]}), flush=True)
+
+
 def main_copy(args):
     """Counter calibration: a plain elementwise copy (1 GiB read, 1 GiB written per launch)."""
     import torch
@@ -834,6 +866,8 @@ def main():
         sys.exit(2)
     if args.config == "copy":
         return main_copy(args)
+    if args.config == "vgg_ea":
+        return main_vgg_ea(args)
     if args.config != "vgg":
         import torch
         import paper_2206_15397_amd as K

@@ -315,9 +315,11 @@ kfac_status kfac_plan_launch_work(const kfac_plan* plan, int index, double* flop
  * (64x64, 128x128, 96x128, 128x64, and 288x64 over the whole sketch width where M <= 288 and
  * no operand is transposed), and for every bf16 sketch / power-iteration launch each
  * kernel (96x128 tiles, or full-sketch-width tiles with split-K and its reduction), over
- * `reps` launches after one warm-up, and keeps the fastest; then uploads the tables again.  Results are keyed by the launch's shapes (layout
- * and every task's M, N, K) and appended to the text file `cache_path` (nullable), whose
- * entries are reused without timing.  Runs kernels and synchronises the stream: call it
+ * `reps` launches after one warm-up, and keeps the fastest; then uploads the tables again.
+ * Results are keyed by a hash of the library's sources and build flags, the device
+ * architecture, the HIP runtime version and the launch's shapes (layout and every task's
+ * M, N, K), and appended to the text file `cache_path` (nullable), whose entries are
+ * reused without timing.  Runs kernels and synchronises the stream: call it
  * after kfac_plan_upload's arguments are final and outside any graph capture.  The tuned
  * launches write only buffers that later launches of the step overwrite (workspace, U, S).
  * With the environment variable KFAC_AUTOTUNE_VERBOSE set (non-zero), every candidate's

@@ -44,6 +44,7 @@ __device__ __forceinline__ float f4_elem(const float4& v, int j) {
 
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 struct TileF32 {
+  static constexpr int BM_ = BM, BN_ = BN, BK_ = BK;
   static constexpr int NT = WM * WN * kWave;
   static constexpr int FM = BM / WM / 16;
   static constexpr int FN = BN / WN / 16;
@@ -167,7 +168,7 @@ struct TileF32 {
   }
 
   // acc += A[m0:m0+BM, kb:ke] * B[kb:ke, n0:n0+BN]; two LDS buffers, one barrier per k-step.
-  __device__ static void run(const GemmP& p, int m0, int n0, int kb, int ke, Smem& sm, f32x4 acc[FM][FN]) {
+  __device__ static __forceinline__ void run(const GemmP& p, int m0, int n0, int kb, int ke, Smem& sm, f32x4 acc[FM][FN]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int am = wm * (BM / WM) + (lane & 15), bn = wn * (BN / WN) + (lane & 15);
@@ -233,6 +234,52 @@ __device__ __forceinline__ void upper_tile(int t, int T, int& I, int& J) {
   int i = 0, rem = t;
   while (rem >= T - i) { rem -= T - i; ++i; }
   I = i; J = i + rem;
+}
+
+// Generic GEMM on tile type T (TileF32): block (bx, by) computes
+// C[by*BM : , bx*BN : ].  With ksplit > 1, by also names the K slice (by = slice * tile rows
+// + tile row) and the raw tile goes to slice `slice` of the partial sums (ksplit x M x N,
+// row-major), to be finished by the slice-reduction kernel, which applies the epilogue.
+template <typename T, bool SPLIT = false>
+__device__ __forceinline__ void gemm_tile_body(const GemmP& p, int bx, int by) {
+  constexpr int BM = T::BM_, BN = T::BN_, BK = T::BK_;
+  __shared__ typename T::Smem sm;
+  int kb = 0, ke = p.K, slice = 0;
+  if constexpr (SPLIT) {
+    if (p.ksplit > 1) {
+      const int ty = (p.M + BM - 1) / BM;
+      slice = by / ty;
+      by -= slice * ty;
+      const int kc = ((p.K + p.ksplit - 1) / p.ksplit + BK - 1) / BK * BK;
+      kb = min(p.K, slice * kc);
+      ke = min(p.K, kb + kc);
+    }
+  }
+  const int m0 = by * BM, n0 = bx * BN;
+  f32x4 acc[T::FM][T::FN];
+#pragma unroll
+  for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  T::run(p, m0, n0, kb, ke, sm, acc);
+  if (SPLIT && p.ksplit > 1) {
+    float* part = p.part + (long)slice * p.M * p.N;
+    T::for_each(acc, [&](int r, int c, float v) {
+      const int i = m0 + r, j = n0 + c;
+      if (i < p.M && j < p.N) part[(long)i * p.N + j] = v;
+    });
+    return;
+  }
+  T::for_each(acc, [&](int r, int c, float v) {
+    int i = m0 + r, j = n0 + c;
+    if (i >= p.M || j >= p.N) return;
+    float s = p.alpha * v;
+    if (p.rowD) s *= damp_weight(p.rowD[i], p.lam);
+    if (p.colD) s *= damp_weight(p.colD[j], p.lam);
+    if (p.X) s += p.beta * p.X[(long)i * p.ldx + j];
+    p.C[(long)i * p.ldc + j] = s;
+    if (p.Cb) p.Cb[(long)i * p.ldcb + j] = f32_to_bf16_rne(s);
+  });
 }
 
 }  // namespace kfac

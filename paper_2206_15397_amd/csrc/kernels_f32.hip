@@ -16,45 +16,10 @@ __global__ void k_fill_identity(float* F, int d, long ldf) {
 }
 
 // ------------------------------------------------------------------------------------
-// Generic GEMM: block (bx, by) computes C[by*BM : , bx*BN : ].  With ksplit > 1, by also
-// names the K slice (by = slice * tile rows + tile row) and the raw tile goes to slice
-// `slice` of the partial sums (ksplit x M x N, row-major), to be finished by
-// gemm_slices_body.
+// Generic GEMM body (gemm_tile_body in gemm_f32.h) on fp32 MFMA tiles.
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT = false>
 __device__ __forceinline__ void gemm_body(const GemmP& p, int bx, int by) {
-  using T = TileF32<BM, BN, BK, WM, WN, TA, TB>;
-  __shared__ typename T::Smem sm;
-  int kb = 0, ke = p.K, slice = 0;
-  if constexpr (SPLIT) {
-    if (p.ksplit > 1) {
-      const int ty = (p.M + BM - 1) / BM;
-      slice = by / ty;
-      by -= slice * ty;
-      const int kc = ((p.K + p.ksplit - 1) / p.ksplit + BK - 1) / BK * BK;
-      kb = min(p.K, slice * kc);
-      ke = min(p.K, kb + kc);
-    }
-  }
-  const int m0 = by * BM, n0 = bx * BN;
-  f32x4 acc[T::FM][T::FN];
-#pragma unroll
-  for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < T::FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  T::run(p, m0, n0, kb, ke, sm, acc);
-  const bool split = SPLIT && p.ksplit > 1;
-  float* part = p.part + (long)slice * p.M * p.N;
-  T::for_each(acc, [&](int r, int c, float v) {
-    int i = m0 + r, j = n0 + c;
-    if (i >= p.M || j >= p.N) return;
-    if (split) { part[(long)i * p.N + j] = v; return; }
-    float s = p.alpha * v;
-    if (p.rowD) s *= damp_weight(p.rowD[i], p.lam);
-    if (p.colD) s *= damp_weight(p.colD[j], p.lam);
-    if (p.X) s += p.beta * p.X[(long)i * p.ldx + j];
-    p.C[(long)i * p.ldc + j] = s;
-    if (p.Cb) p.Cb[(long)i * p.ldcb + j] = f32_to_bf16_rne(s);
-  });
+  gemm_tile_body<TileF32<BM, BN, BK, WM, WN, TA, TB>, SPLIT>(p, bx, by);
 }
 
 // Split-K finish: 1024 consecutive elements of C per block; slices summed in index order,

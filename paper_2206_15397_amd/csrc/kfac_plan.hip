@@ -897,9 +897,27 @@ int kfac_plan_launch_branch(const kfac_plan* plan, int index) {
 // ---- autotuner ---------------------------------------------------------------------------
 namespace {
 
-// Shape key of a grouped fp32 GEMM launch: layout flags and every task's (M, N, K), hashed.
-std::string gemm_key(const kfac_plan* P, const LaunchRec& r) {
+#ifndef KFAC_SRC_HASH
+#define KFAC_SRC_HASH "unknown"
+#endif
+
+// What a stored timing is valid for: the library sources and build flags, the device
+// architecture and the HIP runtime version.
+uint64_t build_env_hash() {
   uint64_t h = 1469598103934665603ull;
+  auto mixs = [&](const char* str) { for (; str && *str; ++str) { h ^= (unsigned char)*str; h *= 1099511628211ull; } };
+  mixs(KFAC_SRC_HASH);
+  int dev = 0, rt = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) mixs(prop.gcnArchName);
+  if (hipRuntimeGetVersion(&rt) == hipSuccess) { h ^= (uint64_t)rt; h *= 1099511628211ull; }
+  return h;
+}
+
+// Cache key of a tunable launch: the build / device / runtime hash, layout flags and every
+// task's (M, N, K), hashed.
+std::string gemm_key(const kfac_plan* P, const LaunchRec& r) {
+  uint64_t h = build_env_hash();
   auto mix = [&](uint64_t v) { h ^= v; h *= 1099511628211ull; };
   mix((uint64_t)r.ta); mix((uint64_t)r.tb); mix((uint64_t)r.ntasks);
   const char* base = P->tab.bytes.data() + r.tasks_off;

@@ -85,9 +85,11 @@ def check_factor(tag, F_post, F_pre, X, append_ones, n, rho, U, D, r, p, q, seed
 # ~1e-3, split-bf16 products (~1e-5 relative, the dropped lo x lo term and the 8-bit lo
 # parts) and bf16 products ~1e-2
 FLAT_TOL = {"fp32": 5e-3, "split": 2e-2, "bf16": 2e-2}
+# the damped inverse on the GPU's own (U, D): fp32 MFMA products
+STAGE_TOL = {"fp32": 1e-5, "split": 1e-5, "bf16": 1e-5}
 
 
-def check_layer(tag, J, S, Ua, Da, Ug, Dg, oa, og, lam, tol, flat):
+def check_layer(tag, J, S, Ua, Da, Ug, Dg, oa, og, lam, tol, flat, stage_tol=1e-5):
     J64, S64 = to_np(J), to_np(S)
     Ua64, Da64, Ug64, Dg64 = to_np(Ua), to_np(Da), to_np(Ug), to_np(Dg)
     stage = rel(S64, O.precondition(J64, Ua64, Da64, Ug64, Dg64, lam))
@@ -97,7 +99,7 @@ def check_layer(tag, J, S, Ua, Da, Ug, Dg, oa, og, lam, tol, flat):
            "dD_damped": float(max(np.max(np.abs(Da64 - oa[1]) / (oa[1] + lam)),
                                   np.max(np.abs(Dg64 - og[1]) / (og[1] + lam))))}
     record(**out)
-    assert stage <= 1e-5, out
+    assert stage <= stage_tol, out
     assert out["e_S"] <= (tol if sep else flat), out
 
 
@@ -128,7 +130,7 @@ def test_vgg16_bn_plan_layer_matches_oracle(vgg_plan, li):
     og = check_factor(f"vgg_plan_{sketch}/{L.shape.name}/G", L.G, L.G0, L.g, False, L.n, wl.rho, L.Ug, L.Dg, L.rg,
                       wl.p, wl.q, wl.seed, 2 * li + 1, tol, F_bf16=L.Gb if sh else None)
     check_layer(f"vgg_plan_{sketch}/{L.shape.name}", L.J, L.S, L.Ua, L.Da, L.Ug, L.Dg, oa, og, wl.lam, tol,
-                FLAT_TOL[sketch])
+                FLAT_TOL[sketch], stage_tol=STAGE_TOL[sketch])
 
 
 # ---- VGG16_bn factor set: the plain per-layer fp32 path (the bench's comparator) -----------
@@ -206,4 +208,4 @@ def test_batched64_layers_match_oracle(batched64, grp):
                                      f["p"], f["q"], 0, i, 1e-4)
         fa, fg = plan.factors[lay["fa"]], plan.factors[lay["fg"]]
         check_layer(f"batched64/l{j}", lay["J"], lay["S"], fa["U"], fa["D"], fg["U"], fg["D"], ors["fa"], ors["fg"],
-                    0.1, 1e-4, FLAT_TOL[bench.BATCHED64_SKETCH])
+                    0.1, 1e-4, FLAT_TOL[bench.BATCHED64_SKETCH], stage_tol=STAGE_TOL[bench.BATCHED64_SKETCH])
