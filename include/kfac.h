@@ -246,6 +246,43 @@ kfac_status kfac_linear_backward(const uint16_t* g, int64_t n, int64_t d_out, in
                                  float rho, float scale, kfac_stream_t stream);
 
 /*
+ * K-FAC convolution layer (the KFC factors that K-FAC uses for convolutions, Sec. 2.1; the
+ * paper's VGG16_bn experiments of Sec. 5 are convolutional).  The input factor of a
+ * convolution is the EA of the im2col patches of its input: one row per output position
+ * (b, oh, ow), the columns ordered (dy, dx, c) -- tap-major, channel-minor -- plus the bias
+ * column.  The patches are read straight from the NHWC input by the kernels' loaders and are
+ * never materialised.
+ *  kfac_conv_geom: input x is batch x height x width x channels, NHWC bf16 (contiguous);
+ *  kernel kh x kw, zero padding `pad`, stride `stride`; output height
+ *  (height + 2 pad - kh) / stride + 1, width likewise.  n = batch * out_h * out_w rows.
+ *
+ * kfac_conv_ea_update: F <- rho F + (1 - rho) scale [P | 1]^T [P | 1] (as kfac_ea_update
+ *   with X = P, the n x (kh kw channels) patch matrix); d = kh kw channels + append_ones.
+ *   workspace: kfac_conv_ea_update_workspace(d, geom) bytes (NULL / 0 disables split-K).
+ * kfac_conv_backward_weight: [dW | db] = g^T [P | 1] (fp32, c_out x (kh kw channels +
+ *   with_bias), lddw >= that; dW's columns in the patch order above, db last) from the output
+ *   gradient g (n x c_out, i.e. NHWC batch x out_h x out_w x c_out, bf16), with the
+ *   backward factor's EA Gamma <- rho Gamma + (1 - rho) scale g^T g fused into the same launch
+ *   (skipped when Gamma == NULL; Gamma_bf16 nullable).
+ * Errors: KFAC_EINVAL for null required pointers, non-positive sizes, an empty output, a
+ * short leading dimension or d != kh kw channels + append_ones; KFAC_EUNSUPPORTED beyond
+ * 32-bit indexing.
+ */
+typedef struct {
+  int64_t batch, height, width, channels;
+  int64_t kh, kw, pad, stride;
+} kfac_conv_geom;
+
+size_t kfac_conv_ea_update_workspace(int64_t d, const kfac_conv_geom* geom);
+kfac_status kfac_conv_ea_update(float* F, int64_t d, int64_t ldf, const uint16_t* x, const kfac_conv_geom* geom,
+                                int append_ones, float rho, float scale, uint16_t* F_bf16, int64_t ldfb,
+                                void* workspace, size_t ws_bytes, kfac_stream_t stream);
+kfac_status kfac_conv_backward_weight(const uint16_t* g, int64_t c_out, const uint16_t* x,
+                                      const kfac_conv_geom* geom, float* dWb, int64_t lddw, int with_bias,
+                                      float* Gamma, int64_t ldgam, uint16_t* Gamma_bf16, int64_t ldgb,
+                                      float rho, float scale, kfac_stream_t stream);
+
+/*
  * Grouped plan -- one K-factor step of a whole network (all factors and layers) as a
  * fixed sequence of grouped launches: every launch covers one phase (EA tiles, sketch
  * GEMM, Gram, Cholesky, eigensolver stage, preconditioner product, ...) of every factor or

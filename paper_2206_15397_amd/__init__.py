@@ -12,11 +12,12 @@ import os
 
 from ._lib import (KFAC_BF16, KFAC_FP32, KFAC_SKETCH_BF16, KFAC_SKETCH_FP32, KFAC_SREVD,
                    KFAC_RSVD, STATUS_BITS, KfacError, lib, library_path)
-from .ops import (Plan, bf16_shadow, ea_update, fill_identity, gaussian_omega, precondition, rand_eig,
-                  rand_eig_noalloc, rand_eig_workspace_bytes, precondition_workspace_bytes)
+from .ops import (Plan, bf16_shadow, conv_backward_weight, conv_ea_update, ea_update, fill_identity,
+                  gaussian_omega, precondition, rand_eig, rand_eig_noalloc, rand_eig_workspace_bytes,
+                  precondition_workspace_bytes)
 
 __all__ = [
     "ea_update", "fill_identity", "gaussian_omega", "rand_eig", "rand_eig_noalloc", "precondition", "lib",
     "library_path", "KfacError", "rand_eig_workspace_bytes", "precondition_workspace_bytes",
-    "STATUS_BITS", "Plan", "bf16_shadow",
+    "STATUS_BITS", "Plan", "bf16_shadow", "conv_ea_update", "conv_backward_weight",
 ]

@@ -36,6 +36,9 @@ SIGNATURES = {
     "kfac_linear_forward": (_i, [_p, _i64, _i64, _i64, _p, _i64, _i64, _p, _p, _i64, _p]),
     "kfac_linear_backward": (_i, [_p, _i64, _i64, _i64, _p, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i,
                                   _p, _i64, _p, _i64, _f, _f, _p]),
+    "kfac_conv_ea_update_workspace": (_sz, [_i64, _p]),
+    "kfac_conv_ea_update": (_i, [_p, _i64, _i64, _p, _p, _i, _f, _f, _p, _i64, _p, _sz, _p]),
+    "kfac_conv_backward_weight": (_i, [_p, _i64, _p, _p, _p, _i64, _i, _p, _i64, _p, _i64, _f, _f, _p]),
     "kfac_plan_create": (_i, [_p, _i, _p, _i, _i, _p]),
     "kfac_plan_workspace": (_sz, [_p]),
     "kfac_plan_set_scalars": (_i, [_p, _f, _f, _u64, _u32, _i, _i, _i]),
@@ -60,6 +63,12 @@ class FactorDesc(ctypes.Structure):
                 ("r", _i64), ("p", _i64), ("q", _i), ("stream_id", _u64),
                 ("X", _p), ("xtype", _i), ("n", _i64), ("d_in", _i64), ("ldx", _i64),
                 ("append_ones", _i), ("scale", _f), ("U", _p), ("ldu", _i64), ("D", _p), ("variant", _i)]
+
+
+class ConvGeom(ctypes.Structure):
+    """Mirror of kfac_conv_geom (include/kfac.h)."""
+    _fields_ = [("batch", _i64), ("height", _i64), ("width", _i64), ("channels", _i64),
+                ("kh", _i64), ("kw", _i64), ("pad", _i64), ("stride", _i64)]
 
 
 class LayerDesc(ctypes.Structure):

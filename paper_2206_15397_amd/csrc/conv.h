@@ -1,0 +1,52 @@
+// im2col addressing of a convolution's patch matrix (ConvGeom in tasks.h), read straight
+// from the NHWC input by the loaders of the EA and weight-gradient kernels: the patches
+// are never materialised.
+#pragma once
+#include "tasks.h"
+
+namespace kfac {
+
+__host__ __device__ inline int conv_out(int in, int k, int pad, int stride) { return (in + 2 * pad - k) / stride + 1; }
+
+// Rows [k0, k0+8) x columns [c0, c0+8) of [P | 1] (P: the im2col patches, n = B Ho Wo rows,
+// kh kw C columns; the ones column at index kh kw C when `ones`), zero beyond row K.
+// Eight columns of one tap are eight consecutive channels of one input pixel: one 16-byte
+// load when g.vec (C a multiple of 8, x 16-byte aligned), element loads otherwise.
+__device__ __forceinline__ void im2col_block(const uint16_t* x, const ConvGeom& g, bool ones, int k0, int K, int c0,
+                                             uint4 v[8]) {
+  const int ncols = g.kh * g.kw * g.C;
+  const int howo = g.Ho * g.Wo;
+  const bool vec8 = g.vec && c0 + 8 <= ncols;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int k = k0 + r;
+    v[r] = make_uint4(0, 0, 0, 0);
+    if (k >= K) continue;
+    const int b = k / howo, rem = k - b * howo, oh = rem / g.Wo, ow = rem - oh * g.Wo;
+    const int ih0 = oh * g.stride - g.pad, iw0 = ow * g.stride - g.pad;
+    if (vec8) {
+      const int tap = c0 / g.C, c = c0 - tap * g.C, dy = tap / g.kw, dx = tap - dy * g.kw;
+      const int ih = ih0 + dy, iw = iw0 + dx;
+      if (ih >= 0 && ih < g.H && iw >= 0 && iw < g.W)
+        v[r] = *(const uint4*)(x + (((long)b * g.H + ih) * g.W + iw) * g.C + c);
+    } else {
+      uint16_t t[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int col = c0 + j;
+        t[j] = 0;
+        if (col < ncols) {
+          const int tap = col / g.C, c = col - tap * g.C, dy = tap / g.kw, dx = tap - dy * g.kw;
+          const int ih = ih0 + dy, iw = iw0 + dx;
+          if (ih >= 0 && ih < g.H && iw >= 0 && iw < g.W) t[j] = x[(((long)b * g.H + ih) * g.W + iw) * g.C + c];
+        } else if (ones && col == ncols) {
+          t[j] = 0x3f80;                       // bf16 1.0
+        }
+      }
+      v[r] = make_uint4(t[0] | ((uint32_t)t[1] << 16), t[2] | ((uint32_t)t[3] << 16),
+                        t[4] | ((uint32_t)t[5] << 16), t[6] | ((uint32_t)t[7] << 16));
+    }
+  }
+}
+
+}  // namespace kfac

@@ -1,6 +1,7 @@
 // bf16 kernels: the sketch / power-iteration product of Alg. 3 in bf16 with fp32
 // accumulation (v_mfma_f32_16x16x32_bf16), and the EA update for bf16 activations.
 #include "kernels.h"
+#include "conv.h"
 
 namespace kfac {
 
@@ -192,7 +193,8 @@ __device__ __forceinline__ void eb_load_block(const uint16_t* X, long ldx, int d
   }
 }
 
-template <int DUMMY = 0>
+// CONV: the rows are the im2col patches of q.cv's NHWC input (the guarded stage path only)
+template <bool CONV = false>
 __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int by) {
   __shared__ EbSmem sm;
   const GemmP& p = q.g;
@@ -219,11 +221,14 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   uint4 v[8];
+  constexpr bool conv = CONV;
   // a thread's 8 x 8 block lies inside the activations (no ones column, no padding): its
   // 8 row loads of full 64-row stages go out unguarded
-  const bool inner = vec && (c0 + 8 <= d_in);
+  const bool inner = !conv && vec && (c0 + 8 <= d_in);
   auto fetch = [&](int k0) {
-    if (inner && k0 + EB_BK <= ke) {
+    if constexpr (CONV) {
+      im2col_block(X, q.cv, ones, k0 + rg * 8, ke, c0, v);
+    } else if (inner && k0 + EB_BK <= ke) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = gload16(X + (long)(k0 + rg * 8 + r) * ldx + c0);
     } else {
@@ -263,7 +268,7 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
     const int lo = P * EB_BT, hi = lo + EB_BT;
     return (d_in & 7) == 0 || d_in <= lo || d_in >= hi;
   };
-  const bool piped = vec && d_in >= 8 && panel_clean(I) && panel_clean(J) &&
+  const bool piped = !conv && vec && d_in >= 8 && panel_clean(I) && panel_clean(J) &&
                      (long)(ke - kb) * ldx * 2 < (1L << 31);
   if (piped) {
     // Full 64-row stages, two stages in flight in registers (va, vb) while the MFMAs run
@@ -412,6 +417,10 @@ __global__ __launch_bounds__(256) void k_ea_bf16_tiles(EaTask q) {
   const int l = xcd_swizzle(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
   ea_bf16_tiles_body(q, l % gridDim.x, l / gridDim.x);
 }
+__global__ __launch_bounds__(256) void k_ea_bf16_tiles_conv(EaTask q) {
+  const int l = xcd_swizzle(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  ea_bf16_tiles_body<true>(q, l % gridDim.x, l / gridDim.x);
+}
 __global__ __launch_bounds__(256) void k_ea_bf16_finalize(EaTask q) { ea_bf16_finalize_body(q, blockIdx.x, 0); }
 // grouped EA tiles: per-task block counts padded to multiples of 8 (the padding blocks
 // have slice index >= nks and exit)
@@ -424,7 +433,8 @@ __global__ __launch_bounds__(256) void k_ea_bf16_tiles_g(const EaTask* tasks, Gr
 KFAC_GROUPED_KERNEL(k_ea_bf16_finalize_g, ea_bf16_finalize_body, EaTask, 256)
 
 hipError_t launch_ea_bf16_tiles(const EaTask& q, int tiles, int ks, hipStream_t s) {
-  hipLaunchKernelGGL(k_ea_bf16_tiles, dim3(tiles, ks), dim3(256), 0, s, q);
+  if (q.cv.C > 0) hipLaunchKernelGGL(k_ea_bf16_tiles_conv, dim3(tiles, ks), dim3(256), 0, s, q);
+  else hipLaunchKernelGGL(k_ea_bf16_tiles, dim3(tiles, ks), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 hipError_t launch_ea_bf16_finalize(const EaTask& q, int tiles, hipStream_t s) {

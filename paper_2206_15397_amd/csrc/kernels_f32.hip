@@ -320,7 +320,7 @@ size_t ea_workspace_bytes(int d, long n) {
 
 static hipError_t launch_ea_common(float* F, int d, long ldf, const float* X, const uint16_t* Xb, int n,
                                    int d_in, long ldx, int ones, float rho, float scale, uint16_t* Fb, long ldfb,
-                                   void* ws, size_t ws_bytes, hipStream_t s) {
+                                   void* ws, size_t ws_bytes, hipStream_t s, const ConvGeom* cv = nullptr) {
   if (n == 0) {
     long total = (long)d * d;
     int blocks = (int)std::min<long>((total + 255) / 256, 4096);
@@ -332,6 +332,7 @@ static hipError_t launch_ea_common(float* F, int d, long ldf, const float* X, co
   int ks = ea_choose_ksplit(d, n, bf);
   if (ks > 1 && (ws == nullptr || ws_bytes < ea_workspace_bytes(d, n, bf))) ks = 1;
   EaTask q = make_ea_task(F, d, ldf, X, Xb, n, d_in, ldx, ones, rho, scale, Fb, ldfb, (float*)ws, ks);
+  if (cv) q.cv = *cv;
   const int tiles = q.T * (q.T + 1) / 2;
   if (bf) {
     hipError_t e = launch_ea_bf16_tiles(q, tiles, ks, s);
@@ -353,6 +354,12 @@ hipError_t launch_ea_bf16(float* F, int d, long ldf, const uint16_t* X, int n, i
                           float rho, float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes,
                           hipStream_t s) {
   return launch_ea_common(F, d, ldf, nullptr, X, n, d_in, ldx, ones, rho, scale, Fb, ldfb, ws, ws_bytes, s);
+}
+
+hipError_t launch_ea_bf16_conv(float* F, int d, long ldf, const uint16_t* x, const ConvGeom& cv, int ones, float rho,
+                               float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes, hipStream_t s) {
+  const int n = cv.B * cv.Ho * cv.Wo, d_in = cv.kh * cv.kw * cv.C;
+  return launch_ea_common(F, d, ldf, nullptr, x, n, d_in, 0, ones, rho, scale, Fb, ldfb, ws, ws_bytes, s, &cv);
 }
 
 OmegaTask make_omega_task(int d, int l, int d_pad, int l_pad, uint64_t seed, uint64_t stream_id, uint32_t inv,

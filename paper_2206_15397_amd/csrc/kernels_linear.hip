@@ -9,6 +9,7 @@
 // LDS buffers.  Operands whose contraction index is the row index (K-major) are loaded as
 // 8 x 8 blocks and transposed in registers, so LDS always holds k-contiguous rows.
 #include "kernels.h"
+#include "conv.h"
 
 namespace kfac {
 
@@ -85,15 +86,18 @@ struct LnOperand {
   int rows;        // M or N extent (K-contiguous) / stored columns (K-major)
   bool ones;       // K-major: implicit ones column at index `rows`
   bool vec;        // 16-byte loads allowed
+  ConvGeom cv;     // K-major, C > 0: X is an NHWC input read as its im2col patches
 };
 
-template <bool KMAJ>
+// CONV: a K-major operand may be im2col patches (o.cv.C > 0), decided per operand at run time
+template <bool KMAJ, bool CONV = false>
 struct LnLoader {
   uint4 v[8];
   __device__ __forceinline__ void load(const LnOperand& o, int tt, int r0, int k0, int K) {
     if (KMAJ) {
       const int cg = tt >> 3, rg = tt & 7;
-      ln_load_kmajor(o.X, o.ld, o.rows, o.ones, o.vec, k0 + rg * 8, K, r0 + cg * 8, v);
+      if (CONV && o.cv.C > 0) im2col_block(o.X, o.cv, o.ones, k0 + rg * 8, K, r0 + cg * 8, v);
+      else ln_load_kmajor(o.X, o.ld, o.rows, o.ones, o.vec, k0 + rg * 8, K, r0 + cg * 8, v);
     } else {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -122,7 +126,7 @@ __device__ __forceinline__ bool ln_vec_ok(const uint16_t* X, long ld) {
 }
 
 // Block bx of a LinTask.  AK / BK: operand stored K-major (rows = contraction index).
-template <bool AK, bool BK>
+template <bool AK, bool BK, bool CONV = false>
 __device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
   __shared__ LinSmem sm;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -130,8 +134,9 @@ __device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
   const int nplain = q.tiles_m * q.tiles_n;
   const bool gam = bx >= nplain;
   int m0, n0, GI = 0, GJ = 0;
-  LnOperand oa{q.A, q.lda, q.M, false, ln_vec_ok(q.A, q.lda)};
-  LnOperand ob{q.B, q.ldb, BK ? (q.b_ones ? q.N - 1 : q.N) : q.N, BK && q.b_ones != 0, ln_vec_ok(q.B, q.ldb)};
+  LnOperand oa{q.A, q.lda, q.M, false, ln_vec_ok(q.A, q.lda), ConvGeom{}};
+  LnOperand ob{q.B, q.ldb, BK ? (q.b_ones ? q.N - 1 : q.N) : q.N, BK && q.b_ones != 0, ln_vec_ok(q.B, q.ldb),
+               CONV ? q.cv : ConvGeom{}};
   if (!gam) {
     m0 = (bx % q.tiles_m) * LN_T;
     n0 = (bx / q.tiles_m) * LN_T;
@@ -152,8 +157,8 @@ __device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   // one register set per thread: threads 0-127 fill the A tile, 128-255 the B tile (with
   // equal layouts a single loader object, so its registers are never selected at run time)
-  LnLoader<AK> la;
-  LnLoader<BK> lb;
+  LnLoader<AK, CONV> la;
+  LnLoader<BK, CONV> lb;
   auto fetch = [&](int k0) {
     if (!loader) return;
     if constexpr (AK == BK) {
@@ -235,6 +240,7 @@ __device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
 __global__ __launch_bounds__(256) void k_lin_nt(LinTask q) { lin_body<false, false>(q, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_lin_nn(LinTask q) { lin_body<false, true>(q, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_lin_tn(LinTask q) { lin_body<true, true>(q, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_lin_tn_conv(LinTask q) { lin_body<true, true, true>(q, blockIdx.x); }
 
 static LinTask lin_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, int b_ones,
                         float* C, long ldc, uint16_t* Cb, long ldcb, const float* bias) {
@@ -276,6 +282,25 @@ hipError_t launch_linear_backward(const uint16_t* g, int n, int d_out, long ldg,
     blocks += q.gam_T * (q.gam_T + 1) / 2;
   }
   if (blocks > 0) hipLaunchKernelGGL(k_lin_tn, dim3(blocks), dim3(256), 0, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_backward_weight(const uint16_t* g, const uint16_t* x, const ConvGeom& cv, int c_out,
+                                       float* dWb, long lddw, int with_bias, float* Gam, long ldgam, uint16_t* Gamb,
+                                       long ldgb, float rho, float scale, hipStream_t s) {
+  // [dW | db][c_out x (kh kw C + 1)] = g^T [P | 1]: A = g (n x c_out, K-major), B = the patches
+  // P (n x kh kw C, K-major, gathered from x), plus the upper tiles of g^T g for Gamma
+  const int n = cv.B * cv.Ho * cv.Wo;
+  const int N = cv.kh * cv.kw * cv.C + (with_bias ? 1 : 0);
+  LinTask q = lin_task(c_out, N, n, g, c_out, x, 0, with_bias, dWb, lddw, nullptr, 0, nullptr);
+  q.cv = cv;
+  int blocks = q.tiles_m * q.tiles_n;
+  if (Gam) {
+    q.gam = EaOut{Gam, ldgam, Gamb, ldgb, c_out, rho, (1.f - rho) * scale};
+    q.gam_T = q.tiles_m;
+    blocks += q.gam_T * (q.gam_T + 1) / 2;
+  }
+  if (blocks > 0) hipLaunchKernelGGL(k_lin_tn_conv, dim3(blocks), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 

@@ -297,3 +297,72 @@ kfac_status kfac_linear_backward(const uint16_t* g, int64_t n, int64_t d_out, in
 }
 
 }  // extern "C"
+
+namespace {
+// Validated device geometry of a kfac_conv_geom (false: invalid or beyond 32-bit indexing).
+bool conv_geom(const kfac_conv_geom* g, const void* x, ConvGeom& cv, kfac_status& err) {
+  err = KFAC_EINVAL;
+  if (!g || g->batch < 1 || g->height < 1 || g->width < 1 || g->channels < 1 || g->kh < 1 || g->kw < 1 ||
+      g->pad < 0 || g->stride < 1)
+    return false;
+  const int64_t ho = (g->height + 2 * g->pad - g->kh) / g->stride + 1;
+  const int64_t wo = (g->width + 2 * g->pad - g->kw) / g->stride + 1;
+  if (g->height + 2 * g->pad < g->kh || g->width + 2 * g->pad < g->kw || ho < 1 || wo < 1) return false;
+  const int64_t lim = (1LL << 31) - 1;
+  if (g->batch * g->height * g->width * g->channels > lim || g->batch * ho * wo > lim ||
+      g->kh * g->kw * g->channels > lim) {
+    err = KFAC_EUNSUPPORTED;
+    return false;
+  }
+  cv = ConvGeom{(int)g->batch, (int)g->height, (int)g->width, (int)g->channels, (int)g->kh, (int)g->kw,
+                (int)g->pad, (int)g->stride, (int)ho, (int)wo,
+                (g->channels % 8 == 0 && (((uintptr_t)x) & 15) == 0) ? 1 : 0};
+  return true;
+}
+}  // namespace
+
+extern "C" {
+
+size_t kfac_conv_ea_update_workspace(int64_t d, const kfac_conv_geom* geom) {
+  ConvGeom cv;
+  kfac_status err;
+  if (d < 1 || !conv_geom(geom, nullptr, cv, err)) return 0;
+  return ea_workspace_bytes((int)d, (long)cv.B * cv.Ho * cv.Wo);
+}
+
+kfac_status kfac_conv_ea_update(float* F, int64_t d, int64_t ldf, const uint16_t* x, const kfac_conv_geom* geom,
+                                int append_ones, float rho, float scale, uint16_t* F_bf16, int64_t ldfb,
+                                void* workspace, size_t ws_bytes, kfac_stream_t stream) {
+  ConvGeom cv;
+  kfac_status err;
+  if (!F || !x || d < 1 || ldf < d) return KFAC_EINVAL;
+  if (!conv_geom(geom, x, cv, err)) return err;
+  if (d != (int64_t)cv.kh * cv.kw * cv.C + (append_ones ? 1 : 0)) return KFAC_EINVAL;
+  if (!(rho >= 0.f && rho < 1.f) || !(scale > 0.f) || !std::isfinite(scale)) return KFAC_EINVAL;
+  if (F_bf16 && ldfb < d) return KFAC_EINVAL;
+  if (d > (1 << 20)) return KFAC_EUNSUPPORTED;
+  if (ws_bytes == 0) workspace = nullptr;
+  if (workspace && ws_bytes < kfac_conv_ea_update_workspace(d, geom)) return KFAC_EWORKSPACE;
+  return hip_status(launch_ea_bf16_conv(F, (int)d, ldf, x, cv, append_ones ? 1 : 0, rho, scale, F_bf16, ldfb,
+                                        workspace, ws_bytes, (hipStream_t)stream));
+}
+
+kfac_status kfac_conv_backward_weight(const uint16_t* g, int64_t c_out, const uint16_t* x,
+                                      const kfac_conv_geom* geom, float* dWb, int64_t lddw, int with_bias,
+                                      float* Gamma, int64_t ldgam, uint16_t* Gamma_bf16, int64_t ldgb, float rho,
+                                      float scale, kfac_stream_t stream) {
+  ConvGeom cv;
+  kfac_status err;
+  if (!g || !x || !dWb || c_out < 1) return KFAC_EINVAL;
+  if (!conv_geom(geom, x, cv, err)) return err;
+  if (lddw < (int64_t)cv.kh * cv.kw * cv.C + (with_bias ? 1 : 0)) return KFAC_EINVAL;
+  if (Gamma) {
+    if (ldgam < c_out || !(rho >= 0.f && rho < 1.f) || !(scale > 0.f)) return KFAC_EINVAL;
+    if (Gamma_bf16 && ldgb < c_out) return KFAC_EINVAL;
+  }
+  if (c_out > (1 << 20)) return KFAC_EUNSUPPORTED;
+  return hip_status(launch_conv_backward_weight(g, x, cv, (int)c_out, dWb, lddw, with_bias ? 1 : 0, Gamma, ldgam,
+                                                Gamma_bf16, ldgb, rho, scale, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -11,11 +11,23 @@ struct EaOut {
   float* F; long ldf; uint16_t* Fb; long ldfb; int d; float rho, c;
 };
 
+// Convolution geometry of an im2col operand: NHWC bf16 input x[B][H][W][C], kernel kh x kw,
+// zero padding `pad`, stride `stride`, output Ho x Wo.  Row k of the patch matrix is the
+// output position (b, oh, ow) = (k / (Ho Wo), (k / Wo) % Ho, k % Wo); column j is the tap
+// and channel (dy, dx, c) = (j / (kw C), (j / C) % kw, j % C), reading
+// x[b][oh stride - pad + dy][ow stride - pad + dx][c] (zero outside the image).  C == 0
+// marks an ordinary row-major operand.
+struct ConvGeom {
+  int B, H, W, C, kh, kw, pad, stride, Ho, Wo;
+  int vec;               // C % 8 == 0 and x 16-byte aligned: 8-channel runs as 16-byte loads
+};
+
 struct EaTask {          // EA update: block (upper tile, K slice)
   GemmP g;
   EaOut o;
   int T;                 // tiles per side
   int nks;               // K slices
+  ConvGeom cv;           // C > 0: the activations are the im2col patches of an NHWC input
 };
 
 struct OmegaTask {       // Gaussian test matrix: block (row block, column group)
@@ -74,6 +86,7 @@ struct LinTask {         // K-FAC linear layer GEMMs on bf16 MFMA: block (flat t
   int tiles_m, tiles_n;
   EaOut gam;             // fused backward-factor EA (upper tiles after the plain tiles)
   int gam_T;             // tiles per side of gam (0: none)
+  ConvGeom cv;           // C > 0: the K-major B operand is the im2col patches of B (NHWC)
 };
 
 struct GramP {           // C = A B^T in fp64 from fp32 rows: block (tile, K slice)

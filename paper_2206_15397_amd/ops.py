@@ -204,6 +204,62 @@ def linear_backward(g: torch.Tensor, x: torch.Tensor, W: torch.Tensor, with_bias
     return dx, dWb
 
 
+def _conv_geom(x: torch.Tensor, kh: int, kw: int, pad: int, stride: int):
+    """kfac_conv_geom of an NHWC bf16 input (batch, height, width, channels), contiguous."""
+    assert x.dim() == 4 and x.dtype == torch.bfloat16 and x.is_contiguous(), "x: contiguous NHWC bf16"
+    B, H, W, C = x.shape
+    return _lib.ConvGeom(B, H, W, C, int(kh), int(kw), int(pad), int(stride))
+
+
+def conv_out_size(h: int, k: int, pad: int, stride: int) -> int:
+    return (h + 2 * pad - k) // stride + 1
+
+
+def conv_ea_update(F: torch.Tensor, x: torch.Tensor, kh: int, kw: int, pad: int, stride: int, rho: float,
+                   scale: float = None, append_ones: bool = False, F_bf16: torch.Tensor = None,
+                   workspace=None) -> torch.Tensor:
+    """In place: F <- rho F + (1 - rho) scale [P|1]^T [P|1], P the im2col patches of the NHWC
+    input x (rows: output positions; columns: (dy, dx, c)); optionally refreshes F_bf16."""
+    import ctypes
+    _require_cuda(F, x, F_bf16)
+    g = _conv_geom(x, kh, kw, pad, stride)
+    n = x.shape[0] * conv_out_size(x.shape[1], kh, pad, stride) * conv_out_size(x.shape[2], kw, pad, stride)
+    if scale is None:
+        scale = 1.0 / max(n, 1)
+    L = lib()
+    d = F.shape[0]
+    if workspace is None:
+        ws_bytes = L.kfac_conv_ea_update_workspace(d, ctypes.byref(g))
+        workspace = _workspace(ws_bytes, F.device) if ws_bytes else None
+    ws_bytes = 0 if workspace is None else workspace.numel()
+    check("kfac_conv_ea_update", L.kfac_conv_ea_update(
+        _ptr(F), d, F.stride(0), _ptr(x), ctypes.byref(g), 1 if append_ones else 0, float(rho), float(scale),
+        _ptr(F_bf16), 0 if F_bf16 is None else F_bf16.stride(0), _ptr(workspace), ws_bytes, _stream()))
+    return F
+
+
+def conv_backward_weight(g: torch.Tensor, x: torch.Tensor, kh: int, kw: int, pad: int, stride: int,
+                         with_bias: bool = True, Gamma: torch.Tensor = None, Gamma_bf16: torch.Tensor = None,
+                         rho: float = 0.95, scale: float = None):
+    """[dW | db] = g^T [P | 1] (fp32, c_out x (kh kw C + with_bias), columns (dy, dx, c) then the
+    bias) from the NHWC output gradient g (batch, out_h, out_w, c_out; bf16) and the NHWC
+    input x; with Gamma, also Gamma <- rho Gamma + (1 - rho) scale g^T g in place (fused)."""
+    import ctypes
+    _require_cuda(g, x, Gamma, Gamma_bf16)
+    geo = _conv_geom(x, kh, kw, pad, stride)
+    assert g.dim() == 4 and g.dtype == torch.bfloat16 and g.is_contiguous()
+    c_out = g.shape[3]
+    ncol = kh * kw * x.shape[3] + (1 if with_bias else 0)
+    dWb = torch.empty((c_out, ncol), dtype=torch.float32, device=g.device)
+    if scale is None:
+        scale = 1.0 / max(g.shape[0] * g.shape[1] * g.shape[2], 1)
+    check("kfac_conv_backward_weight", lib().kfac_conv_backward_weight(
+        _ptr(g), c_out, _ptr(x), ctypes.byref(geo), _ptr(dWb), dWb.stride(0), 1 if with_bias else 0, _ptr(Gamma),
+        c_out if Gamma is None else Gamma.stride(0), _ptr(Gamma_bf16),
+        c_out if Gamma_bf16 is None else Gamma_bf16.stride(0), float(rho), float(scale), _stream()))
+    return dWb
+
+
 def bf16_shadow(F: torch.Tensor) -> torch.Tensor:
     """bf16 copy of F whose row pitch is a multiple of 64 elements (128 bytes), so the
     bf16 sketch kernels read it with aligned 16-byte loads."""

@@ -110,6 +110,29 @@ def test_rand_eig_noalloc_validation(L):
     assert b"scratch" in L.kfac_status_string(_lib.KFAC_ESCRATCH)
 
 
+def test_conv_entry_points_validation(L):
+    from paper_2206_15397_amd import _lib
+    g = _lib.ConvGeom(2, 8, 8, 16, 3, 3, 1, 1)
+    d = 9 * 16 + 1
+    assert L.kfac_conv_ea_update_workspace(d, ctypes.byref(g)) >= 0
+
+    def ea(geom=g, dd=d, ones=1, rho=0.9, F=FAKE, x=FAKE):
+        return L.kfac_conv_ea_update(F, dd, dd, x, ctypes.byref(geom), ones, rho, 0.01, P(0), 0, P(0), 0, P(0))
+    assert ea(dd=d - 1) == 1                                   # d != kh kw C + ones
+    assert ea(ones=0) == 1
+    assert ea(rho=1.0) == 1
+    assert ea(F=P(0)) == 1
+    assert ea(geom=_lib.ConvGeom(2, 2, 2, 16, 3, 3, 0, 1), dd=d) == 1      # empty output
+    assert ea(geom=_lib.ConvGeom(2, 8, 8, 16, 3, 3, 1, 0), dd=d) == 1      # stride 0
+    assert ea(geom=_lib.ConvGeom(2, 8, 8, 16, 3, 3, -1, 1), dd=d) == 1     # negative padding
+
+    def bw(lddw=d, c_out=8, Gam=P(0)):
+        return L.kfac_conv_backward_weight(FAKE, c_out, FAKE, ctypes.byref(g), FAKE, lddw, 1, Gam, 8, P(0), 8, 0.9,
+                                           0.5, P(0))
+    assert bw(lddw=d - 1) == 1
+    assert bw(c_out=0) == 1
+
+
 def test_precondition_validation(L):
     ws = L.kfac_precondition_workspace(8, 9, 3, 2)
     assert ws > 0
