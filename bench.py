@@ -52,11 +52,16 @@ def parse():
                     help="skip the oracle leg (CPU baseline timing and parity of the timed outputs)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default GEMM tile configurations")
-    ap.add_argument("--config", choices=["vgg", "wide", "batched64", "copy", "vgg_ea"], default="vgg",
+    ap.add_argument("--config", choices=["vgg", "wide", "batched64", "copy", "vgg_ea", "conv", "driver"],
+                    default="vgg",
                     help="vgg: VGG16_bn factor set (default); wide: one d x d factor (--d); "
                          "batched64: 64 factors of log-uniform sizes 64..8192; copy: a plain 1 GiB "
                          "device copy that calibrates the HBM byte counters of rocprofv3; vgg_ea: the "
-                         "VGG16_bn EA phase alone (counter harness)")
+                         "VGG16_bn EA phase alone (counter harness); conv: the K-FAC work of the VGG16_bn "
+                         "convolutions (implicit im2col); driver: the K-FAC driver over one inversion "
+                         "period of the paper's schedule")
+    ap.add_argument("--sketch", default="split", choices=["bf16", "split", "fp32"],
+                    help="--config driver: sketch precision of the driver's plans")
     ap.add_argument("--d", type=int, default=16384, help="factor size of --config wide")
     ap.add_argument("--full-eig", action="store_true", help="--config wide: also time torch.linalg.eigh")
     return ap.parse_args()
@@ -229,7 +234,7 @@ def run_batched(wl, layers, steps, warmup, nstreams):
     return g, times
 
 
-def make_plan(wl, layers, sketch="bf16", autotune=True, branches=1):
+def make_plan(wl, layers, sketch="bf16", autotune=True, branches=1, variant="srevd"):
     """All 32 factors and 16 layers of the step in one grouped plan (bf16 activations; sketch
     "split": split-bf16 products of the fp32 factors, "bf16": products of the bf16 shadow,
     which the EA phase refreshes): factor 2i is layer i's A factor, 2i+1 its G factor."""
@@ -238,9 +243,9 @@ def make_plan(wl, layers, sketch="bf16", autotune=True, branches=1):
     sh = sketch == "bf16"
     for li, L in enumerate(layers):
         fd.append(dict(F=L.A, F_bf16=L.Ab if sh else None, X=L.a, append_ones=L.shape.bias, scale=1.0 / L.n, r=L.ra,
-                       p=wl.p, q=wl.q, stream_id=2 * li, U=L.Ua, D=L.Da))
+                       p=wl.p, q=wl.q, stream_id=2 * li, U=L.Ua, D=L.Da, variant=variant))
         fd.append(dict(F=L.G, F_bf16=L.Gb if sh else None, X=L.g, append_ones=False, scale=1.0 / L.n, r=L.rg,
-                       p=wl.p, q=wl.q, stream_id=2 * li + 1, U=L.Ug, D=L.Dg))
+                       p=wl.p, q=wl.q, stream_id=2 * li + 1, U=L.Ug, D=L.Dg, variant=variant))
         ld.append(dict(fa=2 * li, fg=2 * li + 1, J=L.J, S=L.S))
     plan = K.Plan(fd, ld, sketch=sketch)
     plan.set_scalars(wl.rho, wl.lam, wl.seed, 0).upload()
@@ -254,9 +259,9 @@ def make_plan(wl, layers, sketch="bf16", autotune=True, branches=1):
     return plan
 
 
-def run_plan(wl, layers, steps, warmup, autotune=True, sketch="bf16", branches=1):
+def run_plan(wl, layers, steps, warmup, autotune=True, sketch="bf16", branches=1, variant="srevd"):
     import torch
-    plan = make_plan(wl, layers, sketch=sketch, autotune=autotune, branches=branches)
+    plan = make_plan(wl, layers, sketch=sketch, autotune=autotune, branches=branches, variant=variant)
     restore(layers)
     plan.launch()                       # first-launch paths outside the capture
     torch.cuda.synchronize()
@@ -718,6 +723,244 @@ def main_wide(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def event_times(calls, reps):
+    """Average duration of each callable (one library call each) on the current stream: HIP
+    events between consecutive calls, the queue pre-filled behind a spin kernel so that host
+    enqueue gaps do not show up as kernel time."""
+    import torch
+    acc = [0.0] * len(calls)
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
+        torch.cuda._sleep(20_000_000)
+        ev[0].record()
+        for i, c in enumerate(calls):
+            c()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        for i in range(len(calls)):
+            acc[i] += ev[i].elapsed_time(ev[i + 1])
+    return [a / reps for a in acc]
+
+
+def graph_of(fn, steps, warmup):
+    """Capture fn once in a graph and time `steps` replays (ms each)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return g, times
+
+
+CONV_BATCH = 128
+
+
+def main_conv(args, dev):
+    """The K-FAC work of VGG16_bn's 13 convolutions in one step (batch 128, 32x32 inputs, KFC
+    factors): per layer the input factor's EA over the im2col patches of the NHWC input and
+    the weight gradient [dW | db] = g^T [P | 1] with the output factor's EA fused, through the
+    implicit-im2col kernels (kfac_conv_ea_update, kfac_conv_backward_weight).  Beside it the
+    same work with the patches materialised (torch unfold into an n x 9C matrix) and the dense
+    kernels (kfac_ea_update, kfac_linear_backward without dx).  Inputs: post-ReLU-like
+    activations |N(0, 1)| and N(0, 1e-3) output gradients, bf16, seeded."""
+    import torch
+    import torch.nn.functional as Fn
+    import paper_2206_15397_amd as K
+    from paper_2206_15397_amd import synth
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4242)
+    rho, B = 0.95, CONV_BATCH
+    layers = []
+    for ci, co, hw in synth.VGG16_BN_CONVS:
+        L = Layer()
+        L.ci, L.co, L.hw = ci, co, hw
+        L.d_a, L.n = 9 * ci + 1, B * hw * hw
+        L.x = torch.randn((B, hw, hw, ci), generator=gen, device=dev).abs_().to(torch.bfloat16)
+        L.g = (1e-3 * torch.randn((B, hw, hw, co), generator=gen, device=dev)).to(torch.bfloat16)
+        L.A = K.fill_identity(torch.empty((L.d_a, L.d_a), device=dev))
+        L.G = K.fill_identity(torch.empty((co, co), device=dev))
+        L.Ab, L.Gb = K.bf16_shadow(L.A), K.bf16_shadow(L.G)
+        geo = K.ops._conv_geom(L.x, 3, 3, 1, 1)
+        import ctypes
+        wsb = K.lib().kfac_conv_ea_update_workspace(L.d_a, ctypes.byref(geo))
+        L.ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev) if wsb else None
+        wsd = K.lib().kfac_ea_update_workspace(L.d_a, L.n)
+        L.wsd = torch.empty(max(wsd, 1), dtype=torch.uint8, device=dev) if wsd else None
+        wsw = K.lib().kfac_conv_backward_weight_workspace(co, ctypes.byref(geo), 1)
+        L.wsw = torch.empty(max(wsw, 1), dtype=torch.uint8, device=dev) if wsw else None
+        L.dW = torch.empty((co, L.d_a), device=dev)
+        L.Wd = torch.zeros((co, 9 * ci), dtype=torch.bfloat16, device=dev)
+        L.gs = float(B * B) / L.n
+        layers.append(L)
+
+    def ea_call(L):
+        return lambda: K.conv_ea_update(L.A, L.x, 3, 3, 1, 1, rho, append_ones=True, F_bf16=L.Ab, workspace=L.ws)
+
+    def dw_call(L):
+        return lambda: K.conv_backward_weight(L.g, L.x, 3, 3, 1, 1, with_bias=True, Gamma=L.G, Gamma_bf16=L.Gb,
+                                              rho=rho, scale=L.gs, workspace=L.wsw, dWb=L.dW)
+
+    def implicit_step():
+        for L in layers:
+            ea_call(L)()
+            dw_call(L)()
+
+    def patches(L):
+        xn = L.x.permute(0, 3, 1, 2)
+        u = Fn.unfold(xn, (3, 3), padding=1)                            # B x (C 9) x L, (c, dy, dx)
+        return u.view(B, L.ci, 9, -1).permute(0, 3, 2, 1).reshape(L.n, 9 * L.ci).contiguous()
+
+    def explicit_step():
+        for L in layers:
+            P = patches(L)
+            K.ea_update(L.A, P, rho, 1.0 / L.n, append_ones=True, F_bf16=L.Ab, workspace=L.wsd)
+            K.ops.linear_backward(L.g.view(L.n, L.co), P, L.Wd, with_bias=True, want_dx=False, Gamma=L.G,
+                                  Gamma_bf16=L.Gb, rho=rho, scale=L.gs)
+
+    g1, t_imp = graph_of(implicit_step, args.steps, args.warmup)
+    ms_imp = median(t_imp)
+    del g1
+    log(f"implicit im2col (13 convolutions): median {ms_imp:.3f} ms per step")
+    g2, t_exp = graph_of(explicit_step, max(3, args.steps // 2), 1)
+    ms_exp = median(t_exp)
+    del g2
+    log(f"materialised patches + dense kernels: median {ms_exp:.3f} ms per step")
+    calls, kinds = [], []
+    for L in layers:
+        calls += [ea_call(L), dw_call(L)]
+        kinds += [("conv_ea", L), ("conv_dw", L)]
+    ts = event_times(calls, max(3, args.steps // 2))
+    fam = {"conv_ea": [0.0, 0.0, 0.0, 0], "conv_dw": [0.0, 0.0, 0.0, 0]}
+    for (kind, L), t in zip(kinds, ts):
+        d, n = L.d_a, L.n
+        if kind == "conv_ea":
+            fl = float(n) * d * (d + 1)                                  # upper triangle of [P|1]^T [P|1]
+            by = 2.0 * B * L.hw * L.hw * L.ci + 10.0 * d * d           # NHWC input, factor r/w + bf16 shadow
+        else:
+            fl = 2.0 * n * L.co * d + float(n) * L.co * (L.co + 1)     # g^T [P|1] and the fused g^T g
+            by = 2.0 * B * L.hw * L.hw * (L.ci + L.co) + 4.0 * L.co * d + 10.0 * L.co * L.co
+        a = fam[kind]
+        a[0] += t
+        a[1] += fl
+        a[2] += by
+        a[3] += 1
+        log(f"  {kind} C_in={L.ci:3d} C_out={L.co:3d} {L.hw:2d}x{L.hw:<2d} d_A={d:4d}: {t * 1e3:8.1f} us")
+    by_kind = {}
+    for kind, (t, fl, by, cnt) in fam.items():
+        by_kind[kind] = {"us_per_step": round(1e3 * t, 1), "launches": cnt,
+                         "achieved_TFLOPs": round(fl / (t * 1e-3) / 1e12, 2),
+                         "mfma_frac_bf16": round(fl / (t * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"], 4),
+                         "achieved_GBs": round(by / (t * 1e-3) / 1e9, 1),
+                         "hbm_frac": round(by / (t * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    dom = max(fam, key=lambda k: fam[k][0])
+    t, fl, by, cnt = fam[dom]
+    ach = fl / (t * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_TFLOPS["bf16"], 5), "traffic": None, "kernel": dom,
+            "avg_launch_us": round(1e3 * t / cnt, 2), "flops_per_launch": fl / cnt, "bytes_per_launch": by / cnt,
+            "by_kind": by_kind}
+    res = {"metric": "K-FAC convolution work per step (VGG16_bn, 13 convolutions)", "value": round(ms_imp, 4),
+           "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_imp, 4),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+fp32",
+           "data": "synthetic",
+           "config": {"workload": "vgg16_bn_cifar_b128_convolutions", "batch": B, "layers": 13, "kernel": "3x3/p1/s1"},
+           "materialised_patches_ms_per_step": round(ms_exp, 4),
+           "speedup_vs_materialised": round(ms_exp / ms_imp, 3), "roofline": roof}
+    print(json.dumps(res), flush=True)
+
+
+def main_driver(args, dev):
+    """The K-FAC driver over one inversion period of the paper's Sec. 5 schedule on the
+    VGG16_bn layer set (batch 256, the paper's): EA every T_KU = 10 iterations, inversion every
+    T_KI = 50 (epoch 0: r = 220, r_l = 10, n_pwr-it = 4), the damped inverse every iteration,
+    each iteration one replay of a captured graph.  Reports the K-factor work per training
+    iteration amortised over the period, and the three kinds of iteration separately.
+    Inputs are written into the driver's buffers once (their values do not change the work)."""
+    import torch
+    import paper_2206_15397_amd as K
+    from paper_2206_15397_amd import synth
+    from paper_2206_15397_amd.driver import KFACDriver, LayerSpec
+    from paper_2206_15397_amd.schedule import PaperSchedule
+    sched = PaperSchedule()
+    shapes = synth.vgg16_bn_cifar_layers(sched.batch)
+    drv = KFACDriver([LayerSpec(s.m_a, s.d_g, s.n, s.bias) for s in shapes], schedule=sched, sketch=args.sketch,
+                     device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(77)
+    for l in range(len(shapes)):
+        a, g, J = drv.inputs(l)
+        a.copy_(torch.randn(a.shape, generator=gen, device=dev).abs_())
+        g.copy_(1e-3 * torch.randn(g.shape, generator=gen, device=dev))
+        J.copy_(1e-3 * torch.randn(J.shape, generator=gen, device=dev))
+    period = sched.T_KI(0)
+    # the first period builds the plans and graphs; the second is timed
+    for it in range(period):
+        drv.step(it, 0)
+    torch.cuda.synchronize()
+    kinds = {}
+    tot = []
+    for rep in range(max(1, args.steps // 10)):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(period + 1)]
+        e[0].record()
+        for it in range(period):
+            drv.step(period * (rep + 1) + it, 0)
+            e[it + 1].record()
+        torch.cuda.synchronize()
+        for it in range(period):
+            k = period * (rep + 1) + it
+            key = "EA+inversion+precondition" if k % period == 0 else \
+                ("EA+precondition" if k % sched.T_KU == 0 else "precondition")
+            kinds.setdefault(key, []).append(e[it].elapsed_time(e[it + 1]))
+        tot.append(e[0].elapsed_time(e[period]))
+    per_it = median(tot) / period
+    log(f"driver: {period} iterations in {median(tot):.3f} ms, {per_it:.4f} ms per iteration (amortised)")
+    for k, v in kinds.items():
+        log(f"  {k}: median {median(v):.3f} ms over {len(v)}")
+    # the parts of an inversion iteration: the host's re-upload of the plans' tables (new
+    # lambda and inversion index) and the replay of the inversion graph alone
+    t0 = time.perf_counter()
+    drv._upload_all(drv.inversions)
+    up_ms = 1e3 * (time.perf_counter() - t0)
+    ginv, tinv = None, []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        drv._graphs["EIP"].replay()
+        e1.record()
+        torch.cuda.synchronize()
+        tinv.append(e0.elapsed_time(e1))
+    log(f"  inversion iteration: table upload {up_ms:.2f} ms (host), graph replay {median(tinv):.3f} ms")
+    names, pt = phase_times(drv._plans["EIP"], None, 2, restore_fn=lambda: None)
+    agg = {}
+    for nm, t in zip(names, pt):
+        agg[nm] = agg.get(nm, 0.0) + t
+    for nm, t in sorted(agg.items(), key=lambda kv: -kv[1])[:12]:
+        log(f"    {nm:18s} {t * 1e3:9.1f} us")
+    res = {"metric": "K-factor work per training iteration (amortised over T_KI)", "value": round(per_it, 4),
+           "unit": "ms/iteration", "n_gpus": 1, "steps": period * max(1, args.steps // 10), "warmup": period,
+           "ms_per_step": round(per_it, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16+fp32+fp64", "data": "synthetic",
+           "config": {"workload": "vgg16_bn_cifar_b256_paper_schedule_epoch0", "layers": len(shapes),
+                      "T_KU": sched.T_KU, "T_KI": period, "r": sched.rank(0), "r_l": sched.oversampling(0),
+                      "q": sched.q, "rho": sched.rho, "lambda": sched.lam(0), "sketch": args.sketch},
+           "iteration_ms": {k: round(median(v), 4) for k, v in kinds.items()},
+           "inversion_graph_ms": round(median(tinv), 4), "inversion_upload_host_ms": round(up_ms, 3)}
+    print(json.dumps(res), flush=True)
+
+
 BATCHED64_SKETCH = "split"
 
 
@@ -873,6 +1116,10 @@ def main():
         import paper_2206_15397_amd as K
         K.lib()
         dev = torch.device("cuda:0")
+        if args.config == "conv":
+            return main_conv(args, dev)
+        if args.config == "driver":
+            return main_driver(args, dev)
         return main_wide(args, dev) if args.config == "wide" else main_batched64(args, dev)
     import torch
     import paper_2206_15397_amd as K
@@ -890,18 +1137,34 @@ def main():
     ms_b = median(tp_)
     log(f"plan bf16 sketch ({plan.launch_count} grouped launches, {args.branches} branches): median {ms_b:.3f} ms  "
         f"(min {min(tp_):.3f}, max {max(tp_):.3f}) status={int(plan.status.item())}")
+    launches = plan.launch_count
+    del gp
+    # The roofline is timed on the one-branch schedule of the same plan: there every launch
+    # runs one phase of all factors alone on the GPU, so its duration is the kernel's own
+    # (concurrent branches share the compute units, and an eager pass over their launches
+    # would add up latency-bound launches that the graph overlaps).
+    ms_1 = ms_b
+    if args.branches > 1:
+        plan.set_branches(1)
+        if not args.no_autotune:
+            import tempfile
+            restore(layers)
+            plan.autotune(cache_path=os.path.join(tempfile.gettempdir(), "kfac_autotune_cache.txt"), reps=3)
+        g1, t1 = graph_times(plan, max(3, args.steps // 2), 1, lambda: restore(layers))
+        ms_1 = median(t1)
+        del g1
+        log(f"  same plan on one branch ({plan.launch_count} launches): median {ms_1:.3f} ms")
     names, pt = phase_times(plan, layers, max(3, args.steps // 2))
     tot = sum(pt)
     cfgs = plan.launch_configs()
     for i, (nm, t) in enumerate(zip(names, pt)):
         log(f"  [{i:2d}] {nm:18s} {t * 1e3:9.1f} us  {100 * t / tot:5.1f}%  cfg {cfgs[i]}")
     roof = roofline(plan, names, pt, "vgg16_bn_cifar_b128_factor_set")
+    roof["schedule"] = "one branch (per-launch durations of the same plan's kernels)"
     log(f"roofline: {roof}")
-    del gp
     # the step's outputs (the eager replay above ran one whole step from the restored factors)
     if not args.no_check:
         snaps["plan_bf16"] = snapshot(layers, int(plan.status.item()))
-    launches = plan.launch_count
     del plan
     # the same plan with the split-bf16 sketch (fp32-class products)
     plan_b, gb, tb_ = run_plan(wl, layers, max(3, args.steps // 2), 1, autotune=not args.no_autotune, sketch="split",
@@ -915,6 +1178,12 @@ def main():
         torch.cuda.synchronize()
         snaps["plan_split"] = snapshot(layers, int(plan_b.status.item()))
     del plan_b
+    # the RSVD variant (Alg. 2) of the same step: timed only (its parity is a GPU test)
+    plan_r, gr, tr_ = run_plan(wl, layers, max(3, args.steps // 2), 1, autotune=not args.no_autotune, sketch="bf16",
+                               branches=args.branches, variant="rsvd")
+    ms_rs = median(tr_)
+    log(f"plan bf16 sketch, RSVD variant: median {ms_rs:.3f} ms status={int(plan_r.status.item())}")
+    del gr, plan_r
     plain_ms = None
     if args.streams > 0:
         g, tb = run_batched(wl, layers, args.steps, args.warmup, args.streams)
@@ -947,7 +1216,9 @@ def main():
                    "path": "grouped plan (%d launches, %d branches), bf16 sketch, hipGraph" % (launches, args.branches)},
         "plain_fp32_ms_per_step": None if plain_ms is None else round(plain_ms, 4),
         "speedup_vs_plain_fp32": None if plain_ms is None else round(plain_ms / ms_b, 3),
+        "one_branch_ms_per_step": round(ms_1, 4),
         "split_sketch_plan_ms_per_step": round(ms_sp, 4),
+        "rsvd_variant_plan_ms_per_step": round(ms_rs, 4),
         "roofline": roof,
     }
     if not args.no_check:

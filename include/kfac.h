@@ -263,10 +263,14 @@ kfac_status kfac_linear_backward(const uint16_t* g, int64_t n, int64_t d_out, in
  *   with_bias), lddw >= that; dW's columns in the patch order above, db last) from the output
  *   gradient g (n x c_out, i.e. NHWC batch x out_h x out_w x c_out, bf16), with the
  *   backward factor's EA Gamma <- rho Gamma + (1 - rho) scale g^T g fused into the same launch
- *   (skipped when Gamma == NULL; Gamma_bf16 nullable).
+ *   (skipped when Gamma == NULL; Gamma_bf16 nullable).  The contraction over the n positions
+ *   is split into K slices whose raw sums go to the workspace and are summed in slice order
+ *   by a second launch (deterministic): kfac_conv_backward_weight_workspace(c_out, geom,
+ *   with_bias) bytes; NULL / 0 runs the whole contraction in one pass per tile (correct, but
+ *   few workgroups when c_out and kh kw channels are small and n is large).
  * Errors: KFAC_EINVAL for null required pointers, non-positive sizes, an empty output, a
- * short leading dimension or d != kh kw channels + append_ones; KFAC_EUNSUPPORTED beyond
- * 32-bit indexing.
+ * short leading dimension or d != kh kw channels + append_ones; KFAC_EWORKSPACE for a
+ * non-null workspace smaller than the query; KFAC_EUNSUPPORTED beyond 32-bit indexing.
  */
 typedef struct {
   int64_t batch, height, width, channels;
@@ -277,10 +281,12 @@ size_t kfac_conv_ea_update_workspace(int64_t d, const kfac_conv_geom* geom);
 kfac_status kfac_conv_ea_update(float* F, int64_t d, int64_t ldf, const uint16_t* x, const kfac_conv_geom* geom,
                                 int append_ones, float rho, float scale, uint16_t* F_bf16, int64_t ldfb,
                                 void* workspace, size_t ws_bytes, kfac_stream_t stream);
+size_t kfac_conv_backward_weight_workspace(int64_t c_out, const kfac_conv_geom* geom, int with_bias);
 kfac_status kfac_conv_backward_weight(const uint16_t* g, int64_t c_out, const uint16_t* x,
                                       const kfac_conv_geom* geom, float* dWb, int64_t lddw, int with_bias,
                                       float* Gamma, int64_t ldgam, uint16_t* Gamma_bf16, int64_t ldgb,
-                                      float rho, float scale, kfac_stream_t stream);
+                                      float rho, float scale, void* workspace, size_t ws_bytes,
+                                      kfac_stream_t stream);
 
 /*
  * Grouped plan -- one K-factor step of a whole network (all factors and layers) as a

@@ -38,7 +38,8 @@ SIGNATURES = {
                                   _p, _i64, _p, _i64, _f, _f, _p]),
     "kfac_conv_ea_update_workspace": (_sz, [_i64, _p]),
     "kfac_conv_ea_update": (_i, [_p, _i64, _i64, _p, _p, _i, _f, _f, _p, _i64, _p, _sz, _p]),
-    "kfac_conv_backward_weight": (_i, [_p, _i64, _p, _p, _p, _i64, _i, _p, _i64, _p, _i64, _f, _f, _p]),
+    "kfac_conv_backward_weight_workspace": (_sz, [_i64, _p, _i]),
+    "kfac_conv_backward_weight": (_i, [_p, _i64, _p, _p, _p, _i64, _i, _p, _i64, _p, _i64, _f, _f, _p, _sz, _p]),
     "kfac_plan_create": (_i, [_p, _i, _p, _i, _i, _p]),
     "kfac_plan_workspace": (_sz, [_p]),
     "kfac_plan_set_scalars": (_i, [_p, _f, _f, _u64, _u32, _i, _i, _i]),

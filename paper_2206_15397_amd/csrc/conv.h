@@ -11,40 +11,56 @@ __host__ __device__ inline int conv_out(int in, int k, int pad, int stride) { re
 // Rows [k0, k0+8) x columns [c0, c0+8) of [P | 1] (P: the im2col patches, n = B Ho Wo rows,
 // kh kw C columns; the ones column at index kh kw C when `ones`), zero beyond row K.
 // Eight columns of one tap are eight consecutive channels of one input pixel: one 16-byte
-// load when g.vec (C a multiple of 8, x 16-byte aligned), element loads otherwise.
+// load when g.vec (C a multiple of 8, x 16-byte aligned), element loads otherwise.  The
+// output position (b, oh, ow) of row k0 and the tap (dy, dx, c) of column c0 take four
+// integer divisions per call; the later rows and columns step from them (a row advances
+// ow, wrapping into oh and b; a column advances c, wrapping into dx and dy).
 __device__ __forceinline__ void im2col_block(const uint16_t* x, const ConvGeom& g, bool ones, int k0, int K, int c0,
                                              uint4 v[8]) {
   const int ncols = g.kh * g.kw * g.C;
   const int howo = g.Ho * g.Wo;
   const bool vec8 = g.vec && c0 + 8 <= ncols;
+  const int cc = c0 < ncols ? c0 : 0;
+  const int tap0 = cc / g.C, ch0 = cc - tap0 * g.C, dy0 = tap0 / g.kw, dx0 = tap0 - dy0 * g.kw;
+  const int kk = k0 < K ? k0 : 0;
+  int b = kk / howo;
+  const int rem = kk - b * howo;
+  int oh = rem / g.Wo, ow = rem - oh * g.Wo;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const int k = k0 + r;
     v[r] = make_uint4(0, 0, 0, 0);
-    if (k >= K) continue;
-    const int b = k / howo, rem = k - b * howo, oh = rem / g.Wo, ow = rem - oh * g.Wo;
-    const int ih0 = oh * g.stride - g.pad, iw0 = ow * g.stride - g.pad;
-    if (vec8) {
-      const int tap = c0 / g.C, c = c0 - tap * g.C, dy = tap / g.kw, dx = tap - dy * g.kw;
-      const int ih = ih0 + dy, iw = iw0 + dx;
-      if (ih >= 0 && ih < g.H && iw >= 0 && iw < g.W)
-        v[r] = *(const uint4*)(x + (((long)b * g.H + ih) * g.W + iw) * g.C + c);
-    } else {
-      uint16_t t[8];
+    if (k0 + r < K) {
+      const int ih0 = oh * g.stride - g.pad, iw0 = ow * g.stride - g.pad;
+      const uint16_t* xb = x + (long)b * g.H * g.W * g.C;
+      if (vec8) {
+        const int ih = ih0 + dy0, iw = iw0 + dx0;
+        if (ih >= 0 && ih < g.H && iw >= 0 && iw < g.W)
+          v[r] = *(const uint4*)(xb + ((long)ih * g.W + iw) * g.C + ch0);
+      } else {
+        uint16_t t[8];
+        int ch = ch0, dy = dy0, dx = dx0;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int col = c0 + j;
-        t[j] = 0;
-        if (col < ncols) {
-          const int tap = col / g.C, c = col - tap * g.C, dy = tap / g.kw, dx = tap - dy * g.kw;
-          const int ih = ih0 + dy, iw = iw0 + dx;
-          if (ih >= 0 && ih < g.H && iw >= 0 && iw < g.W) t[j] = x[(((long)b * g.H + ih) * g.W + iw) * g.C + c];
-        } else if (ones && col == ncols) {
-          t[j] = 0x3f80;                       // bf16 1.0
+        for (int j = 0; j < 8; ++j) {
+          const int col = c0 + j;
+          t[j] = 0;
+          if (col < ncols) {
+            const int ih = ih0 + dy, iw = iw0 + dx;
+            if (ih >= 0 && ih < g.H && iw >= 0 && iw < g.W) t[j] = xb[((long)ih * g.W + iw) * g.C + ch];
+            if (++ch == g.C) {
+              ch = 0;
+              if (++dx == g.kw) { dx = 0; ++dy; }
+            }
+          } else if (ones && col == ncols) {
+            t[j] = 0x3f80;                     // bf16 1.0
+          }
         }
+        v[r] = make_uint4(t[0] | ((uint32_t)t[1] << 16), t[2] | ((uint32_t)t[3] << 16),
+                          t[4] | ((uint32_t)t[5] << 16), t[6] | ((uint32_t)t[7] << 16));
       }
-      v[r] = make_uint4(t[0] | ((uint32_t)t[1] << 16), t[2] | ((uint32_t)t[3] << 16),
-                        t[4] | ((uint32_t)t[5] << 16), t[6] | ((uint32_t)t[7] << 16));
+    }
+    if (++ow == g.Wo) {
+      ow = 0;
+      if (++oh == g.Ho) { oh = 0; ++b; }
     }
   }
 }

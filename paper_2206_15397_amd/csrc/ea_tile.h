@@ -34,37 +34,62 @@ __device__ __forceinline__ void ea_tile(int t, int T, int& I, int& J) {
   }
 }
 
-// `t` holds the raw sums of upper tile (I, J) (rows of block I, columns of block J).
-template <int BT>
-__device__ void ea_store_tile_t(float (*t)[BT + 1], const EaOut& o, int I, int J) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+// `t` holds the raw sums of upper tile (I, J) (rows of block I, columns of block J); the
+// workgroup has NT threads.  The old upper-block values of F are loaded in batches of 16
+// per thread before any of them is used, so that each wave keeps 16 loads in flight: a
+// load-use loop would leave one load per wave in flight and make this epilogue, not the
+// products, the cost of tiles with short contractions.  Each element is read, blended and
+// stored by one thread; on a diagonal tile only the upper triangle is read and stored, and
+// the mirror pass writes the lower one from the blended upper values (exact symmetry).
+template <int BT, int NT = 256>
+__device__ __forceinline__ void ea_store_tile_t(float (*t)[BT + 1], const EaOut& o, int I, int J) {
+  constexpr int PER = BT * BT / NT, BATCH = PER < 16 ? PER : 16, RS = NT / BT;
+  static_assert(NT % BT == 0 && PER % BATCH == 0, "tile / workgroup shape");
+  // thread tid handles rows a0 + RS u (u < PER) of column b of the tile
+  const int tid = threadIdx.x, a0 = tid / BT, b = tid % BT;
   const int r0 = I * BT, c0 = J * BT;
+  const bool dg = (I == J);
+  const long step = (long)RS * o.ldf, stepb = (long)RS * o.ldfb;
   // upper block (rows of I, columns of J), coalesced along columns
-  for (int e = tid; e < BT * BT; e += nt) {
-    const int a = e / BT, b = e % BT;
-    const int i = r0 + a, j = c0 + b;
-    float v = 0.f;
-    if (i < o.d && j < o.d) v = o.rho * o.F[(long)i * o.ldf + j] + o.c * t[a][b];
-    t[a][b] = v;   // same thread reads and writes the same slot
-  }
-  __syncthreads();
-  for (int e = tid; e < BT * BT; e += nt) {
-    const int a = e / BT, b = e % BT;
-    const int i = r0 + a, j = c0 + b;
-    if (i < o.d && j < o.d && (I != J || a <= b)) {
-      const float v = t[a][b];
-      o.F[(long)i * o.ldf + j] = v;
-      if (o.Fb) o.Fb[(long)i * o.ldfb + j] = f32_to_bf16_rne(v);
+  {
+    float* const src = o.F + (long)(r0 + a0) * o.ldf + (c0 + b);
+    uint16_t* const srcb = o.Fb ? o.Fb + (long)(r0 + a0) * o.ldfb + (c0 + b) : nullptr;
+    const bool colok = c0 + b < o.d;
+#pragma unroll
+    for (int u0 = 0; u0 < PER; u0 += BATCH) {
+      float f[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int a = a0 + RS * (u0 + u);
+        f[u] = (colok && r0 + a < o.d && (!dg || a <= b)) ? src[(u0 + u) * step] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int a = a0 + RS * (u0 + u);
+        const bool st = colok && r0 + a < o.d && (!dg || a <= b);
+        const float v = st ? o.rho * f[u] + o.c * t[a][b] : 0.f;
+        t[a][b] = v;
+        if (st) {
+          src[(u0 + u) * step] = v;
+          if (srcb) srcb[(u0 + u) * stepb] = f32_to_bf16_rne(v);
+        }
+      }
     }
   }
-  // mirror block (rows of J, columns of I): element (c0+a, r0+b) = t[b][a]
-  for (int e = tid; e < BT * BT; e += nt) {
-    const int a = e / BT, b = e % BT;
-    const int i = c0 + a, j = r0 + b;
-    if (i < o.d && j < o.d && (I != J || b < a)) {
-      const float v = t[b][a];
-      o.F[(long)i * o.ldf + j] = v;
-      if (o.Fb) o.Fb[(long)i * o.ldfb + j] = f32_to_bf16_rne(v);
+  __syncthreads();
+  // mirror block (rows of J, columns of I): element (c0 + a, r0 + b) = t[b][a]
+  {
+    float* const dst = o.F + (long)(c0 + a0) * o.ldf + (r0 + b);
+    uint16_t* const dstb = o.Fb ? o.Fb + (long)(c0 + a0) * o.ldfb + (r0 + b) : nullptr;
+    const bool colok = r0 + b < o.d;
+#pragma unroll 8
+    for (int u = 0; u < PER; ++u) {
+      const int a = a0 + RS * u;
+      if (colok && c0 + a < o.d && (!dg || b < a)) {
+        const float v = t[b][a];
+        dst[u * step] = v;
+        if (dstb) dstb[u * stepb] = f32_to_bf16_rne(v);
+      }
     }
   }
 }

@@ -143,10 +143,11 @@ hipError_t launch_gemm_g(const GemmP* t, GroupMap gm, int blocks, bool ta, bool 
 hipError_t launch_ea_bf16_conv(float* F, int d, long ldf, const uint16_t* x, const ConvGeom& cv, int ones, float rho,
                                float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes, hipStream_t s);
 // weight gradient [dW | db] = g^T [P | 1] of a convolution (P: im2col patches of x), with the
-// backward-factor EA of g fused (Gam nullable)
+// backward-factor EA of g fused (Gam nullable); split over K slices into ws when given
 hipError_t launch_conv_backward_weight(const uint16_t* g, const uint16_t* x, const ConvGeom& cv, int c_out,
                                        float* dWb, long lddw, int with_bias, float* Gam, long ldgam, uint16_t* Gamb,
-                                       long ldgb, float rho, float scale, hipStream_t s);
+                                       long ldgb, float rho, float scale, void* ws, size_t ws_bytes, hipStream_t s);
+size_t conv_backward_weight_ws_bytes(int c_out, long n, int N);
 hipError_t launch_gemm_bf16_g(const BfGemmTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_gram_partial_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_gram_reduce_g(const GramP* t, GroupMap gm, int blocks, hipStream_t s);

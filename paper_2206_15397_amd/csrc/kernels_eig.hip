@@ -482,7 +482,9 @@ __device__ __forceinline__ void tri_select_body(const EigTask& q, int, int) {
   const int n = q.n, r = q.r; const TriMeta& m = q.m; double* Dd = q.Dd; float* D = q.D;
   __shared__ double lam[KFAC_MAX_SKETCH];
   const int tid = threadIdx.x;
-  for (int i = tid; i < n; i += blockDim.x) lam[i] = m.lam[i];
+  // the order key maps NaN (a non-finite factor) to -inf, so that the ranks stay a
+  // permutation of 0..n-1 and every col_task entry below r is written with a valid row
+  for (int i = tid; i < n; i += blockDim.x) lam[i] = isnan(m.lam[i]) ? -INFINITY : m.lam[i];
   __syncthreads();
   for (int j = tid; j < n; j += blockDim.x) {
     const double lj = lam[j];
@@ -492,9 +494,10 @@ __device__ __forceinline__ void tri_select_body(const EigTask& q, int, int) {
       rank += (li > lj) || (li == lj && i < j);
     }
     if (rank < r) {
+      const double v = m.lam[j];
       m.col_task[rank] = j;
-      Dd[rank] = lj;
-      D[rank] = q.svd ? (float)sqrt(fmax(lj, 0.0)) : (float)lj;
+      Dd[rank] = v;
+      D[rank] = q.svd ? (float)sqrt(fmax(v, 0.0)) : (float)v;
     }
   }
   __threadfence_block();

@@ -127,7 +127,7 @@ __device__ __forceinline__ bool ln_vec_ok(const uint16_t* X, long ld) {
 
 // Block bx of a LinTask.  AK / BK: operand stored K-major (rows = contraction index).
 template <bool AK, bool BK, bool CONV = false>
-__device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
+__device__ __forceinline__ void lin_body(const LinTask& q, int bx, int ks = 0) {
   __shared__ LinSmem sm;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -141,13 +141,15 @@ __device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
     m0 = (bx % q.tiles_m) * LN_T;
     n0 = (bx / q.tiles_m) * LN_T;
   } else {
-    upper_tile(bx - nplain, q.gam_T, GI, GJ);
+    ea_tile(bx - nplain, q.gam_T, GI, GJ);
     m0 = GI * LN_T;
     n0 = GJ * LN_T;
     ob = oa;                       // g^T g: both operands are g's columns
   }
   const bool same = gam && GI == GJ;
-  const int K = q.K;
+  // contraction rows [kb, K) of this K slice (the whole contraction when nks == 1)
+  int kb = 0, K = q.K;
+  if (q.nks > 1) ea_slice(q.K, q.nks, ks, LN_BK, kb, K);
   const int op = tid >> 7, tt = tid & 127;
   const bool loader = !(same && op == 1);
   f32x4 acc[4][4];
@@ -177,13 +179,13 @@ __device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
       else lb.store(sm.g.b[buf], tt);
     }
   };
-  if (K > 0) {
-    fetch(0);
+  if (kb < K) {
+    fetch(kb);
     stash(0);
     __syncthreads();
   }
   int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += LN_BK) {
+  for (int k0 = kb; k0 < K; k0 += LN_BK) {
     const bool more = k0 + LN_BK < K;
     if (more) fetch(k0 + LN_BK);
     uint16_t (*As)[LN_SK] = sm.g.a[buf];
@@ -207,6 +209,18 @@ __device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
     if (more) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
+  }
+  if (q.nks > 1) {
+    // raw sums of this slice; the reduce launch sums the slices in order
+    float* slot = q.part + ((long)bx * q.nks + ks) * (LN_T * LN_T);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          slot[(wm * 64 + i * 16 + 4 * (lane >> 4) + r) * LN_T + wn * 64 + j * 16 + (lane & 15)] = acc[i][j][r];
+    return;
   }
   if (gam) {
     // backward-factor EA tile: stage raw sums, blend, write tile + mirror + bf16 shadow
@@ -240,7 +254,37 @@ __device__ __forceinline__ void lin_body(const LinTask& q, int bx) {
 __global__ __launch_bounds__(256) void k_lin_nt(LinTask q) { lin_body<false, false>(q, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_lin_nn(LinTask q) { lin_body<false, true>(q, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_lin_tn(LinTask q) { lin_body<true, true>(q, blockIdx.x); }
-__global__ __launch_bounds__(256) void k_lin_tn_conv(LinTask q) { lin_body<true, true, true>(q, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_lin_tn_conv(LinTask q) {
+  lin_body<true, true, true>(q, blockIdx.x, blockIdx.y);
+}
+
+// Split-K reduce of the weight-gradient launch: block = (tile, 16-row chunk).  Plain tiles:
+// C rows [a0, a0 + 16) of the tile = the slices summed in index order.  Fused gam tiles:
+// the EA finalize (slices in order, blend, tile + mirror + bf16 shadow).
+constexpr int LN_CH = LN_T / kEaChunk;
+__global__ __launch_bounds__(256) void k_lin_tn_reduce(LinTask q) {
+  __shared__ float v[kEaChunk][LN_T + 1];
+  const int nplain = q.tiles_m * q.tiles_n;
+  const int tile = blockIdx.x / LN_CH, a0 = (blockIdx.x % LN_CH) * kEaChunk;
+  if (tile >= nplain) {
+    EaTask e{};
+    e.o = q.gam;
+    e.T = q.gam_T;
+    e.nks = q.nks;
+    e.g.part = q.part + (long)nplain * q.nks * (LN_T * LN_T);
+    ea_finalize_chunk<LN_T>(e, blockIdx.x - nplain * LN_CH, v);
+    return;
+  }
+  const int m0 = (tile % q.tiles_m) * LN_T, n0 = (tile / q.tiles_m) * LN_T;
+  const float* base = q.part + (long)tile * q.nks * (LN_T * LN_T) + (long)a0 * LN_T;
+  for (int e = threadIdx.x; e < kEaChunk * LN_T; e += blockDim.x) {
+    float s = 0.f;
+#pragma unroll 8
+    for (int k = 0; k < q.nks; ++k) s += base[(long)k * LN_T * LN_T + e];
+    const int row = m0 + a0 + e / LN_T, col = n0 + e % LN_T;
+    if (row < q.M && col < q.N) q.C[(long)row * q.ldc + col] = s;
+  }
+}
 
 static LinTask lin_task(int M, int N, int K, const uint16_t* A, long lda, const uint16_t* B, long ldb, int b_ones,
                         float* C, long ldc, uint16_t* Cb, long ldcb, const float* bias) {
@@ -251,6 +295,8 @@ static LinTask lin_task(int M, int N, int K, const uint16_t* A, long lda, const 
   q.tiles_m = (M + LN_T - 1) / LN_T;
   q.tiles_n = (N + LN_T - 1) / LN_T;
   q.gam_T = 0;
+  q.nks = 1;
+  q.part = nullptr;
   return q;
 }
 
@@ -285,9 +331,27 @@ hipError_t launch_linear_backward(const uint16_t* g, int n, int d_out, long ldg,
   return hipGetLastError();
 }
 
+// Tiles of the weight-gradient launch (plain dW tiles + the fused gam tiles) and its K
+// slices: enough workgroups to fill the chip twice over, each slice at least four 64-row
+// steps; bounded by the workspace (ws_bytes / per-slice bytes).
+static int conv_dw_tiles(int c_out, int N) {
+  const int tm = (c_out + LN_T - 1) / LN_T, tn = (N + LN_T - 1) / LN_T;
+  return tm * tn + tm * (tm + 1) / 2;
+}
+static int conv_dw_slices(int tiles, long n) {
+  const long want = (512 + tiles - 1) / tiles;
+  const long most = std::max<long>(1, n / (4 * LN_BK));
+  return (int)std::max<long>(1, std::min<long>(std::min(want, most), 1024));
+}
+size_t conv_backward_weight_ws_bytes(int c_out, long n, int N) {
+  const int tiles = conv_dw_tiles(c_out, N);
+  const int nks = conv_dw_slices(tiles, n);
+  return nks > 1 ? (size_t)tiles * nks * LN_T * LN_T * sizeof(float) : 0;
+}
+
 hipError_t launch_conv_backward_weight(const uint16_t* g, const uint16_t* x, const ConvGeom& cv, int c_out,
                                        float* dWb, long lddw, int with_bias, float* Gam, long ldgam, uint16_t* Gamb,
-                                       long ldgb, float rho, float scale, hipStream_t s) {
+                                       long ldgb, float rho, float scale, void* ws, size_t ws_bytes, hipStream_t s) {
   // [dW | db][c_out x (kh kw C + 1)] = g^T [P | 1]: A = g (n x c_out, K-major), B = the patches
   // P (n x kh kw C, K-major, gathered from x), plus the upper tiles of g^T g for Gamma
   const int n = cv.B * cv.Ho * cv.Wo;
@@ -300,7 +364,18 @@ hipError_t launch_conv_backward_weight(const uint16_t* g, const uint16_t* x, con
     q.gam_T = q.tiles_m;
     blocks += q.gam_T * (q.gam_T + 1) / 2;
   }
-  if (blocks > 0) hipLaunchKernelGGL(k_lin_tn_conv, dim3(blocks), dim3(256), 0, s, q);
+  if (blocks <= 0) return hipSuccess;
+  int nks = ws ? conv_dw_slices(conv_dw_tiles(c_out, N), n) : 1;
+  const size_t per_slice = (size_t)blocks * LN_T * LN_T * sizeof(float);
+  if (nks > 1) nks = (int)std::min<size_t>(nks, ws_bytes / per_slice);
+  if (nks > 1) {
+    q.nks = nks;
+    q.part = (float*)ws;
+    hipLaunchKernelGGL(k_lin_tn_conv, dim3(blocks, nks), dim3(256), 0, s, q);
+    hipLaunchKernelGGL(k_lin_tn_reduce, dim3(blocks * LN_CH), dim3(256), 0, s, q);
+  } else {
+    hipLaunchKernelGGL(k_lin_tn_conv, dim3(blocks), dim3(256), 0, s, q);
+  }
   return hipGetLastError();
 }
 

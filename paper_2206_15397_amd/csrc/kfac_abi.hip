@@ -347,10 +347,18 @@ kfac_status kfac_conv_ea_update(float* F, int64_t d, int64_t ldf, const uint16_t
                                         workspace, ws_bytes, (hipStream_t)stream));
 }
 
+size_t kfac_conv_backward_weight_workspace(int64_t c_out, const kfac_conv_geom* geom, int with_bias) {
+  ConvGeom cv;
+  kfac_status err;
+  if (c_out < 1 || c_out > (1 << 20) || !conv_geom(geom, nullptr, cv, err)) return 0;
+  return conv_backward_weight_ws_bytes((int)c_out, (long)cv.B * cv.Ho * cv.Wo,
+                                       cv.kh * cv.kw * cv.C + (with_bias ? 1 : 0));
+}
+
 kfac_status kfac_conv_backward_weight(const uint16_t* g, int64_t c_out, const uint16_t* x,
                                       const kfac_conv_geom* geom, float* dWb, int64_t lddw, int with_bias,
                                       float* Gamma, int64_t ldgam, uint16_t* Gamma_bf16, int64_t ldgb, float rho,
-                                      float scale, kfac_stream_t stream) {
+                                      float scale, void* workspace, size_t ws_bytes, kfac_stream_t stream) {
   ConvGeom cv;
   kfac_status err;
   if (!g || !x || !dWb || c_out < 1) return KFAC_EINVAL;
@@ -361,8 +369,11 @@ kfac_status kfac_conv_backward_weight(const uint16_t* g, int64_t c_out, const ui
     if (Gamma_bf16 && ldgb < c_out) return KFAC_EINVAL;
   }
   if (c_out > (1 << 20)) return KFAC_EUNSUPPORTED;
+  if (ws_bytes == 0) workspace = nullptr;
+  if (workspace && ws_bytes < kfac_conv_backward_weight_workspace(c_out, geom, with_bias)) return KFAC_EWORKSPACE;
   return hip_status(launch_conv_backward_weight(g, x, cv, (int)c_out, dWb, lddw, with_bias ? 1 : 0, Gamma, ldgam,
-                                                Gamma_bf16, ldgb, rho, scale, (hipStream_t)stream));
+                                                Gamma_bf16, ldgb, rho, scale, workspace, ws_bytes,
+                                                (hipStream_t)stream));
 }
 
 }  // extern "C"

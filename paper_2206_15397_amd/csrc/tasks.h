@@ -87,6 +87,8 @@ struct LinTask {         // K-FAC linear layer GEMMs on bf16 MFMA: block (flat t
   EaOut gam;             // fused backward-factor EA (upper tiles after the plain tiles)
   int gam_T;             // tiles per side of gam (0: none)
   ConvGeom cv;           // C > 0: the K-major B operand is the im2col patches of B (NHWC)
+  int nks;               // K slices (1: the epilogue writes C / blends gam directly)
+  float* part;           // nks > 1: [tile][slice][128 x 128] raw sums, plain tiles then gam's
 };
 
 struct GramP {           // C = A B^T in fp64 from fp32 rows: block (tile, K slice)

@@ -240,23 +240,32 @@ def conv_ea_update(F: torch.Tensor, x: torch.Tensor, kh: int, kw: int, pad: int,
 
 def conv_backward_weight(g: torch.Tensor, x: torch.Tensor, kh: int, kw: int, pad: int, stride: int,
                          with_bias: bool = True, Gamma: torch.Tensor = None, Gamma_bf16: torch.Tensor = None,
-                         rho: float = 0.95, scale: float = None):
+                         rho: float = 0.95, scale: float = None, workspace=None, dWb: torch.Tensor = None):
     """[dW | db] = g^T [P | 1] (fp32, c_out x (kh kw C + with_bias), columns (dy, dx, c) then the
     bias) from the NHWC output gradient g (batch, out_h, out_w, c_out; bf16) and the NHWC
-    input x; with Gamma, also Gamma <- rho Gamma + (1 - rho) scale g^T g in place (fused)."""
+    input x; with Gamma, also Gamma <- rho Gamma + (1 - rho) scale g^T g in place (fused).
+    workspace: K-slice partials (default: the size the library asks for)."""
     import ctypes
     _require_cuda(g, x, Gamma, Gamma_bf16)
     geo = _conv_geom(x, kh, kw, pad, stride)
     assert g.dim() == 4 and g.dtype == torch.bfloat16 and g.is_contiguous()
     c_out = g.shape[3]
     ncol = kh * kw * x.shape[3] + (1 if with_bias else 0)
-    dWb = torch.empty((c_out, ncol), dtype=torch.float32, device=g.device)
+    if dWb is None:
+        dWb = torch.empty((c_out, ncol), dtype=torch.float32, device=g.device)
+    assert dWb.dtype == torch.float32 and dWb.shape == (c_out, ncol) and dWb.stride(1) == 1
     if scale is None:
         scale = 1.0 / max(g.shape[0] * g.shape[1] * g.shape[2], 1)
-    check("kfac_conv_backward_weight", lib().kfac_conv_backward_weight(
+    L = lib()
+    if workspace is None:
+        ws_bytes = L.kfac_conv_backward_weight_workspace(c_out, ctypes.byref(geo), 1 if with_bias else 0)
+        workspace = _workspace(ws_bytes, g.device) if ws_bytes else None
+    ws_bytes = 0 if workspace is None else workspace.numel()
+    check("kfac_conv_backward_weight", L.kfac_conv_backward_weight(
         _ptr(g), c_out, _ptr(x), ctypes.byref(geo), _ptr(dWb), dWb.stride(0), 1 if with_bias else 0, _ptr(Gamma),
         c_out if Gamma is None else Gamma.stride(0), _ptr(Gamma_bf16),
-        c_out if Gamma_bf16 is None else Gamma_bf16.stride(0), float(rho), float(scale), _stream()))
+        c_out if Gamma_bf16 is None else Gamma_bf16.stride(0), float(rho), float(scale), _ptr(workspace), ws_bytes,
+        _stream()))
     return dWb
 
 

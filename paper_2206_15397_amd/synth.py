@@ -107,15 +107,19 @@ class LayerShape:
         return self.m_a + (1 if self.bias else 0)
 
 
+# (C_in, C_out, input height = width) of VGG16_bn's 3x3 convolutions (padding 1, stride 1)
+# on 32x32 inputs
+VGG16_BN_CONVS = [(3, 64, 32), (64, 64, 32), (64, 128, 16), (128, 128, 16), (128, 256, 8),
+                  (256, 256, 8), (256, 256, 8), (256, 512, 4), (512, 512, 4), (512, 512, 4),
+                  (512, 512, 2), (512, 512, 2), (512, 512, 2)]
+
+
 def vgg16_bn_cifar_layers(batch: int = 128) -> List[LayerShape]:
     """VGG16_bn on 32x32 inputs with the paper's extra 512->512 FC layer (Sec. 5):
     13 3x3 convolutions (channels 64,64,128,128,256x3,512x6, spatial size halving after
     each block) and FC 512->512->512->10.  A-factor dim = 9*C_in + 1, G-factor dim = C_out."""
-    convs = [(3, 64, 32), (64, 64, 32), (64, 128, 16), (128, 128, 16), (128, 256, 8),
-             (256, 256, 8), (256, 256, 8), (256, 512, 4), (512, 512, 4), (512, 512, 4),
-             (512, 512, 2), (512, 512, 2), (512, 512, 2)]
     out = []
-    for i, (ci, co, hw) in enumerate(convs):
+    for i, (ci, co, hw) in enumerate(VGG16_BN_CONVS):
         out.append(LayerShape(f"conv{i + 1}", 9 * ci, co, batch * hw * hw, True))
     for i, (fi, fo) in enumerate([(512, 512), (512, 512), (512, 10)]):
         out.append(LayerShape(f"fc{i + 1}", fi, fo, batch, True))

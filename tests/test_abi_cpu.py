@@ -126,11 +126,21 @@ def test_conv_entry_points_validation(L):
     assert ea(geom=_lib.ConvGeom(2, 8, 8, 16, 3, 3, 1, 0), dd=d) == 1      # stride 0
     assert ea(geom=_lib.ConvGeom(2, 8, 8, 16, 3, 3, -1, 1), dd=d) == 1     # negative padding
 
-    def bw(lddw=d, c_out=8, Gam=P(0)):
+    def bw(lddw=d, c_out=8, Gam=P(0), ws=P(0), wsb=0):
         return L.kfac_conv_backward_weight(FAKE, c_out, FAKE, ctypes.byref(g), FAKE, lddw, 1, Gam, 8, P(0), 8, 0.9,
-                                           0.5, P(0))
+                                           0.5, ws, wsb, P(0))
     assert bw(lddw=d - 1) == 1
     assert bw(c_out=0) == 1
+    # K slices: positions n = 2 * 8 * 8 = 128 give one slice (no workspace); a large input asks for
+    # slices, and a short non-null workspace is refused before anything is enqueued
+    assert L.kfac_conv_backward_weight_workspace(8, ctypes.byref(g), 1) == 0
+    gb = _lib.ConvGeom(128, 32, 32, 64, 3, 3, 1, 1)
+    need = L.kfac_conv_backward_weight_workspace(64, ctypes.byref(gb), 1)
+    assert need > 0 and need % (128 * 128 * 4) == 0
+    assert L.kfac_conv_backward_weight_workspace(0, ctypes.byref(gb), 1) == 0
+    short = L.kfac_conv_backward_weight(FAKE, 64, FAKE, ctypes.byref(gb), FAKE, 9 * 64 + 1, 1, P(0), 64, P(0), 64,
+                                        0.9, 0.5, FAKE, need - 1, P(0))
+    assert short == _lib.KFAC_EWORKSPACE
 
 
 def test_precondition_validation(L):

@@ -39,6 +39,7 @@ CASES = [  # (B, H, W, C_in, C_out, kh, kw, pad, stride)
     (3, 7, 9, 3, 8, 3, 3, 1, 1),         # C = 3 (the first VGG layer): element loads
     (2, 9, 9, 8, 16, 3, 3, 0, 2),        # stride 2, no padding
     (2, 6, 5, 32, 40, 1, 1, 0, 1),       # 1 x 1
+    (32, 16, 16, 16, 24, 3, 3, 1, 1),    # n = 8192 positions: the weight gradient runs in K slices
 ]
 
 
@@ -140,3 +141,21 @@ def test_conv_factor_vgg_layer_sampled():
             got = float(Fs[i, j])
             worst = max(worst, abs(got - want) / (abs(want) + 1e-3))
     assert worst <= 1e-4, worst
+    # the weight gradient of the same layer at full size (K slices) with the fused output-factor
+    # EA: sampled entries of dW and Gamma against fp64 sums over the n positions
+    Co = 256
+    gy = (1e-2 * torch.randn((B, H, H, Co), generator=g, device=DEV)).to(torch.bfloat16)
+    G = K().fill_identity(torch.empty((Co, Co), device=DEV))
+    dWb = K().conv_backward_weight(gy, x, 3, 3, 1, 1, with_bias=True, Gamma=G, rho=0.95, scale=2.0)
+    torch.cuda.synchronize()
+    g2 = gy.double().reshape(n, Co)
+    outs = rng.choice(Co, 24, replace=False)
+    worst_w = worst_g = 0.0
+    for o, j, o2 in zip(outs, cols[:24], outs[::-1]):
+        want = float((g2[:, o] * col(j)).sum())
+        worst_w = max(worst_w, abs(float(dWb[o, j]) - want) / (abs(want) + 1e-3))
+        wg = 0.95 * (o == o2) + 0.05 * 2.0 * float((g2[:, o] * g2[:, o2]).sum())
+        worst_g = max(worst_g, abs(float(G[o, o2]) - wg) / (abs(wg) + 1e-3))
+    assert worst_w <= 1e-4, worst_w
+    assert worst_g <= 1e-4, worst_g
+    assert torch.equal(G, G.T)
