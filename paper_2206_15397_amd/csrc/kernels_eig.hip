@@ -401,8 +401,10 @@ __device__ __forceinline__ void tri_prep_body(const EigTask& q, int, int) {
 
 // ======================================================================================
 // 3. Bisection.  Task j (one per row) = eigenvalue number j - blo[j] (ascending) of its
-// block; 16 lanes evaluate the Sturm count at 16 interior points of the bracket.  The
-// counts are monotone in the point, so one ballot locates the new bracket.
+// block; 16 lanes evaluate the Sturm count at 16 interior points of the bracket (each step
+// narrows it 17-fold).  The counts are monotone in the point, so one ballot locates the new
+// bracket.  (64 points per task, nine steps instead of thirteen, measured slower: the
+// launch is bound by the fp64 work of the recurrences, which grows with the points.)
 // ======================================================================================
 // a / b from the hardware reciprocal (about 2^-26 relative) and one Newton step (relative
 // error then about 2^-52 plus rounding): a Sturm count only needs each pivot to a few ulps,
@@ -428,6 +430,7 @@ __device__ int sturm_block(const double* d, const double* e2, int lo, int hi, do
 }
 
 constexpr int BIS_LANES = 16;
+constexpr int BIS_PER_BLOCK = 256 / BIS_LANES;
 
 __device__ __forceinline__ void tri_bisect_body(const EigTask& q, int bx, int) {
   const double* diag = q.diag; const int n = q.n; const TriMeta& m = q.m;
@@ -441,7 +444,7 @@ __device__ __forceinline__ void tri_bisect_body(const EigTask& q, int bx, int) {
   }
   __syncthreads();
   const double tn = m.scal[0], pivmin = m.scal[1];
-  const int j = bx * (256 / BIS_LANES) + tid / BIS_LANES;
+  const int j = bx * BIS_PER_BLOCK + tid / BIS_LANES;
   const int sub = tid % BIS_LANES;
   const bool active = j < n;
   const int jj = active ? j : 0;
@@ -466,7 +469,8 @@ __device__ __forceinline__ void tri_bisect_body(const EigTask& q, int bx, int) {
     // the counts grow with the point: the number P of points with count <= target (one
     // ballot) gives the new bracket [point P - 1, point P]
     const unsigned long long bl = __ballot(c <= target);
-    const int P = __popcll((bl >> base) & ((1ull << BIS_LANES) - 1));
+    constexpr unsigned long long lanes_mask = BIS_LANES == 64 ? ~0ull : ((1ull << (BIS_LANES & 63)) - 1);
+    const int P = __popcll((bl >> base) & lanes_mask);
     const double nlo = (P > 0) ? point(lo, w, P - 1) : lo;
     const double nhi = (P < BIS_LANES) ? point(lo, w, P) : hi;
     if (__all(done || !active)) break;
@@ -596,7 +600,10 @@ __device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
 // 6. Tight clusters: inverse iteration on the block with Gram-Schmidt against the earlier
 // members (sequential over members, one workgroup).  Exits at once if there is none.
 // The block's tridiagonal, its LU factors and the iterate live in LDS: the two serial
-// sweeps (one thread) touch only LDS, the rest is spread over the workgroup.
+// sweeps (one thread) touch only LDS, the rest is spread over the workgroup.  Each
+// Gram-Schmidt pass is classical (all projections of one pass computed together: one
+// wavefront per earlier column, then one row-wise update), two passes per solve, so a
+// member costs a fixed number of barriers however many members precede it.
 // ======================================================================================
 __device__ __forceinline__ void tri_cluster_body(const EigTask& q, int, int) {
   const double* diag = q.diag; const int r = q.r; const TriMeta& m = q.m; double* Z = q.Z;
@@ -608,6 +615,7 @@ __device__ __forceinline__ void tri_cluster_body(const EigTask& q, int, int) {
   __shared__ double uu[KFAC_MAX_SKETCH], u2[KFAC_MAX_SKETCH];        // U super-diagonals
   __shared__ double zc[KFAC_MAX_SKETCH];                              // the iterate
   __shared__ unsigned char pv[KFAC_MAX_SKETCH];                        // row interchange at i
+  __shared__ double dots[KFAC_MAX_SKETCH];                            // projections of one pass
   if (m.scal[2] == 0.0) return;
   const int tid = threadIdx.x, nw = blockDim.x >> 6;
   const double tn = m.scal[0];
@@ -679,15 +687,24 @@ __device__ __forceinline__ void tri_cluster_body(const EigTask& q, int, int) {
         }
       }
       __syncthreads();
+      const int lane = tid & 63, wv = tid >> 6;
       for (int pass = 0; pass < 2; ++pass) {
-        for (int c = k0; c < k; ++c) {
-          // column c < k is final and unit-norm: remove its component
+        // columns k0 .. k - 1 are final and unit-norm: their components of the iterate, one
+        // wavefront per column, then all of them removed in one row-wise sweep
+        for (int c = k0 + wv; c < k; c += nw) {
           double s = 0.0;
-          for (int i = tid; i < nb; i += blockDim.x) s += Z[(long)(b0 + i) * ldz + c] * zc[i];
-          const double dt = block_sum(s);
-          for (int i = tid; i < nb; i += blockDim.x) zc[i] -= dt * Z[(long)(b0 + i) * ldz + c];
-          __syncthreads();
+          for (int i = lane; i < nb; i += 64) s += Z[(long)(b0 + i) * ldz + c] * zc[i];
+          s = wave_sum(s);
+          if (lane == 0) dots[c - k0] = s;
         }
+        __syncthreads();
+        for (int i = tid; i < nb; i += blockDim.x) {
+          const double* zr = Z + (long)(b0 + i) * ldz;
+          double acc = 0.0;
+          for (int c = k0; c < k; ++c) acc += dots[c - k0] * zr[c];
+          zc[i] -= acc;
+        }
+        __syncthreads();
         double s = 0.0;
         for (int i = tid; i < nb; i += blockDim.x) s += zc[i] * zc[i];
         const double dt = block_sum(s);
@@ -890,7 +907,7 @@ hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldc
   if (n <= TNMAX) hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(TNT), 0, s, q);
   else hipLaunchKernelGGL(k_tridiag_gmem, dim3(1), dim3(1024), 0, s, q);
   hipLaunchKernelGGL(k_tri_prep, dim3(1), dim3(512), 0, s, q);
-  hipLaunchKernelGGL(k_tri_bisect, dim3((n + 15) / 16), dim3(256), 0, s, q);
+  hipLaunchKernelGGL(k_tri_bisect, dim3(tri_bisect_blocks(n)), dim3(256), 0, s, q);
   hipLaunchKernelGGL(k_tri_select, dim3(1), dim3(512), 0, s, q);
   if (n <= TNMAX) hipLaunchKernelGGL((k_tri_vec<32, TNMAX>), dim3((r + 31) / 32), dim3(32), 0, s, q);
   else hipLaunchKernelGGL((k_tri_vec<16, KFAC_MAX_SKETCH>), dim3((r + 15) / 16), dim3(16), 0, s, q);
@@ -917,7 +934,7 @@ KFAC_GLAUNCH(launch_backtransform4_g, k_backtransform4_g, EigTask, 256)
 hipError_t launch_backtransform_g(const EigTask* t, GroupMap gm, int blocks, int nc, hipStream_t s) {
   return nc == 4 ? launch_backtransform4_g(t, gm, blocks, s) : launch_backtransform1_g(t, gm, blocks, s);
 }
-int tri_bisect_blocks(int n) { return (n + 15) / 16; }
+int tri_bisect_blocks(int n) { return (n + BIS_PER_BLOCK - 1) / BIS_PER_BLOCK; }
 int tri_vec_blocks(int r) { return (r + 31) / 32; }
 int backtransform_blocks(int r, int nc) { return (r + 4 * nc - 1) / (4 * nc); }
 }  // namespace kfac

@@ -344,17 +344,21 @@ __global__ __launch_bounds__(256) void k_trsm(const double* W, long ldw, const d
 
 // ======================================================================================
 // Blocked Cholesky and inverse for l_pad <= 288.
-// Launch 1 (k_cholinv, one workgroup of 1024 threads per Gram, run as attempt 0 and then
+// Launch 1 (k_cholinv, one workgroup of 512 threads per Gram, run as attempt 0 and then
 // attempt 1 = shifted retry only where attempt 0 broke down):
-//   G = L L^T; L overwrites the lower triangle of G in place (the strict upper triangle
-//   and a saved copy of the diagonal keep G for the retry).  Right-looking over 32-wide
-//   block columns K:
-//   (a) one wavefront factors the diagonal block (element (r, c) of the block lives in
-//       lane c + 32 (r mod 2), register r / 2; columns are broadcast through LDS) and
-//       inverts it the same way; X_KK = L_KK^{-1} goes to the output;
-//   (b) panel  L_IK = A_IK X_KK^T               (fp64 MFMA, rows below the block);
-//   (c) update A_IJ -= L_IK L_JK^T, I >= J       (fp64 MFMA on the lower triangle of the
-//       trailing matrix; the panel is staged in LDS, the next tile is prefetched).
+//   G = L L^T, right-looking over 16-wide block columns K, with the trailing matrix on chip
+//   for the whole factorisation: the strictly lower 16 x 16 tiles (I > J) in the registers of
+//   wavefronts 1-7 (tile t = I (I - 1) / 2 + J in slot t / 7 of wavefront 1 + t mod 7, MFMA
+//   accumulator layout), the diagonal tiles in LDS.  Per block column K, two barriers:
+//   (a) panel: the owners of the tiles (I, K), I > K, form L_IK = A_IK X_KK^T (fp64 MFMA;
+//       X_KK = L_KK^{-1} from LDS) into the LDS panel and the output;
+//   (b) update: A_IJ -= L_IK L_JK^T for I >= J > K, operands from the panel.  Look-ahead:
+//       wavefront 0 updates the next diagonal tile first and factors it (block K + 1) while
+//       the others update the rest, the other diagonal tiles included.
+//   The diagonal block is factored by one wavefront (element (r, c) of the symmetric block in
+//   lane c, register r; pivots and columns by readlane) and inverted the same way; X_KK goes
+//   to the output.  L overwrites the lower triangle of G (the strict upper triangle and a
+//   saved copy of the diagonal keep G for the retry).
 // Launch 2 (k_trtri_cols, one workgroup per (Gram, block column K)): the off-diagonal
 //   blocks of X = L^{-1} down column K, X_IK = -X_II sum_{J=K}^{I-1} L_IJ X_JK, with the
 //   column panel of X in LDS.
@@ -363,20 +367,21 @@ __global__ __launch_bounds__(256) void k_trsm(const double* W, long ldw, const d
 // s = 11 (m l + l (l + 1)) u ||Y||_2^2, with ||Y||_2^2 bounded by trace(G).
 // Output X (l_pad x l_pad, zero above the diagonal and outside n x n).
 // ======================================================================================
-constexpr int BC = 16, BC_NT = 1024, TT_NT = 256;
-constexpr int BC_RG = 64 / BC;            // row groups of the factoring wavefront
-constexpr int BC_RT = BC / BC_RG;         // block rows per lane
-static_assert(BC % 16 == 0 && BC_RT * BC_RG == BC, "block shape");
+constexpr int BC = 16, BC_NT = 512, TT_NT = 256;
+constexpr int BC_NB = kCholInvMax / BC;                       // block rows at most
+constexpr int BC_TW = BC_NT / 64 - 1;                         // wavefronts holding tiles
+constexpr int BC_SLOTS = (BC_NB * (BC_NB - 1) / 2 + BC_TW - 1) / BC_TW;
+static_assert(BC == 16 && kCholInvMax % BC == 0, "block shape");
 
 struct BcSmem {
-  double P[288][BC + 1];          // panel of block column K (absolute rows)
-  double X[BC][BC + 1];           // inverse of the current diagonal block
-  double D[BC][BC + 1];           // the next diagonal block after its update (look-ahead)
+  double P[kCholInvMax][BC + 1];  // panel of block column K: A_IK, then L_IK (absolute rows)
+  double D[BC_NB][BC][BC + 1];    // diagonal tiles (current values of the trailing matrix)
+  double X[2][BC][BC + 1];        // inverse of the diagonal block K (buffer K mod 2)
   double shift;
   int fail;
 };
 
-// (a) for block K (wavefront 0 only).  Lane c (c = lane mod 16) holds the whole column c of
+// The diagonal block K (wavefront 0 only).  Lane c (c = lane mod 16) holds the whole column c of
 // the symmetric block, so the multiplier l_cj of its own column is its own entry j; the
 // pivot and column j come from lane j by readlane (uniform values, no LDS round trip).
 // X = L_KK^{-1} follows by forward substitution on the columns of the identity (lane c:
@@ -392,8 +397,8 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ bool bc_diag_block(double* G, long ldg, int n, int K, double* Xo, long ldx, BcSmem& sm,
-                                              const double* src, long lds) {
+__device__ __forceinline__ bool bc_diag_block(double* G, long ldg, int n, int K, double* Xo, long ldx,
+                                              double (*Xs)[BC + 1], const double* src, long lds) {
   static_assert(BC == 16, "one lane per column of the diagonal block");
   // The lane split goes through an opaque move so that lane-dependent predicates and
   // constants are recomputed at each call instead of being hoisted out of the caller's
@@ -453,7 +458,7 @@ __device__ __forceinline__ bool bc_diag_block(double* G, long ldg, int n, int K,
       if (in) G[(long)(k0 + r) * ldg + k0 + c] = d[r];
       const double xr = in ? x[r] : 0.0;               // zero outside n x n
       Xo[(long)(k0 + r) * ldx + k0 + c] = xr;
-      sm.X[r][c] = xr;
+      Xs[r][c] = xr;
     }
   }
   return true;
@@ -469,12 +474,53 @@ __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
   J = t - i * (i + 1) / 2;
 }
 
+// Strictly lower tile t = I (I - 1) / 2 + J (I > J) of the block grid (closed form; t is
+// small, the float estimate is corrected by one step either way).
+__device__ __forceinline__ void strict_lower_tile(int t, int& I, int& J) {
+  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) + 1.0f) * 0.5f);
+  if (i * (i - 1) / 2 > t) --i;
+  if ((i + 1) * i / 2 <= t) ++i;
+  I = i;
+  J = t - i * (i - 1) / 2;
+}
+
+__device__ __forceinline__ void wg_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// A -= P_I P_J^T on a 16 x 16 accumulator tile, operands from the LDS panel (rows of blocks I, J)
+__device__ __forceinline__ f64x4 bc_update(f64x4 acc, const double (*P)[BC + 1], int I, int J, int lane) {
+  double pa[BC / 4], pb[BC / 4];
+#pragma unroll
+  for (int u = 0; u < BC / 4; ++u) {
+    const int kc = 4 * u + (lane >> 4);
+    pa[u] = -P[I * BC + (lane & 15)][kc];
+    pb[u] = P[J * BC + (lane & 15)][kc];
+  }
+#pragma unroll
+  for (int u = 0; u < BC / 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[u], pb[u], acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ __forceinline__ f64x4 bc_load_tile(const double (*T)[BC + 1], int lane) {
+  f64x4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) a[r] = T[(lane >> 4) + 4 * r][lane & 15];
+  return a;
+}
+__device__ __forceinline__ void bc_store_tile(double (*T)[BC + 1], f64x4 a, int lane) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) T[(lane >> 4) + 4 * r][lane & 15] = a[r];
+}
+
 __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
   double* G = q.G; const long ldg = q.ldg; const int n = q.n;
   double* X = q.Linv; const long ldx = q.ldl; const int l_pad = q.l_pad;
   __shared__ BcSmem sm;
   const int attempt = q.attempt;
-  if (attempt == 1 && *q.fail_flag == 0) return;             // uniform
+  if (attempt == 1 && __builtin_amdgcn_readfirstlane(*q.fail_flag) == 0) return;   // uniform
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = BC_NT / 64;
   if (attempt == 0 && q.skip) {
     // second pass of CholeskyQR2: the first pass's basis is kept when its Gram is I to tol
@@ -501,7 +547,7 @@ __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
       *q.skip = keep ? 1 : 0;
       if (keep) *q.fail_flag = 0;
     }
-    if (keep) return;                                         // uniform
+    if (__builtin_amdgcn_readfirstlane(keep ? 1 : 0)) return;  // uniform
   }
   const int NB = l_pad / BC;
   // ---- set-up: save the diagonal (attempt 0) or restore G and shift it (attempt 1)
@@ -509,10 +555,8 @@ __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
     for (int i = tid; i < n; i += BC_NT) q.dsave[i] = G[(long)i * ldg + i];
     if (tid == 0) sm.shift = 0.0;
   } else {
-    for (int e = tid; e < n * n; e += BC_NT) {
-      const int i = e / n, j = e % n;
-      if (i > j) G[(long)i * ldg + j] = G[(long)j * ldg + i];
-    }
+    for (int i = wave + 1; i < n; i += nw)                    // a row per wave: the lower part
+      for (int j = lane; j < i; j += 64) G[(long)i * ldg + j] = G[(long)j * ldg + i];
     if (wave == 0) {
       double tr = 0.0;
       for (int i = lane; i < n; i += 64) tr += q.dsave[i];
@@ -523,116 +567,114 @@ __device__ __forceinline__ void cholinv_body(const CholInvTask& q, int, int) {
     for (int i = tid; i < n; i += BC_NT) G[(long)i * ldg + i] = q.dsave[i] + sm.shift;
   }
   if (tid == 0) sm.fail = 0;
-  // zero the strict upper block triangle of the output
-  for (int e = tid; e < l_pad * l_pad; e += BC_NT) {
-    const int i = e / l_pad, j = e % l_pad;
-    if (j / BC > i / BC) X[(long)i * ldx + j] = 0.0;
+  // zero the strict upper block triangle of the output, a row per wave
+  for (int i = wave; i < l_pad; i += nw)
+    for (int j = (i / BC + 1) * BC + lane; j < l_pad; j += 64) X[(long)i * ldx + j] = 0.0;
+  // the diagonal tiles into LDS (identity outside n x n); G's global writes above are
+  // visible to the whole workgroup after the barrier
+  __syncthreads();
+  for (int e = tid; e < NB * BC * BC; e += BC_NT) {
+    const int J = e / (BC * BC), r = (e / BC) % BC, c = e % BC;
+    const int i = J * BC + r, j = J * BC + c;
+    sm.D[J][r][c] = (i < n && j < n) ? G[(long)i * ldg + j] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  constexpr int CT = BC / 16;                                  // 16-column tiles per block
-  if (wave == 0) {
-    const bool ok = bc_diag_block(G, ldg, n, 0, X, ldx, sm, G, ldg);
-    if (!ok && lane == 0) sm.fail = 1;
-  }
-  __syncthreads();
-  const int wv = __builtin_amdgcn_readfirstlane(wave);
-  for (int K = 0; K < NB; ++K) {
-    const int k0 = K * BC, r0 = k0 + BC, m = l_pad - r0;
-    if (sm.fail) break;                                       // uniform
-    // (b) panel rows [r0, l_pad): L_iK = A_iK X_KK^T, 16 x 16 tiles
-    const int ptiles = (m / 16) * CT;
-    for (int t = wave; t < ptiles; t += nw) {
-      const int i0 = r0 + (t / CT) * 16, c0 = (t % CT) * 16;
-      const int ai = i0 + (lane & 15);
-      double a[BC / 4];
-#pragma unroll
-      for (int u = 0; u < BC / 4; ++u) {
-        const int kc = 4 * u + (lane >> 4);
-        a[u] = (ai < n && k0 + kc < n) ? G[(long)ai * ldg + k0 + kc] : 0.0;
+  // the two roles below run different code with the same barrier sequence (one barrier
+  // after the set-up, then two per block column); the role and the loop exit are
+  // wave-uniform (scalar) values, so every wavefront executes only its own role's barriers
+  if (__builtin_amdgcn_readfirstlane(wave) == 0) {
+    // ---- wavefront 0: the diagonal blocks, one step ahead of the panel
+    if (!bc_diag_block(G, ldg, n, 0, X, ldx, sm.X[0], &sm.D[0][0][0], BC + 1) && lane == 0) sm.fail = 1;
+    wg_barrier();                                             // X_00 and the flag visible
+    for (int K = 0; K < NB; ++K) {
+      if (__builtin_amdgcn_readfirstlane(sm.fail)) break;     // uniform over the workgroup
+      wg_barrier();                                           // (a) panel L_.K in LDS
+      if (K + 1 < NB) {
+        f64x4 acc = bc_load_tile(sm.D[K + 1], lane);
+        acc = bc_update(acc, sm.P, K + 1, K + 1, lane);
+        bc_store_tile(sm.D[K + 1], acc, lane);
+        wave_lds_order();
+        if (!bc_diag_block(G, ldg, n, K + 1, X, ldx, sm.X[(K + 1) & 1], &sm.D[K + 1][0][0], BC + 1) && lane == 0)
+          sm.fail = 1;
       }
-      f64x4 acc = {0, 0, 0, 0};
+      wg_barrier();                                           // (b) updates and X_K+1,K+1
+    }
+  } else {
+    // ---- wavefronts 1-7: the strictly lower tiles in registers.  The block coordinates of
+    // the slots are wave-uniform (scalar registers): slot sl holds tile (tI, tJ), tJ = -1 for
+    // an empty slot
+    const int tw = __builtin_amdgcn_readfirstlane(wave - 1);
+    const int ntile = NB * (NB - 1) / 2;
+    int tI[BC_SLOTS], tJ[BC_SLOTS];
 #pragma unroll
-      for (int u = 0; u < BC / 4; ++u)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], sm.X[c0 + (lane & 15)][4 * u + (lane >> 4)], acc, 0, 0, 0);
+    for (int sl = 0; sl < BC_SLOTS; ++sl) {
+      const int t = tw + BC_TW * sl;
+      int I = 0, J = -1;
+      if (t < ntile) strict_lower_tile(t, I, J);
+      tI[sl] = __builtin_amdgcn_readfirstlane(I);
+      tJ[sl] = __builtin_amdgcn_readfirstlane(J);
+    }
+    f64x4 T[BC_SLOTS];
+#pragma unroll
+    for (int sl = 0; sl < BC_SLOTS; ++sl) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = i0 + (lane >> 4) + 4 * r, col = c0 + (lane & 15);
-        const double v = (row < n && k0 + col < n) ? acc[r] : 0.0;
-        sm.P[row][col] = v;
-        if (row < n && k0 + col < n) G[(long)row * ldg + k0 + col] = v;
+        const int row = tI[sl] * BC + (lane >> 4) + 4 * r, col = tJ[sl] * BC + (lane & 15);
+        T[sl][r] = (tJ[sl] >= 0 && row < n && col < n) ? G[(long)row * ldg + col] : 0.0;
       }
     }
-    __syncthreads();
-    // (c) trailing update of the lower triangle, 16 x 16 tiles.  Look-ahead: wavefront 0
-    // updates the next diagonal tile first and factors it (block K + 1) while the other
-    // wavefronts update the remaining tiles, two per wavefront at a time (both tiles'
-    // loads in flight together, two independent MFMA chains).
-    const int T16 = m / 16, utiles = T16 * (T16 + 1) / 2;
-    const bool ahead = K + 1 < NB;
-    if (ahead && wv == 0) {
-      f64x4 acc;
+    wg_barrier();                                             // X_00 visible
+    for (int K = 0; K < NB; ++K) {
+      if (__builtin_amdgcn_readfirstlane(sm.fail)) break;     // uniform over the workgroup
+      const double (*Xk)[BC + 1] = sm.X[K & 1];
+      // the lane index through an opaque move each step: lane-dependent addresses are then
+      // formed where they are used instead of being hoisted for all slots at once (which
+      // would hold them across the factorisation and spill)
+      int lane;
+      asm volatile("v_and_b32 %0, 63, %1" : "=v"(lane) : "v"((int)threadIdx.x));
+      // (a) panel: L_IK = A_IK X_KK^T for the owned tiles (I, K): all of them staged into the
+      // panel first (one LDS wait for all), then transformed
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + (lane >> 4) + 4 * r, col = r0 + (lane & 15);
-        acc[r] = (row < n && col < n) ? G[(long)row * ldg + col] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < BC / 4; ++u) {
-        const int kc = 4 * u + (lane >> 4);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sm.P[r0 + (lane & 15)][kc], sm.P[r0 + (lane & 15)][kc], acc,
-                                                   0, 0, 0);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int lr = (lane >> 4) + 4 * r, lc = lane & 15, row = r0 + lr, col = r0 + lc;
-        if (row < n && col < n && col <= row) G[(long)row * ldg + col] = acc[r];
-        sm.D[lr][lc] = acc[r];
-      }
+      for (int sl = 0; sl < BC_SLOTS; ++sl)
+        if (tJ[sl] == K) bc_store_tile(&sm.P[tI[sl] * BC], T[sl], lane);   // uniform condition
       wave_lds_order();
-      const bool ok = bc_diag_block(G, ldg, n, K + 1, X, ldx, sm, &sm.D[0][0], BC + 1);
-      if (!ok && lane == 0) sm.fail = 1;
-    }
-    // the other tiles (tile 0 is the look-ahead tile when there is a next block)
-    const int w0 = ahead ? 1 : 0, nwu = nw - w0, first = ahead ? 1 : 0;
-    for (int base = first + (wv - w0); wv >= w0 && base < utiles; base += 2 * nwu) {
-      int ti[2], tj[2];
-      bool on[2];
-      f64x4 acc[2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int t = base + h * nwu;
-        on[h] = t < utiles;
-        lower_tile(on[h] ? t : 0, ti[h], tj[h]);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = r0 + ti[h] * 16 + (lane >> 4) + 4 * r, col = r0 + tj[h] * 16 + (lane & 15);
-          acc[h][r] = (on[h] && row < n && col < n) ? G[(long)row * ldg + col] : 0.0;
-        }
-      }
-      double pa[2][BC / 4], pb[2][BC / 4];
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int sl = 0; sl < BC_SLOTS; ++sl) {
+        const int I = tI[sl];
+        if (tJ[sl] != K) continue;                            // uniform
+        double a[BC / 4], b[BC / 4];
 #pragma unroll
         for (int u = 0; u < BC / 4; ++u) {
           const int kc = 4 * u + (lane >> 4);
-          pa[h][u] = -sm.P[r0 + ti[h] * 16 + (lane & 15)][kc];
-          pb[h][u] = sm.P[r0 + tj[h] * 16 + (lane & 15)][kc];
+          a[u] = sm.P[I * BC + (lane & 15)][kc];
+          b[u] = Xk[lane & 15][kc];
         }
+        f64x4 acc = {0, 0, 0, 0};
 #pragma unroll
-      for (int u = 0; u < BC / 4; ++u)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[h][u], pb[h][u], acc[h], 0, 0, 0);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (!on[h]) continue;                                 // uniform
+        for (int u = 0; u < BC / 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = r0 + ti[h] * 16 + (lane >> 4) + 4 * r, col = r0 + tj[h] * 16 + (lane & 15);
-          if (row < n && col < n && (ti[h] != tj[h] || col <= row)) G[(long)row * ldg + col] = acc[h][r];
+          const int row = I * BC + (lane >> 4) + 4 * r, col = K * BC + (lane & 15);
+          const bool in = row < n && col < n;
+          acc[r] = in ? acc[r] : 0.0;
+          if (in) G[(long)row * ldg + col] = acc[r];
         }
+        bc_store_tile(&sm.P[I * BC], acc, lane);
       }
+      wg_barrier();                                           // (a) panel L_.K in LDS
+      // (b) trailing update of the owned tiles and of the diagonal tiles J >= K + 2
+#pragma unroll
+      for (int sl = 0; sl < BC_SLOTS; ++sl) {
+        if (tJ[sl] <= K) continue;                            // uniform (empty slots: -1)
+        T[sl] = bc_update(T[sl], sm.P, tI[sl], tJ[sl], lane);
+      }
+      for (int J = K + 2 + tw; J < NB; J += BC_TW) {
+        f64x4 acc = bc_load_tile(sm.D[J], lane);
+        acc = bc_update(acc, sm.P, J, J, lane);
+        bc_store_tile(sm.D[J], acc, lane);
+      }
+      wg_barrier();                                           // (b) updates and X_K+1,K+1
     }
-    __syncthreads();
   }
   if (tid == 0) {
     const int failed = sm.fail;
@@ -849,6 +891,7 @@ __device__ __forceinline__ void trmm_body(const TrmmTask& q, int bx, int by) {
 __global__ __launch_bounds__(256) void k_trmm_f64(TrmmTask q) { trmm_body(q, blockIdx.x, blockIdx.y); }
 KFAC_GROUPED_KERNEL(k_trmm_f64_g, trmm_body, TrmmTask, 256)
 
+
 // ======================================================================================
 // Host launchers
 // ======================================================================================
@@ -936,6 +979,7 @@ KFAC_GLAUNCH(launch_cholinv_g, k_cholinv_g, CholInvTask, BC_NT)
 KFAC_GLAUNCH(launch_trtri_cols_g, k_trtri_cols_g, CholInvTask, TT_NT)
 int trtri_col_blocks(int l_pad) { return l_pad / BC - 1; }
 KFAC_GLAUNCH(launch_trmm_g, k_trmm_f64_g, TrmmTask, 256)
+
 int gram_reduce_slices() { return GR_T * GR_T / 256; }
 int trmm_blocks_x(int ncols) { return (ncols + GR_T - 1) / GR_T; }
 int trmm_blocks_y(int l_pad) { return (l_pad + GR_T - 1) / GR_T; }

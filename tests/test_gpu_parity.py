@@ -208,6 +208,34 @@ def test_rand_eig_repeated_eigenvalues_exact_regime():
     np.testing.assert_allclose(Ug[:, :6] @ Ug[:, :6].T, R[:, :6] @ R[:, :6].T, atol=1e-5)
 
 
+@pytest.mark.parametrize("d,r,p", [(272, 250, 22), (600, 256, 16)])
+def test_rand_eig_large_tight_cluster(d, r, p):
+    """An EA factor early in training: rho^k I plus a small low-rank part, so ~200 Ritz values
+    agree to fp32 rounding (~1e-7 relative) and most of them fall into one tight cluster of
+    the tridiagonal eigensolver (gaps below 1e-9 ||T||), which takes inverse iteration with
+    Gram-Schmidt.  Exact regime (l = d): eigenvalues against LAPACK and the eigen-residual;
+    sketch regime: Ritz values against the oracle's SREVD with the same Omega and the
+    Rayleigh-Ritz property U^T F U = diag(D); orthonormal vectors in both."""
+    sig = np.full(d, 0.6)
+    sig[:20] += np.linspace(2.0, 0.1, 20)
+    F = synth.psd_factor(d, sig, 31).astype(np.float32)
+    U, D, st = K().rand_eig(torch.from_numpy(F).to(DEV), r, p, 1, seed=0)
+    torch.cuda.synchronize()
+    assert int(st.item()) & ~1 == 0, int(st.item())
+    Ug, Dg = to_np(U).astype(np.float64), to_np(D).astype(np.float64)
+    F64 = F.astype(np.float64)
+    assert np.abs(Ug.T @ Ug - np.eye(r)).max() < 1e-5
+    if r + p >= d:
+        ref = np.sort(np.linalg.eigvalsh(F64))[::-1][:r]
+        np.testing.assert_allclose(Dg, ref, rtol=1e-5)
+        res = F64 @ Ug - Ug * Dg
+        assert np.linalg.norm(res) <= 1e-5 * np.linalg.norm(F64) * np.sqrt(r)
+    else:
+        _, Do = O.srevd(F64, r, p, 1, 0)
+        assert e_lambda(Dg, Do) <= 1e-4, e_lambda(Dg, Do)
+        assert np.abs(Ug.T @ F64 @ Ug - np.diag(Dg)).max() <= 1e-5 * np.linalg.norm(F64, 2)
+
+
 @pytest.mark.parametrize("sizes", [[1] * 200, [70, 70, 60], [64, 1, 63, 72]])
 def test_rand_eig_exact_regime_split_tridiagonal(sizes):
     """F = blockdiag(B_1, ..., B_m) in the exact regime (l = d): the Householder reduction
