@@ -83,9 +83,21 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
     if (k + 2 >= n) break;                            // uniform
     const int kb = (k + 1) >> 5;                      // first block with rows/cols > k
     const double* col = S.scol[k & 1];
-    // (1) reflector H = I - 2 v v^T (|v| = 1) from column k, in every wave
+    // (1) reflector H = I - 2 v v^T (|v| = 1) from column k, in every wave.  The lane's
+    // entries of the column (i = lane + 64 u) are read once, all loads issued together.
+    constexpr int TCU = (TNMAX + 63) / 64;
+    double cx[TCU];
+#pragma unroll
+    for (int u = 0; u < TCU; ++u) {
+      const int i = lane + 64 * u;
+      cx[u] = (i < TNMAX) ? col[i] : 0.0;
+    }
     double s2 = 0.0;
-    for (int i = k + 1 + lane; i < n; i += 64) { const double x = col[i]; s2 += x * x; }
+#pragma unroll
+    for (int u = 0; u < TCU; ++u) {
+      const int i = lane + 64 * u;
+      if (i > k && i < n) s2 += cx[u] * cx[u];
+    }
     s2 = wave_sum(s2);
     const double x0 = col[k + 1];
     // |x|, alpha = -sign(x0) |x| and 1 / |x - alpha e1| with |x - alpha e1|^2 =
@@ -97,11 +109,14 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
     const double v1 = (x0 - alpha) * inv;
     // v into LDS by every wave (identical values; the wave's own stores precede its
     // loads in LDS order, and the previous step's readers are past the last barrier)
-    for (int i = lane; i < TNMAX; i += 64) {
-      const double x = col[i];
-      const double vi = (i > k + 1 && i < n) ? x * inv : (i == k + 1 ? v1 : 0.0);
-      S.sv[i] = vi;
-      if (wave == 0 && i < n) V[(long)k * n + i] = vi;
+#pragma unroll
+    for (int u = 0; u < TCU; ++u) {
+      const int i = lane + 64 * u;
+      if (i < TNMAX) {
+        const double vi = (i > k + 1 && i < n) ? cx[u] * inv : (i == k + 1 ? v1 : 0.0);
+        S.sv[i] = vi;
+        if (wave == 0 && i < n) V[(long)k * n + i] = vi;
+      }
     }
     if (wave == 0 && lane == 0) {
       diag[k] = col[k];
@@ -158,7 +173,11 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
       __syncthreads();
       // (3) K = v^T p in every wave; w = p - K v (zero on rows <= k); A -= v w^T + w v^T
       double kp = 0.0;
-      for (int i = k + 1 + lane; i < n; i += 64) kp += vval(i) * S.sp[i];
+#pragma unroll
+      for (int u = 0; u < TCU; ++u) {
+        const int i = lane + 64 * u;
+        if (i > k && i < n) kp += vval(i) * S.sp[i];
+      }
       const double K = wave_sum(kp);
       double wc[TNB];
 #pragma unroll
