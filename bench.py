@@ -349,7 +349,7 @@ def measured_traffic(workload, kernel):
         return None
 
 
-# Kernel families of the step (SURVEY-independent names): the launch sequence is walked in
+# Kernel families of the step: the launch sequence is walked in
 # order, since a gemm_f32 / slice_reduce launch belongs to the phase it sits in.
 A8 = {"tridiag", "tri_prep", "tri_bisect", "tri_select", "tri_vec", "tri_cluster_lead", "tri_cluster",
       "backtransform"}
@@ -888,7 +888,7 @@ def main_driver(args, dev):
     T_KI = 50 (epoch 0: r = 220, r_l = 10, n_pwr-it = 4), the damped inverse every iteration,
     each iteration one replay of a captured graph.  Reports the K-factor work per training
     iteration amortised over the period, and the three kinds of iteration separately.
-    Inputs are written into the driver's buffers once (their values do not change the work)."""
+    Inputs (the K-factor step benchmark's recipe) are written into the driver's buffers once."""
     import torch
     import paper_2206_15397_amd as K
     from paper_2206_15397_amd import synth
@@ -898,13 +898,21 @@ def main_driver(args, dev):
     shapes = synth.vgg16_bn_cifar_layers(sched.batch)
     drv = KFACDriver([LayerSpec(s.m_a, s.d_g, s.n, s.bias) for s in shapes], schedule=sched, sketch=args.sketch,
                      device=dev)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(77)
-    for l in range(len(shapes)):
+    # the same input recipe as the K-factor step benchmark: layer inputs and gradients with
+    # power-law covariance spectra on Haar bases, J = g^T [a | 1] / n
+    for l, s in enumerate(shapes):
         a, g, J = drv.inputs(l)
-        a.copy_(torch.randn(a.shape, generator=gen, device=dev).abs_())
-        g.copy_(1e-3 * torch.randn(g.shape, generator=gen, device=dev))
-        J.copy_(1e-3 * torch.randn(J.shape, generator=gen, device=dev))
+        Ra = synth.torch_haar_orthogonal(s.m_a, synth.SEED_ROT_A + l, dev)
+        Rg = synth.torch_haar_orthogonal(s.d_g, synth.SEED_ROT_G + l, dev)
+        sa = torch.tensor(synth.power_spectrum(s.m_a), dtype=torch.float32, device=dev)
+        sg = torch.tensor(synth.power_spectrum(s.d_g), dtype=torch.float32, device=dev)
+        af = synth.torch_activation_batch(s.n, Ra, sa, synth.SEED_ACT_A + l, 0, dev)
+        gf = synth.torch_activation_batch(s.n, Rg, sg, synth.SEED_ACT_G + l, 0, dev)
+        J.copy_(gf.T @ torch.cat([af, torch.ones((s.n, 1), device=dev)], dim=1) / s.n)
+        a.copy_(af)
+        g.copy_(gf)
+        del Ra, Rg, af, gf
+    torch.cuda.synchronize()
     period = sched.T_KI(0)
     # the first period builds the plans and graphs; the second is timed
     for it in range(period):
@@ -1104,8 +1112,8 @@ def main_copy(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(multi-GPU sharding is design-only).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs on one GPU "
+              "per process and has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
     if args.config == "copy":
         return main_copy(args)
