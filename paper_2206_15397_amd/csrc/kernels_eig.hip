@@ -44,7 +44,7 @@ struct TriSh {
   double (*scol)[TNMAX];    // two column buffers
   double* sv;               // v of the current step (written by every wave, same values)
   double* sp;               // p = 2 A v, zero on rows <= k
-  double (*spr)[TB][4];     // row partials, one per 8 columns of a block
+  double (*spr)[TB][8];     // row partials, one per 4 columns of a block
   double (*spc)[TNB][TB];   // column partials per wave
 };
 
@@ -71,17 +71,18 @@ __device__ __forceinline__ void tri_copy_col(const double (&a)[36][THR], const T
   }
 }
 
-template <int J0>
-__device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh& S, int n, double* V, double* diag,
-                                              double* off) {
+// Step k = 32 J0 + c0; LASTC: c0 is the block column's last (then the trailing blocks
+// start at J0 + 1, else at J0; a template parameter, so every block predicate below is a
+// compile-time constant).
+template <int J0, bool LASTC>
+__device__ __forceinline__ void tri_step(double (&a)[36][THR], const TriSh& S, int n, double* V, double* diag,
+                                         double* off, int c0) {
   const int t = threadIdx.x, tr = t >> 5, tc = t & 31, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   double (*Ld)[TB][TB + 1] = S.Ld;
-  if (TB * J0 + 2 >= n) return;                       // uniform
-  for (int c0 = 0; c0 < TB; ++c0) {
+  {
     const int k = TB * J0 + c0;
-    if (k + 2 >= n) break;                            // uniform
-    const int kb = (k + 1) >> 5;                      // first block with rows/cols > k
+    constexpr int kb = J0 + (LASTC ? 1 : 0);          // first block with rows/cols > k
     const double* col = S.scol[k & 1];
     // (1) reflector H = I - 2 v v^T (|v| = 1) from column k, in every wave.  The lane's
     // entries of the column (i = lane + 64 u) are read once, all loads issued together.
@@ -145,10 +146,9 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
               }
             }
             pr += Ld[I][rr][tc] * vc[I];             // diagonal block I, held in full
-            pr += dpp_any<0xB1>(pr);                 // sum over 8 neighbouring columns
+            pr += dpp_any<0xB1>(pr);                 // sum over 4 neighbouring columns
             pr += dpp_any<0x4E>(pr);
-            pr += dpp_any<0x141>(pr);
-            S.spr[I][rr][tc >> 3] = pr;              // the 8 lanes store the same value
+            S.spr[I][rr][tc >> 2] = pr;              // the 4 lanes store the same value
           }
         }
       }
@@ -164,7 +164,8 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
         double p = 0.0;
         if (t > k && t < n) {
           const int I = t >> 5, c = t & 31;
-          p = (S.spr[I][c][0] + S.spr[I][c][1]) + (S.spr[I][c][2] + S.spr[I][c][3]);
+          p = ((S.spr[I][c][0] + S.spr[I][c][1]) + (S.spr[I][c][2] + S.spr[I][c][3])) +
+              ((S.spr[I][c][4] + S.spr[I][c][5]) + (S.spr[I][c][6] + S.spr[I][c][7]));
 #pragma unroll
           for (int w2 = 0; w2 < TNW; ++w2) p += S.spc[w2][I][c];
         }
@@ -198,10 +199,21 @@ __device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh&
       }
     }
     // (4) column k + 1 into the other buffer (its owners updated it just now)
-    if (c0 + 1 < TB) tri_copy_col<J0>(a, S, n, k + 1, S.scol[(k + 1) & 1]);
-    else tri_copy_col<J0 + 1>(a, S, n, k + 1, S.scol[(k + 1) & 1]);
+    tri_copy_col<J0 + (LASTC ? 1 : 0)>(a, S, n, k + 1, S.scol[(k + 1) & 1]);
     __syncthreads();
   }
+}
+
+template <int J0>
+__device__ __forceinline__ void tri_block_col(double (&a)[36][THR], const TriSh& S, int n, double* V, double* diag,
+                                              double* off) {
+  if (TB * J0 + 2 >= n) return;                       // uniform
+  for (int c0 = 0; c0 < TB - 1; ++c0) {
+    if (TB * J0 + c0 + 2 >= n) return;                // uniform
+    tri_step<J0, false>(a, S, n, V, diag, off, c0);
+  }
+  if (TB * J0 + TB - 1 + 2 >= n) return;
+  tri_step<J0, true>(a, S, n, V, diag, off, TB - 1);
 }
 
 template <int... Js>
@@ -217,7 +229,7 @@ __device__ __forceinline__ void tridiag_reg_body(const EigTask& q, int, int) {
   __shared__ double scol[2][TNMAX];
   __shared__ double sv[TNMAX];
   __shared__ double sp[TNMAX];
-  __shared__ double spr[TNB][TB][4];
+  __shared__ double spr[TNB][TB][8];
   __shared__ double spc[TNW][TNB][TB];
   const int t = threadIdx.x, tr = t >> 5, tc = t & 31;
   double a[36][THR];
