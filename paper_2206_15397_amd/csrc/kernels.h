@@ -116,7 +116,7 @@ EigTask make_eig_task(const double* C, long ldc, const float* Cf, long ldcf, int
                       double* Dd, int* status);
 int tri_bisect_blocks(int n);
 int tri_vec_blocks(int r);
-int backtransform_blocks(int r, int nc);   // nc columns per wavefront (1 or 4)
+int backtransform_blocks(int r);   // 32 columns per workgroup
 // grouped fp32 GEMM tiles: 64x64, 128x128, 96x128, 128x64, and 288x64 "skinny" (whole
 // sketch width, no transposes, M <= 288)
 constexpr int kGemmConfigs = 5;
@@ -162,6 +162,6 @@ hipError_t launch_tri_select_g(const EigTask* t, GroupMap gm, int blocks, hipStr
 hipError_t launch_tri_vec_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_tri_cluster_lead_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
 hipError_t launch_tri_cluster_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
-hipError_t launch_backtransform_g(const EigTask* t, GroupMap gm, int blocks, int nc, hipStream_t s);
+hipError_t launch_backtransform_g(const EigTask* t, GroupMap gm, int blocks, hipStream_t s);
 
 }  // namespace kfac

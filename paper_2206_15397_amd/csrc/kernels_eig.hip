@@ -10,7 +10,7 @@
 //   5. eigenvectors by the twisted factorisation T - lambda I = N_k Delta_k N_k^T of the
 //      eigenvalue's block (one thread per eigenvector, factors kept in LDS);
 //   6. inverse iteration with Gram-Schmidt for members of tight clusters (rare);
-//   7. back-transformation by the Householder reflectors (one wavefront per column).
+//   7. back-transformation by the Householder reflectors (eight lanes per column).
 #include <utility>
 #include "kernels.h"
 
@@ -565,11 +565,20 @@ __device__ __forceinline__ void tri_select_body(const EigTask& q, int, int) {
 // ======================================================================================
 template <int NT, int NMAX>
 __device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
-  const double* diag = q.diag; const int n = q.n, r = q.r; const TriMeta& m = q.m; double* Z = q.Z;
+  const int n = q.n, r = q.r; const TriMeta& m = q.m; double* Z = q.Z;
   const long ldz = q.ldz;
-  __shared__ double sL[NT][NMAX];
-  __shared__ double sD[NT][NMAX];
+  // thread t's entry i at [i][t]: the threads of one step touch consecutive words (one
+  // row per thread would put all of them in one LDS bank)
+  __shared__ double sL[NMAX][NT];
+  __shared__ double sD[NMAX][NT];
+  // T's diagonal and off-diagonal in LDS: the recurrences read them at LDS latency
+  __shared__ double td[NMAX], te[NMAX];
   const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += NT) {
+    td[i] = q.diag[i];
+    te[i] = m.es[i];
+  }
+  __syncthreads();
   const int k = bx * NT + tid;
   if (k >= r) return;
   const double pivmin = m.scal[1];
@@ -577,35 +586,35 @@ __device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
   const int j = m.col_task[k];
   const double lam = m.lam[j];
   const int b0 = m.blo[j], b1 = m.bhi[j];
-  double* L = sL[tid];
-  double* Dp = sD[tid];
+  auto L = [&](int i) -> double& { return sL[i][tid]; };
+  auto Dp = [&](int i) -> double& { return sD[i][tid]; };
   // forward
   // divisions by the pivots: hardware reciprocal + one Newton step (about 2^-52 relative,
-  // a rounding-sized perturbation of each pivot); loops unrolled so that the loads of d
+  // a rounding-sized perturbation of each pivot); loops unrolled so that the reads of d
   // and e go out ahead of the dependent recurrence
-  double dp = diag[b0] - lam;
+  double dp = td[b0] - lam;
 #pragma unroll 4
   for (int i = b0; i + 1 < b1; ++i) {
     if (fabs(dp) < tiny) dp = (dp < 0.0) ? -tiny : tiny;
-    const double e = m.es[i];
+    const double e = te[i];
     const double l = fast_div(e, dp);
-    L[i - b0] = l;
-    Dp[i - b0] = dp;
-    dp = (diag[i + 1] - lam) - l * e;
+    L(i - b0) = l;
+    Dp(i - b0) = dp;
+    dp = (td[i + 1] - lam) - l * e;
   }
-  Dp[b1 - 1 - b0] = dp;
+  Dp(b1 - 1 - b0) = dp;
   // backward with twist search
-  double dm = diag[b1 - 1] - lam;
+  double dm = td[b1 - 1] - lam;
   double best = fabs(dp);   // gamma_{b1-1} = D+_{b1-1}
   int kstar = b1 - 1;
 #pragma unroll 4
   for (int i = b1 - 2; i >= b0; --i) {
     if (fabs(dm) < tiny) dm = (dm < 0.0) ? -tiny : tiny;
-    const double e = m.es[i];
+    const double e = te[i];
     const double u = fast_div(e, dm);
-    const double dmi = (diag[i] - lam) - u * e;
-    const double g = Dp[i - b0] + dmi - (diag[i] - lam);
-    Dp[i - b0] = u;           // slot i now holds U_i
+    const double dmi = (td[i] - lam) - u * e;
+    const double g = Dp(i - b0) + dmi - (td[i] - lam);
+    Dp(i - b0) = u;           // slot i now holds U_i
     if (fabs(g) < best) { best = fabs(g); kstar = i; }
     dm = dmi;
   }
@@ -616,13 +625,13 @@ __device__ __forceinline__ void tri_vec_body(const EigTask& q, int bx, int) {
   Z[(long)kstar * ldz + k] = 1.0;
 #pragma unroll 4
   for (int i = kstar - 1; i >= b0; --i) {
-    z = -L[i - b0] * z;
+    z = -L(i - b0) * z;
     Z[(long)i * ldz + k] = z;
   }
   z = 1.0;
 #pragma unroll 4
   for (int i = kstar; i + 1 < b1; ++i) {
-    z = -Dp[i - b0] * z;
+    z = -Dp(i - b0) * z;
     Z[(long)(i + 1) * ldz + k] = z;
   }
 }
@@ -775,101 +784,135 @@ __device__ __forceinline__ void tri_cluster_lead_body(const EigTask& q, int, int
 
 // ======================================================================================
 // 7. Back-transformation P = H_0 ... H_{n-3} z for each of the first r columns (the column
-// is normalised first).  Each wavefront carries NC columns: every staged reflector is read
-// from LDS once for all of them and their NC dot-product reductions run side by side.
-// fp32 output, rows n..n_pad-1 zero.  grid = ceil(r / (4 NC)) blocks of 256 threads.
+// is normalised first).  Eight lanes carry one column: lane 8 c + g holds rows 8 u + g
+// (u < U) of column c of its wavefront, so a reflector's dot product is eight short sums
+// reduced in three DPP steps, and the rows above a chunk's lowest reflector (a prefix of u
+// in blocks of 32 rows, the same for every lane) are skipped.  Reflectors are staged in LDS
+// in chunks of 16 (8 above width 288; row pitch 8 U, zero beyond n), the next chunk's loads
+// in flight while the current one is applied.  fp32 output, rows n..n_pad-1 zero;
+// grid = ceil(r / 32) blocks of 256 threads (8 columns per wavefront).
 // ======================================================================================
-template <int NC, int NMAX>
-__device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int) {
-  const double* V = q.V; const double* Z = q.Z; const long ldz = q.ldz; const int n = q.n, n_pad = q.n_pad;
-  const int r = q.r; float* P = q.P; const long ldp = q.ldp;
-  constexpr int CH = 16;                      // reflectors staged per LDS chunk
-  constexpr int PER = (NMAX + 63) / 64;
-  // A chunk (reflectors klo .. klo + cnt - 1) is one contiguous run of cnt * n doubles of V:
-  // it is copied flat (row pitch n in LDS), every thread's loads in flight together, and
-  // the next chunk's loads go out before the current chunk is applied.
-  constexpr int CPT = (CH * NMAX + 255) / 256;
-  __shared__ double vch[CH * NMAX];
+// reflectors per staged chunk (fewer for the widest matrices: registers)
+template <int NMAX> constexpr int bt_ch() { return NMAX > kPlanMaxSketch ? 8 : 16; }
+
+__device__ __forceinline__ double bt_colsum(double x) {     // over the column's 8 lanes
+  x += dpp_any<0xB1>(x);
+  x += dpp_any<0x4E>(x);
+  x += dpp_any<0x141>(x);
+  return x;
+}
+
+// Reflectors k = kt down to klo of the staged chunk on the lane's rows 8 u + g, u >= U0
+// (rows below 8 U0 are zero in every reflector of the chunk).
+template <int U, int U0>
+__device__ __forceinline__ void bt_apply(double (&z)[U], const double* vch, int kt, int klo, int g) {
+#pragma unroll 1
+  for (int k = kt; k >= klo; --k) {
+    const double* vk = vch + (k - klo) * (8 * U) + g;
+    double vv[U], s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = U0; u < U; ++u) {
+      vv[u] = vk[8 * u];
+      s4[u & 3] = fma(vv[u], z[u], s4[u & 3]);
+    }
+    const double t = 2.0 * bt_colsum((s4[0] + s4[1]) + (s4[2] + s4[3]));
+#pragma unroll
+    for (int u = U0; u < U; ++u) z[u] = fma(-t, vv[u], z[u]);
+  }
+}
+
+// Staging of reflector chunks into LDS, the next chunk's loads in registers meanwhile.
+template <int NMAX>
+struct BtStage {
+  static constexpr int CH = bt_ch<NMAX>(), CPT = (CH * NMAX + 255) / 256;
+  const double* V;
+  int n;
+  double* vch;
   double pre[CPT];
-  auto load_chunk = [&](int klo, int cnt) {
+  // chunk (reflectors klo .. klo + cnt - 1) into registers: element e = j * NMAX + i is row
+  // i of reflector klo + j (zero for i >= n)
+  __device__ __forceinline__ void load(int klo, int cnt) {
     const double* src = V + (long)klo * n;
 #pragma unroll
     for (int t = 0; t < CPT; ++t) {
-      const int e = threadIdx.x + 256 * t;
-      pre[t] = (e < cnt * n) ? src[e] : 0.0;
+      const int e = threadIdx.x + 256 * t, j = e / NMAX, i = e - j * NMAX;
+      pre[t] = (j < cnt && i < n) ? src[(long)j * n + i] : 0.0;
     }
-  };
-  auto store_chunk = [&](int cnt) {
+  }
+  __device__ __forceinline__ void store() {
 #pragma unroll
     for (int t = 0; t < CPT; ++t) {
       const int e = threadIdx.x + 256 * t;
-      if (e < cnt * n) vch[e] = pre[t];
+      if (e < CH * NMAX) vch[e] = pre[t];
     }
-  };
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c0 = (bx * 4 + wave) * NC;
-  double z[NC][PER];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const int c = c0 + j;
-    double nn = 0.0;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = lane + 64 * u;
-      z[j][u] = (c < r && i < n) ? Z[(long)i * ldz + c] : 0.0;
-      nn += z[j][u] * z[j][u];
-    }
-    nn = wave_sum(nn);
-    double sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-    if (q.svd && c < r) {               // left singular vectors: W p_k / sigma_k
-      const double lk = q.Dd[c];
-      sc = (lk > 0.0) ? sc / sqrt(lk) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) z[j][u] *= sc;
   }
-  if (n - 3 >= 0) load_chunk(max(0, n - 3 - CH + 1), n - 3 - max(0, n - 3 - CH + 1) + 1);
-  for (int kt = n - 3; kt >= 0; kt -= CH) {
+};
+
+// The chunks (from kt down) whose lowest reflector klo has (klo + 1) / 32 == B: their
+// rows below 32 B are zero.  kt moves down chunk by chunk; the phases run in decreasing
+// B, each a loop of its own, so z stays in the same registers from phase to phase.
+template <int U, int B, int NMAX>
+__device__ __forceinline__ void bt_phase(double (&z)[U], BtStage<NMAX>& st, int& kt, int g) {
+  constexpr int CH = BtStage<NMAX>::CH;
+  while (kt >= 0) {
     const int klo = max(0, kt - CH + 1);
-    const int cnt = kt - klo + 1;
+    if ((klo + 1) / 32 != B) return;          // uniform
     __syncthreads();                          // the previous chunk's readers are done
-    store_chunk(cnt);
+    st.store();
     __syncthreads();
     if (kt - CH >= 0) {
       const int nlo = max(0, kt - CH - CH + 1);
-      load_chunk(nlo, kt - CH - nlo + 1);
+      st.load(nlo, kt - CH - nlo + 1);
     }
-    for (int k = kt; k >= klo; --k) {
-      const double* vk = vch + (k - klo) * n;
-      double vv[PER];
+    bt_apply<U, 4 * B>(z, st.vch, kt, klo, g);
+    kt -= CH;
+  }
+}
+
+template <int U, int NMAX, int... Is>
+__device__ __forceinline__ void bt_phases(std::integer_sequence<int, Is...>, double (&z)[U], BtStage<NMAX>& st,
+                                          int& kt, int g) {
+  constexpr int NB = NMAX / 32;
+  (bt_phase<U, NB - 1 - Is, NMAX>(z, st, kt, g), ...);
+}
+
+template <int NMAX>
+__device__ __forceinline__ void backtransform_body(const EigTask& q, int bx, int) {
+  constexpr int U = NMAX / 8;
+  static_assert(NMAX % 32 == 0, "row blocks of 32");
+  const double* Z = q.Z; const long ldz = q.ldz; const int n = q.n, n_pad = q.n_pad;
+  const int r = q.r; float* P = q.P; const long ldp = q.ldp;
+  __shared__ double vch[bt_ch<NMAX>() * NMAX];
+  BtStage<NMAX> st;
+  st.V = q.V; st.n = n; st.vch = vch;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane & 7;
+  const int c = (bx * 4 + wave) * 8 + (lane >> 3);
+  const bool cin = c < r;
+  double z[U];
+  double nn = 0.0;
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int i = lane + 64 * u;
-        vv[u] = (i > k && i < n) ? vk[i] : 0.0;
-      }
-      double s[NC];
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        s[j] = 0.0;
-#pragma unroll
-        for (int u = 0; u < PER; ++u) s[j] += vv[u] * z[j][u];
-      }
-#pragma unroll
-      for (int j = 0; j < NC; ++j) s[j] = 2.0 * wave_sum(s[j]);
-#pragma unroll
-      for (int j = 0; j < NC; ++j)
-#pragma unroll
-        for (int u = 0; u < PER; ++u) z[j][u] -= s[j] * vv[u];
-    }
+  for (int u = 0; u < U; ++u) {
+    const int i = 8 * u + g;
+    z[u] = (cin && i < n) ? Z[(long)i * ldz + c] : 0.0;
+    nn = fma(z[u], z[u], nn);
+  }
+  nn = bt_colsum(nn);
+  double sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+  if (q.svd && cin) {                        // left singular vectors: W p_k / sigma_k
+    const double lk = q.Dd[c];
+    sc = (lk > 0.0) ? sc / sqrt(lk) : 0.0;
   }
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const int c = c0 + j;
-    if (c >= r) continue;
+  for (int u = 0; u < U; ++u) z[u] *= sc;
+  int kt = n - 3;
+  constexpr int CH = BtStage<NMAX>::CH;
+  if (kt >= 0) st.load(max(0, kt - CH + 1), kt - max(0, kt - CH + 1) + 1);
+  bt_phases(std::make_integer_sequence<int, NMAX / 32>{}, z, st, kt, g);
+  if (cin) {
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = lane + 64 * u;
-      if (i < n_pad) P[(long)i * ldp + c] = (i < n) ? (float)z[j][u] : 0.f;
+    for (int u = 0; u < U; ++u) {
+      const int i = 8 * u + g;
+      if (i < n_pad) P[(long)i * ldp + c] = (i < n) ? (float)z[u] : 0.f;
     }
   }
 }
@@ -883,8 +926,9 @@ template <int NT, int NMAX>
 __global__ __launch_bounds__(NT) void k_tri_vec(EigTask q) { tri_vec_body<NT, NMAX>(q, blockIdx.x, 0); }
 __global__ __launch_bounds__(256) void k_tri_cluster_lead(EigTask q) { tri_cluster_lead_body(q, 0, 0); }
 __global__ __launch_bounds__(256) void k_tri_cluster(EigTask q) { tri_cluster_body(q, 0, 0); }
+template <int NMAX>
 __global__ __launch_bounds__(256) void k_backtransform(EigTask q) {
-  backtransform_body<1, KFAC_MAX_SKETCH>(q, blockIdx.x, 0);
+  backtransform_body<NMAX>(q, blockIdx.x, 0);
 }
 
 KFAC_GROUPED_KERNEL(k_tridiag_reg_g, tridiag_reg_body, EigTask, TNT)
@@ -898,8 +942,7 @@ __global__ __launch_bounds__(32) void k_tri_vec_g(const EigTask* tasks, GroupMap
 }
 KFAC_GROUPED_KERNEL(k_tri_cluster_lead_g, tri_cluster_lead_body, EigTask, 256)
 KFAC_GROUPED_KERNEL(k_tri_cluster_g, tri_cluster_body, EigTask, 256)
-KFAC_GROUPED_KERNEL(k_backtransform_g, (backtransform_body<1, kPlanMaxSketch>), EigTask, 256)
-KFAC_GROUPED_KERNEL(k_backtransform4_g, (backtransform_body<4, kPlanMaxSketch>), EigTask, 256)
+KFAC_GROUPED_KERNEL(k_backtransform_g, backtransform_body<kPlanMaxSketch>, EigTask, 256)
 
 // ======================================================================================
 size_t small_eig_scratch_doubles(int n, int r) {
@@ -944,7 +987,8 @@ hipError_t launch_small_eig(const double* C, long ldc, const float* Cf, long ldc
   else hipLaunchKernelGGL((k_tri_vec<16, KFAC_MAX_SKETCH>), dim3((r + 15) / 16), dim3(16), 0, s, q);
   hipLaunchKernelGGL(k_tri_cluster_lead, dim3(1), dim3(256), 0, s, q);
   hipLaunchKernelGGL(k_tri_cluster, dim3(1), dim3(256), 0, s, q);
-  hipLaunchKernelGGL(k_backtransform, dim3((r + 3) / 4), dim3(256), 0, s, q);
+  if (n <= kPlanMaxSketch) hipLaunchKernelGGL(k_backtransform<kPlanMaxSketch>, dim3(backtransform_blocks(r)), dim3(256), 0, s, q);
+  else hipLaunchKernelGGL(k_backtransform<KFAC_MAX_SKETCH>, dim3(backtransform_blocks(r)), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 
@@ -960,12 +1004,8 @@ KFAC_GLAUNCH(launch_tri_select_g, k_tri_select_g, EigTask, 512)
 KFAC_GLAUNCH(launch_tri_vec_g, k_tri_vec_g, EigTask, 32)
 KFAC_GLAUNCH(launch_tri_cluster_lead_g, k_tri_cluster_lead_g, EigTask, 256)
 KFAC_GLAUNCH(launch_tri_cluster_g, k_tri_cluster_g, EigTask, 256)
-KFAC_GLAUNCH(launch_backtransform1_g, k_backtransform_g, EigTask, 256)
-KFAC_GLAUNCH(launch_backtransform4_g, k_backtransform4_g, EigTask, 256)
-hipError_t launch_backtransform_g(const EigTask* t, GroupMap gm, int blocks, int nc, hipStream_t s) {
-  return nc == 4 ? launch_backtransform4_g(t, gm, blocks, s) : launch_backtransform1_g(t, gm, blocks, s);
-}
+KFAC_GLAUNCH(launch_backtransform_g, k_backtransform_g, EigTask, 256)
 int tri_bisect_blocks(int n) { return (n + BIS_PER_BLOCK - 1) / BIS_PER_BLOCK; }
 int tri_vec_blocks(int r) { return (r + 31) / 32; }
-int backtransform_blocks(int r, int nc) { return (r + 4 * nc - 1) / (4 * nc); }
+int backtransform_blocks(int r) { return (r + 31) / 32; }
 }  // namespace kfac

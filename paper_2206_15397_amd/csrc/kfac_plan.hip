@@ -440,7 +440,6 @@ void build_branch(kfac_plan* P, char* base, int* status, Tables& T, int br, int&
     // ---- small eigensolver (randomized: C = Q^T F Q; exact: F itself) --------------
     std::vector<EigTask> et;
     std::vector<int> one, onen, gxb, nbb, gxv, nbv, gxbt, nbbt;
-    int bt4 = 0;
     Work wtri, wbt;
     for (size_t i = 0; i < P->f.size(); ++i) {
       if (!in_f(i)) continue;
@@ -461,7 +460,6 @@ void build_branch(kfac_plan* P, char* base, int* status, Tables& T, int br, int&
       one.push_back(1); onen.push_back(1);
       gxb.push_back(tri_bisect_blocks(q.n)); nbb.push_back(tri_bisect_blocks(q.n));
       gxv.push_back(tri_vec_blocks(q.r)); nbv.push_back(tri_vec_blocks(q.r));
-      bt4 += backtransform_blocks(q.r, 4);
     }
     T.add(K_TRIDIAG, et, one, onen, false, false, wtri);
     T.add(K_PREP, et, one, onen);
@@ -470,14 +468,11 @@ void build_branch(kfac_plan* P, char* base, int* status, Tables& T, int br, int&
     T.add(K_VEC, et, gxv, nbv);
     T.add(K_CLEAD, et, one, onen);
     T.add(K_CLUSTER, et, one, onen);
-    // four columns per wavefront when that still gives about a workgroup per compute unit
-    const int bt_nc = bt4 >= 256 ? 4 : 1;
     for (const EigTask& q : et) {
-      gxbt.push_back(backtransform_blocks(q.r, bt_nc));
-      nbbt.push_back(backtransform_blocks(q.r, bt_nc));
+      gxbt.push_back(backtransform_blocks(q.r));
+      nbbt.push_back(backtransform_blocks(q.r));
     }
     T.add(K_BT, et, gxbt, nbbt, false, false, wbt);
-    T.recs.back().cfg = bt_nc == 4 ? 1 : 0;
     // ---- Ritz vectors U = Q P[:, :r] --------------------------------------------------
     {
       std::vector<GemmP> g;
@@ -827,7 +822,7 @@ hipError_t launch_rec(const kfac_plan* plan, const LaunchRec& r, hipStream_t s) 
       case K_VEC: e = launch_tri_vec_g((const EigTask*)tp, gm, r.blocks, s); break;
       case K_CLEAD: e = launch_tri_cluster_lead_g((const EigTask*)tp, gm, r.blocks, s); break;
       case K_CLUSTER: e = launch_tri_cluster_g((const EigTask*)tp, gm, r.blocks, s); break;
-      case K_BT: e = launch_backtransform_g((const EigTask*)tp, gm, r.blocks, r.cfg == 1 ? 4 : 1, s); break;
+      case K_BT: e = launch_backtransform_g((const EigTask*)tp, gm, r.blocks, s); break;
       case K_SIGN_P: e = launch_sign_partial_g((const SignTask*)tp, gm, r.blocks, s); break;
       case K_SIGN_A: e = launch_sign_apply_g((const SignTask*)tp, gm, r.blocks, s); break;
       default: return hipErrorInvalidValue;
