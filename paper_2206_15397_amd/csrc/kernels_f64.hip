@@ -691,7 +691,6 @@ KFAC_GROUPED_KERNEL(k_cholinv_g, cholinv_body, CholInvTask, BC_NT)
 // (partial tiles summed through LDS), then X_IK = -X_II T.
 struct TtSmem {
   double Xc[288][BC + 1];         // X_JK for J >= K (absolute rows)
-  double Lr[BC][288 + 1];         // L_I, [BC K, BC I) (columns relative to BC K)
   double Tp[4][BC][BC + 1];       // per-wavefront partial T
   double Xd[BC][BC + 1];          // X_II
 };
@@ -710,42 +709,41 @@ __device__ __forceinline__ void trtri_cols_body(const CholInvTask& q, int bx, in
   for (int e = tid; e < BC * BC; e += TT_NT) sm.Xc[k0 + e / BC][e % BC] = X[(long)(k0 + e / BC) * ldx + k0 + e % BC];
   const int tile = wave % NTILE, ks = wave / NTILE;
   const int rt = tile % CT, ct = tile / CT;
-  // block row I's operands (L_I,[K, I) and X_II) are loaded into registers one step
-  // ahead, while the MFMAs of the previous row run
-  constexpr int RL = BC * 288 / TT_NT;
+  // block row I's operands are loaded into registers one step ahead, while the MFMAs of
+  // the previous row run: L_I,[K, I) straight in the MFMA operand layout (wavefront ks
+  // takes the k-steps 4 ks + 16 m), and one element of X_II per thread
+  static_assert(CT == 1 && KS == 4, "one 16 x 16 tile, four contraction slices");
+  constexpr int NMK = 288 / 16;
   static_assert(BC * BC == TT_NT, "one element of X_II per thread");
-  double rl[RL], rx = 0.0;
+  double ra[NMK], rx = 0.0;
   auto load = [&](int I) {
-    const int i0 = I * BC, w = i0 - k0;
+    const int i0 = I * BC, w = i0 - k0, row = i0 + (lane & 15);
 #pragma unroll
-    for (int u = 0; u < RL; ++u) {
-      const int e = tid + u * TT_NT;
-      const int r = e / w, cc = e - r * w;
-      rl[u] = (e < BC * w && i0 + r < n && k0 + cc < n) ? L[(long)(i0 + r) * ldg + k0 + cc] : 0.0;
+    for (int m = 0; m < NMK; ++m) {
+      const int kk = 4 * ks + 16 * m, col = k0 + kk + (lane >> 4);
+      ra[m] = (kk < w && row < n && col < n) ? L[(long)row * ldg + col] : 0.0;
     }
     rx = X[(long)(i0 + tid / BC) * ldx + i0 + tid % BC];
   };
   if (K + 1 < NB) load(K + 1);
+  __syncthreads();                                             // X_KK in Xc
   for (int I = K + 1; I < NB; ++I) {
     const int i0 = I * BC, w = i0 - k0;
+    double a[NMK];
 #pragma unroll
-    for (int u = 0; u < RL; ++u) {
-      const int e = tid + u * TT_NT;
-      const int r = e / w, cc = e - r * w;
-      if (e < BC * w) sm.Lr[r][cc] = rl[u];
-    }
+    for (int m = 0; m < NMK; ++m) a[m] = ra[m];
     sm.Xd[tid / BC][tid % BC] = rx;
-    __syncthreads();
     if (I + 1 < NB) load(I + 1);
     {
       f64x4 acc = {0, 0, 0, 0};
-      for (int kk = 4 * ks; kk < w; kk += 4 * KS) {
-        const int kc = kk + (lane >> 4);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sm.Lr[rt * 16 + (lane & 15)][kc], sm.Xc[k0 + kc][ct * 16 + (lane & 15)],
-                                                   acc, 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < NMK; ++m) {
+        const int kk = 4 * ks + 16 * m;
+        if (kk < w)                                            // uniform
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], sm.Xc[k0 + kk + (lane >> 4)][lane & 15], acc, 0, 0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sm.Tp[ks][rt * 16 + (lane >> 4) + 4 * r][ct * 16 + (lane & 15)] = acc[r];
+      for (int r = 0; r < 4; ++r) sm.Tp[ks][(lane >> 4) + 4 * r][lane & 15] = acc[r];
     }
     __syncthreads();
     if (KS > 1) {
