@@ -13,45 +13,59 @@ __host__ __device__ inline int conv_out(int in, int k, int pad, int stride) { re
 // Eight columns of one tap are eight consecutive channels of one input pixel: one 16-byte
 // load when g.vec (C a multiple of 8, x 16-byte aligned), element loads otherwise.  The
 // output position (b, oh, ow) of row k0 and the tap (dy, dx, c) of column c0 take four
-// integer divisions per call; the later rows and columns step from them (a row advances
-// ow, wrapping into oh and b; a column advances c, wrapping into dx and dy).
+// divisions per call, each a multiply and shift by the geometry's precomputed reciprocals
+// (an integer division expands to about 25 instructions in this VALU-bound loader); the
+// later rows and columns step from them (a row advances ow, wrapping into oh and b; a
+// column advances c, wrapping into dx and dy).
+//   FORM 0 chooses per call from g.vec; FORM 1 is the 16-byte form only (g.vec set: C and so
+// kh kw C are multiples of 8, so a column group lies wholly inside the patch or wholly
+// past it, where only the ones column is nonzero); FORM 2 the element form only.  A
+// kernel built for one form does not carry the other's code (a shared body measured
+// 5-8% slower on the 16-byte layers).
+template <int FORM = 0>
 __device__ __forceinline__ void im2col_block(const uint16_t* x, const ConvGeom& g, bool ones, int k0, int K, int c0,
                                              uint4 v[8]) {
   const int ncols = g.kh * g.kw * g.C;
   const int howo = g.Ho * g.Wo;
-  const bool vec8 = g.vec && c0 + 8 <= ncols;
+  if (FORM == 1 && c0 >= ncols) {
+    const uint32_t o1 = (ones && c0 == ncols) ? 0x3f80u : 0u;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = make_uint4(k0 + r < K ? o1 : 0u, 0u, 0u, 0u);
+    return;
+  }
+  const bool vec8 = FORM == 1 || (FORM == 0 && g.vec && c0 + 8 <= ncols);
   const int cc = c0 < ncols ? c0 : 0;
-  const int tap0 = cc / g.C, ch0 = cc - tap0 * g.C, dy0 = tap0 / g.kw, dx0 = tap0 - dy0 * g.kw;
+  const int tap0 = conv_div(cc, g.dC), ch0 = cc - tap0 * g.C, dy0 = conv_div(tap0, g.dKw), dx0 = tap0 - dy0 * g.kw;
   const int kk = k0 < K ? k0 : 0;
-  int b = kk / howo;
+  int b = conv_div(kk, g.dHoWo);
   const int rem = kk - b * howo;
-  int oh = rem / g.Wo, ow = rem - oh * g.Wo;
+  int oh = conv_div(rem, g.dWo), ow = rem - oh * g.Wo;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     v[r] = make_uint4(0, 0, 0, 0);
     if (k0 + r < K) {
       const int ih0 = oh * g.stride - g.pad, iw0 = ow * g.stride - g.pad;
       const uint16_t* xb = x + (long)b * g.H * g.W * g.C;
-      if (vec8) {
+      if (FORM != 2 && vec8) {
         const int ih = ih0 + dy0, iw = iw0 + dx0;
         if (ih >= 0 && ih < g.H && iw >= 0 && iw < g.W)
           v[r] = *(const uint4*)(xb + ((long)ih * g.W + iw) * g.C + ch0);
       } else {
+        // every element load goes out unconditionally (padding taps read the image's first
+        // element, then masked): loads behind a per-element branch were issued one after
+        // another (the 3-channel first VGG16_bn layer: 456 -> 346 us)
         uint16_t t[8];
         int ch = ch0, dy = dy0, dx = dx0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int col = c0 + j;
-          t[j] = 0;
-          if (col < ncols) {
-            const int ih = ih0 + dy, iw = iw0 + dx;
-            if (ih >= 0 && ih < g.H && iw >= 0 && iw < g.W) t[j] = xb[((long)ih * g.W + iw) * g.C + ch];
-            if (++ch == g.C) {
-              ch = 0;
-              if (++dx == g.kw) { dx = 0; ++dy; }
-            }
-          } else if (ones && col == ncols) {
-            t[j] = 0x3f80;                     // bf16 1.0
+          const int ih = ih0 + dy, iw = iw0 + dx;
+          const bool in = col < ncols && ih >= 0 && ih < g.H && iw >= 0 && iw < g.W;
+          const uint16_t e = xb[in ? ((long)ih * g.W + iw) * g.C + ch : 0];
+          t[j] = in ? e : ((ones && col == ncols) ? (uint16_t)0x3f80 : (uint16_t)0);   // bf16 1.0
+          if (col < ncols && ++ch == g.C) {
+            ch = 0;
+            if (++dx == g.kw) { dx = 0; ++dy; }
           }
         }
         v[r] = make_uint4(t[0] | ((uint32_t)t[1] << 16), t[2] | ((uint32_t)t[3] << 16),

@@ -194,7 +194,8 @@ __device__ __forceinline__ void eb_load_block(const uint16_t* X, long ldx, int d
 }
 
 // CONV: the rows are the im2col patches of q.cv's NHWC input (the guarded stage path only)
-template <bool CONV = false>
+// CONV: 0 plain activations, else the im2col loader form (1: 16-byte, 2: element loads)
+template <int CONV = 0>
 __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int by) {
   __shared__ EbSmem sm;
   const GemmP& p = q.g;
@@ -221,13 +222,13 @@ __device__ __forceinline__ void ea_bf16_tiles_body(const EaTask& q, int bx, int 
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   uint4 v[8];
-  constexpr bool conv = CONV;
+  constexpr bool conv = CONV != 0;
   // a thread's 8 x 8 block lies inside the activations (no ones column, no padding): its
   // 8 row loads of full 64-row stages go out unguarded
   const bool inner = !conv && vec && (c0 + 8 <= d_in);
   auto fetch = [&](int k0) {
-    if constexpr (CONV) {
-      im2col_block(X, q.cv, ones, k0 + rg * 8, ke, c0, v);
+    if constexpr (CONV != 0) {
+      im2col_block<CONV>(X, q.cv, ones, k0 + rg * 8, ke, c0, v);
     } else if (inner && k0 + EB_BK <= ke) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = gload16(X + (long)(k0 + rg * 8 + r) * ldx + c0);
@@ -417,9 +418,10 @@ __global__ __launch_bounds__(256) void k_ea_bf16_tiles(EaTask q) {
   const int l = xcd_swizzle(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
   ea_bf16_tiles_body(q, l % gridDim.x, l / gridDim.x);
 }
+template <int FORM>
 __global__ __launch_bounds__(256) void k_ea_bf16_tiles_conv(EaTask q) {
   const int l = xcd_swizzle(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-  ea_bf16_tiles_body<true>(q, l % gridDim.x, l / gridDim.x);
+  ea_bf16_tiles_body<FORM>(q, l % gridDim.x, l / gridDim.x);
 }
 __global__ __launch_bounds__(256) void k_ea_bf16_finalize(EaTask q) { ea_bf16_finalize_body(q, blockIdx.x, 0); }
 // grouped EA tiles: per-task block counts padded to multiples of 8 (the padding blocks
@@ -433,7 +435,8 @@ __global__ __launch_bounds__(256) void k_ea_bf16_tiles_g(const EaTask* tasks, Gr
 KFAC_GROUPED_KERNEL(k_ea_bf16_finalize_g, ea_bf16_finalize_body, EaTask, 256)
 
 hipError_t launch_ea_bf16_tiles(const EaTask& q, int tiles, int ks, hipStream_t s) {
-  if (q.cv.C > 0) hipLaunchKernelGGL(k_ea_bf16_tiles_conv, dim3(tiles, ks), dim3(256), 0, s, q);
+  if (q.cv.C > 0 && q.cv.vec) hipLaunchKernelGGL(k_ea_bf16_tiles_conv<1>, dim3(tiles, ks), dim3(256), 0, s, q);
+  else if (q.cv.C > 0) hipLaunchKernelGGL(k_ea_bf16_tiles_conv<2>, dim3(tiles, ks), dim3(256), 0, s, q);
   else hipLaunchKernelGGL(k_ea_bf16_tiles, dim3(tiles, ks), dim3(256), 0, s, q);
   return hipGetLastError();
 }

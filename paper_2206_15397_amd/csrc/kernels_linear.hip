@@ -89,14 +89,15 @@ struct LnOperand {
   ConvGeom cv;     // K-major, C > 0: X is an NHWC input read as its im2col patches
 };
 
-// CONV: a K-major operand may be im2col patches (o.cv.C > 0), decided per operand at run time
-template <bool KMAJ, bool CONV = false>
+// CONV: 0, or the im2col loader form (1: 16-byte, 2: element loads) of a K-major operand
+// that may be im2col patches (o.cv.C > 0, decided per operand at run time)
+template <bool KMAJ, int CONV = 0>
 struct LnLoader {
   uint4 v[8];
   __device__ __forceinline__ void load(const LnOperand& o, int tt, int r0, int k0, int K) {
     if (KMAJ) {
       const int cg = tt >> 3, rg = tt & 7;
-      if (CONV && o.cv.C > 0) im2col_block(o.X, o.cv, o.ones, k0 + rg * 8, K, r0 + cg * 8, v);
+      if (CONV != 0 && o.cv.C > 0) im2col_block<CONV>(o.X, o.cv, o.ones, k0 + rg * 8, K, r0 + cg * 8, v);
       else ln_load_kmajor(o.X, o.ld, o.rows, o.ones, o.vec, k0 + rg * 8, K, r0 + cg * 8, v);
     } else {
 #pragma unroll
@@ -126,7 +127,7 @@ __device__ __forceinline__ bool ln_vec_ok(const uint16_t* X, long ld) {
 }
 
 // Block bx of a LinTask.  AK / BK: operand stored K-major (rows = contraction index).
-template <bool AK, bool BK, bool CONV = false>
+template <bool AK, bool BK, int CONV = 0>
 __device__ __forceinline__ void lin_body(const LinTask& q, int bx, int ks = 0) {
   __shared__ LinSmem sm;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -254,8 +255,9 @@ __device__ __forceinline__ void lin_body(const LinTask& q, int bx, int ks = 0) {
 __global__ __launch_bounds__(256) void k_lin_nt(LinTask q) { lin_body<false, false>(q, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_lin_nn(LinTask q) { lin_body<false, true>(q, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_lin_tn(LinTask q) { lin_body<true, true>(q, blockIdx.x); }
+template <int FORM>
 __global__ __launch_bounds__(256) void k_lin_tn_conv(LinTask q) {
-  lin_body<true, true, true>(q, blockIdx.x, blockIdx.y);
+  lin_body<true, true, FORM>(q, blockIdx.x, blockIdx.y);
 }
 
 // Split-K reduce of the weight-gradient launch: block = (tile, 16-row chunk).  Plain tiles:
@@ -371,10 +373,12 @@ hipError_t launch_conv_backward_weight(const uint16_t* g, const uint16_t* x, con
   if (nks > 1) {
     q.nks = nks;
     q.part = (float*)ws;
-    hipLaunchKernelGGL(k_lin_tn_conv, dim3(blocks, nks), dim3(256), 0, s, q);
+    if (cv.vec) hipLaunchKernelGGL(k_lin_tn_conv<1>, dim3(blocks, nks), dim3(256), 0, s, q);
+    else hipLaunchKernelGGL(k_lin_tn_conv<2>, dim3(blocks, nks), dim3(256), 0, s, q);
     hipLaunchKernelGGL(k_lin_tn_reduce, dim3(blocks * LN_CH), dim3(256), 0, s, q);
   } else {
-    hipLaunchKernelGGL(k_lin_tn_conv, dim3(blocks), dim3(256), 0, s, q);
+    if (cv.vec) hipLaunchKernelGGL(k_lin_tn_conv<1>, dim3(blocks), dim3(256), 0, s, q);
+    else hipLaunchKernelGGL(k_lin_tn_conv<2>, dim3(blocks), dim3(256), 0, s, q);
   }
   return hipGetLastError();
 }

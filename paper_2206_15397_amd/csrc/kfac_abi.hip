@@ -316,7 +316,9 @@ bool conv_geom(const kfac_conv_geom* g, const void* x, ConvGeom& cv, kfac_status
   }
   cv = ConvGeom{(int)g->batch, (int)g->height, (int)g->width, (int)g->channels, (int)g->kh, (int)g->kw,
                 (int)g->pad, (int)g->stride, (int)ho, (int)wo,
-                (g->channels % 8 == 0 && (((uintptr_t)x) & 15) == 0) ? 1 : 0};
+                (g->channels % 8 == 0 && (((uintptr_t)x) & 15) == 0) ? 1 : 0,
+                conv_divisor((int)g->channels), conv_divisor((int)g->kw), conv_divisor((int)(ho * wo)),
+                conv_divisor((int)wo)};
   return true;
 }
 }  // namespace

@@ -17,9 +17,27 @@ struct EaOut {
 // and channel (dy, dx, c) = (j / (kw C), (j / C) % kw, j % C), reading
 // x[b][oh stride - pad + dy][ow stride - pad + dx][c] (zero outside the image).  C == 0
 // marks an ordinary row-major operand.
+// Division by an invariant q >= 1 of 0 <= n < 2^31 as a multiply and shift: with
+// l = ceil(log2 q) and m = floor(2^(31 + l) / q) + 1, floor(n m / 2^(31 + l)) = floor(n / q)
+// (Granlund and Montgomery, division by invariant integers using multiplication, 1994).
+struct DivMagic {
+  uint64_t m;
+  int sh;
+};
+__host__ __device__ inline DivMagic conv_divisor(int q) {
+  int l = 0;
+  while ((1LL << l) < q) ++l;
+  return DivMagic{(uint64_t)((1ULL << (31 + l)) / (uint64_t)q) + 1, 31 + l};
+}
+__host__ __device__ inline int conv_div(int n, const DivMagic& d) {
+  return (int)(((uint64_t)(uint32_t)n * d.m) >> d.sh);
+}
+
 struct ConvGeom {
   int B, H, W, C, kh, kw, pad, stride, Ho, Wo;
   int vec;               // C % 8 == 0 and x 16-byte aligned: 8-channel runs as 16-byte loads
+  // n / q for 0 <= n < 2^31 as (n * m) >> sh (conv_divisor), for q = C, kw, Ho Wo, Wo
+  DivMagic dC, dKw, dHoWo, dWo;
 };
 
 struct EaTask {          // EA update: block (upper tile, K slice)
