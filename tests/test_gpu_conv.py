@@ -72,6 +72,46 @@ def test_conv_factor_ea_and_weight_gradient(case):
     assert rel(G.double().cpu().numpy(), Go) <= 1e-5
 
 
+# (case, bias, misalign): the two im2col loader forms without the ones column (the 16-byte
+# form's groups past the patch are then all zero), and the element form on a channel count
+# that is a multiple of 8 (an input 2 bytes off 16-byte alignment)
+EXTRA = [((4, 8, 8, 16, 24, 3, 3, 1, 1), False, False),
+         ((3, 7, 9, 3, 8, 3, 3, 1, 1), False, False),
+         ((4, 8, 8, 16, 24, 3, 3, 1, 1), True, True),
+         ((2, 9, 9, 8, 16, 3, 3, 0, 2), False, True)]
+
+
+@pytest.mark.parametrize("case,bias,misalign", EXTRA)
+def test_conv_factor_loader_forms(case, bias, misalign):
+    B, H, W, C, Co, kh, kw, pad, st = case
+    rng = np.random.default_rng(sum(case) + 7 * bias + 3 * misalign)
+    xs = torch.from_numpy(rng.standard_normal((B, H, W, C)).astype(np.float32)).to(torch.bfloat16)
+    if misalign:
+        buf = torch.empty(B * H * W * C + 8, dtype=torch.bfloat16, device=DEV)
+        x = buf[1:1 + B * H * W * C].view(B, H, W, C)
+        x.copy_(xs.to(DEV))
+        assert x.data_ptr() % 16 != 0 and x.is_contiguous()
+    else:
+        x = xs.to(DEV)
+    Ho, Wo = (H + 2 * pad - kh) // st + 1, (W + 2 * pad - kw) // st + 1
+    g = torch.from_numpy(rng.standard_normal((B, Ho, Wo, Co)).astype(np.float32)).to(torch.bfloat16).to(DEV)
+    P = patches(x.double().cpu().numpy(), kh, kw, pad, st)
+    n = P.shape[0]
+    d = kh * kw * C + (1 if bias else 0)
+    F0 = np.eye(d) + 0.01 * (lambda m: m + m.T)(rng.standard_normal((d, d)))
+    F = torch.from_numpy(F0.astype(np.float32)).to(DEV)
+    Fb = K().bf16_shadow(F)
+    K().conv_ea_update(F, x, kh, kw, pad, st, 0.9, 1.0 / n, append_ones=bias, F_bf16=Fb)
+    dWb = K().conv_backward_weight(g, x, kh, kw, pad, st, with_bias=bias)
+    torch.cuda.synchronize()
+    Fo = O.ea_update(F0.astype(np.float32).astype(np.float64), P, 0.9, 1.0 / n, append_ones=bias)
+    assert rel(F.double().cpu().numpy(), Fo) <= 1e-5
+    assert torch.equal(Fb, F.to(torch.bfloat16))
+    g2 = g.double().cpu().numpy().reshape(n, Co)
+    Pb = np.concatenate([P, np.ones((n, 1))], 1) if bias else P
+    assert rel(dWb.double().cpu().numpy(), g2.T @ Pb) <= 1e-5
+
+
 def test_conv_layer_autograd_matches_reference():
     """The autograd Function: output, input gradient (framework convolutions on the same bf16
     operands), dW / db against fp32 autograd of the same convolution, J = [dW | db] in the
