@@ -79,4 +79,16 @@ __device__ __forceinline__ void im2col_block(const uint16_t* x, const ConvGeom& 
   }
 }
 
+// Patch staging for inputs whose channel count is not a multiple of 8 (the 3-channel first
+// layer of an image network): their im2col gather takes one 2-byte load per element, so the
+// patches are gathered once into a zero-padded n x ldp buffer in the caller's workspace
+// (16-byte aligned rows, ldp = kh kw C rounded up to 8) and the EA and weight-gradient
+// kernels read it as a plain row-major / K-major operand with 16-byte loads.
+__host__ __device__ inline int conv_patch_ld(const ConvGeom& g) { return (g.kh * g.kw * g.C + 7) / 8 * 8; }
+inline size_t conv_patch_bytes(const ConvGeom& g) {
+  if (g.C % 8 == 0) return 0;
+  const size_t b = (size_t)g.B * g.Ho * g.Wo * conv_patch_ld(g) * sizeof(uint16_t);
+  return (b + 255) / 256 * 256;
+}
+
 }  // namespace kfac

@@ -140,6 +140,7 @@ hipError_t launch_sign_apply_g(const SignTask* t, GroupMap gm, int blocks, hipSt
 // split: the launch holds split-K tasks (ksplit > 1; no transposes, cfg != 4)
 hipError_t launch_gemm_g(const GemmP* t, GroupMap gm, int blocks, bool ta, bool tb, int cfg, bool split, hipStream_t s);
 // EA update of a convolution's input factor from the im2col patches of NHWC bf16 input x
+hipError_t launch_im2col_stage(const uint16_t* x, const ConvGeom& g, uint16_t* P, int ldp, int n, hipStream_t s);
 hipError_t launch_ea_bf16_conv(float* F, int d, long ldf, const uint16_t* x, const ConvGeom& cv, int ones, float rho,
                                float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes, hipStream_t s);
 // weight gradient [dW | db] = g^T [P | 1] of a convolution (P: im2col patches of x), with the

@@ -413,6 +413,27 @@ __device__ __forceinline__ void ea_bf16_finalize_body(const EaTask& q, int bx, i
   ea_finalize_chunk<EB_BT>(q, bx, v);
 }
 
+// Patch staging (conv_patch_bytes): thread t writes rows 8 (t / G) .. +7 of column group
+// t % G (G = ldp / 8) of P, gathered with the element form of the im2col loader.
+__global__ __launch_bounds__(256) void k_im2col_stage(const uint16_t* x, ConvGeom g, uint16_t* P, int ldp, int n) {
+  const int groups = ldp / 8;
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  const long rb = t / groups;
+  const int cgp = (int)(t - rb * groups);
+  const long k0 = rb * 8;
+  if (k0 >= n) return;
+  uint4 v[8];
+  im2col_block<2>(x, g, false, (int)k0, n, cgp * 8, v);
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    if (k0 + r < n) *(uint4*)&P[(k0 + r) * ldp + cgp * 8] = v[r];
+}
+hipError_t launch_im2col_stage(const uint16_t* x, const ConvGeom& g, uint16_t* P, int ldp, int n, hipStream_t s) {
+  const long threads = (long)((n + 7) / 8) * (ldp / 8);
+  if (threads > 0) hipLaunchKernelGGL(k_im2col_stage, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, g, P, ldp, n);
+  return hipGetLastError();
+}
+
 // blocks spread over the XCDs so that consecutive tiles of one slice share an L2
 __global__ __launch_bounds__(256) void k_ea_bf16_tiles(EaTask q) {
   const int l = xcd_swizzle(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);

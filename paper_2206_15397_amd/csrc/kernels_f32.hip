@@ -2,6 +2,7 @@
 // epilogues, the symmetric EA update (Alg. 1 EA lines) with split-K, the Gaussian test
 // matrix (Alg. 2/3 "Sample Gaussian Matrix") and the column sign convention of U.
 #include "kernels.h"
+#include "conv.h"
 
 namespace kfac {
 
@@ -359,6 +360,15 @@ hipError_t launch_ea_bf16(float* F, int d, long ldf, const uint16_t* X, int n, i
 hipError_t launch_ea_bf16_conv(float* F, int d, long ldf, const uint16_t* x, const ConvGeom& cv, int ones, float rho,
                                float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes, hipStream_t s) {
   const int n = cv.B * cv.Ho * cv.Wo, d_in = cv.kh * cv.kw * cv.C;
+  const size_t pb = conv_patch_bytes(cv);
+  if (pb > 0 && ws && (((uintptr_t)ws) & 15) == 0 && ws_bytes >= pb && n > 0) {
+    uint16_t* P = (uint16_t*)ws;
+    const int ldp = conv_patch_ld(cv);
+    hipError_t e = launch_im2col_stage(x, cv, P, ldp, n, s);
+    if (e != hipSuccess) return e;
+    return launch_ea_common(F, d, ldf, nullptr, P, n, d_in, ldp, ones, rho, scale, Fb, ldfb, (char*)ws + pb,
+                            ws_bytes - pb, s);
+  }
   return launch_ea_common(F, d, ldf, nullptr, x, n, d_in, 0, ones, rho, scale, Fb, ldfb, ws, ws_bytes, s, &cv);
 }
 

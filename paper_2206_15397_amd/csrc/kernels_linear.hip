@@ -358,8 +358,24 @@ hipError_t launch_conv_backward_weight(const uint16_t* g, const uint16_t* x, con
   // P (n x kh kw C, K-major, gathered from x), plus the upper tiles of g^T g for Gamma
   const int n = cv.B * cv.Ho * cv.Wo;
   const int N = cv.kh * cv.kw * cv.C + (with_bias ? 1 : 0);
-  LinTask q = lin_task(c_out, N, n, g, c_out, x, 0, with_bias, dWb, lddw, nullptr, 0, nullptr);
-  q.cv = cv;
+  // staged patches (conv_patch_bytes) at the start of the workspace: B becomes a plain K-major
+  // operand (cv.C = 0 selects the ordinary loader), the slices use the rest
+  const uint16_t* Bop = x;
+  long ldb = 0;
+  ConvGeom cvq = cv;
+  const size_t pb = conv_patch_bytes(cv);
+  if (pb > 0 && ws && (((uintptr_t)ws) & 15) == 0 && ws_bytes >= pb && n > 0) {
+    const int ldp = conv_patch_ld(cv);
+    hipError_t e = launch_im2col_stage(x, cv, (uint16_t*)ws, ldp, n, s);
+    if (e != hipSuccess) return e;
+    Bop = (const uint16_t*)ws;
+    ldb = ldp;
+    cvq.C = 0;
+    ws = (char*)ws + pb;
+    ws_bytes -= pb;
+  }
+  LinTask q = lin_task(c_out, N, n, g, c_out, Bop, ldb, with_bias, dWb, lddw, nullptr, 0, nullptr);
+  q.cv = cvq;
   int blocks = q.tiles_m * q.tiles_n;
   if (Gam) {
     q.gam = EaOut{Gam, ldgam, Gamb, ldgb, c_out, rho, (1.f - rho) * scale};
