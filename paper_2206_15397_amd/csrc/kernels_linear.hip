@@ -340,10 +340,14 @@ static int conv_dw_tiles(int c_out, int N) {
   const int tm = (c_out + LN_T - 1) / LN_T, tn = (N + LN_T - 1) / LN_T;
   return tm * tn + tm * (tm + 1) / 2;
 }
+// At most 64 slices: the slice reduce (and the fused EA finalize, 8 elements per thread)
+// sums every slice serially, so hundreds of slices over a few tiles (the first VGG16_bn
+// convolution: 256 over 2 tiles) cost more than they save (conv weight gradients 1034 ->
+// 945 us with 64 at most; 32 measured slower again).
 static int conv_dw_slices(int tiles, long n) {
   const long want = (512 + tiles - 1) / tiles;
   const long most = std::max<long>(1, n / (4 * LN_BK));
-  return (int)std::max<long>(1, std::min<long>(std::min(want, most), 1024));
+  return (int)std::max<long>(1, std::min<long>(std::min(want, most), 64));
 }
 size_t conv_backward_weight_ws_bytes(int c_out, long n, int N) {
   const int tiles = conv_dw_tiles(c_out, N);
