@@ -79,15 +79,22 @@ __device__ __forceinline__ void im2col_block(const uint16_t* x, const ConvGeom& 
   }
 }
 
-// Patch staging for inputs whose channel count is not a multiple of 8 (the 3-channel first
-// layer of an image network): their im2col gather takes one 2-byte load per element, so the
-// patches are gathered once into a zero-padded n x ldp buffer in the caller's workspace
-// (16-byte aligned rows, ldp = kh kw C rounded up to 8) and the EA and weight-gradient
-// kernels read it as a plain row-major / K-major operand with 16-byte loads.
+// Patch staging: the patches gathered once into a zero-padded n x ldp buffer at the head of
+// the caller's workspace (16-byte aligned rows, ldp = kh kw C rounded up to 8), which the EA
+// and weight-gradient kernels then read as a plain row-major / K-major operand: 16-byte
+// loads and the EA's pipelined stages instead of the per-row im2col address arithmetic.
+// Done for every channel count that is not a multiple of 8 (the 3-channel first layer of
+// an image network: one 2-byte load per element otherwise); for the EA also wherever the
+// buffer takes at most kConvStageMax bytes (larger patch matrices, the 64-channel 32 x 32
+// layers of VGG16_bn at batch 128 at 151 MB, stay implicit).  The weight gradient's 16-byte
+// im2col gather is as fast as its ordinary K-major loader, so it stages only the former
+// (staging every small layer measured 938 -> 1021 us for the VGG16_bn weight gradients,
+// while the EA went 1755 -> 1495 us).
+constexpr size_t kConvStageMax = 64u << 20;
 __host__ __device__ inline int conv_patch_ld(const ConvGeom& g) { return (g.kh * g.kw * g.C + 7) / 8 * 8; }
-inline size_t conv_patch_bytes(const ConvGeom& g) {
-  if (g.C % 8 == 0) return 0;
+inline size_t conv_patch_bytes(const ConvGeom& g, bool ea) {
   const size_t b = (size_t)g.B * g.Ho * g.Wo * conv_patch_ld(g) * sizeof(uint16_t);
+  if (g.C % 8 == 0 && (!ea || b > kConvStageMax)) return 0;
   return (b + 255) / 256 * 256;
 }
 

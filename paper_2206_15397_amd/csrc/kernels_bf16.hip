@@ -414,7 +414,9 @@ __device__ __forceinline__ void ea_bf16_finalize_body(const EaTask& q, int bx, i
 }
 
 // Patch staging (conv_patch_bytes): thread t writes rows 8 (t / G) .. +7 of column group
-// t % G (G = ldp / 8) of P, gathered with the element form of the im2col loader.
+// t % G (G = ldp / 8) of P, gathered with the im2col loader's 16-byte form (FORM 1, g.vec)
+// or its element form (FORM 2).
+template <int FORM>
 __global__ __launch_bounds__(256) void k_im2col_stage(const uint16_t* x, ConvGeom g, uint16_t* P, int ldp, int n) {
   const int groups = ldp / 8;
   const long t = (long)blockIdx.x * 256 + threadIdx.x;
@@ -423,14 +425,16 @@ __global__ __launch_bounds__(256) void k_im2col_stage(const uint16_t* x, ConvGeo
   const long k0 = rb * 8;
   if (k0 >= n) return;
   uint4 v[8];
-  im2col_block<2>(x, g, false, (int)k0, n, cgp * 8, v);
+  im2col_block<FORM>(x, g, false, (int)k0, n, cgp * 8, v);
 #pragma unroll
   for (int r = 0; r < 8; ++r)
     if (k0 + r < n) *(uint4*)&P[(k0 + r) * ldp + cgp * 8] = v[r];
 }
 hipError_t launch_im2col_stage(const uint16_t* x, const ConvGeom& g, uint16_t* P, int ldp, int n, hipStream_t s) {
   const long threads = (long)((n + 7) / 8) * (ldp / 8);
-  if (threads > 0) hipLaunchKernelGGL(k_im2col_stage, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, x, g, P, ldp, n);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (threads > 0 && g.vec) hipLaunchKernelGGL(k_im2col_stage<1>, grid, dim3(256), 0, s, x, g, P, ldp, n);
+  else if (threads > 0) hipLaunchKernelGGL(k_im2col_stage<2>, grid, dim3(256), 0, s, x, g, P, ldp, n);
   return hipGetLastError();
 }
 

@@ -360,7 +360,7 @@ hipError_t launch_ea_bf16(float* F, int d, long ldf, const uint16_t* X, int n, i
 hipError_t launch_ea_bf16_conv(float* F, int d, long ldf, const uint16_t* x, const ConvGeom& cv, int ones, float rho,
                                float scale, uint16_t* Fb, long ldfb, void* ws, size_t ws_bytes, hipStream_t s) {
   const int n = cv.B * cv.Ho * cv.Wo, d_in = cv.kh * cv.kw * cv.C;
-  const size_t pb = conv_patch_bytes(cv);
+  const size_t pb = conv_patch_bytes(cv, true);
   if (pb > 0 && ws && (((uintptr_t)ws) & 15) == 0 && ws_bytes >= pb && n > 0) {
     uint16_t* P = (uint16_t*)ws;
     const int ldp = conv_patch_ld(cv);

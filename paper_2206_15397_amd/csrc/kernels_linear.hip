@@ -367,7 +367,7 @@ hipError_t launch_conv_backward_weight(const uint16_t* g, const uint16_t* x, con
   const uint16_t* Bop = x;
   long ldb = 0;
   ConvGeom cvq = cv;
-  const size_t pb = conv_patch_bytes(cv);
+  const size_t pb = conv_patch_bytes(cv, false);
   if (pb > 0 && ws && (((uintptr_t)ws) & 15) == 0 && ws_bytes >= pb && n > 0) {
     const int ldp = conv_patch_ld(cv);
     hipError_t e = launch_im2col_stage(x, cv, (uint16_t*)ws, ldp, n, s);

@@ -330,7 +330,7 @@ size_t kfac_conv_ea_update_workspace(int64_t d, const kfac_conv_geom* geom) {
   ConvGeom cv;
   kfac_status err;
   if (d < 1 || !conv_geom(geom, nullptr, cv, err)) return 0;
-  return ea_workspace_bytes((int)d, (long)cv.B * cv.Ho * cv.Wo) + conv_patch_bytes(cv);
+  return ea_workspace_bytes((int)d, (long)cv.B * cv.Ho * cv.Wo) + conv_patch_bytes(cv, true);
 }
 
 kfac_status kfac_conv_ea_update(float* F, int64_t d, int64_t ldf, const uint16_t* x, const kfac_conv_geom* geom,
@@ -355,7 +355,7 @@ size_t kfac_conv_backward_weight_workspace(int64_t c_out, const kfac_conv_geom* 
   kfac_status err;
   if (c_out < 1 || c_out > (1 << 20) || !conv_geom(geom, nullptr, cv, err)) return 0;
   return conv_backward_weight_ws_bytes((int)c_out, (long)cv.B * cv.Ho * cv.Wo,
-                                       cv.kh * cv.kw * cv.C + (with_bias ? 1 : 0)) + conv_patch_bytes(cv);
+                                       cv.kh * cv.kw * cv.C + (with_bias ? 1 : 0)) + conv_patch_bytes(cv, false);
 }
 
 kfac_status kfac_conv_backward_weight(const uint16_t* g, int64_t c_out, const uint16_t* x,

@@ -81,8 +81,12 @@ EXTRA = [((4, 8, 8, 16, 24, 3, 3, 1, 1), False, False),
          ((2, 9, 9, 8, 16, 3, 3, 0, 2), False, True)]
 
 
+@pytest.mark.parametrize("implicit", [False, True])
 @pytest.mark.parametrize("case,bias,misalign", EXTRA)
-def test_conv_factor_loader_forms(case, bias, misalign):
+def test_conv_factor_loader_forms(case, bias, misalign, implicit):
+    """implicit: an empty workspace, so that neither call stages the patches and both gather
+    them inside the EA and weight-gradient kernels (the staged path is the default for these
+    small patch matrices)."""
     B, H, W, C, Co, kh, kw, pad, st = case
     rng = np.random.default_rng(sum(case) + 7 * bias + 3 * misalign)
     xs = torch.from_numpy(rng.standard_normal((B, H, W, C)).astype(np.float32)).to(torch.bfloat16)
@@ -101,8 +105,9 @@ def test_conv_factor_loader_forms(case, bias, misalign):
     F0 = np.eye(d) + 0.01 * (lambda m: m + m.T)(rng.standard_normal((d, d)))
     F = torch.from_numpy(F0.astype(np.float32)).to(DEV)
     Fb = K().bf16_shadow(F)
-    K().conv_ea_update(F, x, kh, kw, pad, st, 0.9, 1.0 / n, append_ones=bias, F_bf16=Fb)
-    dWb = K().conv_backward_weight(g, x, kh, kw, pad, st, with_bias=bias)
+    ws = torch.empty(0, dtype=torch.uint8, device=DEV) if implicit else None
+    K().conv_ea_update(F, x, kh, kw, pad, st, 0.9, 1.0 / n, append_ones=bias, F_bf16=Fb, workspace=ws)
+    dWb = K().conv_backward_weight(g, x, kh, kw, pad, st, with_bias=bias, workspace=ws)
     torch.cuda.synchronize()
     Fo = O.ea_update(F0.astype(np.float32).astype(np.float64), P, 0.9, 1.0 / n, append_ones=bias)
     assert rel(F.double().cpu().numpy(), Fo) <= 1e-5
