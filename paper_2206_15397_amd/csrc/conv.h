@@ -85,12 +85,13 @@ __device__ __forceinline__ void im2col_block(const uint16_t* x, const ConvGeom& 
 // loads and the EA's pipelined stages instead of the per-row im2col address arithmetic.
 // Done for every channel count that is not a multiple of 8 (the 3-channel first layer of
 // an image network: one 2-byte load per element otherwise); for the EA also wherever the
-// buffer takes at most kConvStageMax bytes (larger patch matrices, the 64-channel 32 x 32
-// layers of VGG16_bn at batch 128 at 151 MB, stay implicit).  The weight gradient's 16-byte
+// buffer takes at most kConvStageMax bytes (every VGG16_bn layer at batch 128, the largest
+// at 144 MB: 64 MB measured 2.31 ms for the 13 layers' K-FAC work, 256 MB 2.25 ms; larger
+// patch matrices stay implicit).  The weight gradient's 16-byte
 // im2col gather is as fast as its ordinary K-major loader, so it stages only the former
 // (staging every small layer measured 938 -> 1021 us for the VGG16_bn weight gradients,
 // while the EA went 1755 -> 1495 us).
-constexpr size_t kConvStageMax = 64u << 20;
+constexpr size_t kConvStageMax = 256u << 20;
 __host__ __device__ inline int conv_patch_ld(const ConvGeom& g) { return (g.kh * g.kw * g.C + 7) / 8 * 8; }
 inline size_t conv_patch_bytes(const ConvGeom& g, bool ea) {
   const size_t b = (size_t)g.B * g.Ho * g.Wo * conv_patch_ld(g) * sizeof(uint16_t);
